@@ -1,0 +1,182 @@
+"""Benchmark: grid-point updates per second of the batched Teukolsky step.
+
+One step advances every instance of the workload by one full two-step
+Lax-Wendroff update (Eqs. (3)-(4), boundary conditions, source injection,
+waveform sampling).  Inputs are seeded and synthetic and resident in HBM
+before the timed region.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload batched|single]
+                    [--precision fp64|fp32c] [--no-cpu-baseline]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "grid-point updates/sec (batched modes) + % HBM roofline; FP32-comp vs FP64"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_UPDATE = {"fp64": 64, "fp32c": 48}
+KERNEL_NAME = {"fp64": "k_fused_fp64", "fp32c": "k_fused_fp32c"}
+KERNEL_SOURCES = ["paper_1206_0270_amd/csrc/tk_kernels.hip", "paper_1206_0270_amd/csrc/tk_device.h",
+                  "paper_1206_0270_amd/csrc/tk_internal.h"]
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def workload(name):
+    from paper_1206_0270_amd import workloads as W
+    if name == "batched":
+        insts = W.config4()["instances"]
+        desc = ("batched uneven: 40 instances, m=1..8 x a in {0,0.3,0.6,0.9,0.99}, "
+                "N_r 4001-16001, N_theta 33-257, r* in [-300,300]M, half Gaussian data, "
+                "half circular-orbit sources")
+    elif name == "single":
+        insts = W.config2()["instances"]
+        desc = "single instance: Kerr a=0.9, s=-2, m=2, 8001 x 129 on [-300,300]M, Gaussian data"
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return insts, desc
+
+
+def traffic_entry(prec, wl):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            data = json.load(f)
+        ent = data.get(f"{KERNEL_NAME[prec]}:{wl}")
+        if not ent or ent.get("kernel_hash") != kernel_hash():
+            return None
+        return float(ent["bytes_per_launch"])
+    except Exception:
+        return None
+
+
+def cpu_baseline(insts, target_s=15.0):
+    """The oracle as it stands, timed on this host on a bounded sample of the
+    same workload: the first instances, a few steps each, setup excluded."""
+    import numpy as np  # noqa: F401
+    import oracle
+    from paper_1206_0270_amd import workloads as W
+
+    threads = oracle.get_threads()
+    done_upd, spent, used = 0, 0.0, 0
+    steps = 2
+    for inst in insts:
+        g = oracle.Grid(M=inst["M"], a=inst["a"], s=inst["s"], m=inst["m"], n_r=inst["n_r"],
+                        n_theta=inst["n_theta"], rstar_min=inst["rstar_min"],
+                        rstar_max=inst["rstar_max"], dt=inst["dt"], i_obs=inst["i_obs"],
+                        extract_every=inst["extract_every"], source=inst.get("source"))
+        g.set_state(*W.initial_data(inst))
+        t0 = time.perf_counter()
+        g.run(steps)
+        spent += time.perf_counter() - t0
+        done_upd += inst["n_r"] * inst["n_theta"] * steps
+        used += 1
+        del g
+        if spent >= target_s:
+            break
+    return dict(value=done_upd / spent, unit="grid-point updates/s", cores=threads, kind="oracle",
+                sample=f"first {used} of {len(insts)} instances, {steps} steps each "
+                       f"({done_upd:.3g} updates, {spent:.1f} s, setup excluded), FP64 C oracle, "
+                       f"OpenMP over theta rows")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=30)
+    ap.add_argument("--workload", default="batched")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32c"])
+    ap.add_argument("--graph-steps", type=int, default=100)
+    ap.add_argument("--rows", type=int, default=0)
+    ap.add_argument("--kernel", default="fused", choices=["fused", "two_pass"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): the stepper's "
+              f"multi-GPU sharding is a design, not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1206_0270_amd import tk
+    from paper_1206_0270_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    insts, desc = workload(args.workload)
+    prec = tk.TK_FP64 if args.precision == "fp64" else tk.TK_FP32_COMP
+    points = W.points(insts)
+    st = tk.Stepper(insts, precision=prec)
+    kern = tk.TK_KERNEL_FUSED if args.kernel == "fused" else tk.TK_KERNEL_TWO_PASS
+    st.set_tuning(kernel=kern, rows_per_tile=args.rows, graph_steps=args.graph_steps)
+    for k, inst in enumerate(insts):
+        st.set_fields(k, *W.initial_data(inst))
+    print(f"# workload {args.workload}: {len(insts)} instances, {points} points, "
+          f"{st.workspace_bytes / 2**30:.2f} GiB workspace", file=sys.stderr, flush=True)
+    st.step(args.warmup)
+    torch.cuda.synchronize()
+    stream = st.stream
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    st.step(args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    print(f"# timed {args.steps} steps: events {gpu_ms:.3f} ms, wall {wall * 1e3:.3f} ms",
+          file=sys.stderr, flush=True)
+    elapsed = max(wall, gpu_ms / 1e3)
+    value = points * args.steps / elapsed
+    launch_s = gpu_ms / 1e3 / args.steps
+    bpu = BYTES_PER_UPDATE[args.precision]
+    achieved = points * bpu / launch_s / 1e9
+    traffic = traffic_entry(args.precision, args.workload)
+    st.close()
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "grid-point updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+bf16comp",
+        "data": "synthetic",
+        "config": {"workload": desc, "instances": len(insts), "points": points,
+                   "precision": args.precision, "kernel": args.kernel,
+                   "graph_steps": args.graph_steps, "rows_per_tile": args.rows},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": KERNEL_NAME[args.precision] if args.kernel == "fused" else "k_two_pass_*",
+                     "algorithmic_bytes_per_launch": points * bpu,
+                     "avg_launch_ms": launch_s * 1e3},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(insts)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

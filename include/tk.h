@@ -1,0 +1,185 @@
+/*
+ * tk.h -- C ABI of the MI355X Teukolsky m-mode time stepper.
+ *
+ * The library advances the complex fields (Phi, Pi) of one or many
+ * azimuthal m-modes of the Teukolsky master equation (Eq. (1) of McKennon,
+ * Forrester & Khanna, "High Accuracy Gravitational Waveforms from Black Hole
+ * Binary Inspirals Using OpenCL", decomposed by their Eq. (2)) on 2+1D
+ * (r*, theta) grids, with the two-step Lax-Wendroff scheme of Eqs. (3)-(4),
+ * the angular and radial boundary conditions of Section 2.2, a smeared
+ * Gaussian point-particle source (Section 2.3, item 1) and waveform sampling
+ * (Section 5).  All stepping runs in HIP kernels on the device.
+ *
+ * Conventions
+ *  - Units G = c = 1; M is the black hole mass, a its spin (|a| < M), s the
+ *    spin weight (-2 <= s <= 2), m the azimuthal number.
+ *  - Grid: r*_i = rstar_min + i h, h = (rstar_max - rstar_min)/(n_r - 1),
+ *    i = 0 .. n_r-1;  theta_j = j pi/(n_theta - 1), j = 0 .. n_theta-1
+ *    (poles included).
+ *  - Host field arrays are row-major [theta_j][r*_i][re, im] (r* fastest,
+ *    complex interleaved), n_theta * n_r * 2 doubles, caller-owned.
+ *  - Device memory: the library allocates none for the fields.  The caller
+ *    queries tk_workspace_bytes, allocates that much device memory (for
+ *    instance a torch tensor) and binds it with tk_bind_workspace; it stays
+ *    caller-owned and must outlive the context.  The library owns only small
+ *    host structures, its stream events and captured graphs.
+ *  - Every entry point returns a tk_status; on error the context is left
+ *    unchanged and tk_last_error(ctx) describes the failure.  No C++
+ *    exception crosses the ABI.
+ *  - Work is enqueued on the HIP stream given to tk_init_grid.  Entry points
+ *    that return host data (tk_get_fields, tk_extract) synchronise that
+ *    stream first.  A context must not be used from two threads at once.
+ */
+#ifndef TK_H
+#define TK_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TK_ABI_VERSION 1
+
+typedef struct tk_ctx tk_ctx;
+
+typedef enum {
+    TK_OK = 0,
+    TK_E_INVALID = 1,   /* bad argument or description; nothing changed     */
+    TK_E_NOMEM = 2,     /* workspace too small / host allocation failed     */
+    TK_E_DEVICE = 3,    /* a HIP call failed (message in tk_last_error)     */
+    TK_E_STATE = 4,     /* call not allowed now (e.g. no workspace bound,   */
+                        /* waveform ring overrun)                           */
+    TK_E_UNSTABLE = 5,  /* dt above the scheme's stability bound            */
+    TK_E_NONFINITE = 6  /* extracted samples contain NaN or Inf             */
+} tk_status;
+
+typedef enum {
+    TK_FP64 = 0,      /* FP64 storage and arithmetic (the oracle-equivalent path) */
+    TK_FP32_COMP = 1  /* FP32 storage and stencil arithmetic, compensated time
+                         accumulation (bf16 compensation term per value), FP64
+                         source injection                                    */
+} tk_precision;
+
+enum {
+    TK_FLAG_FORCE_DT = 1 /* accept a dt above the stability bound */
+};
+
+/* One instance = one (a, s, m) mode on one grid.
+ * Eqs. (2)-(4); the boundary conditions follow from the parity of |m|
+ * (Section 2.2). */
+typedef struct {
+    double M, a;
+    int s, m;
+    int n_r, n_theta;     /* >= 5 each */
+    double rstar_min, rstar_max;
+    double dt;            /* time step (M) */
+    double rstar_obs;     /* waveform sampling column: nearest node to rstar_obs */
+    int extract_every;    /* steps between waveform samples; 0 = no sampling  */
+    int wave_capacity;    /* device ring size in samples (0 -> 4096)          */
+    int flags;            /* TK_FLAG_* */
+} tk_instance_desc;
+
+typedef enum {
+    TK_SRC_NONE = 0,
+    TK_SRC_CIRCULAR_GAUSSIAN = 1
+} tk_source_kind;
+
+/* Smeared point particle (Section 2.3, item 1): the Pi equation gets
+ *   F = amplitude * exp(-i m (Omega t + phase0)) * g_r(r* - r*(r0)) * g_th(theta - pi/2)
+ * with g(xi) = exp(-xi^2/(2 sigma^2)) / (sigma sqrt(2 pi)) for
+ * |xi| <= window_sigmas * sigma and 0 beyond; sigma_r = sigma_r_cells * h,
+ * sigma_th = sigma_th_cells * dtheta; Omega = sqrt(M)/(r0^{3/2} + a sqrt(M))
+ * (prograde circular equatorial orbit).  Evaluated in FP64 in every
+ * precision mode, at t^n in the first Lax-Wendroff step and t^n + dt/2 in
+ * the second. */
+typedef struct {
+    int kind;
+    double r0, amplitude, phase0;
+    double sigma_r_cells, sigma_th_cells, window_sigmas;
+} tk_source_desc;
+
+/* Kernel choice and launch shape (the only per-architecture tuning the
+ * paper reports is the work-group size, Section 4). */
+typedef enum {
+    TK_KERNEL_AUTO = 0,
+    TK_KERNEL_TWO_PASS = 1, /* half-step array through HBM, one thread per point */
+    TK_KERNEL_FUSED = 2     /* both steps in one pass, theta-marching columns   */
+} tk_kernel;
+
+typedef struct {
+    int kernel;        /* tk_kernel */
+    int rows_per_tile; /* fused kernel: theta rows per work item (0 = default) */
+    int graph_steps;   /* steps per captured HIP graph (0 = no graphs)        */
+} tk_tuning;
+
+/* Set up the grids of n_inst instances (tortoise inversion, radial and
+ * angular coefficient tables, work decomposition) on the host.  No device
+ * memory is touched.  hip_stream is a hipStream_t (NULL = default stream).
+ * Returns TK_E_UNSTABLE if some instance's dt exceeds the stability bound of
+ * the scheme with its angular terms (unless TK_FLAG_FORCE_DT), TK_E_INVALID
+ * for an invalid description.  On success *out owns the context. */
+tk_status tk_init_grid(const tk_instance_desc *inst, int n_inst, tk_precision prec, void *hip_stream,
+                       tk_ctx **out);
+
+/* Bytes of device workspace the context needs (fields double-buffered,
+ * tables, waveform rings). */
+tk_status tk_workspace_bytes(const tk_ctx *ctx, size_t *bytes);
+
+/* Bind caller-owned device memory of at least tk_workspace_bytes bytes
+ * (256-byte aligned).  Uploads the tables and zeroes the fields and the
+ * step counter.  May be called once per context. */
+tk_status tk_bind_workspace(tk_ctx *ctx, void *dev_ptr, size_t bytes);
+
+/* Copy host fields of instance inst into the current state (synchronous).
+ * phi, pi: [n_theta][n_r][2] doubles.  Does not change the step counter. */
+tk_status tk_set_fields(tk_ctx *ctx, int inst, const double *phi, const double *pi);
+
+/* Copy the current state of instance inst to host arrays (synchronises). */
+tk_status tk_get_fields(tk_ctx *ctx, int inst, double *phi, double *pi);
+
+/* Set (or with kind = TK_SRC_NONE, remove) the particle source of inst. */
+tk_status tk_set_source(tk_ctx *ctx, int inst, const tk_source_desc *src);
+
+/* Advance every instance by n_steps full Lax-Wendroff steps (Eqs. (3)-(4)
+ * with the Section 2.2 boundary conditions), asynchronously on the stream. */
+tk_status tk_step(tk_ctx *ctx, long n_steps);
+
+/* Copy the waveform samples of inst taken since the last call, oldest first,
+ * to out ([sample][theta][re, im], at most max_samples samples) and drain
+ * them.  Sample k holds Phi(t, r*_obs, theta_j) at t = (k+1) extract_every dt
+ * after step counter 0.  Returns TK_E_STATE if more samples than the ring
+ * holds were produced since the last call, TK_E_NONFINITE if a copied
+ * sample is not finite. */
+tk_status tk_extract(tk_ctx *ctx, int inst, double *out, long max_samples, long *n_samples);
+
+/* Step counter (steps taken since tk_bind_workspace or the last
+ * tk_set_step); time of instance k is step * dt_k. */
+tk_status tk_get_step(const tk_ctx *ctx, long *step);
+tk_status tk_set_step(tk_ctx *ctx, long step);
+
+/* Kernel variant / launch shape (TK_E_INVALID for unsupported values). */
+tk_status tk_set_tuning(tk_ctx *ctx, const tk_tuning *t);
+tk_status tk_get_tuning(const tk_ctx *ctx, tk_tuning *t);
+
+/* Wait for all work enqueued by the context. */
+tk_status tk_synchronize(tk_ctx *ctx);
+
+/* Release the context (never frees the caller's workspace). */
+tk_status tk_destroy(tk_ctx *ctx);
+
+/* Last error message of ctx (or of the last failed tk_init_grid if ctx is
+ * NULL).  Valid until the next call on the same context. */
+const char *tk_last_error(const tk_ctx *ctx);
+
+/* Largest stable dt of the scheme for one description (same rule as the
+ * TK_E_UNSTABLE check). */
+tk_status tk_stable_dt(const tk_instance_desc *inst, double *dt_max);
+
+int tk_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TK_H */

@@ -1,0 +1,696 @@
+// C ABI of the Teukolsky m-mode stepper: context management, workspace
+// layout on caller-owned device memory, stepping (eager or HIP graphs),
+// field I/O and waveform extraction.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "tk_internal.h"
+#include "tk_kernels.h"
+
+using namespace tk;
+
+struct tk_ctx {
+    std::vector<HostInst> inst;
+    tk_precision prec = TK_FP64;
+    hipStream_t stream = nullptr;
+    std::string err;
+    int device = 0;
+    // workspace
+    char *ws = nullptr;
+    size_t ws_bytes = 0, need = 0;
+    size_t off_ctl = 0, off_inst = 0, off_blocks = 0, off_work = 0;
+    std::vector<int2> blocks;          // two-pass decomposition
+    std::vector<WorkItem> work;        // fused decomposition
+    int work_rows = 0;                 // rows_per_tile the work list was built for
+    size_t work_cap = 0;               // capacity of the work list area (items)
+    std::vector<DevInst> hdev;         // host mirror of the device descriptors
+    long long step = 0;
+    tk_tuning tuning{TK_KERNEL_AUTO, 0, 0};
+    // captured graph (steps, kernel, rows) for replay
+    hipGraphExec_t gexec = nullptr;
+    int g_steps = 0, g_kernel = -1, g_rows = -1;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+tk_status fail(tk_ctx *c, tk_status s, const std::string &msg)
+{
+    if (c)
+        c->err = msg;
+    else
+        g_err = msg;
+    return s;
+}
+
+#define TK_HIP(ctx, call)                                                                                  \
+    do {                                                                                                   \
+        hipError_t e_ = (call);                                                                            \
+        if (e_ != hipSuccess)                                                                              \
+            return fail((ctx), TK_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_));            \
+    } while (0)
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+bool finite_all(const double *p, size_t n)
+{
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+std::string validate(const tk_instance_desc &d)
+{
+    char b[256];
+    if (!(d.M > 0) || !std::isfinite(d.M)) return "M must be positive and finite";
+    if (!(std::fabs(d.a) < d.M)) return "|a| must be below M";
+    if (d.s < -2 || d.s > 2) return "s must be in [-2, 2]";
+    if (d.n_r < 5 || d.n_theta < 5) return "n_r and n_theta must be >= 5";
+    if (d.n_r > (1 << 22) || d.n_theta > (1 << 16) || (double)d.n_r * d.n_theta > 1.5e9)
+        return "grid too large";
+    if (!(d.rstar_max > d.rstar_min) || !std::isfinite(d.rstar_min) || !std::isfinite(d.rstar_max))
+        return "need rstar_min < rstar_max, finite";
+    if (!(d.dt > 0) || !std::isfinite(d.dt)) return "dt must be positive and finite";
+    if (d.extract_every < 0 || d.wave_capacity < 0) return "extract_every and wave_capacity must be >= 0";
+    if (!std::isfinite(d.rstar_obs)) return "rstar_obs must be finite";
+    double h = (d.rstar_max - d.rstar_min) / (d.n_r - 1);
+    long io = std::lround((d.rstar_obs - d.rstar_min) / h);
+    if (io < 0 || io >= d.n_r) {
+        std::snprintf(b, sizeof b, "rstar_obs %.17g outside the grid", d.rstar_obs);
+        return b;
+    }
+    return "";
+}
+
+// Fused work list: strips of kFusedCols output columns x chunks of rows,
+// longest first (waves are dispatched roughly in order).
+void build_work(tk_ctx *c, int rows)
+{
+    c->work.clear();
+    for (size_t k = 0; k < c->inst.size(); ++k) {
+        const tk_instance_desc &d = c->inst[k].desc;
+        int rc = rows > 0 ? std::max(rows, 3) : d.n_theta;
+        for (int j0 = 0; j0 < d.n_theta; j0 += rc) {
+            int j1 = std::min(d.n_theta, j0 + rc);
+            // keep a pole chunk at least 3 rows (pole extrapolation needs rows 1, 2)
+            if (d.n_theta - j1 > 0 && d.n_theta - j1 < 3) j1 = d.n_theta;
+            for (int i0 = 0; i0 < d.n_r; i0 += kFusedCols) c->work.push_back(WorkItem{(int)k, i0, j0, j1});
+            if (j1 == d.n_theta) break;
+        }
+    }
+    std::stable_sort(c->work.begin(), c->work.end(),
+                     [](const WorkItem &x, const WorkItem &y) { return (x.j1 - x.j0) > (y.j1 - y.j0); });
+    c->work_rows = rows;
+}
+
+size_t work_capacity(const tk_ctx *c)
+{
+    // upper bound over rows_per_tile >= 3: chunks of 3 rows
+    size_t n = 0;
+    for (const HostInst &h : c->inst) {
+        size_t strips = (h.desc.n_r + kFusedCols - 1) / kFusedCols;
+        n += strips * ((h.desc.n_theta + 2) / 3 + 1);
+    }
+    return n;
+}
+
+void layout(tk_ctx *c)
+{
+    size_t off = 0;
+    const size_t A = 4096;
+    c->off_ctl = off;
+    off = align_up(off + sizeof(DevCtl), A);
+    c->off_inst = off;
+    off = align_up(off + c->inst.size() * sizeof(DevInst), A);
+    c->off_blocks = off;
+    off = align_up(off + c->blocks.size() * sizeof(int2), A);
+    c->off_work = off;
+    c->work_cap = work_capacity(c);
+    off = align_up(off + c->work_cap * sizeof(WorkItem), A);
+    for (HostInst &h : c->inst) {
+        const tk_instance_desc &d = h.desc;
+        size_t pts = (size_t)d.n_theta * h.pitch;
+        h.off_rad = off;
+        off = align_up(off + (size_t)(2 * d.n_r - 1) * sizeof(Radial), A);
+        h.off_ang = off;
+        off = align_up(off + (size_t)d.n_theta * sizeof(Angular), A);
+        size_t ubytes = c->prec == TK_FP64 ? pts * 32 : pts * 16;
+        size_t cbytes = c->prec == TK_FP64 ? 0 : pts * 8;
+        for (int b = 0; b < 2; ++b) {
+            h.off_u[b] = off;
+            off = align_up(off + ubytes, A);
+            h.off_c[b] = off;
+            off = align_up(off + cbytes, A);
+        }
+        h.off_half = off;
+        off = align_up(off + (c->prec == TK_FP64 ? pts * 32 : 0), A);
+        h.off_wave = off;
+        off = align_up(off + (size_t)h.wave_cap * d.n_theta * 16, A);
+    }
+    c->need = off;
+}
+
+DevInst make_dev(const tk_ctx *c, const HostInst &h)
+{
+    DevInst D;
+    std::memset(&D, 0, sizeof D);
+    const tk_instance_desc &d = h.desc;
+    D.n_r = d.n_r;
+    D.n_theta = d.n_theta;
+    D.pitch = h.pitch;
+    D.m_even = (std::abs(d.m) % 2) == 0;
+    D.m = d.m;
+    D.i_obs = h.i_obs;
+    D.extract_every = d.extract_every;
+    D.wave_cap = h.wave_cap;
+    D.h = h.h;
+    D.dth = h.dth;
+    D.dt = d.dt;
+    D.inv_h = 1.0 / h.h;
+    D.inv_dth2 = 1.0 / (h.dth * h.dth);
+    D.inv_2dth = 1.0 / (2.0 * h.dth);
+    D.rstar_min = d.rstar_min;
+    char *ws = c->ws;
+    for (int b = 0; b < 2; ++b) {
+        D.u[b] = ws + h.off_u[b];
+        D.c[b] = ws + h.off_c[b];
+    }
+    D.half = ws + h.off_half;
+    D.rad = (const Radial *)(ws + h.off_rad);
+    D.ang = (const Angular *)(ws + h.off_ang);
+    D.wave = (double *)(ws + h.off_wave);
+    D.src_kind = h.src.kind;
+    D.src_amp = h.src.amplitude;
+    D.src_phase0 = h.src.phase0;
+    D.src_Omega = h.src_Omega;
+    D.src_rstar_p = h.src_rstar_p;
+    D.src_sig_r = h.src.sigma_r_cells * h.h;
+    D.src_sig_th = h.src.sigma_th_cells * h.dth;
+    D.src_win = h.src.window_sigmas;
+    return D;
+}
+
+int resolve_kernel(const tk_ctx *c)
+{
+    int k = c->tuning.kernel;
+    if (k == TK_KERNEL_AUTO) k = TK_KERNEL_FUSED;
+    if (c->prec != TK_FP64) k = TK_KERNEL_FUSED;
+    return k;
+}
+
+tk_status ensure_work(tk_ctx *c)
+{
+    int rows = c->tuning.rows_per_tile;
+    if (!c->work.empty() && c->work_rows == rows) return TK_OK;
+    build_work(c, rows);
+    if (c->work.size() > c->work_cap) return fail(c, TK_E_STATE, "work list exceeds its reserved area");
+    TK_HIP(c, hipMemcpyAsync(c->ws + c->off_work, c->work.data(), c->work.size() * sizeof(WorkItem),
+                             hipMemcpyHostToDevice, c->stream));
+    TK_HIP(c, hipStreamSynchronize(c->stream));
+    return TK_OK;
+}
+
+hipError_t launch_one(tk_ctx *c, int kernel, int kstep)
+{
+    const DevInst *di = (const DevInst *)(c->ws + c->off_inst);
+    const DevCtl *ctl = (const DevCtl *)(c->ws + c->off_ctl);
+    if (kernel == TK_KERNEL_TWO_PASS)
+        return launch_two_pass(di, (const int2 *)(c->ws + c->off_blocks), (int)c->blocks.size(), ctl, kstep,
+                               c->stream);
+    const WorkItem *wk = (const WorkItem *)(c->ws + c->off_work);
+    if (c->prec == TK_FP64) return launch_fused_fp64(di, wk, (int)c->work.size(), ctl, kstep, c->stream);
+    return launch_fused_fp32c(di, wk, (int)c->work.size(), ctl, kstep, c->stream);
+}
+
+tk_status enqueue_eager(tk_ctx *c, int kernel, long n)
+{
+    for (long k = 0; k < n; ++k) {
+        hipError_t e = launch_one(c, kernel, (int)k);
+        if (e != hipSuccess) return fail(c, TK_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+    }
+    TK_HIP(c, launch_bump((DevCtl *)(c->ws + c->off_ctl), (int)n, c->stream));
+    return TK_OK;
+}
+
+void drop_graph(tk_ctx *c)
+{
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+    c->g_steps = 0;
+    c->g_kernel = -1;
+    c->g_rows = -1;
+}
+
+tk_status ensure_graph(tk_ctx *c, int kernel, int G)
+{
+    if (c->gexec && c->g_steps == G && c->g_kernel == kernel && c->g_rows == c->tuning.rows_per_tile) return TK_OK;
+    drop_graph(c);
+    hipGraph_t g = nullptr;
+    TK_HIP(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    tk_status st = TK_OK;
+    for (int k = 0; k < G && st == TK_OK; ++k) {
+        hipError_t e = launch_one(c, kernel, k);
+        if (e != hipSuccess) st = fail(c, TK_E_DEVICE, std::string("capture launch: ") + hipGetErrorString(e));
+    }
+    if (st == TK_OK) {
+        hipError_t e = launch_bump((DevCtl *)(c->ws + c->off_ctl), G, c->stream);
+        if (e != hipSuccess) st = fail(c, TK_E_DEVICE, std::string("capture bump: ") + hipGetErrorString(e));
+    }
+    hipError_t e = hipStreamEndCapture(c->stream, &g);
+    if (st != TK_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return fail(c, TK_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        c->gexec = nullptr;
+        return fail(c, TK_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    c->g_steps = G;
+    c->g_kernel = kernel;
+    c->g_rows = c->tuning.rows_per_tile;
+    return TK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tk_abi_version(void) { return TK_ABI_VERSION; }
+
+const char *tk_last_error(const tk_ctx *ctx) { return ctx ? ctx->err.c_str() : g_err.c_str(); }
+
+tk_status tk_stable_dt(const tk_instance_desc *inst, double *dt_max)
+{
+    if (!inst || !dt_max) return fail(nullptr, TK_E_INVALID, "null argument");
+    std::string v = validate(*inst);
+    if (!v.empty()) return fail(nullptr, TK_E_INVALID, v);
+    *dt_max = stable_dt_bound(*inst);
+    return TK_OK;
+}
+
+tk_status tk_init_grid(const tk_instance_desc *inst, int n_inst, tk_precision prec, void *hip_stream, tk_ctx **out)
+{
+    if (!inst || !out || n_inst <= 0) return fail(nullptr, TK_E_INVALID, "need instances and an output pointer");
+    if (prec != TK_FP64 && prec != TK_FP32_COMP) return fail(nullptr, TK_E_INVALID, "unknown precision");
+    tk_ctx *c = new (std::nothrow) tk_ctx();
+    if (!c) return fail(nullptr, TK_E_NOMEM, "host allocation failed");
+    c->prec = prec;
+    c->stream = (hipStream_t)hip_stream;
+    c->inst.resize(n_inst);
+    for (int k = 0; k < n_inst; ++k) {
+        const tk_instance_desc &d = inst[k];
+        std::string v = validate(d);
+        if (!v.empty()) {
+            delete c;
+            return fail(nullptr, TK_E_INVALID, "instance " + std::to_string(k) + ": " + v);
+        }
+        double bound = stable_dt_bound(d);
+        if (d.dt > bound * (1.0 + 1e-12) && !(d.flags & TK_FLAG_FORCE_DT)) {
+            char b[256];
+            std::snprintf(b, sizeof b, "instance %d: dt %.6g exceeds the stability bound %.6g", k, d.dt, bound);
+            delete c;
+            return fail(nullptr, TK_E_UNSTABLE, b);
+        }
+        HostInst &h = c->inst[k];
+        std::memset(&h, 0, sizeof h);
+        h.desc = d;
+        h.src.kind = TK_SRC_NONE;
+        h.h = (d.rstar_max - d.rstar_min) / (d.n_r - 1);
+        h.dth = M_PI / (d.n_theta - 1);
+        double q = std::sqrt((d.M - d.a) * (d.M + d.a));
+        h.rp = d.M + q;
+        h.rm = d.M - q;
+        h.i_obs = (int)std::lround((d.rstar_obs - d.rstar_min) / h.h);
+        h.pitch = (d.n_r + 63) / 64 * 64;
+        h.wave_cap = d.wave_capacity > 0 ? d.wave_capacity : 4096;
+        h.wave_drained = 0;
+        long long nb = ((long long)d.n_theta * d.n_r + 255) / 256;
+        for (long long b = 0; b < nb; ++b) c->blocks.push_back(int2{k, (int)b});
+    }
+    if (c->blocks.size() > 0x7fffffff) {
+        delete c;
+        return fail(nullptr, TK_E_INVALID, "too many points");
+    }
+    layout(c);
+    *out = c;
+    return TK_OK;
+}
+
+tk_status tk_workspace_bytes(const tk_ctx *ctx, size_t *bytes)
+{
+    if (!ctx || !bytes) return fail(const_cast<tk_ctx *>(ctx), TK_E_INVALID, "null argument");
+    *bytes = ctx->need;
+    return TK_OK;
+}
+
+tk_status tk_bind_workspace(tk_ctx *c, void *dev_ptr, size_t bytes)
+{
+    if (!c || !dev_ptr) return fail(c, TK_E_INVALID, "null argument");
+    if (c->ws) return fail(c, TK_E_STATE, "workspace already bound");
+    if (bytes < c->need) return fail(c, TK_E_NOMEM, "workspace smaller than tk_workspace_bytes");
+    if ((uintptr_t)dev_ptr % 256 != 0) return fail(c, TK_E_INVALID, "workspace must be 256-byte aligned");
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, dev_ptr) != hipSuccess || attr.type != hipMemoryTypeDevice)
+        return fail(c, TK_E_INVALID, "workspace is not device memory");
+    c->ws = (char *)dev_ptr;
+    c->ws_bytes = bytes;
+    tk_status st = TK_OK;
+    // tables
+    c->hdev.resize(c->inst.size());
+    for (size_t k = 0; k < c->inst.size() && st == TK_OK; ++k) {
+        HostInst &h = c->inst[k];
+        std::vector<Radial> rad(2 * h.desc.n_r - 1);
+        std::vector<Angular> ang(h.desc.n_theta);
+        fill_radial(h, rad.data());
+        fill_angular(h, ang.data());
+        c->hdev[k] = make_dev(c, h);
+        hipError_t e = hipMemcpyAsync(c->ws + h.off_rad, rad.data(), rad.size() * sizeof(Radial),
+                                      hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(c->ws + h.off_ang, ang.data(), ang.size() * sizeof(Angular), hipMemcpyHostToDevice,
+                               c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) st = fail(c, TK_E_DEVICE, std::string("table upload: ") + hipGetErrorString(e));
+    }
+    if (st == TK_OK) {
+        // zero everything after the tables: fields, compensation, half array, rings, control
+        hipError_t e = hipMemsetAsync(c->ws + c->off_ctl, 0, sizeof(DevCtl), c->stream);
+        for (size_t k = 0; k < c->inst.size() && e == hipSuccess; ++k) {
+            const HostInst &h = c->inst[k];
+            e = hipMemsetAsync(c->ws + h.off_u[0], 0, h.off_wave - h.off_u[0], c->stream);
+            if (e == hipSuccess)
+                e = hipMemsetAsync(c->ws + h.off_wave, 0, (size_t)h.wave_cap * h.desc.n_theta * 16, c->stream);
+        }
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(c->ws + c->off_inst, c->hdev.data(), c->hdev.size() * sizeof(DevInst),
+                               hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(c->ws + c->off_blocks, c->blocks.data(), c->blocks.size() * sizeof(int2),
+                               hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) st = fail(c, TK_E_DEVICE, std::string("workspace init: ") + hipGetErrorString(e));
+    }
+    if (st == TK_OK) st = ensure_work(c);
+    if (st != TK_OK) {
+        c->ws = nullptr;
+        c->ws_bytes = 0;
+        return st;
+    }
+    c->step = 0;
+    return TK_OK;
+}
+
+static tk_status check_inst(tk_ctx *c, int inst)
+{
+    if (!c) return TK_E_INVALID;
+    if (inst < 0 || inst >= (int)c->inst.size()) return fail(c, TK_E_INVALID, "instance index out of range");
+    if (!c->ws) return fail(c, TK_E_STATE, "no workspace bound");
+    return TK_OK;
+}
+
+// FP32-compensated storage: value = f + c with f = fp32(x), c = bf16(x - f).
+static inline uint16_t bf16_rne(float x)
+{
+    uint32_t u;
+    std::memcpy(&u, &x, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+static inline float bf16_to_f(uint16_t b)
+{
+    uint32_t u = (uint32_t)b << 16;
+    float x;
+    std::memcpy(&x, &u, 4);
+    return x;
+}
+
+tk_status tk_set_fields(tk_ctx *c, int inst, const double *phi, const double *pi)
+{
+    tk_status st = check_inst(c, inst);
+    if (st != TK_OK) return st;
+    if (!phi || !pi) return fail(c, TK_E_INVALID, "null field pointer");
+    const HostInst &h = c->inst[inst];
+    const int nr = h.desc.n_r, nt = h.desc.n_theta, p = h.pitch;
+    const int cur = (int)(c->step & 1);
+    if (c->prec == TK_FP64) {
+        std::vector<double> buf((size_t)nt * p * 4, 0.0);
+        for (int j = 0; j < nt; ++j)
+            for (int i = 0; i < nr; ++i) {
+                size_t s = ((size_t)j * nr + i) * 2, d = ((size_t)j * p + i) * 4;
+                buf[d + 0] = phi[s];
+                buf[d + 1] = phi[s + 1];
+                buf[d + 2] = pi[s];
+                buf[d + 3] = pi[s + 1];
+            }
+        TK_HIP(c, hipMemcpyAsync(c->ws + h.off_u[cur], buf.data(), buf.size() * sizeof(double),
+                                 hipMemcpyHostToDevice, c->stream));
+        TK_HIP(c, hipStreamSynchronize(c->stream));
+    } else {
+        std::vector<float> fb((size_t)nt * p * 4, 0.0f);
+        std::vector<uint16_t> cb((size_t)nt * p * 4, 0);
+        for (int j = 0; j < nt; ++j)
+            for (int i = 0; i < nr; ++i) {
+                size_t s = ((size_t)j * nr + i) * 2, d = ((size_t)j * p + i) * 4;
+                const double v[4] = {phi[s], phi[s + 1], pi[s], pi[s + 1]};
+                for (int q = 0; q < 4; ++q) {
+                    float f = (float)v[q];
+                    fb[d + q] = f;
+                    cb[d + q] = bf16_rne((float)(v[q] - (double)f));
+                }
+            }
+        TK_HIP(c, hipMemcpyAsync(c->ws + h.off_u[cur], fb.data(), fb.size() * sizeof(float), hipMemcpyHostToDevice,
+                                 c->stream));
+        TK_HIP(c, hipMemcpyAsync(c->ws + h.off_c[cur], cb.data(), cb.size() * sizeof(uint16_t),
+                                 hipMemcpyHostToDevice, c->stream));
+        TK_HIP(c, hipStreamSynchronize(c->stream));
+    }
+    return TK_OK;
+}
+
+tk_status tk_get_fields(tk_ctx *c, int inst, double *phi, double *pi)
+{
+    tk_status st = check_inst(c, inst);
+    if (st != TK_OK) return st;
+    if (!phi || !pi) return fail(c, TK_E_INVALID, "null field pointer");
+    const HostInst &h = c->inst[inst];
+    const int nr = h.desc.n_r, nt = h.desc.n_theta, p = h.pitch;
+    const int cur = (int)(c->step & 1);
+    if (c->prec == TK_FP64) {
+        std::vector<double> buf((size_t)nt * p * 4);
+        TK_HIP(c, hipMemcpyAsync(buf.data(), c->ws + h.off_u[cur], buf.size() * sizeof(double),
+                                 hipMemcpyDeviceToHost, c->stream));
+        TK_HIP(c, hipStreamSynchronize(c->stream));
+        for (int j = 0; j < nt; ++j)
+            for (int i = 0; i < nr; ++i) {
+                size_t d = ((size_t)j * nr + i) * 2, s = ((size_t)j * p + i) * 4;
+                phi[d] = buf[s];
+                phi[d + 1] = buf[s + 1];
+                pi[d] = buf[s + 2];
+                pi[d + 1] = buf[s + 3];
+            }
+    } else {
+        std::vector<float> fb((size_t)nt * p * 4);
+        std::vector<uint16_t> cb((size_t)nt * p * 4);
+        TK_HIP(c, hipMemcpyAsync(fb.data(), c->ws + h.off_u[cur], fb.size() * sizeof(float), hipMemcpyDeviceToHost,
+                                 c->stream));
+        TK_HIP(c, hipMemcpyAsync(cb.data(), c->ws + h.off_c[cur], cb.size() * sizeof(uint16_t),
+                                 hipMemcpyDeviceToHost, c->stream));
+        TK_HIP(c, hipStreamSynchronize(c->stream));
+        for (int j = 0; j < nt; ++j)
+            for (int i = 0; i < nr; ++i) {
+                size_t d = ((size_t)j * nr + i) * 2, s = ((size_t)j * p + i) * 4;
+                double v[4];
+                for (int q = 0; q < 4; ++q) v[q] = (double)fb[s + q] + (double)bf16_to_f(cb[s + q]);
+                phi[d] = v[0];
+                phi[d + 1] = v[1];
+                pi[d] = v[2];
+                pi[d + 1] = v[3];
+            }
+    }
+    return TK_OK;
+}
+
+tk_status tk_set_source(tk_ctx *c, int inst, const tk_source_desc *src)
+{
+    tk_status st = check_inst(c, inst);
+    if (st != TK_OK) return st;
+    if (!src) return fail(c, TK_E_INVALID, "null source");
+    HostInst &h = c->inst[inst];
+    tk_source_desc s = *src;
+    double Om = 0.0, rsp = 0.0;
+    if (s.kind == TK_SRC_CIRCULAR_GAUSSIAN) {
+        if (!(s.r0 > h.rp) || !std::isfinite(s.r0)) return fail(c, TK_E_INVALID, "r0 must lie outside the horizon");
+        if (!(s.sigma_r_cells > 0) || !(s.sigma_th_cells > 0) || !(s.window_sigmas > 0) ||
+            !std::isfinite(s.amplitude) || !std::isfinite(s.phase0))
+            return fail(c, TK_E_INVALID, "source widths, window, amplitude and phase must be positive/finite");
+        Om = orbit_frequency(h.desc.M, h.desc.a, s.r0);
+        rsp = tortoise_of_x(h.desc.M, h.desc.a, s.r0 - h.rp);
+    } else if (s.kind != TK_SRC_NONE) {
+        return fail(c, TK_E_INVALID, "unknown source kind");
+    }
+    h.src = s;
+    h.src_Omega = Om;
+    h.src_rstar_p = rsp;
+    c->hdev[inst] = make_dev(c, h);
+    TK_HIP(c, hipMemcpyAsync(c->ws + c->off_inst + inst * sizeof(DevInst), &c->hdev[inst], sizeof(DevInst),
+                             hipMemcpyHostToDevice, c->stream));
+    TK_HIP(c, hipStreamSynchronize(c->stream));
+    return TK_OK;
+}
+
+tk_status tk_step(tk_ctx *c, long n_steps)
+{
+    if (!c) return TK_E_INVALID;
+    if (n_steps < 0 || n_steps > (1L << 40)) return fail(c, TK_E_INVALID, "n_steps out of range");
+    if (!c->ws) return fail(c, TK_E_STATE, "no workspace bound");
+    if (n_steps == 0) return TK_OK;
+    const int kernel = resolve_kernel(c);
+    if (kernel == TK_KERNEL_FUSED) {
+        tk_status st = ensure_work(c);
+        if (st != TK_OK) return st;
+    }
+    long left = n_steps;
+    const int G = c->tuning.graph_steps;
+    if (G > 0 && c->stream != nullptr && left >= G) {
+        tk_status st = ensure_graph(c, kernel, G);
+        if (st != TK_OK) return st;
+        while (left >= G) {
+            TK_HIP(c, hipGraphLaunch(c->gexec, c->stream));
+            left -= G;
+        }
+    }
+    while (left > 0) {
+        long chunk = std::min(left, 1L << 20);
+        tk_status st = enqueue_eager(c, kernel, chunk);
+        if (st != TK_OK) return st;
+        left -= chunk;
+    }
+    c->step += n_steps;
+    return TK_OK;
+}
+
+tk_status tk_extract(tk_ctx *c, int inst, double *out, long max_samples, long *n_samples)
+{
+    tk_status st = check_inst(c, inst);
+    if (st != TK_OK) return st;
+    if (!n_samples || (max_samples > 0 && !out) || max_samples < 0) return fail(c, TK_E_INVALID, "bad output");
+    HostInst &h = c->inst[inst];
+    *n_samples = 0;
+    const int K = h.desc.extract_every;
+    if (K <= 0) return TK_OK;
+    const long long produced = c->step / K;
+    const long long pending = produced - h.wave_drained;
+    if (pending > h.wave_cap) {
+        char b[200];
+        std::snprintf(b, sizeof b, "waveform ring overrun: %lld samples since the last extract, capacity %d",
+                      pending, h.wave_cap);
+        return fail(c, TK_E_STATE, b);
+    }
+    const long long cnt = std::min<long long>(pending, max_samples);
+    const size_t row = (size_t)h.desc.n_theta * 2;
+    long long done = 0;
+    while (done < cnt) {
+        long long k0 = h.wave_drained + done;
+        long long slot = k0 % h.wave_cap;
+        long long run = std::min<long long>(cnt - done, h.wave_cap - slot);
+        TK_HIP(c, hipMemcpyAsync(out + (size_t)done * row, c->ws + h.off_wave + (size_t)slot * row * sizeof(double),
+                                 (size_t)run * row * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        done += run;
+    }
+    TK_HIP(c, hipStreamSynchronize(c->stream));
+    h.wave_drained += cnt;
+    *n_samples = (long)cnt;
+    if (!finite_all(out, (size_t)cnt * row)) return fail(c, TK_E_NONFINITE, "non-finite waveform sample");
+    return TK_OK;
+}
+
+tk_status tk_get_step(const tk_ctx *c, long *step)
+{
+    if (!c || !step) return TK_E_INVALID;
+    *step = (long)c->step;
+    return TK_OK;
+}
+
+tk_status tk_set_step(tk_ctx *c, long step)
+{
+    if (!c) return TK_E_INVALID;
+    if (step < 0) return fail(c, TK_E_INVALID, "step must be >= 0");
+    if (!c->ws) return fail(c, TK_E_STATE, "no workspace bound");
+    TK_HIP(c, hipStreamSynchronize(c->stream));
+    if ((step & 1) != (c->step & 1)) {
+        // keep the current state: move it into the buffer the new parity reads
+        const int from = (int)(c->step & 1), to = (int)(step & 1);
+        for (const HostInst &h : c->inst) {
+            size_t pts = (size_t)h.desc.n_theta * h.pitch;
+            size_t ub = c->prec == TK_FP64 ? pts * 32 : pts * 16;
+            TK_HIP(c, hipMemcpyAsync(c->ws + h.off_u[to], c->ws + h.off_u[from], ub, hipMemcpyDeviceToDevice,
+                                     c->stream));
+            if (c->prec != TK_FP64)
+                TK_HIP(c, hipMemcpyAsync(c->ws + h.off_c[to], c->ws + h.off_c[from], pts * 8,
+                                         hipMemcpyDeviceToDevice, c->stream));
+        }
+    }
+    DevCtl ctl;
+    std::memset(&ctl, 0, sizeof ctl);
+    ctl.step = step;
+    TK_HIP(c, hipMemcpyAsync(c->ws + c->off_ctl, &ctl, sizeof ctl, hipMemcpyHostToDevice, c->stream));
+    TK_HIP(c, hipStreamSynchronize(c->stream));
+    c->step = step;
+    for (HostInst &h : c->inst) h.wave_drained = h.desc.extract_every > 0 ? step / h.desc.extract_every : 0;
+    return TK_OK;
+}
+
+tk_status tk_set_tuning(tk_ctx *c, const tk_tuning *t)
+{
+    if (!c || !t) return TK_E_INVALID;
+    if (t->kernel < TK_KERNEL_AUTO || t->kernel > TK_KERNEL_FUSED)
+        return fail(c, TK_E_INVALID, "unknown kernel");
+    if (t->kernel == TK_KERNEL_TWO_PASS && c->prec != TK_FP64)
+        return fail(c, TK_E_INVALID, "the two-pass kernel is FP64 only");
+    if (t->rows_per_tile < 0 || (t->rows_per_tile > 0 && t->rows_per_tile < 3))
+        return fail(c, TK_E_INVALID, "rows_per_tile must be 0 or >= 3");
+    if (t->graph_steps < 0 || t->graph_steps > 100000) return fail(c, TK_E_INVALID, "graph_steps out of range");
+    c->tuning = *t;
+    if (c->ws && resolve_kernel(c) == TK_KERNEL_FUSED) {
+        tk_status st = ensure_work(c);
+        if (st != TK_OK) return st;
+    }
+    return TK_OK;
+}
+
+tk_status tk_get_tuning(const tk_ctx *c, tk_tuning *t)
+{
+    if (!c || !t) return TK_E_INVALID;
+    *t = c->tuning;
+    return TK_OK;
+}
+
+tk_status tk_synchronize(tk_ctx *c)
+{
+    if (!c) return TK_E_INVALID;
+    TK_HIP(c, hipStreamSynchronize(c->stream));
+    return TK_OK;
+}
+
+tk_status tk_destroy(tk_ctx *c)
+{
+    if (!c) return TK_E_INVALID;
+    if (c->ws) (void)hipStreamSynchronize(c->stream);
+    drop_graph(c);
+    delete c;
+    return TK_OK;
+}
+
+}  // extern "C"

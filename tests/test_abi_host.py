@@ -1,0 +1,102 @@
+"""CPU checks of the C ABI library: it loads, exports every entry point the
+header declares, and its host-side logic (validation, stability bound) works
+without a device.  No compute call is made here."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1206_0270_amd import tk
+from paper_1206_0270_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "tk.h")).read()
+    return sorted(set(re.findall(r"^(?:tk_status|int|const char \*)\s*(tk_\w+)\s*\(", src, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = tk.load()
+    names = header_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(tk.EXPORTS)
+    assert lib.tk_abi_version() == 1
+
+
+def test_struct_layout_matches_header():
+    # the ctypes mirrors must have the C sizes (x86-64 ABI)
+    assert ctypes.sizeof(tk.InstanceDesc) == 80
+    assert ctypes.sizeof(tk.SourceDesc) == 56
+    assert ctypes.sizeof(tk.Tuning) == 12
+
+
+def _init(insts):
+    lib = tk.load()
+    arr = (tk.InstanceDesc * len(insts))(*insts)
+    ctx = ctypes.c_void_p()
+    st = lib.tk_init_grid(arr, len(insts), tk.TK_FP64, None, ctypes.byref(ctx))
+    return st, ctx
+
+
+def test_init_validation_errors():
+    good = W.config1()["instances"][0]
+    lib = tk.load()
+    for field, val in [("n_r", 3), ("a", 1.0), ("s", 3), ("dt", -1.0), ("rstar_obs", 1e9)]:
+        d = tk.make_desc(good)
+        setattr(d, field, val)
+        st, ctx = _init([d])
+        assert st == tk.TK_E_INVALID, field
+        assert lib.tk_last_error(None)
+    d = tk.make_desc(good)
+    d.rstar_max = d.rstar_min
+    assert _init([d])[0] == tk.TK_E_INVALID
+
+
+def test_unstable_dt_rejected_unless_forced():
+    inst = dict(W.config1()["instances"][0])
+    inst["dt"] = 0.125  # dr*/2: above the angular stability bound
+    st, ctx = _init([tk.make_desc(inst)])
+    assert st == tk.TK_E_UNSTABLE
+    assert b"stability" in tk.load().tk_last_error(None)
+    st, ctx = _init([tk.make_desc(inst, force_dt=True)])
+    assert st == tk.TK_OK
+    lib = tk.load()
+    n = ctypes.c_size_t()
+    assert lib.tk_workspace_bytes(ctx, ctypes.byref(n)) == tk.TK_OK and n.value > 801 * 33 * 64
+    # stepping without a bound workspace is a state error, not a crash
+    assert lib.tk_step(ctx, 1) == tk.TK_E_STATE
+    assert lib.tk_destroy(ctx) == tk.TK_OK
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 5])
+def test_workload_dts_are_below_library_bound(k):
+    for inst in W.CONFIGS[k]()["instances"]:
+        bound = tk.stable_dt(inst)
+        assert inst["dt"] <= bound * (1 + 1e-12), (inst["name"], inst["dt"], bound)
+
+
+def test_batched_workload_dts_are_below_library_bound():
+    for inst in W.config4()["instances"]:
+        assert inst["dt"] <= tk.stable_dt(inst) * (1 + 1e-12), inst["name"]
+
+
+def test_tuning_validation():
+    inst = W.config1()["instances"][0]
+    st, ctx = _init([tk.make_desc(inst)])
+    assert st == tk.TK_OK
+    lib = tk.load()
+    bad = tk.Tuning(7, 0, 0)
+    assert lib.tk_set_tuning(ctx, ctypes.byref(bad)) == tk.TK_E_INVALID
+    bad = tk.Tuning(tk.TK_KERNEL_FUSED, 2, 0)
+    assert lib.tk_set_tuning(ctx, ctypes.byref(bad)) == tk.TK_E_INVALID
+    ok = tk.Tuning(tk.TK_KERNEL_TWO_PASS, 8, 50)
+    assert lib.tk_set_tuning(ctx, ctypes.byref(ok)) == tk.TK_OK
+    got = tk.Tuning()
+    assert lib.tk_get_tuning(ctx, ctypes.byref(got)) == tk.TK_OK
+    assert (got.kernel, got.rows_per_tile, got.graph_steps) == (1, 8, 50)
+    lib.tk_destroy(ctx)

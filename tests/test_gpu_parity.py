@@ -1,0 +1,213 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bar (FP64): relative L2 <= 1e-12 on Phi and Pi over all points, element by
+element on the same seeded inputs; waveform samples to the same bar.
+Determinism checks (batched vs alone, tile shapes, graph vs eager,
+checkpoint/resume) are bitwise.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1206_0270_amd import tk
+from paper_1206_0270_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def oracle_run(inst, steps, phi0=None, pi0=None):
+    g = oracle.Grid(M=inst["M"], a=inst["a"], s=inst["s"], m=inst["m"], n_r=inst["n_r"],
+                    n_theta=inst["n_theta"], rstar_min=inst["rstar_min"],
+                    rstar_max=inst["rstar_max"], dt=inst["dt"], i_obs=inst["i_obs"],
+                    extract_every=inst["extract_every"], source=inst.get("source"))
+    if phi0 is None:
+        phi0, pi0 = W.initial_data(inst)
+    g.set_state(phi0, pi0)
+    g.run(steps)
+    phi, pi = g.get_state()
+    return phi, pi, g.waveform()
+
+
+def gpu_run(insts, steps, kernel=tk.TK_KERNEL_AUTO, rows=0, graph=0, inits=None, chunks=None):
+    st = tk.Stepper(insts, force_dt=True)
+    st.set_tuning(kernel=kernel, rows_per_tile=rows, graph_steps=graph)
+    for k, inst in enumerate(insts):
+        phi0, pi0 = W.initial_data(inst) if inits is None else inits[k]
+        st.set_fields(k, phi0, pi0)
+    for n in (chunks or [steps]):
+        st.step(n)
+    out = [st.get_fields(k) + (st.extract(k),) for k in range(len(insts))]
+    st.close()
+    return out
+
+
+def small_instances():
+    rng = W.rng_for(99)
+    out = []
+    for (n_r, n_th, a, m, src) in [(101, 9, 0.0, 2, None), (130, 17, 0.9, 2, "s"),
+                                   (77, 11, 0.6, 3, None), (200, 13, 0.3, -1, "s"),
+                                   (63, 5, 0.99, 8, None), (125, 33, 0.5, 4, "s")]:
+        init = None if src else dict(center=2.0, width=3.0,
+                                     amps={max(abs(m), 2): complex(rng.standard_normal(), rng.standard_normal())})
+        source = dict(r0=6.0 + 3 * rng.uniform(), phase0=float(rng.uniform(0, 6.28)),
+                      sigma_r_cells=2.0, sigma_th_cells=2.0, window_sigmas=6.0) if src else None
+        out.append(W.instance(a=a, m=m, n_r=n_r, n_theta=n_th, rstar_min=-20.0, rstar_max=25.0,
+                              rstar_obs=20.0, extract_every=3, init=init, source=source,
+                              name=f"small.{n_r}x{n_th}.a{a}.m{m}"))
+    return out
+
+
+@pytest.mark.parametrize("kernel", [tk.TK_KERNEL_FUSED, tk.TK_KERNEL_TWO_PASS])
+def test_small_grids_vs_oracle(kernel):
+    insts = small_instances()
+    steps = 150
+    say("small grids", [i["name"] for i in insts], "kernel", kernel)
+    res = gpu_run(insts, steps, kernel=kernel)
+    for inst, (phi, pi, wave) in zip(insts, res):
+        ophi, opi, owave = oracle_run(inst, steps)
+        e = (rel(phi, ophi), rel(pi, opi), rel(wave, owave))
+        say(inst["name"], e)
+        assert wave.shape == owave.shape
+        assert max(e) <= TOL, (inst["name"], e)
+
+
+def test_first_workload_full_run():
+    inst = W.config1()["instances"][0]
+    steps = W.config1()["steps"]
+    say("first workload 801x33, a=0, steps", steps)
+    (phi, pi, wave), = gpu_run([inst], steps)
+    ophi, opi, owave = oracle_run(inst, steps)
+    e = (rel(phi, ophi), rel(pi, opi), rel(wave, owave))
+    say("rel L2", e)
+    assert wave.shape == owave.shape == (100, 33)
+    assert max(e) <= TOL
+
+
+def test_second_workload_prefix():
+    inst = W.config2()["instances"][0]
+    steps = 300
+    say("second workload 8001x129, a=0.9, steps", steps)
+    (phi, pi, wave), = gpu_run([inst], steps, graph=100)
+    ophi, opi, owave = oracle_run(inst, steps)
+    e = (rel(phi, ophi), rel(pi, opi), rel(wave, owave))
+    say("rel L2", e)
+    assert max(e) <= TOL
+
+
+def test_third_workload_sourced_prefix():
+    inst = W.config3()["instances"][0]
+    steps = 40
+    say("third workload 16001x257 sourced, steps", steps)
+    (phi, pi, wave), = gpu_run([inst], steps)
+    ophi, opi, owave = oracle_run(inst, steps)
+    e = (rel(phi, ophi), rel(pi, opi))
+    say("rel L2", e)
+    assert np.linalg.norm(ophi) > 0
+    assert max(e) <= TOL
+
+
+def test_batched_uneven_workload_vs_oracle():
+    insts = W.config4()["instances"]
+    steps = 6
+    say("batched 40 instances, steps", steps, "points", W.points(insts))
+    res = gpu_run(insts, steps, graph=3)
+    worst = 0.0
+    for inst, (phi, pi, _) in zip(insts, res):
+        ophi, opi, _ = oracle_run(inst, steps)
+        e = max(rel(phi, ophi), rel(pi, opi))
+        worst = max(worst, e)
+        assert e <= TOL, (inst["name"], e)
+    say("worst rel L2", worst)
+
+
+def test_batched_equals_alone_bitwise():
+    insts = small_instances()
+    steps = 40
+    together = gpu_run(insts, steps)
+    for k, inst in enumerate(insts):
+        (phi, pi, wave), = gpu_run([inst], steps)
+        assert np.array_equal(phi, together[k][0]) and np.array_equal(pi, together[k][1])
+        assert np.array_equal(wave, together[k][2])
+
+
+@pytest.mark.parametrize("rows", [3, 4, 7, 16])
+def test_row_chunking_bitwise(rows):
+    insts = small_instances()
+    steps = 30
+    base = gpu_run(insts, steps, rows=0)
+    other = gpu_run(insts, steps, rows=rows)
+    for (a, b) in zip(base, other):
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+
+
+def test_graph_replay_equals_eager_bitwise():
+    insts = small_instances()
+    eager = gpu_run(insts, 70, graph=0)
+    graph = gpu_run(insts, 70, graph=20, chunks=[25, 20, 5, 20])
+    for (a, b) in zip(eager, graph):
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+
+
+def test_checkpoint_resume_bitwise():
+    insts = small_instances()
+    full = gpu_run(insts, 60)
+    st = tk.Stepper(insts, force_dt=True)
+    for k, inst in enumerate(insts):
+        st.set_fields(k, *W.initial_data(inst))
+    st.step(31)
+    saved = [st.get_fields(k) for k in range(len(insts))]
+    st.close()
+    st2 = tk.Stepper(insts, force_dt=True)
+    st2.set_step(31)
+    for k in range(len(insts)):
+        st2.set_fields(k, *saved[k])
+    st2.step(29)
+    for k in range(len(insts)):
+        phi, pi = st2.get_fields(k)
+        assert np.array_equal(phi, full[k][0]) and np.array_equal(pi, full[k][1])
+    assert st2.step_index == 60
+    st2.close()
+
+
+def test_two_pass_and_fused_agree():
+    insts = small_instances()
+    a = gpu_run(insts, 100, kernel=tk.TK_KERNEL_FUSED)
+    b = gpu_run(insts, 100, kernel=tk.TK_KERNEL_TWO_PASS)
+    for x, y in zip(a, b):
+        assert rel(x[0], y[0]) < 1e-13 and rel(x[1], y[1]) < 1e-13
+
+
+def test_extract_overrun_and_nonfinite():
+    inst = W.instance(a=0.3, m=2, n_r=64, n_theta=9, rstar_min=-20.0, rstar_max=20.0,
+                      rstar_obs=10.0, extract_every=1, init=dict(center=0.0, width=3.0, amps={2: 1.0}))
+    st = tk.Stepper([inst], wave_capacity=8)
+    st.set_fields(0, *W.initial_data(inst))
+    st.step(9)
+    with pytest.raises(tk.TkError) as ei:
+        st.extract(0)
+    assert ei.value.status == tk.TK_E_STATE
+    st.set_step(st.step_index)  # restart sampling
+    st.step(5)
+    assert st.extract(0).shape == (5, 9)
+    phi, pi = W.initial_data(inst)
+    phi[4, 40] = np.nan
+    st.set_fields(0, phi, pi)
+    st.step(2)
+    with pytest.raises(tk.TkError) as ei:
+        st.extract(0)
+    assert ei.value.status == tk.TK_E_NONFINITE
+    st.close()
