@@ -74,7 +74,7 @@ typedef struct {
     int n_r, n_theta;     /* >= 5 each */
     double rstar_min, rstar_max;
     double dt;            /* time step (M) */
-    double rstar_obs;     /* waveform sampling column: nearest node to rstar_obs */
+    double rstar_obs;     /* waveform column: node floor((rstar_obs - rstar_min)/h + 1/2) */
     int extract_every;    /* steps between waveform samples; 0 = no sampling  */
     int wave_capacity;    /* device ring size in samples (0 -> 4096)          */
     int flags;            /* TK_FLAG_* */

@@ -31,6 +31,8 @@ struct tk_ctx {
     int work_rows = 0;                 // rows_per_tile the work list was built for
     size_t work_cap = 0;               // capacity of the work list area (items)
     std::vector<DevInst> hdev;         // host mirror of the device descriptors
+    std::vector<std::vector<Radial>> hrad;   // host copies of the coefficient tables
+    std::vector<std::vector<Angular>> hang;
     long long step = 0;
     tk_tuning tuning{TK_KERNEL_AUTO, 0, 0};
     // captured graph (steps, kernel, rows) for replay
@@ -82,7 +84,7 @@ std::string validate(const tk_instance_desc &d)
     if (d.extract_every < 0 || d.wave_capacity < 0) return "extract_every and wave_capacity must be >= 0";
     if (!std::isfinite(d.rstar_obs)) return "rstar_obs must be finite";
     double h = (d.rstar_max - d.rstar_min) / (d.n_r - 1);
-    long io = std::lround((d.rstar_obs - d.rstar_min) / h);
+    long io = (long)std::floor((d.rstar_obs - d.rstar_min) / h + 0.5);
     if (io < 0 || io >= d.n_r) {
         std::snprintf(b, sizeof b, "rstar_obs %.17g outside the grid", d.rstar_obs);
         return b;
@@ -331,7 +333,7 @@ tk_status tk_init_grid(const tk_instance_desc *inst, int n_inst, tk_precision pr
         double q = std::sqrt((d.M - d.a) * (d.M + d.a));
         h.rp = d.M + q;
         h.rm = d.M - q;
-        h.i_obs = (int)std::lround((d.rstar_obs - d.rstar_min) / h.h);
+        h.i_obs = (int)std::floor((d.rstar_obs - d.rstar_min) / h.h + 0.5);  // nearest node, ties up
         h.pitch = (d.n_r + 63) / 64 * 64;
         h.wave_cap = d.wave_capacity > 0 ? d.wave_capacity : 4096;
         h.wave_drained = 0;
@@ -368,12 +370,17 @@ tk_status tk_bind_workspace(tk_ctx *c, void *dev_ptr, size_t bytes)
     tk_status st = TK_OK;
     // tables
     c->hdev.resize(c->inst.size());
+    c->hrad.resize(c->inst.size());
+    c->hang.resize(c->inst.size());
     for (size_t k = 0; k < c->inst.size() && st == TK_OK; ++k) {
         HostInst &h = c->inst[k];
-        std::vector<Radial> rad(2 * h.desc.n_r - 1);
-        std::vector<Angular> ang(h.desc.n_theta);
+        std::vector<Radial> &rad = c->hrad[k];
+        std::vector<Angular> &ang = c->hang[k];
+        rad.resize(2 * h.desc.n_r - 1);
+        ang.resize(h.desc.n_theta);
         fill_radial(h, rad.data());
         fill_angular(h, ang.data());
+        fill_source(h, rad.data(), ang.data());
         c->hdev[k] = make_dev(c, h);
         hipError_t e = hipMemcpyAsync(c->ws + h.off_rad, rad.data(), rad.size() * sizeof(Radial),
                                       hipMemcpyHostToDevice, c->stream);
@@ -544,6 +551,11 @@ tk_status tk_set_source(tk_ctx *c, int inst, const tk_source_desc *src)
     h.src_Omega = Om;
     h.src_rstar_p = rsp;
     c->hdev[inst] = make_dev(c, h);
+    fill_source(h, c->hrad[inst].data(), c->hang[inst].data());
+    TK_HIP(c, hipMemcpyAsync(c->ws + h.off_rad, c->hrad[inst].data(), c->hrad[inst].size() * sizeof(Radial),
+                             hipMemcpyHostToDevice, c->stream));
+    TK_HIP(c, hipMemcpyAsync(c->ws + h.off_ang, c->hang[inst].data(), c->hang[inst].size() * sizeof(Angular),
+                             hipMemcpyHostToDevice, c->stream));
     TK_HIP(c, hipMemcpyAsync(c->ws + c->off_inst + inst * sizeof(DevInst), &c->hdev[inst], sizeof(DevInst),
                              hipMemcpyHostToDevice, c->stream));
     TK_HIP(c, hipStreamSynchronize(c->stream));

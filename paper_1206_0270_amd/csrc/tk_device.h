@@ -89,30 +89,19 @@ __device__ __forceinline__ P4 lw_point(const Coef &c, const P4 &base, cd phm, cd
     return o;
 }
 
-// Normalised Gaussian with a cut at win * sig.
-__device__ __forceinline__ double gauss_cut(double xi, double sig, double win)
+// Time factor of the smeared particle source, exp(-i m (Omega t + phase0)).
+__device__ __forceinline__ cd source_phase(const DevInst &I, double t)
 {
-    if (fabs(xi) > win * sig) return 0.0;
-    return exp(-xi * xi / (2.0 * sig * sig)) / (sig * sqrt(2.0 * M_PI));
-}
-
-// Smeared particle source F(t, r*, theta), FP64.
-__device__ __forceinline__ cd source_at(const DevInst &I, double t, double rstar, double theta)
-{
-    if (I.src_kind != TK_SRC_CIRCULAR_GAUSSIAN) return mk(0, 0);
-    const double gr = gauss_cut(rstar - I.src_rstar_p, I.src_sig_r, I.src_win);
-    if (gr == 0.0) return mk(0, 0);
-    const double gt = gauss_cut(theta - M_PI / 2, I.src_sig_th, I.src_win);
-    if (gt == 0.0) return mk(0, 0);
     const double ph = -(double)I.m * (I.src_Omega * t + I.src_phase0);
-    const double A = I.src_amp * gr * gt;
-    return mk(A * cos(ph), A * sin(ph));
+    return mk(cos(ph), sin(ph));
 }
 
-// Whether a (radial, row) point can carry source at all (cheap pre-test).
-__device__ __forceinline__ bool source_near(const DevInst &I, double rstar)
+// F(t, r*_q, theta_j) = [A g_r(q)] g_theta(j) exp(-i m (Omega t + phase0));
+// the bracket and g_theta are tabulated (zero off the source window).
+__device__ __forceinline__ cd source_value(double gq, double gj, cd e)
 {
-    return I.src_kind == TK_SRC_CIRCULAR_GAUSSIAN && fabs(rstar - I.src_rstar_p) <= I.src_win * I.src_sig_r;
+    const double s = gq * gj;
+    return mk(s * e.re, s * e.im);
 }
 
 }  // namespace tk

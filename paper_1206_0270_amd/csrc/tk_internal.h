@@ -27,14 +27,18 @@ struct alignas(16) Radial {
     double rho2, a2D, rho, Dl;
     double ct_re, ct_im0, ct_imc, K;
     double c1_re, c1_im, c0_re, c0_im;
-    double rstar, pad0, pad1, pad2;
+    double rstar;
+    double srcg;  // amplitude * g_r(r* - r*_p) of the particle source (0 off its window)
+    double pad1, pad2;
 };
 static_assert(sizeof(Radial) == 128, "Radial must stay 128 bytes");
 
 // Angular factors at row j (rows 1 .. n_theta-2; pole rows unused).
 struct alignas(16) Angular {
     double sn2, cs, cot, V;  // sin^2, cos, cot, (m + s cos)^2/sin^2 - s
-    double theta, pad0, pad1, pad2;
+    double theta;
+    double srcg;  // g_theta(theta - pi/2) of the particle source (0 off its window)
+    double pad1, pad2;
 };
 static_assert(sizeof(Angular) == 64, "Angular must stay 64 bytes");
 
@@ -81,6 +85,11 @@ struct HostInst {
     size_t off_u[2], off_c[2], off_half, off_rad, off_ang, off_wave;  // workspace offsets
     long long wave_drained;  // samples already handed out
 };
+
+// Time-independent factors of the smeared particle source: with
+// g(xi) = exp(-xi^2/(2 sig^2)) / (sig sqrt(2 pi)) cut at |xi| > win sig,
+// F(t, r*_q, theta_j) = [A g_r(q)] g_theta(j) exp(-i m (Omega t + phase0)).
+void fill_source(const HostInst &hi, Radial *rad, Angular *ang);
 
 // Host-side setup (tk_setup.cpp)
 double tortoise_of_x(double M, double a, double x);

@@ -30,7 +30,7 @@ __device__ __forceinline__ P4 stage1_at(const DevInst &I, const double4 *u, int 
     const Radial &R = I.rad[2 * i + 1];
     const Angular &A = I.ang[j];
     const Coef c = coef_at(R, A);
-    const cd F = source_at(I, t, R.rstar, A.theta);
+    const cd F = R.srcg * A.srcg != 0.0 ? source_value(R.srcg, A.srcg, source_phase(I, t)) : mk(0, 0);
     return lw_point(c, bar, phm, bar.phi, php, bar.pi, a1 - a0, 0.5 * I.dt, I.inv_h, I.inv_dth2, I.inv_2dth, F);
 }
 
@@ -46,7 +46,7 @@ __device__ __forceinline__ P4 stage2_at(const DevInst &I, const double4 *u, cons
     const Radial &R = I.rad[2 * i];
     const Angular &A = I.ang[j];
     const Coef c = coef_at(R, A);
-    const cd F = source_at(I, t, R.rstar, A.theta);
+    const cd F = R.srcg * A.srcg != 0.0 ? source_value(R.srcg, A.srcg, source_phase(I, t)) : mk(0, 0);
     const P4 un = ld_p4(u + (size_t)j * p + i);
     return lw_point(c, un, phm, til.phi, php, til.pi, h1 - h0, I.dt, I.inv_h, I.inv_dth2, I.inv_2dth, F);
 }
@@ -152,15 +152,6 @@ hipError_t launch_bump(DevCtl *ctl, int n, hipStream_t s)
 
 namespace {
 
-__device__ __forceinline__ P4 shfl_down1(P4 v)
-{
-    return P4{mk(__shfl_down(v.phi.re, 1), __shfl_down(v.phi.im, 1)),
-              mk(__shfl_down(v.pi.re, 1), __shfl_down(v.pi.im, 1))};
-}
-__device__ __forceinline__ P4 shfl_up1(P4 v)
-{
-    return P4{mk(__shfl_up(v.phi.re, 1), __shfl_up(v.phi.im, 1)), mk(__shfl_up(v.pi.re, 1), __shfl_up(v.pi.im, 1))};
-}
 
 struct Lane64 {
     const DevInst *I;
@@ -168,21 +159,18 @@ struct Lane64 {
     double4 *un;
     int c, p, nt;
     bool cin, hv, icol, ov;
-    bool near_h, near_n;
-    double t1, t2;
+    bool near_h, near_n;  // this lane's half node / node lies on the source window
+    cd e1, e2;            // source time factors at t^n and t^n + dt/2
     long long n;
     bool ext;         // this step writes a waveform sample
     long long wslot;  // its ring slot
 };
 
 struct Roll {
-    P4 U[3];   // u^n(c, row)
-    P4 B[3];   // (u^n(c+1,row) + u^n(c,row)) / 2
-    P4 DU[3];  // u^n(c+1,row) - u^n(c,row)
-    P4 HT[3];  // (h(c+1/2,row) + h(c-1/2,row)) / 2
-    P4 DH[3];  // h(c+1/2,row) - h(c-1/2,row)
-    P4 pre;    // prefetched u^n row
-    P4 keep;   // an output row kept for the pole condition
+    P4 U[3];  // u^n(c, row), slot = row mod 3 (rows r-1, r, r+1 at march row r)
+    P4 H[3];  // u^{n+1/2}(c+1/2, row), slot = row mod 3 (rows r-2, r-1, r)
+    P4 pre;   // prefetched u^n row
+    P4 keep;  // an output row kept for the pole condition
 };
 
 __device__ __forceinline__ P4 load_row(const Lane64 &L, int row)
@@ -190,14 +178,11 @@ __device__ __forceinline__ P4 load_row(const Lane64 &L, int row)
     return L.cin ? ld_p4(L.u + (size_t)row * L.p + L.c) : zero4();
 }
 
-template <int S>
-__device__ __forceinline__ void take_u(Roll &R, P4 own)
-{
-    const P4 nb = shfl_down1(own);
-    R.U[S] = own;
-    R.B[S] = half_sum(nb, own);
-    R.DU[S] = nb - own;
-}
+__device__ __forceinline__ cd shfl_down1(cd v) { return mk(__shfl_down(v.re, 1), __shfl_down(v.im, 1)); }
+__device__ __forceinline__ cd shfl_up1(cd v) { return mk(__shfl_up(v.re, 1), __shfl_up(v.im, 1)); }
+__device__ __forceinline__ P4 shfl_down1(const P4 &v) { return P4{shfl_down1(v.phi), shfl_down1(v.pi)}; }
+__device__ __forceinline__ P4 shfl_up1(const P4 &v) { return P4{shfl_up1(v.phi), shfl_up1(v.pi)}; }
+__device__ __forceinline__ cd avg(cd a, cd b) { return mk((a.re + b.re) * 0.5, (a.im + b.im) * 0.5); }
 
 __device__ __forceinline__ void emit(const Lane64 &L, int row, P4 v)
 {
@@ -209,17 +194,38 @@ __device__ __forceinline__ void emit(const Lane64 &L, int row, P4 v)
     }
 }
 
-// Eq. (4) at output row o with half rows in slots SM (o-1), S0 (o), SP (o+1).
-template <int SM, int S0, int SP>
-__device__ __forceinline__ P4 out_row(const Lane64 &L, const Radial &Rn, const Roll &R, int o)
+// Eq. (3) at half row r: u^n rows r-1 (UM), r (U0), r+1 (UP) of this column;
+// the column to the right comes by lane shuffles.
+__device__ __forceinline__ P4 half_row(const Lane64 &L, const Radial &Rh, const P4 &UM, const P4 &U0, const P4 &UP,
+                                       int r)
 {
     const DevInst &I = *L.I;
+    const cd nm = shfl_down1(UM.phi), np = shfl_down1(UP.phi);
+    const P4 n0 = shfl_down1(U0);
+    if (!L.hv) return zero4();
+    const P4 bar = half_sum(n0, U0);
+    const Angular &A = I.ang[r];
+    const Coef cf = coef_at(Rh, A);
+    const cd F = L.near_h ? source_value(Rh.srcg, A.srcg, L.e1) : mk(0, 0);
+    return lw_point(cf, bar, avg(nm, UM.phi), bar.phi, avg(np, UP.phi), bar.pi, n0 - U0, 0.5 * I.dt, I.inv_h,
+                    I.inv_dth2, I.inv_2dth, F);
+}
+
+// Eq. (4) at output row o: half rows o-1 (HM), o (H0), o+1 (HP) of this
+// column (at c+1/2); the column at c-1/2 comes by lane shuffles.
+__device__ __forceinline__ P4 out_row(const Lane64 &L, const Radial &Rn, const P4 &Uo, const P4 &HM, const P4 &H0,
+                                      const P4 &HP, int o)
+{
+    const DevInst &I = *L.I;
+    const cd lm = shfl_up1(HM.phi), lp = shfl_up1(HP.phi);
+    const P4 l0 = shfl_up1(H0);
     if (!L.icol) return zero4();
+    const P4 til = half_sum(H0, l0);
     const Angular &A = I.ang[o];
     const Coef cf = coef_at(Rn, A);
-    const cd F = L.near_n ? source_at(I, L.t2, Rn.rstar, A.theta) : mk(0, 0);
-    return lw_point(cf, R.U[S0], R.HT[SM].phi, R.HT[S0].phi, R.HT[SP].phi, R.HT[S0].pi, R.DH[S0], I.dt, I.inv_h,
-                    I.inv_dth2, I.inv_2dth, F);
+    const cd F = L.near_n ? source_value(Rn.srcg, A.srcg, L.e2) : mk(0, 0);
+    return lw_point(cf, Uo, avg(HM.phi, lm), til.phi, avg(HP.phi, lp), til.pi, H0 - l0, I.dt, I.inv_h, I.inv_dth2,
+                    I.inv_2dth, F);
 }
 
 // One march iteration at half row r (slot SR = r mod 3).
@@ -227,45 +233,20 @@ template <int SR>
 __device__ __forceinline__ void march(const Lane64 &L, const Radial &Rh, const Radial &Rn, Roll &R, int r,
                                       int out_lo, int out_hi, int u_last, bool north)
 {
-    constexpr int SM = (SR + 2) % 3;  // row r-1 (and r+2)
-    constexpr int SP = (SR + 1) % 3;  // row r+1 (and r-2)
+    constexpr int SM = (SR + 2) % 3;  // row r-1
+    constexpr int SP = (SR + 1) % 3;  // row r+1 (U) / row r-2 (H)
     const DevInst &I = *L.I;
-    // u^n row r+1 (prefetched last iteration), then prefetch row r+2
-    take_u<SP>(R, R.pre);
+    R.U[SP] = R.pre;
     if (r + 2 <= u_last) R.pre = load_row(L, r + 2);
-    // Eq. (3): half step at (c+1/2, r); row r-1 of B sits in slot SM
-    P4 h = zero4();
-    if (L.hv) {
-        const Angular &A = I.ang[r];
-        const Coef cf = coef_at(Rh, A);
-        const cd F = L.near_h ? source_at(I, L.t1, Rh.rstar, A.theta) : mk(0, 0);
-        h = lw_point(cf, R.B[SR], R.B[SM].phi, R.B[SR].phi, R.B[SP].phi, R.B[SR].pi, R.DU[SR], 0.5 * I.dt, I.inv_h,
-                     I.inv_dth2, I.inv_2dth, F);
-    }
-    const P4 hl = shfl_up1(h);
-    R.HT[SR] = half_sum(h, hl);
-    R.DH[SR] = h - hl;
-    if (north && r == 2) {
-        // half-step pole row 0 (slot of row r-2 = SP) from rows 1, 2
-        R.HT[SP].phi = I.m_even ? mk(pole_x(R.HT[SM].phi.re, R.HT[SR].phi.re), pole_x(R.HT[SM].phi.im, R.HT[SR].phi.im))
-                                : mk(0, 0);
-    }
+    R.H[SR] = half_row(L, Rh, R.U[SM], R.U[SR], R.U[SP], r);
+    if (north && r == 2) R.H[SP] = I.m_even ? pole_bc(R.H[SM], R.H[SR]) : zero4();  // half row 0
     const int o = r - 1;
     if (o >= out_lo && o <= out_hi) {
-        // Eq. (4) at row o = r-1: half rows r-2 (SP), r-1 (SM), r (SR); u^n row r-1 (SM)
-        const DevInst &II = I;
-        P4 v = zero4();
-        if (L.icol) {
-            const Angular &A = II.ang[o];
-            const Coef cf = coef_at(Rn, A);
-            const cd F = L.near_n ? source_at(II, L.t2, Rn.rstar, A.theta) : mk(0, 0);
-            v = lw_point(cf, R.U[SM], R.HT[SP].phi, R.HT[SM].phi, R.HT[SR].phi, R.HT[SM].pi, R.DH[SM], II.dt, II.inv_h,
-                         II.inv_dth2, II.inv_2dth, F);
-        }
+        const P4 v = out_row(L, Rn, R.U[SM], R.H[SP], R.H[SM], R.H[SR], o);
         emit(L, o, v);
         if (north && o == 1) R.keep = v;
-        if (north && o == 2) emit(L, 0, II.m_even ? pole_bc(R.keep, v) : zero4());
-        if (o == II.n_theta - 3) R.keep = v;
+        if (north && o == 2) emit(L, 0, I.m_even ? pole_bc(R.keep, v) : zero4());
+        if (o == I.n_theta - 3) R.keep = v;
     }
 }
 
@@ -277,9 +258,8 @@ __device__ __forceinline__ void south(const Lane64 &L, const Radial &Rn, Roll &R
     constexpr int SP = (SR + 1) % 3;  // row nt-1 (free slot)
     const DevInst &I = *L.I;
     const int nt = I.n_theta;
-    R.HT[SP].phi = I.m_even ? mk(pole_x(R.HT[SR].phi.re, R.HT[SM].phi.re), pole_x(R.HT[SR].phi.im, R.HT[SM].phi.im))
-                            : mk(0, 0);
-    const P4 v = out_row<SM, SR, SP>(L, Rn, R, nt - 2);
+    R.H[SP] = I.m_even ? pole_bc(R.H[SR], R.H[SM]) : zero4();  // half row nt-1
+    const P4 v = out_row(L, Rn, R.U[SR], R.H[SM], R.H[SR], R.H[SP], nt - 2);
     emit(L, nt - 2, v);
     emit(L, nt - 1, I.m_even ? pole_bc(v, R.keep) : zero4());
 }
@@ -307,8 +287,12 @@ __global__ void __launch_bounds__(256) k_fused_fp64(const DevInst *__restrict__ 
     L.hv = L.c >= 0 && L.c <= nr - 2;
     L.icol = L.c >= 1 && L.c <= nr - 2;
     L.ov = lane >= 1 && lane <= kFusedCols && L.c < nr;
-    L.t1 = (double)L.n * I.dt;
-    L.t2 = (double)L.n * I.dt + 0.5 * I.dt;
+    if (I.src_kind == TK_SRC_CIRCULAR_GAUSSIAN) {
+        L.e1 = source_phase(I, (double)L.n * I.dt);
+        L.e2 = source_phase(I, (double)L.n * I.dt + 0.5 * I.dt);
+    } else {
+        L.e1 = L.e2 = mk(0, 0);
+    }
     L.ext = I.extract_every > 0 && (L.n + 1) % I.extract_every == 0;
     L.wslot = L.ext ? ((L.n + 1) / I.extract_every - 1) % I.wave_cap : 0;
 
@@ -317,8 +301,8 @@ __global__ void __launch_bounds__(256) k_fused_fp64(const DevInst *__restrict__ 
     else Rh = I.rad[0];
     if (L.icol) Rn = I.rad[2 * L.c];
     else Rn = I.rad[0];
-    L.near_h = L.hv && source_near(I, Rh.rstar);
-    L.near_n = L.icol && source_near(I, Rn.rstar);
+    L.near_h = L.hv && Rh.srcg != 0.0;
+    L.near_n = L.icol && Rn.srcg != 0.0;
 
     const int j0 = it.j0, j1 = it.j1;
     const bool north = j0 == 0, southp = j1 == nt;
@@ -334,14 +318,9 @@ __global__ void __launch_bounds__(256) k_fused_fp64(const DevInst *__restrict__ 
         const P4 va = load_row(L, a), vb = load_row(L, b);
         R.pre = load_row(L, b + 1);
         switch (a % 3) {
-        case 0: take_u<0>(R, va); break;
-        case 1: take_u<1>(R, va); break;
-        default: take_u<2>(R, va); break;
-        }
-        switch (b % 3) {
-        case 0: take_u<0>(R, vb); break;
-        case 1: take_u<1>(R, vb); break;
-        default: take_u<2>(R, vb); break;
+        case 0: R.U[0] = va; R.U[1] = vb; break;
+        case 1: R.U[1] = va; R.U[2] = vb; break;
+        default: R.U[2] = va; R.U[0] = vb; break;
         }
     }
     R.keep = zero4();

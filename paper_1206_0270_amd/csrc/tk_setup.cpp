@@ -112,7 +112,7 @@ void fill_radial(const HostInst &hi, Radial *rad)
         R.c0_re = 6.0 * Dl * Dl / (r * r) + 6.0 * (1.0 + s) * Dl * (r - M) / r;
         R.c0_im = 6.0 * m * a * Dl / r + 4.0 * m * s * a * (r - M);
         R.rstar = rs;
-        R.pad0 = R.pad1 = R.pad2 = 0.0;
+        R.srcg = R.pad1 = R.pad2 = 0.0;
     }
 }
 
@@ -123,7 +123,7 @@ void fill_angular(const HostInst &hi, Angular *ang)
         Angular &A = ang[j];
         double th = j * hi.dth;
         A.theta = th;
-        A.pad0 = A.pad1 = A.pad2 = 0.0;
+        A.srcg = A.pad1 = A.pad2 = 0.0;
         if (j == 0 || j == d.n_theta - 1) {  // coefficients never used on the poles
             A.sn2 = A.cs = A.cot = A.V = 0.0;
             continue;
@@ -135,6 +135,25 @@ void fill_angular(const HostInst &hi, Angular *ang)
         double w = d.m + d.s * cs;
         A.V = w * w / A.sn2 - d.s;
     }
+}
+
+namespace {
+double gauss_cut(double xi, double sig, double win)
+{
+    if (std::fabs(xi) > win * sig) return 0.0;
+    return std::exp(-xi * xi / (2.0 * sig * sig)) / (sig * std::sqrt(2.0 * M_PI));
+}
+}  // namespace
+
+void fill_source(const HostInst &hi, Radial *rad, Angular *ang)
+{
+    const tk_instance_desc &d = hi.desc;
+    const bool on = hi.src.kind == TK_SRC_CIRCULAR_GAUSSIAN;
+    const double sig_r = hi.src.sigma_r_cells * hi.h, sig_t = hi.src.sigma_th_cells * hi.dth;
+    for (int q = 0; q < 2 * d.n_r - 1; ++q)
+        rad[q].srcg = on ? hi.src.amplitude * gauss_cut(rad[q].rstar - hi.src_rstar_p, sig_r, hi.src.window_sigmas) : 0.0;
+    for (int j = 0; j < d.n_theta; ++j)
+        ang[j].srcg = on ? gauss_cut(ang[j].theta - M_PI / 2, sig_t, hi.src.window_sigmas) : 0.0;
 }
 
 // Time-step bound.  With the angular terms inside S, one Lax-Wendroff step

@@ -104,7 +104,7 @@ def instance(M=1.0, a=0.0, s=-2, m=2, n_r=801, n_theta=33, rstar_min=-100.0,
     return dict(M=M, a=a, s=s, m=m, n_r=n_r, n_theta=n_theta,
                 rstar_min=rstar_min, rstar_max=rstar_max, dt=dt,
                 rstar_obs=rstar_obs, extract_every=extract_every,
-                i_obs=int(round((rstar_obs - rstar_min) / h)),
+                i_obs=int(math.floor((rstar_obs - rstar_min) / h + 0.5)),
                 source=source, init=init, name=name)
 
 
