@@ -21,7 +21,7 @@ sys.path.insert(0, ROOT)
 METRIC = "grid-point updates/sec (batched modes) + % HBM roofline; FP32-comp vs FP64"
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_UPDATE = {"fp64": 64, "fp32c": 48}
-KERNEL_NAME = {"fp64": "k_fused_fp64", "fp32c": "k_fused_fp32c"}
+KERNEL_NAME = {"fp64": "k_fused<PolicyF64>", "fp32c": "k_fused<PolicyF32C>"}
 KERNEL_SOURCES = ["paper_1206_0270_amd/csrc/tk_kernels.hip", "paper_1206_0270_amd/csrc/tk_device.h",
                   "paper_1206_0270_amd/csrc/tk_internal.h"]
 
@@ -107,6 +107,9 @@ def main():
     ap.add_argument("--rows", type=int, default=0)
     ap.add_argument("--kernel", default="fused", choices=["fused", "two_pass"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-gib", type=float, default=0.0,
+                    help="instead of the stepper, run a plain device copy of this many GiB "
+                         "(calibrates the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): the stepper's "
@@ -118,6 +121,24 @@ def main():
     from paper_1206_0270_amd import workloads as W
 
     torch.cuda.set_device(0)
+    if args.copy_gib > 0:
+        n = int(args.copy_gib * 2 ** 30)
+        x = torch.ones(n, dtype=torch.uint8, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(args.warmup):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(args.steps):
+            y.copy_(x)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / args.steps
+        print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "ms_per_copy": ms,
+                          "GB_per_s": 2 * n / ms / 1e6}), flush=True)
+        return
     insts, desc = workload(args.workload)
     prec = tk.TK_FP64 if args.precision == "fp64" else tk.TK_FP32_COMP
     points = W.points(insts)

@@ -42,10 +42,14 @@ _dp = ctypes.POINTER(ctypes.c_double)
 
 
 def _lib(kind="f64"):
+    """kind: "f64", "ld", or the path of another build of teuk_oracle.c."""
     if kind not in _LIBS:
-        path = _build.LIBS[kind]
-        if not os.path.exists(path):
-            _build.build()
+        if kind in _build.LIBS:
+            path = _build.LIBS[kind]
+            if not os.path.exists(path):
+                _build.build()
+        else:
+            path = kind
         lib = ctypes.CDLL(path)
         lib.or_tortoise.restype = ctypes.c_double
         lib.or_tortoise.argtypes = [ctypes.c_double] * 3

@@ -21,10 +21,20 @@ LIBS = {
 }
 
 
+BASE_FLAGS = ["gcc", "-std=c99", "-O2", "-fPIC", "-shared", "-fopenmp",
+              "-ffp-contract=off", "-fcx-fortran-rules", "-Wall", "-Wextra",
+              "-Wno-unused-parameter"]
+
+
+def build_one(src, out, long_double=False):
+    """Compile one build of the oracle source (also used by tests that
+    compile deliberately altered copies)."""
+    cmd = list(BASE_FLAGS) + (["-DOR_LONG_DOUBLE"] if long_double else [])
+    subprocess.run(cmd + [src, "-o", out, "-lm"], check=True)
+
+
 def build(verbose=False):
-    base = ["gcc", "-std=c99", "-O2", "-fPIC", "-shared", "-fopenmp",
-            "-ffp-contract=off", "-fcx-fortran-rules", "-Wall", "-Wextra",
-            "-Wno-unused-parameter"]
+    base = list(BASE_FLAGS)
     for kind, out in LIBS.items():
         cmd = list(base)
         if kind == "ld":

@@ -297,19 +297,22 @@ static cplx S_pi(const or_grid *g, int q, int j, cplx phim, cplx phi0, cplx phip
     return g->ct[c] * pi0 + g->cthth[c] * d2 + g->cth[c] * d1 + g->c0[c] * phi0 + F;
 }
 
-/* Pole rows from the two next interior rows (Section 2.2). */
+/* Pole value from the two next interior rows (Section 2.2): for even |m|
+ * d_theta X = 0 to second order, X_pole = (4 X_1 - X_2) / 3; for odd |m|
+ * X_pole = 0.  Used by the stepper and by or_rhs_column alike. */
+static cplx pole_value(const or_grid *g, cplx x1, cplx x2)
+{
+    if (abs(g->desc.m) % 2 == 0)
+        return (4 * x1 - x2) / 3;
+    return 0;
+}
+
 static void pole_bc_rows(const or_grid *g, cplx *X, int ncols)
 {
     int n = g->nth;
-    int even = (abs(g->desc.m) % 2) == 0;
     for (int i = 0; i < ncols; ++i) {
-        if (even) {
-            X[IDX(g, 0, i)] = (4 * X[IDX(g, 1, i)] - X[IDX(g, 2, i)]) / 3;
-            X[IDX(g, n - 1, i)] = (4 * X[IDX(g, n - 2, i)] - X[IDX(g, n - 3, i)]) / 3;
-        } else {
-            X[IDX(g, 0, i)] = 0;
-            X[IDX(g, n - 1, i)] = 0;
-        }
+        X[IDX(g, 0, i)] = pole_value(g, X[IDX(g, 1, i)], X[IDX(g, 2, i)]);
+        X[IDX(g, n - 1, i)] = pole_value(g, X[IDX(g, n - 2, i)], X[IDX(g, n - 3, i)]);
     }
 }
 
@@ -599,21 +602,16 @@ void or_rhs_column(void *hd, int q, const double *phi_col, const double *pi_col,
 {
     or_grid *g = (or_grid *)hd;
     int n = g->nth;
-    int even = (abs(g->desc.m) % 2) == 0;
     cplx *ph = (cplx *)malloc((size_t)n * sizeof(cplx));
     cplx *pp = (cplx *)malloc((size_t)n * sizeof(cplx));
     for (int j = 0; j < n; ++j) {
         ph[j] = (real)phi_col[2 * j] + IU * (real)phi_col[2 * j + 1];
         pp[j] = (real)pi_col[2 * j] + IU * (real)pi_col[2 * j + 1];
     }
-    if (even) {
-        ph[0] = (4 * ph[1] - ph[2]) / 3;
-        ph[n - 1] = (4 * ph[n - 2] - ph[n - 3]) / 3;
-        pp[0] = (4 * pp[1] - pp[2]) / 3;
-        pp[n - 1] = (4 * pp[n - 2] - pp[n - 3]) / 3;
-    } else {
-        ph[0] = ph[n - 1] = pp[0] = pp[n - 1] = 0;
-    }
+    ph[0] = pole_value(g, ph[1], ph[2]);
+    ph[n - 1] = pole_value(g, ph[n - 2], ph[n - 3]);
+    pp[0] = pole_value(g, pp[1], pp[2]);
+    pp[n - 1] = pole_value(g, pp[n - 2], pp[n - 3]);
     out[0] = out[1] = out[2 * (n - 1)] = out[2 * (n - 1) + 1] = 0;
     for (int j = 1; j < n - 1; ++j) {
         cplx v = S_pi(g, q, j, ph[j - 1], ph[j], ph[j + 1], pp[j], 0);

@@ -197,6 +197,8 @@ DevInst make_dev(const tk_ctx *c, const HostInst &h)
     D.src_sig_r = h.src.sigma_r_cells * h.h;
     D.src_sig_th = h.src.sigma_th_cells * h.dth;
     D.src_win = h.src.window_sigmas;
+    D.a2 = d.a * d.a;
+    D.kct = -2.0 * d.s * d.a;
     return D;
 }
 

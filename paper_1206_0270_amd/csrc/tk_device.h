@@ -1,6 +1,8 @@
 // Device-side helpers shared by the HIP kernels: complex arithmetic, the
 // pointwise coefficients of the first-order system, the Lax-Wendroff update
-// of Eqs. (3)-(4) at one point, and the smeared particle source.
+// of Eqs. (3)-(4) at one point, and the smeared particle source.  Templated
+// on the arithmetic type (double for the FP64 path, float for the
+// FP32-compensated path).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -9,34 +11,83 @@
 
 namespace tk {
 
-struct cd {  // complex double
-    double re, im;
+template <typename T>
+struct cx {
+    T re, im;
 };
+using cd = cx<double>;
+
+template <typename T>
+__device__ __forceinline__ cx<T> mkc(T r, T i)
+{
+    return cx<T>{r, i};
+}
 __device__ __forceinline__ cd mk(double r, double i) { return cd{r, i}; }
-__device__ __forceinline__ cd operator+(cd a, cd b) { return cd{a.re + b.re, a.im + b.im}; }
-__device__ __forceinline__ cd operator-(cd a, cd b) { return cd{a.re - b.re, a.im - b.im}; }
-__device__ __forceinline__ cd operator*(double s, cd a) { return cd{s * a.re, s * a.im}; }
-__device__ __forceinline__ cd cmul(cd a, cd b) { return cd{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+template <typename T>
+__device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b)
+{
+    return cx<T>{a.re + b.re, a.im + b.im};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b)
+{
+    return cx<T>{a.re - b.re, a.im - b.im};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> operator*(T s, cx<T> a)
+{
+    return cx<T>{s * a.re, s * a.im};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b)
+{
+    return cx<T>{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> avg(cx<T> a, cx<T> b)
+{
+    return cx<T>{(a.re + b.re) * T(0.5), (a.im + b.im) * T(0.5)};
+}
 
 // (Phi, Pi) at one point
-struct P4 {
-    cd phi, pi;
+template <typename T>
+struct Q4 {
+    cx<T> phi, pi;
 };
-__device__ __forceinline__ P4 operator+(P4 a, P4 b) { return P4{a.phi + b.phi, a.pi + b.pi}; }
-__device__ __forceinline__ P4 operator-(P4 a, P4 b) { return P4{a.phi - b.phi, a.pi - b.pi}; }
-__device__ __forceinline__ P4 half_sum(P4 a, P4 b)
+using P4 = Q4<double>;
+template <typename T>
+__device__ __forceinline__ Q4<T> operator+(Q4<T> a, Q4<T> b)
 {
-    return P4{mk((a.phi.re + b.phi.re) * 0.5, (a.phi.im + b.phi.im) * 0.5),
-              mk((a.pi.re + b.pi.re) * 0.5, (a.pi.im + b.pi.im) * 0.5)};
+    return Q4<T>{a.phi + b.phi, a.pi + b.pi};
+}
+template <typename T>
+__device__ __forceinline__ Q4<T> operator-(Q4<T> a, Q4<T> b)
+{
+    return Q4<T>{a.phi - b.phi, a.pi - b.pi};
+}
+template <typename T>
+__device__ __forceinline__ Q4<T> half_sum(Q4<T> a, Q4<T> b)
+{
+    return Q4<T>{avg(a.phi, b.phi), avg(a.pi, b.pi)};
 }
 // Second-order one-sided Neumann value at a pole: (4 X1 - X2) / 3
-__device__ __forceinline__ double pole_x(double x1, double x2) { return (4.0 * x1 - x2) / 3.0; }
-__device__ __forceinline__ P4 pole_bc(P4 a1, P4 a2)
+template <typename T>
+__device__ __forceinline__ T pole_x(T x1, T x2)
 {
-    return P4{mk(pole_x(a1.phi.re, a2.phi.re), pole_x(a1.phi.im, a2.phi.im)),
-              mk(pole_x(a1.pi.re, a2.pi.re), pole_x(a1.pi.im, a2.pi.im))};
+    return (T(4) * x1 - x2) / T(3);
 }
-__device__ __forceinline__ P4 zero4() { return P4{mk(0, 0), mk(0, 0)}; }
+template <typename T>
+__device__ __forceinline__ Q4<T> pole_bc(Q4<T> a1, Q4<T> a2)
+{
+    return Q4<T>{mkc(pole_x(a1.phi.re, a2.phi.re), pole_x(a1.phi.im, a2.phi.im)),
+                 mkc(pole_x(a1.pi.re, a2.pi.re), pole_x(a1.pi.im, a2.pi.im))};
+}
+template <typename T>
+__device__ __forceinline__ Q4<T> zero_q4()
+{
+    return Q4<T>{mkc(T(0), T(0)), mkc(T(0), T(0))};
+}
+__device__ __forceinline__ P4 zero4() { return zero_q4<double>(); }
 
 __device__ __forceinline__ P4 ld_p4(const double4 *p)
 {
@@ -46,14 +97,16 @@ __device__ __forceinline__ P4 ld_p4(const double4 *p)
 __device__ __forceinline__ void st_p4(double4 *p, P4 v) { *p = make_double4(v.phi.re, v.phi.im, v.pi.re, v.pi.im); }
 
 // Coefficients of u_t + D u_{r*} = S at one (radial position, theta row).
+template <typename T>
 struct Coef {
-    double b, cthth, cth;
-    cd ct, c0, d;
+    T b, cthth, cth;
+    cx<T> ct, c0, d;
 };
 
-__device__ __forceinline__ Coef coef_at(const Radial &R, const Angular &A)
+// From the full tables (two-pass kernel).
+__device__ __forceinline__ Coef<double> coef_at(const Radial &R, const Angular &A)
 {
-    Coef c;
+    Coef<double> c;
     const double Sh2 = R.rho2 - R.a2D * A.sn2;
     const double W = 1.0 / Sh2;
     const double sig = sqrt(W);
@@ -69,24 +122,80 @@ __device__ __forceinline__ Coef coef_at(const Radial &R, const Angular &A)
     return c;
 }
 
-// One Lax-Wendroff update at a point (Eq. (3) with base = averaged fields and
-// fac = dt/2, or Eq. (4) with base = u^n and fac = dt):
-//   out = base - fac [ D du / h - S ],
+// 1/sqrt(x) for x > 0: hardware estimate refined by Newton steps
+// y <- y (3 - x y^2) / 2 (two for double, one for float).
+__device__ __forceinline__ double inv_sqrt(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    const double hx = 0.5 * x;
+    y = fma(y, fma(-hx * y, y, 0.5), y);
+    y = fma(y, fma(-hx * y, y, 0.5), y);
+    return y;
+}
+__device__ __forceinline__ float inv_sqrt(float x)
+{
+    float y = __builtin_amdgcn_rsqf(x);
+    const float hx = 0.5f * x;
+    return fmaf(y, fmaf(-hx * y, y, 0.5f), y);
+}
+
+// Radial factors a fused-kernel lane keeps for its node or half node; the
+// rest of the table is rebuilt from them: rho^2 = rho*rho, a^2 Delta =
+// a2 * Dl, the cos-part of Im ct = kct * Dl with kct = -2 s a.
+template <typename T>
+struct RadV {
+    T rho, Dl, ct_re, ct_im0, K, c1_re, c1_im, c0_re, c0_im;
+};
+constexpr int kRadVals = 9;
+
+template <typename T>
+struct AngV {
+    T sn2, cs, cot, V;
+};
+
+template <typename T>
+__device__ __forceinline__ Coef<T> coef_lean(const RadV<T> &R, const AngV<T> &A, T a2, T kct)
+{
+    Coef<T> c;
+    const T Sh2 = R.rho * R.rho - (a2 * R.Dl) * A.sn2;
+    const T sig = inv_sqrt(Sh2);
+    const T W = sig * sig;
+    c.b = R.rho * sig;
+    c.cthth = R.Dl * W;
+    c.cth = c.cthth * A.cot;
+    c.ct = mkc(W * R.ct_re, W * (R.ct_im0 + (kct * R.Dl) * A.cs));
+    const cx<T> c1 = mkc(W * R.c1_re, W * R.c1_im);
+    c.c0 = mkc(W * (R.c0_re - R.Dl * A.V), W * R.c0_im);
+    const T bp = R.K * A.sn2 * W * sig;
+    c.d = mkc(c.b * bp + c.b * c.ct.re - c1.re, c.b * c.ct.im - c1.im);
+    return c;
+}
+
+// The bracket of Eqs. (3)/(4) at a point: D du / h - S with
 //   S = (Pi_a, ct Pi_a + cthth (d2 Phi_a + cot d1 Phi_a) + c0 Phi_a + F)
 // where Phi_a / Pi_a are the averaged fields (rows j-1, j, j+1 for Phi) and
 // du the difference across the radial stencil.
-__device__ __forceinline__ P4 lw_point(const Coef &c, const P4 &base, cd phm, cd ph0, cd php, cd pi0, const P4 &du,
-                                       double fac, double inv_h, double inv_dth2, double inv_2dth, cd F)
+template <typename T>
+__device__ __forceinline__ Q4<T> lw_bracket(const Coef<T> &c, cx<T> phm, cx<T> ph0, cx<T> php, cx<T> pi0,
+                                            const Q4<T> &du, T inv_h, T inv_dth2, T inv_2dth, cx<T> F)
 {
-    const cd d2 = inv_dth2 * (php - 2.0 * ph0 + phm);
-    const cd d1 = inv_2dth * (php - phm);
-    const cd spi = cmul(c.ct, pi0) + c.cthth * d2 + c.cth * d1 + cmul(c.c0, ph0) + F;
-    const cd adv_phi = inv_h * (c.b * du.phi);
-    const cd adv_pi = inv_h * (cmul(c.d, du.phi) - c.b * du.pi);
-    P4 o;
-    o.phi = base.phi - fac * (adv_phi - pi0);
-    o.pi = base.pi - fac * (adv_pi - spi);
-    return o;
+    const cx<T> d2 = inv_dth2 * (php - T(2) * ph0 + phm);
+    const cx<T> d1 = inv_2dth * (php - phm);
+    const cx<T> spi = cmul(c.ct, pi0) + c.cthth * d2 + c.cth * d1 + cmul(c.c0, ph0) + F;
+    const cx<T> adv_phi = inv_h * (c.b * du.phi);
+    const cx<T> adv_pi = inv_h * (cmul(c.d, du.phi) - c.b * du.pi);
+    return Q4<T>{adv_phi - pi0, adv_pi - spi};
+}
+
+// One Lax-Wendroff update at a point (Eq. (3) with base = averaged fields and
+// fac = dt/2, or Eq. (4) with base = u^n and fac = dt):
+//   out = base - fac [ D du / h - S ].
+template <typename T>
+__device__ __forceinline__ Q4<T> lw_point(const Coef<T> &c, const Q4<T> &base, cx<T> phm, cx<T> ph0, cx<T> php,
+                                          cx<T> pi0, const Q4<T> &du, T fac, T inv_h, T inv_dth2, T inv_2dth, cx<T> F)
+{
+    const Q4<T> br = lw_bracket(c, phm, ph0, php, pi0, du, inv_h, inv_dth2, inv_2dth, F);
+    return Q4<T>{base.phi - fac * br.phi, base.pi - fac * br.pi};
 }
 
 // Time factor of the smeared particle source, exp(-i m (Omega t + phase0)).

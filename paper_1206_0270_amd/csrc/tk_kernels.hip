@@ -137,148 +137,339 @@ hipError_t launch_bump(DevCtl *ctl, int n, hipStream_t s)
 }
 
 // ---------------------------------------------------------------------------
-// Fused FP64 kernel.
+// Fused kernel (FP64, and FP32 with compensated time accumulation).
 //
 // One wavefront per work item: 64 lanes hold r* columns i0-1 .. i0+62 and
 // write the 62 columns i0 .. i0+61; the wave marches over the theta rows of
-// its chunk.  At row r it reads u^n row r+1 once (coalesced, 2 KB), takes
-// the neighbour column u^n_{i+1} by a lane shuffle, forms the half-step
-// value at (i+1/2, r) (Eq. (3)), takes u^{n+1/2}_{i-1/2} by a second
-// shuffle and forms u^{n+1} at row r-1 (Eq. (4)).  The half-step array never
-// leaves registers; u^n is read once and u^{n+1} written once.  Rolling rows
-// live in three register slots indexed by row mod 3 (every index is a
-// compile-time constant inside each unrolled phase).
+// its chunk.  At row r it reads u^n row r+1 once (coalesced, prefetched one
+// row ahead), takes the neighbour column u^n_{i+1} by lane shuffles, forms
+// the half-step value at (i+1/2, r) (Eq. (3)), takes u^{n+1/2}_{i-1/2} by
+// another shuffle and forms u^{n+1} at row r-1 (Eq. (4)).  The half-step
+// array never leaves registers; u^n is read once and u^{n+1} written once.
+// Rolling rows live in three register slots indexed by row mod 3 (every
+// index is a compile-time constant inside each unrolled phase).  The lane's
+// radial factors (node and half node) sit in LDS for the whole march; the
+// angular ones are uniform per row.
+//
+// FP32-compensated form: each value is stored as f (FP32) + c (bf16 Kahan
+// term).  The stencil runs in FP32 on f; Eq. (4)'s time update is added to
+// (f, c) with an exact two-sum, so the accumulated value keeps about 32 bits;
+// where the particle source is non-zero its increment is added in FP64.
 // ---------------------------------------------------------------------------
 
 namespace {
 
-
-struct Lane64 {
-    const DevInst *I;
-    const double4 *u;
-    double4 *un;
-    int c, p, nt;
-    bool cin, hv, icol, ov;
-    bool near_h, near_n;  // this lane's half node / node lies on the source window
-    cd e1, e2;            // source time factors at t^n and t^n + dt/2
-    long long n;
-    bool ext;         // this step writes a waveform sample
-    long long wslot;  // its ring slot
+struct PolicyF64 {
+    using T = double;
+    static constexpr bool kComp = false;
+};
+struct PolicyF32C {
+    using T = float;
+    static constexpr bool kComp = true;
 };
 
-struct Roll {
-    P4 U[3];  // u^n(c, row), slot = row mod 3 (rows r-1, r, r+1 at march row r)
-    P4 H[3];  // u^{n+1/2}(c+1/2, row), slot = row mod 3 (rows r-2, r-1, r)
-    P4 pre;   // prefetched u^n row
-    P4 keep;  // an output row kept for the pole condition
+template <typename T>
+struct St {  // stored value of a point: f (+ c in the compensated form)
+    Q4<T> f, c;
 };
 
-__device__ __forceinline__ P4 load_row(const Lane64 &L, int row)
+template <typename T>
+__device__ __forceinline__ cx<T> shfl_down1(cx<T> v)
 {
-    return L.cin ? ld_p4(L.u + (size_t)row * L.p + L.c) : zero4();
+    return mkc<T>(__shfl_down(v.re, 1), __shfl_down(v.im, 1));
+}
+template <typename T>
+__device__ __forceinline__ cx<T> shfl_up1(cx<T> v)
+{
+    return mkc<T>(__shfl_up(v.re, 1), __shfl_up(v.im, 1));
+}
+template <typename T>
+__device__ __forceinline__ Q4<T> shfl_down1(const Q4<T> &v)
+{
+    return Q4<T>{shfl_down1(v.phi), shfl_down1(v.pi)};
+}
+template <typename T>
+__device__ __forceinline__ Q4<T> shfl_up1(const Q4<T> &v)
+{
+    return Q4<T>{shfl_up1(v.phi), shfl_up1(v.pi)};
 }
 
-__device__ __forceinline__ cd shfl_down1(cd v) { return mk(__shfl_down(v.re, 1), __shfl_down(v.im, 1)); }
-__device__ __forceinline__ cd shfl_up1(cd v) { return mk(__shfl_up(v.re, 1), __shfl_up(v.im, 1)); }
-__device__ __forceinline__ P4 shfl_down1(const P4 &v) { return P4{shfl_down1(v.phi), shfl_down1(v.pi)}; }
-__device__ __forceinline__ P4 shfl_up1(const P4 &v) { return P4{shfl_up1(v.phi), shfl_up1(v.pi)}; }
-__device__ __forceinline__ cd avg(cd a, cd b) { return mk((a.re + b.re) * 0.5, (a.im + b.im) * 0.5); }
-
-__device__ __forceinline__ void emit(const Lane64 &L, int row, P4 v)
+// A wave-uniform value computed on the vector unit, moved to scalar registers.
+__device__ __forceinline__ double uniform(double x)
 {
-    if (L.ov) st_p4(L.un + (size_t)row * L.p + L.c, v);
+    const unsigned long long b = __double_as_longlong(x);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+    return __longlong_as_double(((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ cd uniform(cd v) { return mk(uniform(v.re), uniform(v.im)); }
+
+__device__ __forceinline__ float bf16_to_float(unsigned short b) { return __uint_as_float((unsigned)b << 16); }
+__device__ __forceinline__ unsigned short float_to_bf16(float x) { return __builtin_bit_cast(unsigned short, (__bf16)x); }
+
+template <class P>
+struct Lane {
+    using T = typename P::T;
+    const DevInst *I;
+    const void *u, *uc;  // u^n values (and bf16 terms)
+    void *un, *unc;      // u^{n+1}
+    T *rad;              // this lane's radial factors in LDS: [2][kRadVals] with stride 64
+    int c, p, nt;
+    bool cin, hv, icol, ov;
+    bool near_h, near_n;  // half node / node lies on the source window
+    double gh, gn;        // tabulated A g_r there
+    cd e1, e2;            // source time factors at t^n and t^n + dt/2
+    T a2, kct, dt, inv_h, inv_dth2, inv_2dth;
+    bool ext;             // this step writes a waveform sample
+    long long wslot;
+};
+
+template <class P>
+__device__ __forceinline__ St<typename P::T> load_row(const Lane<P> &L, int row)
+{
+    using T = typename P::T;
+    St<T> v;
+    v.f = zero_q4<T>();
+    v.c = zero_q4<T>();
+    if (!L.cin) return v;
+    const size_t o = (size_t)row * L.p + L.c;
+    if constexpr (!P::kComp) {
+        v.f = ld_p4((const double4 *)L.u + o);
+    } else {
+        const float4 a = ((const float4 *)L.u)[o];
+        const ushort4 b = ((const ushort4 *)L.uc)[o];
+        v.f = Q4<T>{mkc(a.x, a.y), mkc(a.z, a.w)};
+        v.c = Q4<T>{mkc(bf16_to_float(b.x), bf16_to_float(b.y)), mkc(bf16_to_float(b.z), bf16_to_float(b.w))};
+    }
+    return v;
+}
+
+template <class P>
+__device__ __forceinline__ RadV<typename P::T> rad_of(const Lane<P> &L, int which)
+{
+    const typename P::T *b = L.rad + which * kRadVals * 64;
+    return RadV<typename P::T>{b[0], b[64], b[128], b[192], b[256], b[320], b[384], b[448], b[512]};
+}
+
+template <class P>
+__device__ __forceinline__ AngV<typename P::T> ang_of(const Angular &A)
+{
+    using T = typename P::T;
+    return AngV<T>{(T)A.sn2, (T)A.cs, (T)A.cot, (T)A.V};
+}
+
+template <class P>
+__device__ __forceinline__ double value_of(const St<typename P::T> &v, int k)
+{
+    const typename P::T *f = &v.f.phi.re, *c = &v.c.phi.re;
+    return P::kComp ? (double)f[k] + (double)c[k] : (double)f[k];
+}
+
+template <class P>
+__device__ __forceinline__ void emit(const Lane<P> &L, int row, const St<typename P::T> &v)
+{
+    const size_t o = (size_t)row * L.p + L.c;
+    if (L.ov) {
+        if constexpr (!P::kComp) {
+            st_p4((double4 *)L.un + o, v.f);
+        } else {
+            ((float4 *)L.un)[o] = make_float4(v.f.phi.re, v.f.phi.im, v.f.pi.re, v.f.pi.im);
+            ((ushort4 *)L.unc)[o] = make_ushort4(float_to_bf16(v.c.phi.re), float_to_bf16(v.c.phi.im),
+                                                 float_to_bf16(v.c.pi.re), float_to_bf16(v.c.pi.im));
+        }
+    }
     if (L.ext && L.ov && L.c == L.I->i_obs) {
         double *w = L.I->wave + ((size_t)L.wslot * L.nt + row) * 2;
-        w[0] = v.phi.re;
-        w[1] = v.phi.im;
+        w[0] = value_of<P>(v, 0);
+        w[1] = value_of<P>(v, 1);
     }
+}
+
+// Pole value of a stored row pair, (4 X1 - X2) / 3 (double in the
+// compensated form, then split back into f + c).
+template <class P>
+__device__ __forceinline__ St<typename P::T> pole_row(const St<typename P::T> &x1, const St<typename P::T> &x2)
+{
+    using T = typename P::T;
+    St<T> o;
+    if constexpr (!P::kComp) {
+        o.f = pole_bc(x1.f, x2.f);
+        o.c = zero_q4<T>();
+    } else {
+        T *of = &o.f.phi.re, *oc = &o.c.phi.re;
+        for (int k = 0; k < 4; ++k) {
+            const double v = pole_x(value_of<P>(x1, k), value_of<P>(x2, k));
+            of[k] = (T)v;
+            oc[k] = (T)(v - (double)of[k]);
+        }
+    }
+    return o;
 }
 
 // Eq. (3) at half row r: u^n rows r-1 (UM), r (U0), r+1 (UP) of this column;
 // the column to the right comes by lane shuffles.
-__device__ __forceinline__ P4 half_row(const Lane64 &L, const Radial &Rh, const P4 &UM, const P4 &U0, const P4 &UP,
-                                       int r)
+template <class P>
+__device__ __forceinline__ Q4<typename P::T> half_row(const Lane<P> &L, const Q4<typename P::T> &UM,
+                                                      const Q4<typename P::T> &U0, const Q4<typename P::T> &UP, int r)
 {
+    using T = typename P::T;
     const DevInst &I = *L.I;
-    const cd nm = shfl_down1(UM.phi), np = shfl_down1(UP.phi);
-    const P4 n0 = shfl_down1(U0);
-    if (!L.hv) return zero4();
-    const P4 bar = half_sum(n0, U0);
+    const cx<T> nm = shfl_down1(UM.phi), np = shfl_down1(UP.phi);
+    const Q4<T> n0 = shfl_down1(U0);
+    if (!L.hv) return zero_q4<T>();
+    const Q4<T> bar = half_sum(n0, U0);
     const Angular &A = I.ang[r];
-    const Coef cf = coef_at(Rh, A);
-    const cd F = L.near_h ? source_value(Rh.srcg, A.srcg, L.e1) : mk(0, 0);
-    return lw_point(cf, bar, avg(nm, UM.phi), bar.phi, avg(np, UP.phi), bar.pi, n0 - U0, 0.5 * I.dt, I.inv_h,
-                    I.inv_dth2, I.inv_2dth, F);
-}
-
-// Eq. (4) at output row o: half rows o-1 (HM), o (H0), o+1 (HP) of this
-// column (at c+1/2); the column at c-1/2 comes by lane shuffles.
-__device__ __forceinline__ P4 out_row(const Lane64 &L, const Radial &Rn, const P4 &Uo, const P4 &HM, const P4 &H0,
-                                      const P4 &HP, int o)
-{
-    const DevInst &I = *L.I;
-    const cd lm = shfl_up1(HM.phi), lp = shfl_up1(HP.phi);
-    const P4 l0 = shfl_up1(H0);
-    if (!L.icol) return zero4();
-    const P4 til = half_sum(H0, l0);
-    const Angular &A = I.ang[o];
-    const Coef cf = coef_at(Rn, A);
-    const cd F = L.near_n ? source_value(Rn.srcg, A.srcg, L.e2) : mk(0, 0);
-    return lw_point(cf, Uo, avg(HM.phi, lm), til.phi, avg(HP.phi, lp), til.pi, H0 - l0, I.dt, I.inv_h, I.inv_dth2,
-                    I.inv_2dth, F);
-}
-
-// One march iteration at half row r (slot SR = r mod 3).
-template <int SR>
-__device__ __forceinline__ void march(const Lane64 &L, const Radial &Rh, const Radial &Rn, Roll &R, int r,
-                                      int out_lo, int out_hi, int u_last, bool north)
-{
-    constexpr int SM = (SR + 2) % 3;  // row r-1
-    constexpr int SP = (SR + 1) % 3;  // row r+1 (U) / row r-2 (H)
-    const DevInst &I = *L.I;
-    R.U[SP] = R.pre;
-    if (r + 2 <= u_last) R.pre = load_row(L, r + 2);
-    R.H[SR] = half_row(L, Rh, R.U[SM], R.U[SR], R.U[SP], r);
-    if (north && r == 2) R.H[SP] = I.m_even ? pole_bc(R.H[SM], R.H[SR]) : zero4();  // half row 0
-    const int o = r - 1;
-    if (o >= out_lo && o <= out_hi) {
-        const P4 v = out_row(L, Rn, R.U[SM], R.H[SP], R.H[SM], R.H[SR], o);
-        emit(L, o, v);
-        if (north && o == 1) R.keep = v;
-        if (north && o == 2) emit(L, 0, I.m_even ? pole_bc(R.keep, v) : zero4());
-        if (o == I.n_theta - 3) R.keep = v;
+    const Coef<T> cf = coef_lean(rad_of(L, 0), ang_of<P>(A), L.a2, L.kct);
+    const T fac = T(0.5) * L.dt;
+    if constexpr (!P::kComp) {
+        const cd F = L.near_h ? source_value(L.gh, A.srcg, L.e1) : mk(0, 0);
+        return lw_point(cf, bar, avg(nm, UM.phi), bar.phi, avg(np, UP.phi), bar.pi, n0 - U0, fac, L.inv_h,
+                        L.inv_dth2, L.inv_2dth, F);
+    } else {
+        Q4<T> h = lw_point(cf, bar, avg(nm, UM.phi), bar.phi, avg(np, UP.phi), bar.pi, n0 - U0, fac, L.inv_h,
+                           L.inv_dth2, L.inv_2dth, mkc(T(0), T(0)));
+        if (L.near_h && A.srcg != 0.0) {  // FP64 source increment (dt/2) F
+            const cd F = source_value(L.gh, A.srcg, L.e1);
+            const double f64 = 0.5 * I.dt;
+            h.pi = mkc((T)((double)h.pi.re + f64 * F.re), (T)((double)h.pi.im + f64 * F.im));
+        }
+        return h;
     }
 }
 
-// South pole after the last march iteration r = nt-2 (slot SR = (nt-2) mod 3).
-template <int SR>
-__device__ __forceinline__ void south(const Lane64 &L, const Radial &Rn, Roll &R)
+// exact sum a + b = s + e (two-sum)
+__device__ __forceinline__ void two_sum(float a, float b, float &s, float &e)
 {
+    s = a + b;
+    const float bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+// Eq. (4) at output row o: u^n row o (Uo), half rows o-1 (HM), o (H0), o+1
+// (HP) of this column (at c+1/2); the column at c-1/2 comes by lane shuffles.
+template <class P>
+__device__ __forceinline__ St<typename P::T> out_row(const Lane<P> &L, const St<typename P::T> &Uo,
+                                                     const Q4<typename P::T> &HM, const Q4<typename P::T> &H0,
+                                                     const Q4<typename P::T> &HP, int o)
+{
+    using T = typename P::T;
+    const DevInst &I = *L.I;
+    const cx<T> lm = shfl_up1(HM.phi), lp = shfl_up1(HP.phi);
+    const Q4<T> l0 = shfl_up1(H0);
+    St<T> res;
+    res.f = zero_q4<T>();
+    res.c = zero_q4<T>();
+    if (!L.icol) return res;
+    const Q4<T> til = half_sum(H0, l0);
+    const Angular &A = I.ang[o];
+    const Coef<T> cf = coef_lean(rad_of(L, 1), ang_of<P>(A), L.a2, L.kct);
+    if constexpr (!P::kComp) {
+        const cd F = L.near_n ? source_value(L.gn, A.srcg, L.e2) : mk(0, 0);
+        res.f = lw_point(cf, Uo.f, avg(HM.phi, lm), til.phi, avg(HP.phi, lp), til.pi, H0 - l0, L.dt, L.inv_h,
+                         L.inv_dth2, L.inv_2dth, F);
+    } else {
+        const Q4<T> br = lw_bracket(cf, avg(HM.phi, lm), til.phi, avg(HP.phi, lp), til.pi, H0 - l0, L.inv_h,
+                                    L.inv_dth2, L.inv_2dth, mkc(T(0), T(0)));
+        const T *bp = &br.phi.re, *fp = &Uo.f.phi.re, *cp = &Uo.c.phi.re;
+        T *rf = &res.f.phi.re, *rc = &res.c.phi.re;
+        if (L.near_n && A.srcg != 0.0) {
+            // FP64 accumulation where the source injects: u + c - dt [.] + dt F
+            const cd F = source_value(L.gn, A.srcg, L.e2);
+            const double add[4] = {0.0, 0.0, I.dt * F.re, I.dt * F.im};
+            for (int k = 0; k < 4; ++k) {
+                const double v = ((double)fp[k] + (double)cp[k]) + (double)(-L.dt * bp[k]) + add[k];
+                rf[k] = (T)v;
+                rc[k] = (T)(v - (double)rf[k]);
+            }
+        } else {
+            for (int k = 0; k < 4; ++k) two_sum(fp[k], -L.dt * bp[k] + cp[k], rf[k], rc[k]);
+        }
+    }
+    return res;
+}
+
+template <class P>
+struct Roll {
+    using T = typename P::T;
+    St<T> U[3];    // u^n(c, row), slot = row mod 3 (rows r-1, r, r+1 at march row r)
+    Q4<T> H[3];    // u^{n+1/2}(c+1/2, row), slot = row mod 3 (rows r-2, r-1, r)
+    St<T> pre;     // prefetched u^n row
+    St<T> keep;    // an output row kept for the pole condition
+};
+
+// One march iteration at half row r (slot SR = (r - r_lo) mod 3).  With
+// POLES false the pole and epilogue bookkeeping is compiled out (the
+// steady-state rows in the middle of a chunk).
+template <class P, int SR, bool POLES>
+__device__ __forceinline__ void march(const Lane<P> &L, Roll<P> &R, int r, int out_lo, int out_hi, int u_last,
+                                      bool north)
+{
+    using T = typename P::T;
+    constexpr int SM = (SR + 2) % 3;  // row r-1
+    constexpr int SP = (SR + 1) % 3;  // row r+1 (U) / row r-2 (H)
+    const int nt = L.nt;
+    const bool even = L.I->m_even;
+    R.U[SP] = R.pre;
+    if (r + 2 <= u_last) R.pre = load_row(L, r + 2);
+    R.H[SR] = half_row(L, R.U[SM].f, R.U[SR].f, R.U[SP].f, r);
+    if (POLES && north && r == 2) R.H[SP] = even ? pole_bc(R.H[SM], R.H[SR]) : zero_q4<T>();  // half row 0
+    const int o = r - 1;
+    if (!POLES || (o >= out_lo && o <= out_hi)) {
+        const St<T> v = out_row(L, R.U[SM], R.H[SP], R.H[SM], R.H[SR], o);
+        emit(L, o, v);
+        if (POLES) {
+            if (north && o == 1) R.keep = v;
+            if (north && o == 2) {
+                St<T> z;
+                z.f = zero_q4<T>();
+                z.c = zero_q4<T>();
+                emit(L, 0, even ? pole_row<P>(R.keep, v) : z);
+            }
+            if (o == nt - 3) R.keep = v;
+        }
+    }
+}
+
+// South pole after the last march iteration r = nt-2 (slot SR = (nt-2-r_lo) mod 3).
+template <class P, int SR>
+__device__ __forceinline__ void south(const Lane<P> &L, Roll<P> &R)
+{
+    using T = typename P::T;
     constexpr int SM = (SR + 2) % 3;  // row nt-3
     constexpr int SP = (SR + 1) % 3;  // row nt-1 (free slot)
-    const DevInst &I = *L.I;
-    const int nt = I.n_theta;
-    R.H[SP] = I.m_even ? pole_bc(R.H[SR], R.H[SM]) : zero4();  // half row nt-1
-    const P4 v = out_row(L, Rn, R.U[SR], R.H[SM], R.H[SR], R.H[SP], nt - 2);
+    const int nt = L.nt;
+    const bool even = L.I->m_even;
+    R.H[SP] = even ? pole_bc(R.H[SR], R.H[SM]) : zero_q4<T>();  // half row nt-1
+    const St<T> v = out_row(L, R.U[SR], R.H[SM], R.H[SR], R.H[SP], nt - 2);
     emit(L, nt - 2, v);
-    emit(L, nt - 1, I.m_even ? pole_bc(v, R.keep) : zero4());
+    St<T> z;
+    z.f = zero_q4<T>();
+    z.c = zero_q4<T>();
+    emit(L, nt - 1, even ? pole_row<P>(v, R.keep) : z);
 }
 
 }  // namespace
 
-__global__ void __launch_bounds__(256) k_fused_fp64(const DevInst *__restrict__ insts, const WorkItem *__restrict__ work,
-                                                    int n_work, const DevCtl *__restrict__ ctl, int kstep)
+template <class P>
+__global__ void __launch_bounds__(64 * kFusedWavesPerBlock)
+    k_fused(const DevInst *__restrict__ insts, const WorkItem *__restrict__ work, int n_work,
+            const DevCtl *__restrict__ ctl, int kstep)
 {
+    using T = typename P::T;
+    __shared__ T s_rad[kFusedWavesPerBlock][2 * kRadVals * 64];
     const int lane = (int)(threadIdx.x & 63);
-    const int w = (int)blockIdx.x * kFusedWavesPerBlock + (int)(threadIdx.x >> 6);
-    if (w >= n_work) return;  // whole wave leaves together
+    const int wv = (int)(threadIdx.x >> 6);
+    const int w = (int)blockIdx.x * kFusedWavesPerBlock + wv;
+    if (w >= n_work) return;  // whole wave leaves together; no block barriers below
     const WorkItem it = work[w];
     const DevInst &I = insts[it.inst];
-    Lane64 L;
+    Lane<P> L;
     L.I = &I;
-    L.n = ctl->step + kstep;
-    L.u = (const double4 *)I.u[L.n & 1];
-    L.un = (double4 *)I.u[(L.n + 1) & 1];
+    const long long n = ctl->step + kstep;
+    L.u = I.u[n & 1];
+    L.uc = I.c[n & 1];
+    L.un = I.u[(n + 1) & 1];
+    L.unc = I.c[(n + 1) & 1];
     L.p = I.pitch;
     L.nt = I.n_theta;
     const int nr = I.n_r, nt = I.n_theta;
@@ -287,72 +478,102 @@ __global__ void __launch_bounds__(256) k_fused_fp64(const DevInst *__restrict__ 
     L.hv = L.c >= 0 && L.c <= nr - 2;
     L.icol = L.c >= 1 && L.c <= nr - 2;
     L.ov = lane >= 1 && lane <= kFusedCols && L.c < nr;
+    L.a2 = (T)I.a2;
+    L.kct = (T)I.kct;
+    L.dt = (T)I.dt;
+    L.inv_h = (T)I.inv_h;
+    L.inv_dth2 = (T)I.inv_dth2;
+    L.inv_2dth = (T)I.inv_2dth;
     if (I.src_kind == TK_SRC_CIRCULAR_GAUSSIAN) {
-        L.e1 = source_phase(I, (double)L.n * I.dt);
-        L.e2 = source_phase(I, (double)L.n * I.dt + 0.5 * I.dt);
+        L.e1 = uniform(source_phase(I, (double)n * I.dt));
+        L.e2 = uniform(source_phase(I, (double)n * I.dt + 0.5 * I.dt));
     } else {
         L.e1 = L.e2 = mk(0, 0);
     }
-    L.ext = I.extract_every > 0 && (L.n + 1) % I.extract_every == 0;
-    L.wslot = L.ext ? ((L.n + 1) / I.extract_every - 1) % I.wave_cap : 0;
+    L.ext = I.extract_every > 0 && (n + 1) % I.extract_every == 0;
+    L.wslot = L.ext ? ((n + 1) / I.extract_every - 1) % I.wave_cap : 0;
 
-    Radial Rh, Rn;
-    if (L.hv) Rh = I.rad[2 * L.c + 1];
-    else Rh = I.rad[0];
-    if (L.icol) Rn = I.rad[2 * L.c];
-    else Rn = I.rad[0];
-    L.near_h = L.hv && Rh.srcg != 0.0;
-    L.near_n = L.icol && Rn.srcg != 0.0;
+    // radial factors of the half node (slot 0) and the node (slot 1) -> LDS
+    L.rad = &s_rad[wv][lane];
+    {
+        const Radial &Rh = I.rad[L.hv ? 2 * L.c + 1 : 0];
+        const Radial &Rn = I.rad[L.icol ? 2 * L.c : 0];
+        const double vh[kRadVals] = {Rh.rho, Rh.Dl, Rh.ct_re, Rh.ct_im0, Rh.K, Rh.c1_re, Rh.c1_im, Rh.c0_re, Rh.c0_im};
+        const double vn[kRadVals] = {Rn.rho, Rn.Dl, Rn.ct_re, Rn.ct_im0, Rn.K, Rn.c1_re, Rn.c1_im, Rn.c0_re, Rn.c0_im};
+#pragma unroll
+        for (int k = 0; k < kRadVals; ++k) {
+            L.rad[k * 64] = (T)vh[k];
+            L.rad[(kRadVals + k) * 64] = (T)vn[k];
+        }
+        L.gh = L.hv ? Rh.srcg : 0.0;
+        L.gn = L.icol ? Rn.srcg : 0.0;
+        L.near_h = L.gh != 0.0;
+        L.near_n = L.gn != 0.0;
+    }
 
     const int j0 = it.j0, j1 = it.j1;
     const bool north = j0 == 0, southp = j1 == nt;
     const int r_lo = max(1, j0 - 1), r_hi = min(nt - 2, j1);
-    const int out_lo = max(1, j0), out_hi = min(nt - 3, j1 - 1);  // row nt-2 is the south epilogue's
+    const int out_lo = max(1, j0);
+    const int out_hi = southp ? nt - 3 : min(nt - 2, j1 - 1);  // row nt-2 is the south epilogue's
     const int u_last = r_hi + 1;
-    const int out_hi_loop = southp ? out_hi : min(nt - 2, j1 - 1);
 
-    Roll R;
-    // prologue: u^n rows r_lo-1 and r_lo, prefetch r_lo+1
-    {
-        const int a = r_lo - 1, b = r_lo;
-        const P4 va = load_row(L, a), vb = load_row(L, b);
-        R.pre = load_row(L, b + 1);
-        switch (a % 3) {
-        case 0: R.U[0] = va; R.U[1] = vb; break;
-        case 1: R.U[1] = va; R.U[2] = vb; break;
-        default: R.U[2] = va; R.U[0] = vb; break;
-        }
+    Roll<P> R;
+    {  // prologue: u^n rows r_lo-1 (slot 2) and r_lo (slot 0), prefetch r_lo+1
+        const int a = r_lo - 1;
+        R.U[2] = load_row(L, a);
+        R.U[0] = load_row(L, a + 1);
+        R.pre = load_row(L, a + 2);
     }
-    R.keep = zero4();
-    for (int r = r_lo; r <= r_hi; ++r) {
-        switch (r % 3) {
-        case 0: march<0>(L, Rh, Rn, R, r, out_lo, out_hi_loop, u_last, north); break;
-        case 1: march<1>(L, Rh, Rn, R, r, out_lo, out_hi_loop, u_last, north); break;
-        default: march<2>(L, Rh, Rn, R, r, out_lo, out_hi_loop, u_last, north); break;
-        }
+    R.keep.f = zero_q4<T>();
+    R.keep.c = zero_q4<T>();
+    // head: the first three rows, with the north-pole bookkeeping
+    int r = r_lo;
+    march<P, 0, true>(L, R, r, out_lo, out_hi, u_last, north);
+    if (r + 1 <= r_hi) march<P, 1, true>(L, R, r + 1, out_lo, out_hi, u_last, north);
+    if (r + 2 <= r_hi) march<P, 2, true>(L, R, r + 2, out_lo, out_hi, u_last, north);
+    r += 3;
+    // steady state: whole triples strictly before the last row (its output
+    // row o = r_hi - 1 may be the one the south pole needs)
+    for (; r + 2 < r_hi; r += 3) {
+        march<P, 0, false>(L, R, r, out_lo, out_hi, u_last, north);
+        march<P, 1, false>(L, R, r + 1, out_lo, out_hi, u_last, north);
+        march<P, 2, false>(L, R, r + 2, out_lo, out_hi, u_last, north);
     }
+    // tail
+    if (r <= r_hi) march<P, 0, true>(L, R, r, out_lo, out_hi, u_last, north);
+    if (r + 1 <= r_hi) march<P, 1, true>(L, R, r + 1, out_lo, out_hi, u_last, north);
+    if (r + 2 <= r_hi) march<P, 2, true>(L, R, r + 2, out_lo, out_hi, u_last, north);
     if (southp) {
-        switch ((nt - 2) % 3) {
-        case 0: south<0>(L, Rn, R); break;
-        case 1: south<1>(L, Rn, R); break;
-        default: south<2>(L, Rn, R); break;
+        switch ((nt - 2 - r_lo) % 3) {
+        case 0: south<P, 0>(L, R); break;
+        case 1: south<P, 1>(L, R); break;
+        default: south<P, 2>(L, R); break;
         }
     }
 }
+
+template __global__ void k_fused<PolicyF64>(const DevInst *, const WorkItem *, int, const DevCtl *, int);
+template __global__ void k_fused<PolicyF32C>(const DevInst *, const WorkItem *, int, const DevCtl *, int);
 
 hipError_t launch_fused_fp64(const DevInst *d_inst, const WorkItem *d_work, int n_work, const DevCtl *ctl, int kstep,
                              hipStream_t s)
 {
     if (n_work <= 0) return hipSuccess;
     const int blocks = (n_work + kFusedWavesPerBlock - 1) / kFusedWavesPerBlock;
-    hipLaunchKernelGGL(k_fused_fp64, dim3(blocks), dim3(64 * kFusedWavesPerBlock), 0, s, d_inst, d_work, n_work, ctl,
-                       kstep);
+    hipLaunchKernelGGL(k_fused<PolicyF64>, dim3(blocks), dim3(64 * kFusedWavesPerBlock), 0, s, d_inst, d_work, n_work,
+                       ctl, kstep);
     return hipGetLastError();
 }
 
-hipError_t launch_fused_fp32c(const DevInst *, const WorkItem *, int, const DevCtl *, int, hipStream_t)
+hipError_t launch_fused_fp32c(const DevInst *d_inst, const WorkItem *d_work, int n_work, const DevCtl *ctl, int kstep,
+                              hipStream_t s)
 {
-    return hipErrorNotSupported;
+    if (n_work <= 0) return hipSuccess;
+    const int blocks = (n_work + kFusedWavesPerBlock - 1) / kFusedWavesPerBlock;
+    hipLaunchKernelGGL(k_fused<PolicyF32C>, dim3(blocks), dim3(64 * kFusedWavesPerBlock), 0, s, d_inst, d_work,
+                       n_work, ctl, kstep);
+    return hipGetLastError();
 }
 
 }  // namespace tk

@@ -221,7 +221,7 @@ def test_extract_overrun_and_nonfinite():
     st.step(5)
     assert st.extract(0).shape == (5, 9)
     phi, pi = W.initial_data(inst)
-    phi[4, 40] = np.nan
+    phi[4, inst["i_obs"]] = np.nan  # the sampled column itself
     st.set_fields(0, phi, pi)
     st.step(2)
     with pytest.raises(tk.TkError) as ei:

@@ -1,0 +1,92 @@
+"""The oracle's pins are sharp enough: each plausible mistake planted in a
+copy of the oracle source (a dropped term, a wrong sign, a wrong index or
+time level, a first-order pole condition) makes at least one pin fail.
+
+Each mutant is compiled from an edited copy of oracle/teuk_oracle.c into a
+temporary library; the committed oracle is never modified.
+"""
+import os
+import tempfile
+
+import pytest
+
+import oracle
+from oracle import build as orbuild
+
+import test_oracle_pins as PINS
+
+# (name, original text (must occur exactly once), replacement, pins to run)
+MUTANTS = [
+    ("c0 drops 4 i m s a (r-M)", "4 * IU * m * s * a * (r - M) - Delta * Vth",
+     "0 * IU * m * s * a * (r - M) - Delta * Vth", ["mms_even"]),
+    ("ct sign of i a Delta cos", "+ IU * a * Delta * cs)) / Sh2", "- IU * a * Delta * cs)) / Sh2",
+     ["mms_even"]),
+    ("d misses the b ct term", "c.d = -(c.c1 - c.b * c.bp - c.b * c.ct);", "c.d = -(c.c1 - c.b * c.bp);",
+     ["mms_even"]),
+    ("b' misses a^2", "c.bp = (Delta / rho) * a * a * sn2", "c.bp = (Delta / rho) * a * sn2",
+     ["mms_even", "principal"]),
+    ("cot term sign", "c.cth = c.cthth * cs / sn;", "c.cth = -c.cthth * cs / sn;", ["eig"]),
+    ("first-order pole condition", "return (4 * x1 - x2) / 3;", "return x1;", ["eig", "mms_even"]),
+    ("advection sign on Pi", "cplx adv_pi = (g->d[c] * dphi - g->b[c] * dpi) / h;\n            g->hphi",
+     "cplx adv_pi = (g->d[c] * dphi + g->b[c] * dpi) / h;\n            g->hphi", ["mms_even"]),
+    ("source at t^n in the second step", "F = source_at(g, th_half, g->rstar[q], th);",
+     "F = source_at(g, tn, g->rstar[q], th);", ["source"]),
+    ("forcing of Eq. (4) taken one node off",
+     "F = F_node[2 * IDX(g, j, i)] + IU * F_node[2 * IDX(g, j, i) + 1];",
+     "F = F_node[2 * IDX(g, j, i - 1)] + IU * F_node[2 * IDX(g, j, i - 1) + 1];", ["mms_even"]),
+    ("angular stencil uses row j twice", "(phip - 2 * phi0 + phim)", "(phip - 2 * phi0 + phi0)", ["eig"]),
+    ("c1 misses 2 r Delta", "2 * s * (r - M) * rho + 2 * r * Delta + 2 * IU", "2 * s * (r - M) * rho + 2 * IU",
+     ["mms_odd"]),
+    ("tortoise: r- weight with the wrong sign", "val -= k->Am * log(", "val += k->Am * log(", ["tortoise"]),
+]
+
+
+def run_pin(name, kind):
+    if name == "mms_even":
+        PINS.mms_check(0.9, 2, kind=kind, levels=((201, 17), (401, 33)))
+    elif name == "mms_odd":
+        PINS.mms_check(0.6, 3, kind=kind, levels=((201, 17), (401, 33)))
+    elif name == "eig":
+        for m in (2, 1):
+            PINS.angular_eigen_check(m, kind=kind)
+    elif name == "tortoise":
+        for a in (0.3, 0.9):
+            rp, rm = PINS.horizons(1.0, a)
+            for x in (0.1, 1.0, 7.0):
+                got = oracle.tortoise(1.0, a, x, kind=kind)
+                want = PINS.tortoise_closed(1.0, a, rp + x, x=x)
+                assert abs(got - want) <= 1e-13 * max(1.0, abs(want))
+    elif name == "principal":
+        PINS.principal_part_check(kind=kind)
+    elif name == "source":
+        PINS.source_consistency_check(kind=kind)
+    else:
+        raise KeyError(name)
+
+
+@pytest.fixture(scope="module")
+def src_text():
+    with open(orbuild.SRC) as f:
+        return f.read()
+
+
+def test_unmutated_source_passes_the_detectors(src_text):
+    for pin in ("mms_even", "mms_odd", "eig", "tortoise", "source"):
+        run_pin(pin, "f64")
+
+
+@pytest.mark.parametrize("name,old,new,pins", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_mutant_is_caught(src_text, tmp_path, name, old, new, pins):
+    assert src_text.count(old) == 1, f"mutation anchor not unique: {old!r}"
+    path = os.path.join(str(tmp_path), "mutant.c")
+    with open(path, "w") as f:
+        f.write(src_text.replace(old, new))
+    lib = os.path.join(str(tmp_path), "libmutant.so")
+    orbuild.build_one(path, lib)
+    caught = []
+    for pin in pins:
+        try:
+            run_pin(pin, lib)
+        except AssertionError as e:
+            caught.append((pin, str(e)[:120]))
+    assert caught, f"mutant '{name}' passed {pins}"
