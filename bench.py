@@ -66,16 +66,15 @@ def traffic_entry(prec, wl):
         return None
 
 
-def cpu_baseline(insts, target_s=15.0):
+def cpu_baseline(insts, target_s=15.0, steps=20):
     """The oracle as it stands, timed on this host on a bounded sample of the
-    same workload: the first instances, a few steps each, setup excluded."""
-    import numpy as np  # noqa: F401
+    same workload: instances in workload order, `steps` steps each, until
+    about target_s seconds of stepping (grid setup excluded)."""
     import oracle
     from paper_1206_0270_amd import workloads as W
 
     threads = oracle.get_threads()
     done_upd, spent, used = 0, 0.0, 0
-    steps = 2
     for inst in insts:
         g = oracle.Grid(M=inst["M"], a=inst["a"], s=inst["s"], m=inst["m"], n_r=inst["n_r"],
                         n_theta=inst["n_theta"], rstar_min=inst["rstar_min"],
@@ -91,9 +90,9 @@ def cpu_baseline(insts, target_s=15.0):
         if spent >= target_s:
             break
     return dict(value=done_upd / spent, unit="grid-point updates/s", cores=threads, kind="oracle",
-                sample=f"first {used} of {len(insts)} instances, {steps} steps each "
-                       f"({done_upd:.3g} updates, {spent:.1f} s, setup excluded), FP64 C oracle, "
-                       f"OpenMP over theta rows")
+                sample=f"first {used} of {len(insts)} instances of the same workload, {steps} steps each "
+                       f"({done_upd:.3g} updates in {spent:.1f} s, grid setup excluded); FP64 C oracle "
+                       f"with OpenMP over theta rows")
 
 
 def main():
