@@ -105,6 +105,9 @@ def main():
     ap.add_argument("--graph-steps", type=int, default=100)
     ap.add_argument("--rows", type=int, default=0)
     ap.add_argument("--kernel", default="fused", choices=["fused", "two_pass"])
+    ap.add_argument("--prefetch", type=int, default=3, choices=[1, 3])
+    ap.add_argument("--no-nt", action="store_true", help="plain (not non-temporal) stores")
+    ap.add_argument("--waves", type=int, default=0, choices=[0, 3, 4])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="instead of the stepper, run a plain device copy of this many GiB "
@@ -143,7 +146,8 @@ def main():
     points = W.points(insts)
     st = tk.Stepper(insts, precision=prec)
     kern = tk.TK_KERNEL_FUSED if args.kernel == "fused" else tk.TK_KERNEL_TWO_PASS
-    st.set_tuning(kernel=kern, rows_per_tile=args.rows, graph_steps=args.graph_steps)
+    st.set_tuning(kernel=kern, rows_per_tile=args.rows, graph_steps=args.graph_steps,
+                  prefetch_rows=args.prefetch, nt_stores=not args.no_nt, waves_per_simd=args.waves)
     for k, inst in enumerate(insts):
         st.set_fields(k, *W.initial_data(inst))
     print(f"# workload {args.workload}: {len(insts)} instances, {points} points, "
@@ -186,7 +190,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "instances": len(insts), "points": points,
                    "precision": args.precision, "kernel": args.kernel,
-                   "graph_steps": args.graph_steps, "rows_per_tile": args.rows},
+                   "graph_steps": args.graph_steps, "rows_per_tile": args.rows,
+                   "prefetch_rows": args.prefetch, "nt_stores": not args.no_nt,
+                   "waves_per_simd": args.waves},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": KERNEL_NAME[args.precision] if args.kernel == "fused" else "k_two_pass_*",

@@ -107,10 +107,20 @@ typedef enum {
     TK_KERNEL_FUSED = 2     /* both steps in one pass, theta-marching columns   */
 } tk_kernel;
 
+enum {
+    TK_TUNE_NT_STORES = 1 /* fused kernel: non-temporal stores of u^{n+1} */
+};
+
 typedef struct {
     int kernel;        /* tk_kernel */
-    int rows_per_tile; /* fused kernel: theta rows per work item (0 = default) */
+    int rows_per_tile; /* fused kernel: theta rows per work item (0 = all)   */
     int graph_steps;   /* steps per captured HIP graph (0 = no graphs)        */
+    int prefetch_rows; /* fused kernel: u^n rows in flight per wave, 1 or 3 (0 = 3) */
+    int flags;         /* TK_TUNE_* */
+    int waves_per_simd;/* fused kernel: register budget for 3 or 4 waves per SIMD
+                          (0 = the compiler's choice); compiled combinations:
+                          prefetch 3 with non-temporal stores at 0/3/4, and
+                          prefetch 1 or 3 at 0; others give TK_E_INVALID */
 } tk_tuning;
 
 /* Set up the grids of n_inst instances (tortoise inversion, radial and

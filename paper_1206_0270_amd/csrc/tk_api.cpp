@@ -34,10 +34,10 @@ struct tk_ctx {
     std::vector<std::vector<Radial>> hrad;   // host copies of the coefficient tables
     std::vector<std::vector<Angular>> hang;
     long long step = 0;
-    tk_tuning tuning{TK_KERNEL_AUTO, 0, 0};
+    tk_tuning tuning{TK_KERNEL_AUTO, 0, 0, 3, TK_TUNE_NT_STORES, 0};
     // captured graph (steps, kernel, rows) for replay
     hipGraphExec_t gexec = nullptr;
-    int g_steps = 0, g_kernel = -1, g_rows = -1;
+    int g_steps = 0, g_kernel = -1, g_rows = -1, g_pf = -1, g_flags = -1, g_waves = -1;
 };
 
 namespace {
@@ -230,8 +230,11 @@ hipError_t launch_one(tk_ctx *c, int kernel, int kstep)
         return launch_two_pass(di, (const int2 *)(c->ws + c->off_blocks), (int)c->blocks.size(), ctl, kstep,
                                c->stream);
     const WorkItem *wk = (const WorkItem *)(c->ws + c->off_work);
-    if (c->prec == TK_FP64) return launch_fused_fp64(di, wk, (int)c->work.size(), ctl, kstep, c->stream);
-    return launch_fused_fp32c(di, wk, (int)c->work.size(), ctl, kstep, c->stream);
+    const int pf = c->tuning.prefetch_rows == 1 ? 1 : 3;
+    const bool nt = (c->tuning.flags & TK_TUNE_NT_STORES) != 0;
+    const int w = c->tuning.waves_per_simd == 0 ? 1 : c->tuning.waves_per_simd;
+    if (c->prec == TK_FP64) return launch_fused_fp64(di, wk, (int)c->work.size(), ctl, kstep, pf, nt, w, c->stream);
+    return launch_fused_fp32c(di, wk, (int)c->work.size(), ctl, kstep, pf, nt, w, c->stream);
 }
 
 tk_status enqueue_eager(tk_ctx *c, int kernel, long n)
@@ -251,11 +254,17 @@ void drop_graph(tk_ctx *c)
     c->g_steps = 0;
     c->g_kernel = -1;
     c->g_rows = -1;
+    c->g_pf = -1;
+    c->g_flags = -1;
+    c->g_waves = -1;
 }
 
 tk_status ensure_graph(tk_ctx *c, int kernel, int G)
 {
-    if (c->gexec && c->g_steps == G && c->g_kernel == kernel && c->g_rows == c->tuning.rows_per_tile) return TK_OK;
+    if (c->gexec && c->g_steps == G && c->g_kernel == kernel && c->g_rows == c->tuning.rows_per_tile &&
+        c->g_pf == c->tuning.prefetch_rows && c->g_flags == c->tuning.flags &&
+        c->g_waves == c->tuning.waves_per_simd)
+        return TK_OK;
     drop_graph(c);
     hipGraph_t g = nullptr;
     TK_HIP(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
@@ -283,6 +292,9 @@ tk_status ensure_graph(tk_ctx *c, int kernel, int G)
     c->g_steps = G;
     c->g_kernel = kernel;
     c->g_rows = c->tuning.rows_per_tile;
+    c->g_pf = c->tuning.prefetch_rows;
+    c->g_flags = c->tuning.flags;
+    c->g_waves = c->tuning.waves_per_simd;
     return TK_OK;
 }
 
@@ -676,7 +688,18 @@ tk_status tk_set_tuning(tk_ctx *c, const tk_tuning *t)
     if (t->rows_per_tile < 0 || (t->rows_per_tile > 0 && t->rows_per_tile < 3))
         return fail(c, TK_E_INVALID, "rows_per_tile must be 0 or >= 3");
     if (t->graph_steps < 0 || t->graph_steps > 100000) return fail(c, TK_E_INVALID, "graph_steps out of range");
+    if (t->prefetch_rows != 0 && t->prefetch_rows != 1 && t->prefetch_rows != 3)
+        return fail(c, TK_E_INVALID, "prefetch_rows must be 0, 1 or 3");
+    if (t->flags & ~TK_TUNE_NT_STORES) return fail(c, TK_E_INVALID, "unknown tuning flags");
+    {
+        const int pf = t->prefetch_rows == 0 ? 3 : t->prefetch_rows;
+        const bool nt = (t->flags & TK_TUNE_NT_STORES) != 0;
+        const int w = t->waves_per_simd;
+        const bool compiled = (pf == 3 && nt && (w == 0 || w == 3 || w == 4)) || (w == 0);
+        if (!compiled) return fail(c, TK_E_INVALID, "launch variant not compiled (waves_per_simd needs prefetch 3 + NT)");
+    }
     c->tuning = *t;
+    if (c->tuning.prefetch_rows == 0) c->tuning.prefetch_rows = 3;
     if (c->ws && resolve_kernel(c) == TK_KERNEL_FUSED) {
         tk_status st = ensure_work(c);
         if (st != TK_OK) return st;

@@ -16,10 +16,13 @@ hipError_t launch_two_pass(const DevInst *d_inst, const int2 *d_blocks, int n_bl
 // Fused step: both Lax-Wendroff stages in one pass over theta-marching
 // column strips.  d_work[w] = work item of wave w; waves_per_block waves of
 // 64 lanes per block.
+// prefetch: u^n rows in flight per wave (1 or 3); nt: non-temporal stores;
+// waves: occupancy target per SIMD (1 = compiler's choice, 3, 4).  Returns
+// hipErrorInvalidValue for a combination that is not compiled.
 hipError_t launch_fused_fp64(const DevInst *d_inst, const WorkItem *d_work, int n_work, const DevCtl *ctl, int kstep,
-                             hipStream_t s);
+                             int prefetch, bool nt, int waves, hipStream_t s);
 hipError_t launch_fused_fp32c(const DevInst *d_inst, const WorkItem *d_work, int n_work, const DevCtl *ctl, int kstep,
-                              hipStream_t s);
+                              int prefetch, bool nt, int waves, hipStream_t s);
 
 // ctl->step += n
 hipError_t launch_bump(DevCtl *ctl, int n, hipStream_t s);

@@ -159,13 +159,24 @@ hipError_t launch_bump(DevCtl *ctl, int n, hipStream_t s)
 
 namespace {
 
+// Arithmetic / storage policy, prefetch depth (u^n rows in flight per wave:
+// 1 or 3), non-temporal stores, and the occupancy the register allocator
+// must reach (waves per SIMD; 1 leaves the choice to the compiler).
+template <int PD, bool NT, int W>
 struct PolicyF64 {
     using T = double;
     static constexpr bool kComp = false;
+    static constexpr int kPD = PD;
+    static constexpr bool kNT = NT;
+    static constexpr int kWaves = W;
 };
+template <int PD, bool NT, int W>
 struct PolicyF32C {
     using T = float;
     static constexpr bool kComp = true;
+    static constexpr int kPD = PD;
+    static constexpr bool kNT = NT;
+    static constexpr int kWaves = W;
 };
 
 template <typename T>
@@ -265,17 +276,32 @@ __device__ __forceinline__ double value_of(const St<typename P::T> &v, int k)
     return P::kComp ? (double)f[k] + (double)c[k] : (double)f[k];
 }
 
+typedef double dvec4 __attribute__((ext_vector_type(4)));
+typedef float fvec4 __attribute__((ext_vector_type(4)));
+typedef unsigned short hvec4 __attribute__((ext_vector_type(4)));
+
 template <class P>
 __device__ __forceinline__ void emit(const Lane<P> &L, int row, const St<typename P::T> &v)
 {
     const size_t o = (size_t)row * L.p + L.c;
     if (L.ov) {
         if constexpr (!P::kComp) {
-            st_p4((double4 *)L.un + o, v.f);
+            const dvec4 x = {v.f.phi.re, v.f.phi.im, v.f.pi.re, v.f.pi.im};
+            if (P::kNT)
+                __builtin_nontemporal_store(x, (dvec4 *)L.un + o);
+            else
+                ((dvec4 *)L.un)[o] = x;
         } else {
-            ((float4 *)L.un)[o] = make_float4(v.f.phi.re, v.f.phi.im, v.f.pi.re, v.f.pi.im);
-            ((ushort4 *)L.unc)[o] = make_ushort4(float_to_bf16(v.c.phi.re), float_to_bf16(v.c.phi.im),
-                                                 float_to_bf16(v.c.pi.re), float_to_bf16(v.c.pi.im));
+            const fvec4 x = {v.f.phi.re, v.f.phi.im, v.f.pi.re, v.f.pi.im};
+            const hvec4 y = {float_to_bf16(v.c.phi.re), float_to_bf16(v.c.phi.im), float_to_bf16(v.c.pi.re),
+                             float_to_bf16(v.c.pi.im)};
+            if (P::kNT) {
+                __builtin_nontemporal_store(x, (fvec4 *)L.un + o);
+                __builtin_nontemporal_store(y, (hvec4 *)L.unc + o);
+            } else {
+                ((fvec4 *)L.un)[o] = x;
+                ((hvec4 *)L.unc)[o] = y;
+            }
         }
     }
     if (L.ext && L.ov && L.c == L.I->i_obs) {
@@ -393,7 +419,7 @@ struct Roll {
     using T = typename P::T;
     St<T> U[3];    // u^n(c, row), slot = row mod 3 (rows r-1, r, r+1 at march row r)
     Q4<T> H[3];    // u^{n+1/2}(c+1/2, row), slot = row mod 3 (rows r-2, r-1, r)
-    St<T> pre;     // prefetched u^n row
+    St<T> pre[3];  // prefetched u^n rows (slot = row mod 3, or slot 0 only at depth 1)
     St<T> keep;    // an output row kept for the pole condition
 };
 
@@ -409,8 +435,13 @@ __device__ __forceinline__ void march(const Lane<P> &L, Roll<P> &R, int r, int o
     constexpr int SP = (SR + 1) % 3;  // row r+1 (U) / row r-2 (H)
     const int nt = L.nt;
     const bool even = L.I->m_even;
-    R.U[SP] = R.pre;
-    if (r + 2 <= u_last) R.pre = load_row(L, r + 2);
+    if constexpr (P::kPD == 3) {
+        R.U[SP] = R.pre[SP];  // row r+1; refill its slot with row r+4
+        if (r + 4 <= u_last) R.pre[SP] = load_row(L, r + 4);
+    } else {
+        R.U[SP] = R.pre[0];
+        if (r + 2 <= u_last) R.pre[0] = load_row(L, r + 2);
+    }
     R.H[SR] = half_row(L, R.U[SM].f, R.U[SR].f, R.U[SP].f, r);
     if (POLES && north && r == 2) R.H[SP] = even ? pole_bc(R.H[SM], R.H[SR]) : zero_q4<T>();  // half row 0
     const int o = r - 1;
@@ -451,7 +482,7 @@ __device__ __forceinline__ void south(const Lane<P> &L, Roll<P> &R)
 }  // namespace
 
 template <class P>
-__global__ void __launch_bounds__(64 * kFusedWavesPerBlock)
+__global__ void __launch_bounds__(64 * kFusedWavesPerBlock) __attribute__((amdgpu_waves_per_eu(P::kWaves, 8)))
     k_fused(const DevInst *__restrict__ insts, const WorkItem *__restrict__ work, int n_work,
             const DevCtl *__restrict__ ctl, int kstep)
 {
@@ -519,11 +550,16 @@ __global__ void __launch_bounds__(64 * kFusedWavesPerBlock)
     const int u_last = r_hi + 1;
 
     Roll<P> R;
-    {  // prologue: u^n rows r_lo-1 (slot 2) and r_lo (slot 0), prefetch r_lo+1
-        const int a = r_lo - 1;
-        R.U[2] = load_row(L, a);
-        R.U[0] = load_row(L, a + 1);
-        R.pre = load_row(L, a + 2);
+    {  // prologue: u^n rows r_lo-1 (slot 2) and r_lo (slot 0), then the prefetch
+        R.U[2] = load_row(L, r_lo - 1);
+        R.U[0] = load_row(L, r_lo);
+        if constexpr (P::kPD == 3) {
+            R.pre[1] = load_row(L, r_lo + 1);
+            if (r_lo + 2 <= u_last) R.pre[2] = load_row(L, r_lo + 2);
+            if (r_lo + 3 <= u_last) R.pre[0] = load_row(L, r_lo + 3);
+        } else {
+            R.pre[0] = load_row(L, r_lo + 1);
+        }
     }
     R.keep.f = zero_q4<T>();
     R.keep.c = zero_q4<T>();
@@ -553,27 +589,44 @@ __global__ void __launch_bounds__(64 * kFusedWavesPerBlock)
     }
 }
 
-template __global__ void k_fused<PolicyF64>(const DevInst *, const WorkItem *, int, const DevCtl *, int);
-template __global__ void k_fused<PolicyF32C>(const DevInst *, const WorkItem *, int, const DevCtl *, int);
-
-hipError_t launch_fused_fp64(const DevInst *d_inst, const WorkItem *d_work, int n_work, const DevCtl *ctl, int kstep,
-                             hipStream_t s)
+template <class P>
+hipError_t launch_fused_as(const DevInst *d_inst, const WorkItem *d_work, int n_work, const DevCtl *ctl, int kstep,
+                           hipStream_t s)
 {
     if (n_work <= 0) return hipSuccess;
     const int blocks = (n_work + kFusedWavesPerBlock - 1) / kFusedWavesPerBlock;
-    hipLaunchKernelGGL(k_fused<PolicyF64>, dim3(blocks), dim3(64 * kFusedWavesPerBlock), 0, s, d_inst, d_work, n_work,
-                       ctl, kstep);
+    hipLaunchKernelGGL(k_fused<P>, dim3(blocks), dim3(64 * kFusedWavesPerBlock), 0, s, d_inst, d_work, n_work, ctl,
+                       kstep);
     return hipGetLastError();
 }
 
-hipError_t launch_fused_fp32c(const DevInst *d_inst, const WorkItem *d_work, int n_work, const DevCtl *ctl, int kstep,
-                              hipStream_t s)
+template <template <int, bool, int> class Pol>
+hipError_t launch_fused_variant(const DevInst *d_inst, const WorkItem *d_work, int n_work, const DevCtl *ctl, int kstep,
+                                int prefetch, bool nt, int waves, hipStream_t s)
 {
-    if (n_work <= 0) return hipSuccess;
-    const int blocks = (n_work + kFusedWavesPerBlock - 1) / kFusedWavesPerBlock;
-    hipLaunchKernelGGL(k_fused<PolicyF32C>, dim3(blocks), dim3(64 * kFusedWavesPerBlock), 0, s, d_inst, d_work,
-                       n_work, ctl, kstep);
-    return hipGetLastError();
+#define TK_VARIANT(PD, NT, W)                                                                  \
+    if (prefetch == PD && nt == NT && waves == W)                                              \
+        return launch_fused_as<Pol<PD, NT, W>>(d_inst, d_work, n_work, ctl, kstep, s);
+    TK_VARIANT(3, true, 1)
+    TK_VARIANT(3, true, 3)
+    TK_VARIANT(3, true, 4)
+    TK_VARIANT(3, false, 1)
+    TK_VARIANT(1, true, 1)
+    TK_VARIANT(1, false, 1)
+#undef TK_VARIANT
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_fused_fp64(const DevInst *d_inst, const WorkItem *d_work, int n_work, const DevCtl *ctl, int kstep,
+                             int prefetch, bool nt, int waves, hipStream_t s)
+{
+    return launch_fused_variant<PolicyF64>(d_inst, d_work, n_work, ctl, kstep, prefetch, nt, waves, s);
+}
+
+hipError_t launch_fused_fp32c(const DevInst *d_inst, const WorkItem *d_work, int n_work, const DevCtl *ctl, int kstep,
+                              int prefetch, bool nt, int waves, hipStream_t s)
+{
+    return launch_fused_variant<PolicyF32C>(d_inst, d_work, n_work, ctl, kstep, prefetch, nt, waves, s);
 }
 
 }  // namespace tk

@@ -50,9 +50,13 @@ class SourceDesc(ctypes.Structure):
                 ("sigma_th_cells", ctypes.c_double), ("window_sigmas", ctypes.c_double)]
 
 
+TK_TUNE_NT_STORES = 1
+
+
 class Tuning(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int), ("rows_per_tile", ctypes.c_int),
-                ("graph_steps", ctypes.c_int)]
+                ("graph_steps", ctypes.c_int), ("prefetch_rows", ctypes.c_int),
+                ("flags", ctypes.c_int), ("waves_per_simd", ctypes.c_int)]
 
 
 _lib = None
@@ -222,14 +226,18 @@ class Stepper:
     def set_step(self, n):
         _check(self.lib.tk_set_step(self.ctx, int(n)), self.ctx)
 
-    def set_tuning(self, kernel=TK_KERNEL_AUTO, rows_per_tile=0, graph_steps=0):
-        t = Tuning(kernel, rows_per_tile, graph_steps)
+    def set_tuning(self, kernel=TK_KERNEL_AUTO, rows_per_tile=0, graph_steps=0, prefetch_rows=0,
+                   nt_stores=True, waves_per_simd=0):
+        t = Tuning(kernel, rows_per_tile, graph_steps, prefetch_rows,
+                   TK_TUNE_NT_STORES if nt_stores else 0, waves_per_simd)
         _check(self.lib.tk_set_tuning(self.ctx, ctypes.byref(t)), self.ctx)
 
     def get_tuning(self):
         t = Tuning()
         _check(self.lib.tk_get_tuning(self.ctx, ctypes.byref(t)), self.ctx)
-        return dict(kernel=t.kernel, rows_per_tile=t.rows_per_tile, graph_steps=t.graph_steps)
+        return dict(kernel=t.kernel, rows_per_tile=t.rows_per_tile, graph_steps=t.graph_steps,
+                    prefetch_rows=t.prefetch_rows, nt_stores=bool(t.flags & TK_TUNE_NT_STORES),
+                    waves_per_simd=t.waves_per_simd)
 
     def synchronize(self):
         _check(self.lib.tk_synchronize(self.ctx), self.ctx)

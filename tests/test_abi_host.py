@@ -32,7 +32,7 @@ def test_struct_layout_matches_header():
     # the ctypes mirrors must have the C sizes (x86-64 ABI)
     assert ctypes.sizeof(tk.InstanceDesc) == 80
     assert ctypes.sizeof(tk.SourceDesc) == 56
-    assert ctypes.sizeof(tk.Tuning) == 12
+    assert ctypes.sizeof(tk.Tuning) == 24
 
 
 def _init(insts):
@@ -90,13 +90,15 @@ def test_tuning_validation():
     st, ctx = _init([tk.make_desc(inst)])
     assert st == tk.TK_OK
     lib = tk.load()
-    bad = tk.Tuning(7, 0, 0)
-    assert lib.tk_set_tuning(ctx, ctypes.byref(bad)) == tk.TK_E_INVALID
-    bad = tk.Tuning(tk.TK_KERNEL_FUSED, 2, 0)
-    assert lib.tk_set_tuning(ctx, ctypes.byref(bad)) == tk.TK_E_INVALID
-    ok = tk.Tuning(tk.TK_KERNEL_TWO_PASS, 8, 50)
+    for bad in (tk.Tuning(7, 0, 0, 0, 0, 0), tk.Tuning(tk.TK_KERNEL_FUSED, 2, 0, 0, 0, 0),
+                tk.Tuning(tk.TK_KERNEL_FUSED, 0, 0, 2, 0, 0), tk.Tuning(tk.TK_KERNEL_FUSED, 0, 0, 3, 8, 0),
+                tk.Tuning(tk.TK_KERNEL_FUSED, 0, 0, 1, 1, 4)):
+        assert lib.tk_set_tuning(ctx, ctypes.byref(bad)) == tk.TK_E_INVALID
+    ok = tk.Tuning(tk.TK_KERNEL_TWO_PASS, 8, 50, 1, tk.TK_TUNE_NT_STORES, 0)
     assert lib.tk_set_tuning(ctx, ctypes.byref(ok)) == tk.TK_OK
     got = tk.Tuning()
     assert lib.tk_get_tuning(ctx, ctypes.byref(got)) == tk.TK_OK
-    assert (got.kernel, got.rows_per_tile, got.graph_steps) == (1, 8, 50)
+    assert (got.kernel, got.rows_per_tile, got.graph_steps, got.prefetch_rows, got.flags) == (1, 8, 50, 1, 1)
+    ok = tk.Tuning(tk.TK_KERNEL_FUSED, 0, 0, 3, tk.TK_TUNE_NT_STORES, 4)
+    assert lib.tk_set_tuning(ctx, ctypes.byref(ok)) == tk.TK_OK
     lib.tk_destroy(ctx)

@@ -73,9 +73,11 @@ def check_parity(inst, steps, got, ref, phi0=None, pi0=None):
     return e
 
 
-def gpu_run(insts, steps, kernel=tk.TK_KERNEL_AUTO, rows=0, graph=0, inits=None, chunks=None):
-    st = tk.Stepper(insts, force_dt=True)
-    st.set_tuning(kernel=kernel, rows_per_tile=rows, graph_steps=graph)
+def gpu_run(insts, steps, kernel=tk.TK_KERNEL_AUTO, rows=0, graph=0, inits=None, chunks=None,
+            prefetch=0, nt=True, waves=0, precision=tk.TK_FP64):
+    st = tk.Stepper(insts, force_dt=True, precision=precision)
+    st.set_tuning(kernel=kernel, rows_per_tile=rows, graph_steps=graph, prefetch_rows=prefetch, nt_stores=nt,
+                  waves_per_simd=waves)
     for k, inst in enumerate(insts):
         phi0, pi0 = W.initial_data(inst) if inits is None else inits[k]
         st.set_fields(k, phi0, pi0)
@@ -169,6 +171,17 @@ def test_row_chunking_bitwise(rows):
     other = gpu_run(insts, steps, rows=rows)
     for (a, b) in zip(base, other):
         assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+
+
+@pytest.mark.parametrize("precision", [tk.TK_FP64, tk.TK_FP32_COMP])
+def test_launch_variants_bitwise(precision):
+    # prefetch depth and store kind change scheduling only, never arithmetic
+    insts = small_instances()
+    base = gpu_run(insts, 40, prefetch=3, precision=precision)
+    for pf, nt, rows, w in [(1, False, 0, 0), (3, False, 0, 0), (1, True, 5, 0), (3, True, 0, 3), (3, True, 7, 4)]:
+        other = gpu_run(insts, 40, prefetch=pf, nt=nt, rows=rows, waves=w, precision=precision)
+        for (a, b) in zip(base, other):
+            assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
 
 
 def test_graph_replay_equals_eager_bitwise():
