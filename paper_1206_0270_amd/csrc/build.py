@@ -20,9 +20,13 @@ HOST_SOURCES = ["tk_setup.cpp", "tk_api.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wextra", "-Wno-unused-parameter",
           "-I" + os.path.join(ROOT, "include")]
-# device code: gfx950 only; packed FP32 instructions disabled
+# device code: gfx950 only; packed FP32 instructions disabled.  Multiply-adds
+# are fused per source expression (contract=on), never across statements:
+# with cross-statement fusion the compiler fuses differently in different
+# inlined copies of the same row update, and the result of a row would then
+# depend on where the launch's tiling puts it.
 DEVICE = ["-x", "hip", "--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang",
-          "-packed-fp32-ops", "-ffp-contract=fast", "-munsafe-fp-atomics"]
+          "-packed-fp32-ops", "-ffp-contract=on", "-munsafe-fp-atomics"]
 
 
 def run(cmd, verbose):

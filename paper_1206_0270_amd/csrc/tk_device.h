@@ -11,6 +11,57 @@
 
 namespace tk {
 
+// Pointers read out of device-side descriptors are generic to the compiler,
+// which then emits FLAT memory instructions; those are counted against the
+// LDS wait counter as well, so every LDS wait would also drain the loads in
+// flight.  These casts state that the memory is global.
+#define TK_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ const TK_GLOBAL T *gload_ptr(const T *p)
+{
+    return (const TK_GLOBAL T *)p;
+}
+template <typename T>
+__device__ __forceinline__ TK_GLOBAL T *gstore_ptr(T *p)
+{
+    return (TK_GLOBAL T *)p;
+}
+// Tables that no kernel writes (coefficients): through the constant address
+// space a wave-uniform index becomes a scalar load, which does not queue
+// behind the vector loads in flight.
+#define TK_CONST __attribute__((address_space(4)))
+template <typename T>
+__device__ __forceinline__ const TK_CONST T *cload_ptr(const T *p)
+{
+    return (const TK_CONST T *)p;
+}
+
+// Copy of a table entry (a struct of doubles) through a qualified pointer:
+// the implicit copy constructor cannot bind to an address-space lvalue, so
+// the fields are read one by one (unused ones are dropped by the compiler).
+template <typename S>
+__device__ __forceinline__ S load_entry(const TK_GLOBAL S *p)
+{
+    static_assert(sizeof(S) % sizeof(double) == 0, "table entries are arrays of doubles");
+    S s;
+    double *d = reinterpret_cast<double *>(&s);
+    const TK_GLOBAL double *q = reinterpret_cast<const TK_GLOBAL double *>(p);
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(S) / sizeof(double)); ++k) d[k] = q[k];
+    return s;
+}
+template <typename S>
+__device__ __forceinline__ S load_entry(const TK_CONST S *p)
+{
+    static_assert(sizeof(S) % sizeof(double) == 0, "table entries are arrays of doubles");
+    S s;
+    double *d = reinterpret_cast<double *>(&s);
+    const TK_CONST double *q = reinterpret_cast<const TK_CONST double *>(p);
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(S) / sizeof(double)); ++k) d[k] = q[k];
+    return s;
+}
+
 template <typename T>
 struct cx {
     T re, im;
@@ -89,12 +140,20 @@ __device__ __forceinline__ Q4<T> zero_q4()
 }
 __device__ __forceinline__ P4 zero4() { return zero_q4<double>(); }
 
+typedef double dvec4 __attribute__((ext_vector_type(4)));
+typedef float fvec4 __attribute__((ext_vector_type(4)));
+typedef unsigned short hvec4 __attribute__((ext_vector_type(4)));
+
 __device__ __forceinline__ P4 ld_p4(const double4 *p)
 {
-    double4 v = *p;
+    const dvec4 v = *gload_ptr((const dvec4 *)p);
     return P4{mk(v.x, v.y), mk(v.z, v.w)};
 }
-__device__ __forceinline__ void st_p4(double4 *p, P4 v) { *p = make_double4(v.phi.re, v.phi.im, v.pi.re, v.pi.im); }
+__device__ __forceinline__ void st_p4(double4 *p, P4 v)
+{
+    const dvec4 x = {v.phi.re, v.phi.im, v.pi.re, v.pi.im};
+    *gstore_ptr((dvec4 *)p) = x;
+}
 
 // Coefficients of u_t + D u_{r*} = S at one (radial position, theta row).
 template <typename T>

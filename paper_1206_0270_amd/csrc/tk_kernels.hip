@@ -27,8 +27,8 @@ __device__ __forceinline__ P4 stage1_at(const DevInst &I, const double4 *u, int 
     const P4 ap0 = ld_p4(u + (size_t)(j + 1) * p + i), ap1 = ld_p4(u + (size_t)(j + 1) * p + i + 1);
     const P4 bar = half_sum(a1, a0);
     const cd phm = half_sum(am1, am0).phi, php = half_sum(ap1, ap0).phi;
-    const Radial &R = I.rad[2 * i + 1];
-    const Angular &A = I.ang[j];
+    const Radial R = load_entry(gload_ptr(I.rad) + (2 * i + 1));
+    const Angular A = load_entry(gload_ptr(I.ang) + (j));
     const Coef c = coef_at(R, A);
     const cd F = R.srcg * A.srcg != 0.0 ? source_value(R.srcg, A.srcg, source_phase(I, t)) : mk(0, 0);
     return lw_point(c, bar, phm, bar.phi, php, bar.pi, a1 - a0, 0.5 * I.dt, I.inv_h, I.inv_dth2, I.inv_2dth, F);
@@ -43,8 +43,8 @@ __device__ __forceinline__ P4 stage2_at(const DevInst &I, const double4 *u, cons
     const P4 hp0 = ld_p4(hf + (size_t)(j + 1) * p + i - 1), hp1 = ld_p4(hf + (size_t)(j + 1) * p + i);
     const P4 til = half_sum(h1, h0);
     const cd phm = half_sum(hm1, hm0).phi, php = half_sum(hp1, hp0).phi;
-    const Radial &R = I.rad[2 * i];
-    const Angular &A = I.ang[j];
+    const Radial R = load_entry(gload_ptr(I.rad) + (2 * i));
+    const Angular A = load_entry(gload_ptr(I.ang) + (j));
     const Coef c = coef_at(R, A);
     const cd F = R.srcg * A.srcg != 0.0 ? source_value(R.srcg, A.srcg, source_phase(I, t)) : mk(0, 0);
     const P4 un = ld_p4(u + (size_t)j * p + i);
@@ -104,7 +104,7 @@ __global__ void __launch_bounds__(256) k_two_pass_full(const DevInst *__restrict
     st_p4(un + (size_t)j * I.pitch + i, out);
     if (i == I.i_obs && I.extract_every > 0 && (n + 1) % I.extract_every == 0) {
         const long long k = (n + 1) / I.extract_every - 1;
-        double *w = I.wave + ((size_t)(k % I.wave_cap) * nt + j) * 2;
+        TK_GLOBAL double *w = gstore_ptr(I.wave) + ((size_t)(k % I.wave_cap) * nt + j) * 2;
         w[0] = out.phi.re;
         w[1] = out.phi.im;
     }
@@ -247,8 +247,8 @@ __device__ __forceinline__ St<typename P::T> load_row(const Lane<P> &L, int row)
     if constexpr (!P::kComp) {
         v.f = ld_p4((const double4 *)L.u + o);
     } else {
-        const float4 a = ((const float4 *)L.u)[o];
-        const ushort4 b = ((const ushort4 *)L.uc)[o];
+        const fvec4 a = gload_ptr((const fvec4 *)L.u)[o];
+        const hvec4 b = gload_ptr((const hvec4 *)L.uc)[o];
         v.f = Q4<T>{mkc(a.x, a.y), mkc(a.z, a.w)};
         v.c = Q4<T>{mkc(bf16_to_float(b.x), bf16_to_float(b.y)), mkc(bf16_to_float(b.z), bf16_to_float(b.w))};
     }
@@ -276,10 +276,6 @@ __device__ __forceinline__ double value_of(const St<typename P::T> &v, int k)
     return P::kComp ? (double)f[k] + (double)c[k] : (double)f[k];
 }
 
-typedef double dvec4 __attribute__((ext_vector_type(4)));
-typedef float fvec4 __attribute__((ext_vector_type(4)));
-typedef unsigned short hvec4 __attribute__((ext_vector_type(4)));
-
 template <class P>
 __device__ __forceinline__ void emit(const Lane<P> &L, int row, const St<typename P::T> &v)
 {
@@ -288,24 +284,24 @@ __device__ __forceinline__ void emit(const Lane<P> &L, int row, const St<typenam
         if constexpr (!P::kComp) {
             const dvec4 x = {v.f.phi.re, v.f.phi.im, v.f.pi.re, v.f.pi.im};
             if (P::kNT)
-                __builtin_nontemporal_store(x, (dvec4 *)L.un + o);
+                __builtin_nontemporal_store(x, gstore_ptr((dvec4 *)L.un) + o);
             else
-                ((dvec4 *)L.un)[o] = x;
+                gstore_ptr((dvec4 *)L.un)[o] = x;
         } else {
             const fvec4 x = {v.f.phi.re, v.f.phi.im, v.f.pi.re, v.f.pi.im};
             const hvec4 y = {float_to_bf16(v.c.phi.re), float_to_bf16(v.c.phi.im), float_to_bf16(v.c.pi.re),
                              float_to_bf16(v.c.pi.im)};
             if (P::kNT) {
-                __builtin_nontemporal_store(x, (fvec4 *)L.un + o);
-                __builtin_nontemporal_store(y, (hvec4 *)L.unc + o);
+                __builtin_nontemporal_store(x, gstore_ptr((fvec4 *)L.un) + o);
+                __builtin_nontemporal_store(y, gstore_ptr((hvec4 *)L.unc) + o);
             } else {
-                ((fvec4 *)L.un)[o] = x;
-                ((hvec4 *)L.unc)[o] = y;
+                gstore_ptr((fvec4 *)L.un)[o] = x;
+                gstore_ptr((hvec4 *)L.unc)[o] = y;
             }
         }
     }
     if (L.ext && L.ov && L.c == L.I->i_obs) {
-        double *w = L.I->wave + ((size_t)L.wslot * L.nt + row) * 2;
+        TK_GLOBAL double *w = gstore_ptr(L.I->wave) + ((size_t)L.wslot * L.nt + row) * 2;
         w[0] = value_of<P>(v, 0);
         w[1] = value_of<P>(v, 1);
     }
@@ -344,7 +340,7 @@ __device__ __forceinline__ Q4<typename P::T> half_row(const Lane<P> &L, const Q4
     const Q4<T> n0 = shfl_down1(U0);
     if (!L.hv) return zero_q4<T>();
     const Q4<T> bar = half_sum(n0, U0);
-    const Angular &A = I.ang[r];
+    const Angular A = load_entry(cload_ptr(I.ang) + (r));
     const Coef<T> cf = coef_lean(rad_of(L, 0), ang_of<P>(A), L.a2, L.kct);
     const T fac = T(0.5) * L.dt;
     if constexpr (!P::kComp) {
@@ -387,7 +383,7 @@ __device__ __forceinline__ St<typename P::T> out_row(const Lane<P> &L, const St<
     res.c = zero_q4<T>();
     if (!L.icol) return res;
     const Q4<T> til = half_sum(H0, l0);
-    const Angular &A = I.ang[o];
+    const Angular A = load_entry(cload_ptr(I.ang) + (o));
     const Coef<T> cf = coef_lean(rad_of(L, 1), ang_of<P>(A), L.a2, L.kct);
     if constexpr (!P::kComp) {
         const cd F = L.near_n ? source_value(L.gn, A.srcg, L.e2) : mk(0, 0);
@@ -489,7 +485,10 @@ __global__ void __launch_bounds__(64 * kFusedWavesPerBlock) __attribute__((amdgp
     using T = typename P::T;
     __shared__ T s_rad[kFusedWavesPerBlock][2 * kRadVals * 64];
     const int lane = (int)(threadIdx.x & 63);
-    const int wv = (int)(threadIdx.x >> 6);
+    // wave index within the block: uniform per wave, said so explicitly so that
+    // the work item, the instance descriptor and the angular tables are read
+    // with scalar loads into scalar registers
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int w = (int)blockIdx.x * kFusedWavesPerBlock + wv;
     if (w >= n_work) return;  // whole wave leaves together; no block barriers below
     const WorkItem it = work[w];
@@ -527,8 +526,8 @@ __global__ void __launch_bounds__(64 * kFusedWavesPerBlock) __attribute__((amdgp
     // radial factors of the half node (slot 0) and the node (slot 1) -> LDS
     L.rad = &s_rad[wv][lane];
     {
-        const Radial &Rh = I.rad[L.hv ? 2 * L.c + 1 : 0];
-        const Radial &Rn = I.rad[L.icol ? 2 * L.c : 0];
+        const Radial Rh = load_entry(gload_ptr(I.rad) + (L.hv ? 2 * L.c + 1 : 0));
+        const Radial Rn = load_entry(gload_ptr(I.rad) + (L.icol ? 2 * L.c : 0));
         const double vh[kRadVals] = {Rh.rho, Rh.Dl, Rh.ct_re, Rh.ct_im0, Rh.K, Rh.c1_re, Rh.c1_im, Rh.c0_re, Rh.c0_im};
         const double vn[kRadVals] = {Rn.rho, Rn.Dl, Rn.ct_re, Rn.ct_im0, Rn.K, Rn.c1_re, Rn.c1_im, Rn.c0_re, Rn.c0_im};
 #pragma unroll
