@@ -21,7 +21,7 @@ sys.path.insert(0, ROOT)
 METRIC = "grid-point updates/sec (batched modes) + % HBM roofline; FP32-comp vs FP64"
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_UPDATE = {"fp64": 64, "fp32c": 48}
-KERNEL_NAME = {"fp64": "k_fused<PolicyF64>", "fp32c": "k_fused<PolicyF32C>"}
+KERNEL_POLICY = {"fp64": "PolicyF64", "fp32c": "PolicyF32C"}
 KERNEL_SOURCES = ["paper_1206_0270_amd/csrc/tk_kernels.hip", "paper_1206_0270_amd/csrc/tk_device.h",
                   "paper_1206_0270_amd/csrc/tk_internal.h"]
 
@@ -49,7 +49,13 @@ def workload(name):
     return insts, desc
 
 
-def traffic_entry(prec, wl):
+def kernel_name(prec, prefetch, nt, waves):
+    """The fused kernel variant as rocprofv3 names it (template arguments:
+    prefetch depth, non-temporal stores, occupancy target)."""
+    return f"k_fused<{KERNEL_POLICY[prec]}<{prefetch}, {'true' if nt else 'false'}, {waves or 1}>>"
+
+
+def traffic_entry(name, wl):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel source."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
@@ -58,7 +64,7 @@ def traffic_entry(prec, wl):
     try:
         with open(path) as f:
             data = json.load(f)
-        ent = data.get(f"{KERNEL_NAME[prec]}:{wl}")
+        ent = data.get(f"{name}:{wl}")
         if not ent or ent.get("kernel_hash") != kernel_hash():
             return None
         return float(ent["bytes_per_launch"])
@@ -172,7 +178,9 @@ def main():
     launch_s = gpu_ms / 1e3 / args.steps
     bpu = BYTES_PER_UPDATE[args.precision]
     achieved = points * bpu / launch_s / 1e9
-    traffic = traffic_entry(args.precision, args.workload)
+    kname = (kernel_name(args.precision, args.prefetch, not args.no_nt, args.waves)
+             if args.kernel == "fused" else "k_two_pass_half + k_two_pass_full")
+    traffic = traffic_entry(kname, args.workload)
     st.close()
 
     out = {
@@ -195,7 +203,7 @@ def main():
                    "waves_per_simd": args.waves},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": KERNEL_NAME[args.precision] if args.kernel == "fused" else "k_two_pass_*",
+                     "kernel": kname,
                      "algorithmic_bytes_per_launch": points * bpu,
                      "avg_launch_ms": launch_s * 1e3},
     }
