@@ -49,10 +49,11 @@ def workload(name):
     return insts, desc
 
 
-def kernel_name(prec, prefetch, nt, waves):
+def kernel_name(prec, prefetch, nt, waves, two_step=False):
     """The fused kernel variant as rocprofv3 names it (template arguments:
     prefetch depth, non-temporal stores, occupancy target)."""
-    return f"k_fused<{KERNEL_POLICY[prec]}<{prefetch}, {'true' if nt else 'false'}, {waves or 1}>>"
+    k = "k_fused2" if two_step else "k_fused"
+    return f"{k}<{KERNEL_POLICY[prec]}<{prefetch}, {'true' if nt else 'false'}, {waves or 1}>>"
 
 
 def traffic_entry(name, wl):
@@ -110,7 +111,9 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32c"])
     ap.add_argument("--graph-steps", type=int, default=100)
     ap.add_argument("--rows", type=int, default=0)
-    ap.add_argument("--kernel", default="fused", choices=["fused", "two_pass"])
+    ap.add_argument("--kernel", default="fused2", choices=["fused2", "fused", "two_pass"],
+                    help="fused2: two time steps per pass (needs --rows 0); fused: one step per pass; "
+                         "two_pass: half-step array through HBM")
     ap.add_argument("--prefetch", type=int, default=3, choices=[1, 3])
     ap.add_argument("--no-nt", action="store_true", help="plain (not non-temporal) stores")
     ap.add_argument("--waves", type=int, default=0, choices=[0, 3, 4])
@@ -151,7 +154,10 @@ def main():
     prec = tk.TK_FP64 if args.precision == "fp64" else tk.TK_FP32_COMP
     points = W.points(insts)
     st = tk.Stepper(insts, precision=prec)
-    kern = tk.TK_KERNEL_FUSED if args.kernel == "fused" else tk.TK_KERNEL_TWO_PASS
+    kern = {"fused2": tk.TK_KERNEL_FUSED2, "fused": tk.TK_KERNEL_FUSED, "two_pass": tk.TK_KERNEL_TWO_PASS}[args.kernel]
+    two_step = args.kernel == "fused2"
+    if two_step and (args.steps % 2 or args.warmup % 2 or args.graph_steps % 2):
+        raise SystemExit("--kernel fused2 times whole two-step launches: use even --steps, --warmup, --graph-steps")
     st.set_tuning(kernel=kern, rows_per_tile=args.rows, graph_steps=args.graph_steps,
                   prefetch_rows=args.prefetch, nt_stores=not args.no_nt, waves_per_simd=args.waves)
     for k, inst in enumerate(insts):
@@ -175,11 +181,15 @@ def main():
           file=sys.stderr, flush=True)
     elapsed = max(wall, gpu_ms / 1e3)
     value = points * args.steps / elapsed
-    launch_s = gpu_ms / 1e3 / args.steps
+    # one launch reads the state once and writes it once, for one step (or
+    # two with the two-step kernel): algorithmic bytes per launch = bytes
+    # per point update x points
+    launches = args.steps // 2 if two_step else args.steps
+    launch_s = gpu_ms / 1e3 / launches
     bpu = BYTES_PER_UPDATE[args.precision]
     achieved = points * bpu / launch_s / 1e9
-    kname = (kernel_name(args.precision, args.prefetch, not args.no_nt, args.waves)
-             if args.kernel == "fused" else "k_two_pass_half + k_two_pass_full")
+    kname = (kernel_name(args.precision, args.prefetch, not args.no_nt, args.waves, two_step)
+             if args.kernel != "two_pass" else "k_two_pass_half + k_two_pass_full")
     traffic = traffic_entry(kname, args.workload)
     st.close()
 
@@ -205,6 +215,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": kname,
                      "algorithmic_bytes_per_launch": points * bpu,
+                     "steps_per_launch": 2 if two_step else 1,
                      "avg_launch_ms": launch_s * 1e3},
     }
     if not args.no_cpu_baseline:

@@ -102,9 +102,14 @@ typedef struct {
 /* Kernel choice and launch shape (the only per-architecture tuning the
  * paper reports is the work-group size, Section 4). */
 typedef enum {
-    TK_KERNEL_AUTO = 0,
+    TK_KERNEL_AUTO = 0,     /* FUSED2 with rows_per_tile 0, else FUSED (FP32: the
+                               fused forms only) */
     TK_KERNEL_TWO_PASS = 1, /* half-step array through HBM, one thread per point */
-    TK_KERNEL_FUSED = 2     /* both steps in one pass, theta-marching columns   */
+    TK_KERNEL_FUSED = 2,    /* both stages in one pass, theta-marching columns   */
+    TK_KERNEL_FUSED2 = 3    /* two time steps per pass over whole column strips:
+                               u^n read and u^{n+2} written once, u^{n+1} kept
+                               on chip (an odd step count ends with one FUSED
+                               step); results are bitwise those of FUSED */
 } tk_kernel;
 
 enum {
@@ -113,7 +118,8 @@ enum {
 
 typedef struct {
     int kernel;        /* tk_kernel */
-    int rows_per_tile; /* fused kernel: theta rows per work item (0 = all)   */
+    int rows_per_tile; /* fused kernel: theta rows per work item (0 = all;
+                          FUSED2 needs 0)                                     */
     int graph_steps;   /* steps per captured HIP graph (0 = no graphs)        */
     int prefetch_rows; /* fused kernel: u^n rows in flight per wave, 1 or 3 (0 = 3) */
     int flags;         /* TK_TUNE_* */
@@ -152,7 +158,9 @@ tk_status tk_get_fields(tk_ctx *ctx, int inst, double *phi, double *pi);
 tk_status tk_set_source(tk_ctx *ctx, int inst, const tk_source_desc *src);
 
 /* Advance every instance by n_steps full Lax-Wendroff steps (Eqs. (3)-(4)
- * with the Section 2.2 boundary conditions), asynchronously on the stream. */
+ * with the Section 2.2 boundary conditions), asynchronously on the stream.
+ * The state alternates between two buffers, one flip per kernel launch; the
+ * context tracks which one is current. */
 tk_status tk_step(tk_ctx *ctx, long n_steps);
 
 /* Copy the waveform samples of inst taken since the last call, oldest first,
@@ -164,7 +172,9 @@ tk_status tk_step(tk_ctx *ctx, long n_steps);
 tk_status tk_extract(tk_ctx *ctx, int inst, double *out, long max_samples, long *n_samples);
 
 /* Step counter (steps taken since tk_bind_workspace or the last
- * tk_set_step); time of instance k is step * dt_k. */
+ * tk_set_step); time of instance k is step * dt_k.  tk_set_step changes the
+ * time index only: the current state is kept as it is (resume a
+ * checkpoint with tk_set_step then tk_set_fields, in either order). */
 tk_status tk_get_step(const tk_ctx *ctx, long *step);
 tk_status tk_set_step(tk_ctx *ctx, long step);
 

@@ -29,15 +29,17 @@ struct tk_ctx {
     std::vector<int2> blocks;          // two-pass decomposition
     std::vector<WorkItem> work;        // fused decomposition
     int work_rows = 0;                 // rows_per_tile the work list was built for
+    int work_cols = 0;                 // strip width it was built for
     size_t work_cap = 0;               // capacity of the work list area (items)
     std::vector<DevInst> hdev;         // host mirror of the device descriptors
     std::vector<std::vector<Radial>> hrad;   // host copies of the coefficient tables
     std::vector<std::vector<Angular>> hang;
     long long step = 0;
+    int cur = 0;  // state buffer holding u^step (mirror of the device control block)
     tk_tuning tuning{TK_KERNEL_AUTO, 0, 0, 3, TK_TUNE_NT_STORES, 0};
     // captured graph (steps, kernel, rows) for replay
     hipGraphExec_t gexec = nullptr;
-    int g_steps = 0, g_kernel = -1, g_rows = -1, g_pf = -1, g_flags = -1, g_waves = -1;
+    int g_steps = 0, g_flips = 0, g_kernel = -1, g_rows = -1, g_pf = -1, g_flags = -1, g_waves = -1;
 };
 
 namespace {
@@ -92,9 +94,9 @@ std::string validate(const tk_instance_desc &d)
     return "";
 }
 
-// Fused work list: strips of kFusedCols output columns x chunks of rows,
+// Fused work list: strips of `cols` output columns x chunks of rows,
 // longest first (waves are dispatched roughly in order).
-void build_work(tk_ctx *c, int rows)
+void build_work(tk_ctx *c, int rows, int cols)
 {
     c->work.clear();
     for (size_t k = 0; k < c->inst.size(); ++k) {
@@ -104,22 +106,25 @@ void build_work(tk_ctx *c, int rows)
             int j1 = std::min(d.n_theta, j0 + rc);
             // keep a pole chunk at least 3 rows (pole extrapolation needs rows 1, 2)
             if (d.n_theta - j1 > 0 && d.n_theta - j1 < 3) j1 = d.n_theta;
-            for (int i0 = 0; i0 < d.n_r; i0 += kFusedCols) c->work.push_back(WorkItem{(int)k, i0, j0, j1});
+            for (int i0 = 0; i0 < d.n_r; i0 += cols) c->work.push_back(WorkItem{(int)k, i0, j0, j1});
             if (j1 == d.n_theta) break;
         }
     }
     std::stable_sort(c->work.begin(), c->work.end(),
                      [](const WorkItem &x, const WorkItem &y) { return (x.j1 - x.j0) > (y.j1 - y.j0); });
     c->work_rows = rows;
+    c->work_cols = cols;
 }
 
 size_t work_capacity(const tk_ctx *c)
 {
-    // upper bound over rows_per_tile >= 3: chunks of 3 rows
+    // upper bound over the shapes: chunks of 3 rows of kFusedCols-wide
+    // strips, or whole kFused2Cols-wide strips
     size_t n = 0;
     for (const HostInst &h : c->inst) {
         size_t strips = (h.desc.n_r + kFusedCols - 1) / kFusedCols;
-        n += strips * ((h.desc.n_theta + 2) / 3 + 1);
+        size_t strips2 = (h.desc.n_r + kFused2Cols - 1) / kFused2Cols;
+        n += std::max(strips * ((h.desc.n_theta + 2) / 3 + 1), strips2);
     }
     return n;
 }
@@ -205,16 +210,17 @@ DevInst make_dev(const tk_ctx *c, const HostInst &h)
 int resolve_kernel(const tk_ctx *c)
 {
     int k = c->tuning.kernel;
-    if (k == TK_KERNEL_AUTO) k = TK_KERNEL_FUSED;
-    if (c->prec != TK_FP64) k = TK_KERNEL_FUSED;
+    if (k == TK_KERNEL_AUTO) k = c->tuning.rows_per_tile == 0 ? TK_KERNEL_FUSED2 : TK_KERNEL_FUSED;
+    if (c->prec != TK_FP64 && k == TK_KERNEL_TWO_PASS) k = TK_KERNEL_FUSED;
     return k;
 }
 
-tk_status ensure_work(tk_ctx *c)
+tk_status ensure_work(tk_ctx *c, int kernel)
 {
-    int rows = c->tuning.rows_per_tile;
-    if (!c->work.empty() && c->work_rows == rows) return TK_OK;
-    build_work(c, rows);
+    const int rows = c->tuning.rows_per_tile;
+    const int cols = kernel == TK_KERNEL_FUSED2 ? kFused2Cols : kFusedCols;
+    if (!c->work.empty() && c->work_rows == rows && c->work_cols == cols) return TK_OK;
+    build_work(c, rows, cols);
     if (c->work.size() > c->work_cap) return fail(c, TK_E_STATE, "work list exceeds its reserved area");
     TK_HIP(c, hipMemcpyAsync(c->ws + c->off_work, c->work.data(), c->work.size() * sizeof(WorkItem),
                              hipMemcpyHostToDevice, c->stream));
@@ -222,28 +228,45 @@ tk_status ensure_work(tk_ctx *c)
     return TK_OK;
 }
 
-hipError_t launch_one(tk_ctx *c, int kernel, int kstep)
+// One launch advancing `steps` (1, or 2 with the two-step kernel) from step
+// offset kstep, reading buffer (cur + kflip) & 1.
+hipError_t launch_one(tk_ctx *c, int kernel, int steps, int kstep, int kflip)
 {
     const DevInst *di = (const DevInst *)(c->ws + c->off_inst);
     const DevCtl *ctl = (const DevCtl *)(c->ws + c->off_ctl);
     if (kernel == TK_KERNEL_TWO_PASS)
-        return launch_two_pass(di, (const int2 *)(c->ws + c->off_blocks), (int)c->blocks.size(), ctl, kstep,
+        return launch_two_pass(di, (const int2 *)(c->ws + c->off_blocks), (int)c->blocks.size(), ctl, kstep, kflip,
                                c->stream);
     const WorkItem *wk = (const WorkItem *)(c->ws + c->off_work);
-    const int pf = c->tuning.prefetch_rows == 1 ? 1 : 3;
-    const bool nt = (c->tuning.flags & TK_TUNE_NT_STORES) != 0;
-    const int w = c->tuning.waves_per_simd == 0 ? 1 : c->tuning.waves_per_simd;
-    if (c->prec == TK_FP64) return launch_fused_fp64(di, wk, (int)c->work.size(), ctl, kstep, pf, nt, w, c->stream);
-    return launch_fused_fp32c(di, wk, (int)c->work.size(), ctl, kstep, pf, nt, w, c->stream);
+    FusedShape f;
+    f.prefetch = c->tuning.prefetch_rows == 1 ? 1 : 3;
+    f.nt = (c->tuning.flags & TK_TUNE_NT_STORES) != 0;
+    f.waves = c->tuning.waves_per_simd == 0 ? 1 : c->tuning.waves_per_simd;
+    f.two_step = steps == 2;
+    return launch_fused(c->prec == TK_FP64, di, wk, (int)c->work.size(), c->work_cols, ctl, kstep, kflip, f,
+                        c->stream);
 }
 
-tk_status enqueue_eager(tk_ctx *c, int kernel, long n)
+// The launches of n steps: pairs of steps with the two-step kernel, the
+// rest one step at a time; then the control-block bump.  Returns the number
+// of launches (buffer flips) in *flips.
+tk_status enqueue_steps(tk_ctx *c, int kernel, long n, int *flips)
 {
-    for (long k = 0; k < n; ++k) {
-        hipError_t e = launch_one(c, kernel, (int)k);
+    long k = 0;
+    int f = 0;
+    if (kernel == TK_KERNEL_FUSED2) {
+        for (; n - k >= 2; k += 2, ++f) {
+            hipError_t e = launch_one(c, kernel, 2, (int)k, f & 1);
+            if (e != hipSuccess) return fail(c, TK_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+        }
+    }
+    for (; k < n; ++k, ++f) {
+        hipError_t e = launch_one(c, kernel, 1, (int)k, f & 1);
         if (e != hipSuccess) return fail(c, TK_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
     }
-    TK_HIP(c, launch_bump((DevCtl *)(c->ws + c->off_ctl), (int)n, c->stream));
+    hipError_t e = launch_bump((DevCtl *)(c->ws + c->off_ctl), (int)n, f & 1, c->stream);
+    if (e != hipSuccess) return fail(c, TK_E_DEVICE, std::string("bump launch: ") + hipGetErrorString(e));
+    *flips = f;
     return TK_OK;
 }
 
@@ -268,15 +291,8 @@ tk_status ensure_graph(tk_ctx *c, int kernel, int G)
     drop_graph(c);
     hipGraph_t g = nullptr;
     TK_HIP(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-    tk_status st = TK_OK;
-    for (int k = 0; k < G && st == TK_OK; ++k) {
-        hipError_t e = launch_one(c, kernel, k);
-        if (e != hipSuccess) st = fail(c, TK_E_DEVICE, std::string("capture launch: ") + hipGetErrorString(e));
-    }
-    if (st == TK_OK) {
-        hipError_t e = launch_bump((DevCtl *)(c->ws + c->off_ctl), G, c->stream);
-        if (e != hipSuccess) st = fail(c, TK_E_DEVICE, std::string("capture bump: ") + hipGetErrorString(e));
-    }
+    int flips = 0;
+    tk_status st = enqueue_steps(c, kernel, G, &flips);
     hipError_t e = hipStreamEndCapture(c->stream, &g);
     if (st != TK_OK) {
         if (g) (void)hipGraphDestroy(g);
@@ -290,6 +306,7 @@ tk_status ensure_graph(tk_ctx *c, int kernel, int G)
         return fail(c, TK_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
     }
     c->g_steps = G;
+    c->g_flips = flips;
     c->g_kernel = kernel;
     c->g_rows = c->tuning.rows_per_tile;
     c->g_pf = c->tuning.prefetch_rows;
@@ -422,13 +439,14 @@ tk_status tk_bind_workspace(tk_ctx *c, void *dev_ptr, size_t bytes)
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
         if (e != hipSuccess) st = fail(c, TK_E_DEVICE, std::string("workspace init: ") + hipGetErrorString(e));
     }
-    if (st == TK_OK) st = ensure_work(c);
+    if (st == TK_OK) st = ensure_work(c, TK_KERNEL_FUSED);
     if (st != TK_OK) {
         c->ws = nullptr;
         c->ws_bytes = 0;
         return st;
     }
     c->step = 0;
+    c->cur = 0;
     return TK_OK;
 }
 
@@ -464,7 +482,7 @@ tk_status tk_set_fields(tk_ctx *c, int inst, const double *phi, const double *pi
     if (!phi || !pi) return fail(c, TK_E_INVALID, "null field pointer");
     const HostInst &h = c->inst[inst];
     const int nr = h.desc.n_r, nt = h.desc.n_theta, p = h.pitch;
-    const int cur = (int)(c->step & 1);
+    const int cur = c->cur;
     if (c->prec == TK_FP64) {
         std::vector<double> buf((size_t)nt * p * 4, 0.0);
         for (int j = 0; j < nt; ++j)
@@ -507,7 +525,7 @@ tk_status tk_get_fields(tk_ctx *c, int inst, double *phi, double *pi)
     if (!phi || !pi) return fail(c, TK_E_INVALID, "null field pointer");
     const HostInst &h = c->inst[inst];
     const int nr = h.desc.n_r, nt = h.desc.n_theta, p = h.pitch;
-    const int cur = (int)(c->step & 1);
+    const int cur = c->cur;
     if (c->prec == TK_FP64) {
         std::vector<double> buf((size_t)nt * p * 4);
         TK_HIP(c, hipMemcpyAsync(buf.data(), c->ws + h.off_u[cur], buf.size() * sizeof(double),
@@ -583,8 +601,8 @@ tk_status tk_step(tk_ctx *c, long n_steps)
     if (!c->ws) return fail(c, TK_E_STATE, "no workspace bound");
     if (n_steps == 0) return TK_OK;
     const int kernel = resolve_kernel(c);
-    if (kernel == TK_KERNEL_FUSED) {
-        tk_status st = ensure_work(c);
+    if (kernel != TK_KERNEL_TWO_PASS) {
+        tk_status st = ensure_work(c, kernel);
         if (st != TK_OK) return st;
     }
     long left = n_steps;
@@ -595,15 +613,19 @@ tk_status tk_step(tk_ctx *c, long n_steps)
         while (left >= G) {
             TK_HIP(c, hipGraphLaunch(c->gexec, c->stream));
             left -= G;
+            c->step += G;
+            c->cur = (c->cur + c->g_flips) & 1;
         }
     }
     while (left > 0) {
         long chunk = std::min(left, 1L << 20);
-        tk_status st = enqueue_eager(c, kernel, chunk);
+        int flips = 0;
+        tk_status st = enqueue_steps(c, kernel, chunk, &flips);
         if (st != TK_OK) return st;
         left -= chunk;
+        c->step += chunk;
+        c->cur = (c->cur + flips) & 1;
     }
-    c->step += n_steps;
     return TK_OK;
 }
 
@@ -655,22 +677,11 @@ tk_status tk_set_step(tk_ctx *c, long step)
     if (step < 0) return fail(c, TK_E_INVALID, "step must be >= 0");
     if (!c->ws) return fail(c, TK_E_STATE, "no workspace bound");
     TK_HIP(c, hipStreamSynchronize(c->stream));
-    if ((step & 1) != (c->step & 1)) {
-        // keep the current state: move it into the buffer the new parity reads
-        const int from = (int)(c->step & 1), to = (int)(step & 1);
-        for (const HostInst &h : c->inst) {
-            size_t pts = (size_t)h.desc.n_theta * h.pitch;
-            size_t ub = c->prec == TK_FP64 ? pts * 32 : pts * 16;
-            TK_HIP(c, hipMemcpyAsync(c->ws + h.off_u[to], c->ws + h.off_u[from], ub, hipMemcpyDeviceToDevice,
-                                     c->stream));
-            if (c->prec != TK_FP64)
-                TK_HIP(c, hipMemcpyAsync(c->ws + h.off_c[to], c->ws + h.off_c[from], pts * 8,
-                                         hipMemcpyDeviceToDevice, c->stream));
-        }
-    }
+    // the state stays where it is; only the time index changes
     DevCtl ctl;
     std::memset(&ctl, 0, sizeof ctl);
     ctl.step = step;
+    ctl.cur = c->cur;
     TK_HIP(c, hipMemcpyAsync(c->ws + c->off_ctl, &ctl, sizeof ctl, hipMemcpyHostToDevice, c->stream));
     TK_HIP(c, hipStreamSynchronize(c->stream));
     c->step = step;
@@ -681,8 +692,10 @@ tk_status tk_set_step(tk_ctx *c, long step)
 tk_status tk_set_tuning(tk_ctx *c, const tk_tuning *t)
 {
     if (!c || !t) return TK_E_INVALID;
-    if (t->kernel < TK_KERNEL_AUTO || t->kernel > TK_KERNEL_FUSED)
+    if (t->kernel < TK_KERNEL_AUTO || t->kernel > TK_KERNEL_FUSED2)
         return fail(c, TK_E_INVALID, "unknown kernel");
+    if (t->kernel == TK_KERNEL_FUSED2 && t->rows_per_tile != 0)
+        return fail(c, TK_E_INVALID, "the two-step kernel marches whole strips: rows_per_tile must be 0");
     if (t->kernel == TK_KERNEL_TWO_PASS && c->prec != TK_FP64)
         return fail(c, TK_E_INVALID, "the two-pass kernel is FP64 only");
     if (t->rows_per_tile < 0 || (t->rows_per_tile > 0 && t->rows_per_tile < 3))
@@ -700,8 +713,8 @@ tk_status tk_set_tuning(tk_ctx *c, const tk_tuning *t)
     }
     c->tuning = *t;
     if (c->tuning.prefetch_rows == 0) c->tuning.prefetch_rows = 3;
-    if (c->ws && resolve_kernel(c) == TK_KERNEL_FUSED) {
-        tk_status st = ensure_work(c);
+    if (c->ws && resolve_kernel(c) != TK_KERNEL_TWO_PASS) {
+        tk_status st = ensure_work(c, resolve_kernel(c));
         if (st != TK_OK) return st;
     }
     return TK_OK;

@@ -73,7 +73,8 @@ struct alignas(16) WorkItem {
 // Device-resident control block of a context.
 struct alignas(16) DevCtl {
     long long step;  // step counter n (time of instance k = n dt_k)
-    long long pad[7];
+    long long cur;   // state buffer (0 or 1) holding u^n; every launch flips it
+    long long pad[6];
 };
 
 // Host-side description after validation (one per instance).

@@ -9,26 +9,37 @@ namespace tk {
 
 // Two-pass step (half-step array through HBM).  d_blocks[b] = {instance,
 // block index within the instance}; one 256-thread block per 256 points of
-// the instance's n_theta x n_r grid.
+// the instance's n_theta x n_r grid.  The state is read from buffer
+// (ctl->cur + kflip) & 1 and written to the other one.
 hipError_t launch_two_pass(const DevInst *d_inst, const int2 *d_blocks, int n_blocks, const DevCtl *ctl, int kstep,
-                           hipStream_t s);
+                           int kflip, hipStream_t s);
 
-// Fused step: both Lax-Wendroff stages in one pass over theta-marching
-// column strips.  d_work[w] = work item of wave w; waves_per_block waves of
-// 64 lanes per block.
-// prefetch: u^n rows in flight per wave (1 or 3); nt: non-temporal stores;
-// waves: occupancy target per SIMD (1 = compiler's choice, 3, 4).  Returns
-// hipErrorInvalidValue for a combination that is not compiled.
-hipError_t launch_fused_fp64(const DevInst *d_inst, const WorkItem *d_work, int n_work, const DevCtl *ctl, int kstep,
-                             int prefetch, bool nt, int waves, hipStream_t s);
-hipError_t launch_fused_fp32c(const DevInst *d_inst, const WorkItem *d_work, int n_work, const DevCtl *ctl, int kstep,
-                              int prefetch, bool nt, int waves, hipStream_t s);
+// Launch shape of the fused kernels: u^n rows in flight per wave (1 or 3),
+// non-temporal stores, occupancy target per SIMD (1 = compiler's choice, 3,
+// 4), and one or two time steps per pass.
+struct FusedShape {
+    int prefetch;
+    bool nt;
+    int waves;
+    bool two_step;
+};
 
-// ctl->step += n
-hipError_t launch_bump(DevCtl *ctl, int n, hipStream_t s);
+// Fused step(s): both Lax-Wendroff stages in one pass over theta-marching
+// column strips.  d_work[w] = work item of wave w; kFusedWavesPerBlock waves
+// of 64 lanes per block.  One step: the strips are `cols` output columns
+// wide (at most kFusedCols) and may be split in rows; two steps: strips of
+// kFused2Cols columns over all rows.  Buffers as for the two-pass step.
+// Returns hipErrorInvalidValue for a shape that is not compiled.
+hipError_t launch_fused(bool fp64, const DevInst *d_inst, const WorkItem *d_work, int n_work, int cols,
+                        const DevCtl *ctl, int kstep, int kflip, const FusedShape &f, hipStream_t s);
 
-// Output columns per fused work item (64 lanes minus the two halo lanes).
+// ctl->step += n; ctl->cur flips `flips` times
+hipError_t launch_bump(DevCtl *ctl, int n, int flips, hipStream_t s);
+
+// Output columns per fused work item: 64 lanes minus one halo lane per side
+// and time step.
 constexpr int kFusedCols = 62;
+constexpr int kFused2Cols = 60;
 constexpr int kFusedWavesPerBlock = 4;
 
 }  // namespace tk

@@ -52,12 +52,13 @@ __device__ __forceinline__ P4 stage2_at(const DevInst &I, const double4 *u, cons
 }
 
 __global__ void __launch_bounds__(256) k_two_pass_half(const DevInst *__restrict__ insts, const int2 *__restrict__ blocks,
-                                                       const DevCtl *__restrict__ ctl, int kstep)
+                                                       const DevCtl *__restrict__ ctl, int kstep, int kflip)
 {
     const int2 bl = blocks[blockIdx.x];
     const DevInst &I = insts[bl.x];
     const long long n = ctl->step + kstep;
-    const double4 *u = (const double4 *)I.u[n & 1];
+    const int b = (int)((ctl->cur + kflip) & 1);
+    const double4 *u = (const double4 *)I.u[b];
     double4 *hf = (double4 *)I.half;
     const int L = bl.y * 256 + (int)threadIdx.x;
     const int j = L / I.n_r, i = L - j * I.n_r;
@@ -77,13 +78,14 @@ __global__ void __launch_bounds__(256) k_two_pass_half(const DevInst *__restrict
 }
 
 __global__ void __launch_bounds__(256) k_two_pass_full(const DevInst *__restrict__ insts, const int2 *__restrict__ blocks,
-                                                       const DevCtl *__restrict__ ctl, int kstep)
+                                                       const DevCtl *__restrict__ ctl, int kstep, int kflip)
 {
     const int2 bl = blocks[blockIdx.x];
     const DevInst &I = insts[bl.x];
     const long long n = ctl->step + kstep;
-    const double4 *u = (const double4 *)I.u[n & 1];
-    double4 *un = (double4 *)I.u[(n + 1) & 1];
+    const int b = (int)((ctl->cur + kflip) & 1);
+    const double4 *u = (const double4 *)I.u[b];
+    double4 *un = (double4 *)I.u[b ^ 1];
     const double4 *hf = (const double4 *)I.half;
     const int L = bl.y * 256 + (int)threadIdx.x;
     const int j = L / I.n_r, i = L - j * I.n_r;
@@ -110,9 +112,12 @@ __global__ void __launch_bounds__(256) k_two_pass_full(const DevInst *__restrict
     }
 }
 
-__global__ void k_bump(DevCtl *ctl, int n)
+__global__ void k_bump(DevCtl *ctl, int n, int flips)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) ctl->step += n;
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        ctl->step += n;
+        ctl->cur = (ctl->cur + flips) & 1;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -120,19 +125,19 @@ __global__ void k_bump(DevCtl *ctl, int n)
 // ---------------------------------------------------------------------------
 
 hipError_t launch_two_pass(const DevInst *d_inst, const int2 *d_blocks, int n_blocks, const DevCtl *ctl, int kstep,
-                           hipStream_t s)
+                           int kflip, hipStream_t s)
 {
     if (n_blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_two_pass_half, dim3(n_blocks), dim3(256), 0, s, d_inst, d_blocks, ctl, kstep);
+    hipLaunchKernelGGL(k_two_pass_half, dim3(n_blocks), dim3(256), 0, s, d_inst, d_blocks, ctl, kstep, kflip);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_two_pass_full, dim3(n_blocks), dim3(256), 0, s, d_inst, d_blocks, ctl, kstep);
+    hipLaunchKernelGGL(k_two_pass_full, dim3(n_blocks), dim3(256), 0, s, d_inst, d_blocks, ctl, kstep, kflip);
     return hipGetLastError();
 }
 
-hipError_t launch_bump(DevCtl *ctl, int n, hipStream_t s)
+hipError_t launch_bump(DevCtl *ctl, int n, int flips, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_bump, dim3(1), dim3(64), 0, s, ctl, n);
+    hipLaunchKernelGGL(k_bump, dim3(1), dim3(64), 0, s, ctl, n, flips);
     return hipGetLastError();
 }
 
@@ -217,6 +222,31 @@ __device__ __forceinline__ cd uniform(cd v) { return mk(uniform(v.re), uniform(v
 
 __device__ __forceinline__ float bf16_to_float(unsigned short b) { return __uint_as_float((unsigned)b << 16); }
 __device__ __forceinline__ unsigned short float_to_bf16(float x) { return __builtin_bit_cast(unsigned short, (__bf16)x); }
+// x rounded to the nearest bf16 value (the stored precision of the Kahan term)
+__device__ __forceinline__ float bf16_round(float x) { return bf16_to_float(float_to_bf16(x)); }
+
+// What one time level of a launch needs besides the lane: the source time
+// factors at the start of the step and half a step later, and whether (and
+// where in the ring) the step's result is sampled for the waveform.
+struct Level {
+    cd eh, ef;  // exp(-i m (Omega t + phase0)) at t^n and t^n + dt/2
+    bool ext;   // u^{n+1} is a waveform sample
+    long long wslot;
+};
+
+__device__ __forceinline__ Level make_level(const DevInst &I, long long n)
+{
+    Level v;
+    if (I.src_kind == TK_SRC_CIRCULAR_GAUSSIAN) {
+        v.eh = uniform(source_phase(I, (double)n * I.dt));
+        v.ef = uniform(source_phase(I, (double)n * I.dt + 0.5 * I.dt));
+    } else {
+        v.eh = v.ef = mk(0, 0);
+    }
+    v.ext = I.extract_every > 0 && (n + 1) % I.extract_every == 0;
+    v.wslot = v.ext ? ((n + 1) / I.extract_every - 1) % I.wave_cap : 0;
+    return v;
+}
 
 template <class P>
 struct Lane {
@@ -226,13 +256,11 @@ struct Lane {
     void *un, *unc;      // u^{n+1}
     T *rad;              // this lane's radial factors in LDS: [2][kRadVals] with stride 64
     int c, p, nt;
-    bool cin, hv, icol, ov;
+    bool cin, hv, icol;
+    bool ov;              // this lane's column is one the work item writes
     bool near_h, near_n;  // half node / node lies on the source window
     double gh, gn;        // tabulated A g_r there
-    cd e1, e2;            // source time factors at t^n and t^n + dt/2
     T a2, kct, dt, inv_h, inv_dth2, inv_2dth;
-    bool ext;             // this step writes a waveform sample
-    long long wslot;
 };
 
 template <class P>
@@ -276,8 +304,20 @@ __device__ __forceinline__ double value_of(const St<typename P::T> &v, int k)
     return P::kComp ? (double)f[k] + (double)c[k] : (double)f[k];
 }
 
+// Waveform sample of an output row (column i_obs) when the level extracts.
 template <class P>
-__device__ __forceinline__ void emit(const Lane<P> &L, int row, const St<typename P::T> &v)
+__device__ __forceinline__ void sample(const Lane<P> &L, const Level &lv, int row, const St<typename P::T> &v)
+{
+    if (lv.ext && L.ov && L.c == L.I->i_obs) {
+        TK_GLOBAL double *w = gstore_ptr(L.I->wave) + ((size_t)lv.wslot * L.nt + row) * 2;
+        w[0] = value_of<P>(v, 0);
+        w[1] = value_of<P>(v, 1);
+    }
+}
+
+// Store an output row of u^{n+1} (and sample it).
+template <class P>
+__device__ __forceinline__ void emit(const Lane<P> &L, const Level &lv, int row, const St<typename P::T> &v)
 {
     const size_t o = (size_t)row * L.p + L.c;
     if (L.ov) {
@@ -300,29 +340,38 @@ __device__ __forceinline__ void emit(const Lane<P> &L, int row, const St<typenam
             }
         }
     }
-    if (L.ext && L.ov && L.c == L.I->i_obs) {
-        TK_GLOBAL double *w = gstore_ptr(L.I->wave) + ((size_t)L.wslot * L.nt + row) * 2;
-        w[0] = value_of<P>(v, 0);
-        w[1] = value_of<P>(v, 1);
-    }
+    sample(L, lv, row, v);
 }
 
-// Pole value of a stored row pair, (4 X1 - X2) / 3 (double in the
-// compensated form, then split back into f + c).
+// Pole rows (Section 2.2): (4 X1 - X2) / 3 from the two rows next to the
+// pole for even |m|, zero for odd |m|.  The parity is selected per component
+// (a select between whole structs would keep them in memory).
+template <typename T>
+__device__ __forceinline__ Q4<T> pole_half(bool even, const Q4<T> &x1, const Q4<T> &x2)
+{
+    const Q4<T> v = pole_bc(x1, x2);
+    const T z = T(0);
+    return Q4<T>{mkc(even ? v.phi.re : z, even ? v.phi.im : z), mkc(even ? v.pi.re : z, even ? v.pi.im : z)};
+}
+
+// The same on a stored row pair (in double in the compensated form, then
+// split back into f + c).
 template <class P>
-__device__ __forceinline__ St<typename P::T> pole_row(const St<typename P::T> &x1, const St<typename P::T> &x2)
+__device__ __forceinline__ St<typename P::T> pole_row(bool even, const St<typename P::T> &x1,
+                                                      const St<typename P::T> &x2)
 {
     using T = typename P::T;
     St<T> o;
     if constexpr (!P::kComp) {
-        o.f = pole_bc(x1.f, x2.f);
+        o.f = pole_half(even, x1.f, x2.f);
         o.c = zero_q4<T>();
     } else {
         T *of = &o.f.phi.re, *oc = &o.c.phi.re;
         for (int k = 0; k < 4; ++k) {
             const double v = pole_x(value_of<P>(x1, k), value_of<P>(x2, k));
-            of[k] = (T)v;
-            oc[k] = (T)(v - (double)of[k]);
+            const T f = (T)v;
+            of[k] = even ? f : T(0);
+            oc[k] = even ? bf16_round((T)(v - (double)f)) : T(0);
         }
     }
     return o;
@@ -331,7 +380,7 @@ __device__ __forceinline__ St<typename P::T> pole_row(const St<typename P::T> &x
 // Eq. (3) at half row r: u^n rows r-1 (UM), r (U0), r+1 (UP) of this column;
 // the column to the right comes by lane shuffles.
 template <class P>
-__device__ __forceinline__ Q4<typename P::T> half_row(const Lane<P> &L, const Q4<typename P::T> &UM,
+__device__ __forceinline__ Q4<typename P::T> half_row(const Lane<P> &L, const Level &lv, const Q4<typename P::T> &UM,
                                                       const Q4<typename P::T> &U0, const Q4<typename P::T> &UP, int r)
 {
     using T = typename P::T;
@@ -344,14 +393,14 @@ __device__ __forceinline__ Q4<typename P::T> half_row(const Lane<P> &L, const Q4
     const Coef<T> cf = coef_lean(rad_of(L, 0), ang_of<P>(A), L.a2, L.kct);
     const T fac = T(0.5) * L.dt;
     if constexpr (!P::kComp) {
-        const cd F = L.near_h ? source_value(L.gh, A.srcg, L.e1) : mk(0, 0);
+        const cd F = L.near_h ? source_value(L.gh, A.srcg, lv.eh) : mk(0, 0);
         return lw_point(cf, bar, avg(nm, UM.phi), bar.phi, avg(np, UP.phi), bar.pi, n0 - U0, fac, L.inv_h,
                         L.inv_dth2, L.inv_2dth, F);
     } else {
         Q4<T> h = lw_point(cf, bar, avg(nm, UM.phi), bar.phi, avg(np, UP.phi), bar.pi, n0 - U0, fac, L.inv_h,
                            L.inv_dth2, L.inv_2dth, mkc(T(0), T(0)));
         if (L.near_h && A.srcg != 0.0) {  // FP64 source increment (dt/2) F
-            const cd F = source_value(L.gh, A.srcg, L.e1);
+            const cd F = source_value(L.gh, A.srcg, lv.eh);
             const double f64 = 0.5 * I.dt;
             h.pi = mkc((T)((double)h.pi.re + f64 * F.re), (T)((double)h.pi.im + f64 * F.im));
         }
@@ -370,7 +419,7 @@ __device__ __forceinline__ void two_sum(float a, float b, float &s, float &e)
 // Eq. (4) at output row o: u^n row o (Uo), half rows o-1 (HM), o (H0), o+1
 // (HP) of this column (at c+1/2); the column at c-1/2 comes by lane shuffles.
 template <class P>
-__device__ __forceinline__ St<typename P::T> out_row(const Lane<P> &L, const St<typename P::T> &Uo,
+__device__ __forceinline__ St<typename P::T> out_row(const Lane<P> &L, const Level &lv, const St<typename P::T> &Uo,
                                                      const Q4<typename P::T> &HM, const Q4<typename P::T> &H0,
                                                      const Q4<typename P::T> &HP, int o)
 {
@@ -386,7 +435,7 @@ __device__ __forceinline__ St<typename P::T> out_row(const Lane<P> &L, const St<
     const Angular A = load_entry(cload_ptr(I.ang) + (o));
     const Coef<T> cf = coef_lean(rad_of(L, 1), ang_of<P>(A), L.a2, L.kct);
     if constexpr (!P::kComp) {
-        const cd F = L.near_n ? source_value(L.gn, A.srcg, L.e2) : mk(0, 0);
+        const cd F = L.near_n ? source_value(L.gn, A.srcg, lv.ef) : mk(0, 0);
         res.f = lw_point(cf, Uo.f, avg(HM.phi, lm), til.phi, avg(HP.phi, lp), til.pi, H0 - l0, L.dt, L.inv_h,
                          L.inv_dth2, L.inv_2dth, F);
     } else {
@@ -396,7 +445,7 @@ __device__ __forceinline__ St<typename P::T> out_row(const Lane<P> &L, const St<
         T *rf = &res.f.phi.re, *rc = &res.c.phi.re;
         if (L.near_n && A.srcg != 0.0) {
             // FP64 accumulation where the source injects: u + c - dt [.] + dt F
-            const cd F = source_value(L.gn, A.srcg, L.e2);
+            const cd F = source_value(L.gn, A.srcg, lv.ef);
             const double add[4] = {0.0, 0.0, I.dt * F.re, I.dt * F.im};
             for (int k = 0; k < 4; ++k) {
                 const double v = ((double)fp[k] + (double)cp[k]) + (double)(-L.dt * bp[k]) + add[k];
@@ -406,6 +455,9 @@ __device__ __forceinline__ St<typename P::T> out_row(const Lane<P> &L, const St<
         } else {
             for (int k = 0; k < 4; ++k) two_sum(fp[k], -L.dt * bp[k] + cp[k], rf[k], rc[k]);
         }
+        // the Kahan term is kept at its stored precision from here on, so
+        // that a value used on chip equals the value a later step reloads
+        for (int k = 0; k < 4; ++k) rc[k] = bf16_round(rc[k]);
     }
     return res;
 }
@@ -413,24 +465,27 @@ __device__ __forceinline__ St<typename P::T> out_row(const Lane<P> &L, const St<
 template <class P>
 struct Roll {
     using T = typename P::T;
-    St<T> U[3];    // u^n(c, row), slot = row mod 3 (rows r-1, r, r+1 at march row r)
-    Q4<T> H[3];    // u^{n+1/2}(c+1/2, row), slot = row mod 3 (rows r-2, r-1, r)
-    St<T> pre[3];  // prefetched u^n rows (slot = row mod 3, or slot 0 only at depth 1)
+    St<T> U[3];    // u^n(c, row), slot = (row - r_lo) mod 3 (rows r-1, r, r+1 at march row r)
+    Q4<T> H[3];    // u^{n+1/2}(c+1/2, row), same slots (rows r-2, r-1, r)
+    St<T> pre[3];  // prefetched u^n rows (same slots, or slot 0 only at depth 1)
     St<T> keep;    // an output row kept for the pole condition
 };
 
-// One march iteration at half row r (slot SR = (r - r_lo) mod 3).  With
-// POLES false the pole and epilogue bookkeeping is compiled out (the
-// steady-state rows in the middle of a chunk).
-template <class P, int SR, bool POLES>
-__device__ __forceinline__ void march(const Lane<P> &L, Roll<P> &R, int r, int out_lo, int out_hi, int u_last,
-                                      bool north)
+template <class P>
+__device__ __forceinline__ St<typename P::T> zero_st()
 {
-    using T = typename P::T;
-    constexpr int SM = (SR + 2) % 3;  // row r-1
-    constexpr int SP = (SR + 1) % 3;  // row r+1 (U) / row r-2 (H)
-    const int nt = L.nt;
-    const bool even = L.I->m_even;
+    St<typename P::T> z;
+    z.f = zero_q4<typename P::T>();
+    z.c = zero_q4<typename P::T>();
+    return z;
+}
+
+// u^n row r+1 moves from the prefetch ring into the rolling rows, and the
+// ring slot is refilled (march row r, slot SR; u_last = last row to read).
+template <class P, int SR, class RR>
+__device__ __forceinline__ void advance_rows(const Lane<P> &L, RR &R, int r, int u_last)
+{
+    constexpr int SP = (SR + 1) % 3;
     if constexpr (P::kPD == 3) {
         R.U[SP] = R.pre[SP];  // row r+1; refill its slot with row r+4
         if (r + 4 <= u_last) R.pre[SP] = load_row(L, r + 4);
@@ -438,20 +493,46 @@ __device__ __forceinline__ void march(const Lane<P> &L, Roll<P> &R, int r, int o
         R.U[SP] = R.pre[0];
         if (r + 2 <= u_last) R.pre[0] = load_row(L, r + 2);
     }
-    R.H[SR] = half_row(L, R.U[SM].f, R.U[SR].f, R.U[SP].f, r);
-    if (POLES && north && r == 2) R.H[SP] = even ? pole_bc(R.H[SM], R.H[SR]) : zero_q4<T>();  // half row 0
+}
+
+// Rows r_lo-1, r_lo into the rolling slots 2 and 0, the next ones into the
+// prefetch ring.
+template <class P, class RR>
+__device__ __forceinline__ void prologue_rows(const Lane<P> &L, RR &R, int r_lo, int u_last)
+{
+    R.U[2] = load_row(L, r_lo - 1);
+    R.U[0] = load_row(L, r_lo);
+    if constexpr (P::kPD == 3) {
+        R.pre[1] = load_row(L, r_lo + 1);
+        if (r_lo + 2 <= u_last) R.pre[2] = load_row(L, r_lo + 2);
+        if (r_lo + 3 <= u_last) R.pre[0] = load_row(L, r_lo + 3);
+    } else {
+        R.pre[0] = load_row(L, r_lo + 1);
+    }
+}
+
+// One march iteration at half row r (slot SR = (r - r_lo) mod 3).  With
+// POLES false the pole and epilogue bookkeeping is compiled out (the
+// steady-state rows in the middle of a chunk).
+template <class P, int SR, bool POLES>
+__device__ __forceinline__ void march(const Lane<P> &L, const Level &lv, Roll<P> &R, int r, int out_lo, int out_hi,
+                                      int u_last, bool north)
+{
+    using T = typename P::T;
+    constexpr int SM = (SR + 2) % 3;  // row r-1
+    constexpr int SP = (SR + 1) % 3;  // row r+1 (U) / row r-2 (H)
+    const int nt = L.nt;
+    const bool even = L.I->m_even;
+    advance_rows<P, SR>(L, R, r, u_last);
+    R.H[SR] = half_row(L, lv, R.U[SM].f, R.U[SR].f, R.U[SP].f, r);
+    if (POLES && north && r == 2) R.H[SP] = pole_half(even, R.H[SM], R.H[SR]);  // half row 0
     const int o = r - 1;
     if (!POLES || (o >= out_lo && o <= out_hi)) {
-        const St<T> v = out_row(L, R.U[SM], R.H[SP], R.H[SM], R.H[SR], o);
-        emit(L, o, v);
+        const St<T> v = out_row(L, lv, R.U[SM], R.H[SP], R.H[SM], R.H[SR], o);
+        emit(L, lv, o, v);
         if (POLES) {
             if (north && o == 1) R.keep = v;
-            if (north && o == 2) {
-                St<T> z;
-                z.f = zero_q4<T>();
-                z.c = zero_q4<T>();
-                emit(L, 0, even ? pole_row<P>(R.keep, v) : z);
-            }
+            if (north && o == 2) emit(L, lv, 0, pole_row<P>(even, R.keep, v));
             if (o == nt - 3) R.keep = v;
         }
     }
@@ -459,88 +540,171 @@ __device__ __forceinline__ void march(const Lane<P> &L, Roll<P> &R, int r, int o
 
 // South pole after the last march iteration r = nt-2 (slot SR = (nt-2-r_lo) mod 3).
 template <class P, int SR>
-__device__ __forceinline__ void south(const Lane<P> &L, Roll<P> &R)
+__device__ __forceinline__ void south(const Lane<P> &L, const Level &lv, Roll<P> &R)
 {
     using T = typename P::T;
     constexpr int SM = (SR + 2) % 3;  // row nt-3
     constexpr int SP = (SR + 1) % 3;  // row nt-1 (free slot)
     const int nt = L.nt;
     const bool even = L.I->m_even;
-    R.H[SP] = even ? pole_bc(R.H[SR], R.H[SM]) : zero_q4<T>();  // half row nt-1
-    const St<T> v = out_row(L, R.U[SR], R.H[SM], R.H[SR], R.H[SP], nt - 2);
-    emit(L, nt - 2, v);
-    St<T> z;
-    z.f = zero_q4<T>();
-    z.c = zero_q4<T>();
-    emit(L, nt - 1, even ? pole_row<P>(v, R.keep) : z);
+    R.H[SP] = pole_half(even, R.H[SR], R.H[SM]);  // half row nt-1
+    const St<T> v = out_row(L, lv, R.U[SR], R.H[SM], R.H[SR], R.H[SP], nt - 2);
+    emit(L, lv, nt - 2, v);
+    emit(L, lv, nt - 1, pole_row<P>(even, v, R.keep));
 }
 
-}  // namespace
-
+// Two time levels in one pass.  Level 1 is the march above without stores;
+// level 2 runs two rows behind it on the u^{n+1} rows level 1 leaves in
+// registers and writes u^{n+2}.  Slots are (row - 1) mod 3 for every ring.
 template <class P>
-__global__ void __launch_bounds__(64 * kFusedWavesPerBlock) __attribute__((amdgpu_waves_per_eu(P::kWaves, 8)))
-    k_fused(const DevInst *__restrict__ insts, const WorkItem *__restrict__ work, int n_work,
-            const DevCtl *__restrict__ ctl, int kstep)
+struct Roll2 {
+    using T = typename P::T;
+    St<T> U[3], pre[3];  // u^n rows and the prefetch ring
+    Q4<T> H[3];          // u^{n+1/2} half rows
+    St<T> V[3];          // u^{n+1} rows (level-1 output)
+    Q4<T> G[3];          // u^{n+3/2} half rows
+    St<T> keep;          // a u^{n+2} row kept for a pole
+};
+
+// Iteration r (1 <= r <= nt+1, slot S = (r - 1) mod 3): level 1 takes u^n
+// row r+1 and forms half row r and u^{n+1} row r-1; level 2 forms half row
+// r-2 of the next step and u^{n+2} row r-3.  The pole rows of both levels
+// come from the rows next to them as in the one-step march.  With EDGE
+// false (rows 7 .. nt-2) the pole and end bookkeeping is compiled out.
+template <typename T>
+__device__ __forceinline__ Q4<T> pick(bool c, const Q4<T> &a, const Q4<T> &b)
+{
+    return Q4<T>{mkc(c ? a.phi.re : b.phi.re, c ? a.phi.im : b.phi.im), mkc(c ? a.pi.re : b.pi.re, c ? a.pi.im : b.pi.im)};
+}
+template <typename T>
+__device__ __forceinline__ St<T> pick(bool c, const St<T> &a, const St<T> &b)
+{
+    return St<T>{pick(c, a.f, b.f), pick(c, a.c, b.c)};
+}
+
+// Iteration r (1 <= r <= nt+1, slot S = (r - 1) mod 3): level 1 takes u^n
+// row r+1 and forms half row r and u^{n+1} row r-1; level 2 forms half row
+// r-2 of the next step and u^{n+2} row r-3.  The pole rows of both levels
+// come from the rows next to them as in the one-step march.  With EDGE
+// false (rows 7 .. nt-2) the pole and end bookkeeping is compiled out.
+// Each ring slot is written from one place only, the rows that feed a pole
+// being picked by value: two pole updates of different slots under
+// different conditions would otherwise be merged by the compiler into one
+// store through a selected address, which keeps the rings in memory.
+template <class P, int S, bool EDGE>
+__device__ __forceinline__ void march2(const Lane<P> &L, const Level &l1, const Level &l2, Roll2<P> &R, int r)
+{
+    constexpr int SM = (S + 2) % 3;  // rows r-1 and r-4
+    constexpr int SP = (S + 1) % 3;  // rows r+1 and r-2
+    const int nt = L.nt;
+    const bool even = L.I->m_even;
+    // level 1: half rows r-2 (SP), r-1 (SM), r (S); u^n rows r-1 (SM), r (S), r+1 (SP)
+    if (!EDGE || r <= nt - 2) {
+        advance_rows<P, S>(L, R, r, nt - 1);
+        R.H[S] = half_row(L, l1, R.U[SM].f, R.U[S].f, R.U[SP].f, r);
+    } else {  // r = nt-1: half row nt-1 from nt-2 (SM), nt-3 (SP); unused after that
+        R.H[S] = pole_half(even, R.H[SM], R.H[SP]);
+    }
+    if (EDGE && r == 2) R.H[SP] = pole_half(even, R.H[SM], R.H[S]);  // half row 0 from 1 (SM), 2 (S)
+    if (!EDGE || (r >= 2 && r <= nt - 1)) {  // u^{n+1} row r-1 -> V slot SM
+        R.V[SM] = out_row(L, l1, R.U[SM], R.H[SP], R.H[SM], R.H[S], r - 1);
+        sample(L, l1, r - 1, R.V[SM]);
+    }
+    if (EDGE && r == 3) {  // u^{n+1} row 0 (slot S) from rows 1 (SP) and 2 (SM)
+        R.V[S] = pole_row<P>(even, R.V[SP], R.V[SM]);
+        sample(L, l1, 0, R.V[S]);
+    }
+    // level 2: u^{n+1} rows r-3 (S), r-2 (SP), r-1 (SM); its half rows r-4 (SM), r-3 (S), r-2 (SP)
+    if (!EDGE || r >= 3) {
+        if (!EDGE || r <= nt)
+            R.G[SP] = half_row(L, l2, R.V[S].f, R.V[SP].f, R.V[SM].f, r - 2);
+        else  // r = nt+1: half row nt-1 from nt-2 (S), nt-3 (SM)
+            R.G[SP] = pole_half(even, R.G[S], R.G[SM]);
+    }
+    if (EDGE && r == 4) R.G[SM] = pole_half(even, R.G[S], R.G[SP]);  // half row 0 from 1 (S), 2 (SP)
+    if (!EDGE || (r >= 4 && r <= nt + 1)) {  // u^{n+2} row o = r-3
+        const int o = r - 3;
+        const St<typename P::T> v = out_row(L, l2, R.V[S], R.G[SM], R.G[S], R.G[SP], o);
+        emit(L, l2, o, v);
+        if (EDGE) {
+            const bool pn = o == 2, ps = o == nt - 2;  // row 0 from rows 1, 2; row nt-1 from nt-2, nt-3
+            if (pn || ps) emit(L, l2, pn ? 0 : nt - 1, pole_row<P>(even, pick(pn, R.keep, v), pick(pn, v, R.keep)));
+            if (o == 1 || o == nt - 3) R.keep = v;
+        }
+    }
+    if (EDGE && r == nt - 1) {  // u^{n+1} row nt-1 from nt-2 (SM), nt-3 (SP), into the slot level 2 is done with
+        R.V[S] = pole_row<P>(even, R.V[SM], R.V[SP]);
+        sample(L, l1, nt - 1, R.V[S]);
+    }
+}
+
+// Lane set-up shared by the fused kernels: lane `lane` holds r* column
+// i0 - halo + lane and the work item writes lanes halo .. halo+cols-1; the
+// lane's radial factors (half node, node) go to its LDS slots.
+template <class P>
+__device__ __forceinline__ void init_lane(Lane<P> &L, const DevInst &I, const WorkItem &it, int lane, int halo,
+                                          int cols, int buf, typename P::T *rad)
 {
     using T = typename P::T;
-    __shared__ T s_rad[kFusedWavesPerBlock][2 * kRadVals * 64];
-    const int lane = (int)(threadIdx.x & 63);
-    // wave index within the block: uniform per wave, said so explicitly so that
-    // the work item, the instance descriptor and the angular tables are read
-    // with scalar loads into scalar registers
-    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int w = (int)blockIdx.x * kFusedWavesPerBlock + wv;
-    if (w >= n_work) return;  // whole wave leaves together; no block barriers below
-    const WorkItem it = work[w];
-    const DevInst &I = insts[it.inst];
-    Lane<P> L;
     L.I = &I;
-    const long long n = ctl->step + kstep;
-    L.u = I.u[n & 1];
-    L.uc = I.c[n & 1];
-    L.un = I.u[(n + 1) & 1];
-    L.unc = I.c[(n + 1) & 1];
+    L.u = I.u[buf];
+    L.uc = I.c[buf];
+    L.un = I.u[buf ^ 1];
+    L.unc = I.c[buf ^ 1];
     L.p = I.pitch;
     L.nt = I.n_theta;
-    const int nr = I.n_r, nt = I.n_theta;
-    L.c = it.i0 - 1 + lane;
+    const int nr = I.n_r;
+    L.c = it.i0 - halo + lane;
     L.cin = L.c >= 0 && L.c < nr;
     L.hv = L.c >= 0 && L.c <= nr - 2;
     L.icol = L.c >= 1 && L.c <= nr - 2;
-    L.ov = lane >= 1 && lane <= kFusedCols && L.c < nr;
+    L.ov = lane >= halo && lane < halo + cols && L.c < nr;
     L.a2 = (T)I.a2;
     L.kct = (T)I.kct;
     L.dt = (T)I.dt;
     L.inv_h = (T)I.inv_h;
     L.inv_dth2 = (T)I.inv_dth2;
     L.inv_2dth = (T)I.inv_2dth;
-    if (I.src_kind == TK_SRC_CIRCULAR_GAUSSIAN) {
-        L.e1 = uniform(source_phase(I, (double)n * I.dt));
-        L.e2 = uniform(source_phase(I, (double)n * I.dt + 0.5 * I.dt));
-    } else {
-        L.e1 = L.e2 = mk(0, 0);
-    }
-    L.ext = I.extract_every > 0 && (n + 1) % I.extract_every == 0;
-    L.wslot = L.ext ? ((n + 1) / I.extract_every - 1) % I.wave_cap : 0;
-
-    // radial factors of the half node (slot 0) and the node (slot 1) -> LDS
-    L.rad = &s_rad[wv][lane];
-    {
-        const Radial Rh = load_entry(gload_ptr(I.rad) + (L.hv ? 2 * L.c + 1 : 0));
-        const Radial Rn = load_entry(gload_ptr(I.rad) + (L.icol ? 2 * L.c : 0));
-        const double vh[kRadVals] = {Rh.rho, Rh.Dl, Rh.ct_re, Rh.ct_im0, Rh.K, Rh.c1_re, Rh.c1_im, Rh.c0_re, Rh.c0_im};
-        const double vn[kRadVals] = {Rn.rho, Rn.Dl, Rn.ct_re, Rn.ct_im0, Rn.K, Rn.c1_re, Rn.c1_im, Rn.c0_re, Rn.c0_im};
+    L.rad = rad;
+    const Radial Rh = load_entry(gload_ptr(I.rad) + (L.hv ? 2 * L.c + 1 : 0));
+    const Radial Rn = load_entry(gload_ptr(I.rad) + (L.icol ? 2 * L.c : 0));
+    const double vh[kRadVals] = {Rh.rho, Rh.Dl, Rh.ct_re, Rh.ct_im0, Rh.K, Rh.c1_re, Rh.c1_im, Rh.c0_re, Rh.c0_im};
+    const double vn[kRadVals] = {Rn.rho, Rn.Dl, Rn.ct_re, Rn.ct_im0, Rn.K, Rn.c1_re, Rn.c1_im, Rn.c0_re, Rn.c0_im};
 #pragma unroll
-        for (int k = 0; k < kRadVals; ++k) {
-            L.rad[k * 64] = (T)vh[k];
-            L.rad[(kRadVals + k) * 64] = (T)vn[k];
-        }
-        L.gh = L.hv ? Rh.srcg : 0.0;
-        L.gn = L.icol ? Rn.srcg : 0.0;
-        L.near_h = L.gh != 0.0;
-        L.near_n = L.gn != 0.0;
+    for (int k = 0; k < kRadVals; ++k) {
+        L.rad[k * 64] = (T)vh[k];
+        L.rad[(kRadVals + k) * 64] = (T)vn[k];
     }
+    L.gh = L.hv ? Rh.srcg : 0.0;
+    L.gn = L.icol ? Rn.srcg : 0.0;
+    L.near_h = L.gh != 0.0;
+    L.near_n = L.gn != 0.0;
+}
 
+}  // namespace
+
+// One step.  The wave index within the block is made uniform explicitly so
+// that the work item, the instance descriptor and the angular tables are
+// read with scalar loads into scalar registers.
+template <class P>
+__global__ void __launch_bounds__(64 * kFusedWavesPerBlock) __attribute__((amdgpu_waves_per_eu(P::kWaves, 8)))
+    k_fused(const DevInst *__restrict__ insts, const WorkItem *__restrict__ work, int n_work, int cols,
+            const DevCtl *__restrict__ ctl, int kstep, int kflip)
+{
+    using T = typename P::T;
+    __shared__ T s_rad[kFusedWavesPerBlock][2 * kRadVals * 64];
+    const int lane = (int)(threadIdx.x & 63);
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int w = (int)blockIdx.x * kFusedWavesPerBlock + wv;
+    if (w >= n_work) return;  // whole wave leaves together; no block barriers below
+    const WorkItem it = work[w];
+    const DevInst &I = insts[it.inst];
+    const long long n = ctl->step + kstep;
+    Lane<P> L;
+    init_lane(L, I, it, lane, 1, cols, (int)((ctl->cur + kflip) & 1), &s_rad[wv][lane]);
+    const Level lv = make_level(I, n);
+
+    const int nt = I.n_theta;
     const int j0 = it.j0, j1 = it.j1;
     const bool north = j0 == 0, southp = j1 == nt;
     const int r_lo = max(1, j0 - 1), r_hi = min(nt - 2, j1);
@@ -549,63 +713,101 @@ __global__ void __launch_bounds__(64 * kFusedWavesPerBlock) __attribute__((amdgp
     const int u_last = r_hi + 1;
 
     Roll<P> R;
-    {  // prologue: u^n rows r_lo-1 (slot 2) and r_lo (slot 0), then the prefetch
-        R.U[2] = load_row(L, r_lo - 1);
-        R.U[0] = load_row(L, r_lo);
-        if constexpr (P::kPD == 3) {
-            R.pre[1] = load_row(L, r_lo + 1);
-            if (r_lo + 2 <= u_last) R.pre[2] = load_row(L, r_lo + 2);
-            if (r_lo + 3 <= u_last) R.pre[0] = load_row(L, r_lo + 3);
-        } else {
-            R.pre[0] = load_row(L, r_lo + 1);
-        }
-    }
-    R.keep.f = zero_q4<T>();
-    R.keep.c = zero_q4<T>();
+    prologue_rows(L, R, r_lo, u_last);
+    R.keep = zero_st<P>();
     // head: the first three rows, with the north-pole bookkeeping
     int r = r_lo;
-    march<P, 0, true>(L, R, r, out_lo, out_hi, u_last, north);
-    if (r + 1 <= r_hi) march<P, 1, true>(L, R, r + 1, out_lo, out_hi, u_last, north);
-    if (r + 2 <= r_hi) march<P, 2, true>(L, R, r + 2, out_lo, out_hi, u_last, north);
+    march<P, 0, true>(L, lv, R, r, out_lo, out_hi, u_last, north);
+    if (r + 1 <= r_hi) march<P, 1, true>(L, lv, R, r + 1, out_lo, out_hi, u_last, north);
+    if (r + 2 <= r_hi) march<P, 2, true>(L, lv, R, r + 2, out_lo, out_hi, u_last, north);
     r += 3;
     // steady state: whole triples strictly before the last row (its output
     // row o = r_hi - 1 may be the one the south pole needs)
     for (; r + 2 < r_hi; r += 3) {
-        march<P, 0, false>(L, R, r, out_lo, out_hi, u_last, north);
-        march<P, 1, false>(L, R, r + 1, out_lo, out_hi, u_last, north);
-        march<P, 2, false>(L, R, r + 2, out_lo, out_hi, u_last, north);
+        march<P, 0, false>(L, lv, R, r, out_lo, out_hi, u_last, north);
+        march<P, 1, false>(L, lv, R, r + 1, out_lo, out_hi, u_last, north);
+        march<P, 2, false>(L, lv, R, r + 2, out_lo, out_hi, u_last, north);
     }
     // tail
-    if (r <= r_hi) march<P, 0, true>(L, R, r, out_lo, out_hi, u_last, north);
-    if (r + 1 <= r_hi) march<P, 1, true>(L, R, r + 1, out_lo, out_hi, u_last, north);
-    if (r + 2 <= r_hi) march<P, 2, true>(L, R, r + 2, out_lo, out_hi, u_last, north);
+    if (r <= r_hi) march<P, 0, true>(L, lv, R, r, out_lo, out_hi, u_last, north);
+    if (r + 1 <= r_hi) march<P, 1, true>(L, lv, R, r + 1, out_lo, out_hi, u_last, north);
+    if (r + 2 <= r_hi) march<P, 2, true>(L, lv, R, r + 2, out_lo, out_hi, u_last, north);
     if (southp) {
         switch ((nt - 2 - r_lo) % 3) {
-        case 0: south<P, 0>(L, R); break;
-        case 1: south<P, 1>(L, R); break;
-        default: south<P, 2>(L, R); break;
+        case 0: south<P, 0>(L, lv, R); break;
+        case 1: south<P, 1>(L, lv, R); break;
+        default: south<P, 2>(L, lv, R); break;
         }
     }
 }
 
+// Two steps (n -> n+2) in one pass over whole column strips: u^n is read
+// and u^{n+2} written once; u^{n+1} exists only in registers (and in the
+// waveform ring when sampled).
 template <class P>
-hipError_t launch_fused_as(const DevInst *d_inst, const WorkItem *d_work, int n_work, const DevCtl *ctl, int kstep,
-                           hipStream_t s)
+__global__ void __launch_bounds__(64 * kFusedWavesPerBlock) __attribute__((amdgpu_waves_per_eu(P::kWaves, 8)))
+    k_fused2(const DevInst *__restrict__ insts, const WorkItem *__restrict__ work, int n_work,
+             const DevCtl *__restrict__ ctl, int kstep, int kflip)
+{
+    using T = typename P::T;
+    __shared__ T s_rad[kFusedWavesPerBlock][2 * kRadVals * 64];
+    const int lane = (int)(threadIdx.x & 63);
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int w = (int)blockIdx.x * kFusedWavesPerBlock + wv;
+    if (w >= n_work) return;  // whole wave leaves together; no block barriers below
+    const WorkItem it = work[w];
+    const DevInst &I = insts[it.inst];
+    const long long n = ctl->step + kstep;
+    Lane<P> L;
+    init_lane(L, I, it, lane, 2, kFused2Cols, (int)((ctl->cur + kflip) & 1), &s_rad[wv][lane]);
+    const Level l1 = make_level(I, n), l2 = make_level(I, n + 1);
+    const int nt = I.n_theta;  // >= 5: the six head iterations all exist
+
+    Roll2<P> R;
+    prologue_rows(L, R, 1, nt - 1);
+    R.keep = zero_st<P>();
+    march2<P, 0, true>(L, l1, l2, R, 1);
+    march2<P, 1, true>(L, l1, l2, R, 2);
+    march2<P, 2, true>(L, l1, l2, R, 3);
+    march2<P, 0, true>(L, l1, l2, R, 4);
+    march2<P, 1, true>(L, l1, l2, R, 5);
+    march2<P, 2, true>(L, l1, l2, R, 6);
+    int r = 7;
+    for (; r + 2 <= nt - 2; r += 3) {
+        march2<P, 0, false>(L, l1, l2, R, r);
+        march2<P, 1, false>(L, l1, l2, R, r + 1);
+        march2<P, 2, false>(L, l1, l2, R, r + 2);
+    }
+    // tail: iterations r .. nt+1 (at most five)
+    if (r <= nt + 1) march2<P, 0, true>(L, l1, l2, R, r);
+    if (r + 1 <= nt + 1) march2<P, 1, true>(L, l1, l2, R, r + 1);
+    if (r + 2 <= nt + 1) march2<P, 2, true>(L, l1, l2, R, r + 2);
+    if (r + 3 <= nt + 1) march2<P, 0, true>(L, l1, l2, R, r + 3);
+    if (r + 4 <= nt + 1) march2<P, 1, true>(L, l1, l2, R, r + 4);
+}
+
+template <class P>
+hipError_t launch_as(const DevInst *d_inst, const WorkItem *d_work, int n_work, int cols, const DevCtl *ctl, int kstep,
+                     int kflip, bool two_step, hipStream_t s)
 {
     if (n_work <= 0) return hipSuccess;
     const int blocks = (n_work + kFusedWavesPerBlock - 1) / kFusedWavesPerBlock;
-    hipLaunchKernelGGL(k_fused<P>, dim3(blocks), dim3(64 * kFusedWavesPerBlock), 0, s, d_inst, d_work, n_work, ctl,
-                       kstep);
+    if (two_step)
+        hipLaunchKernelGGL(k_fused2<P>, dim3(blocks), dim3(64 * kFusedWavesPerBlock), 0, s, d_inst, d_work, n_work,
+                           ctl, kstep, kflip);
+    else
+        hipLaunchKernelGGL(k_fused<P>, dim3(blocks), dim3(64 * kFusedWavesPerBlock), 0, s, d_inst, d_work, n_work,
+                           cols, ctl, kstep, kflip);
     return hipGetLastError();
 }
 
 template <template <int, bool, int> class Pol>
-hipError_t launch_fused_variant(const DevInst *d_inst, const WorkItem *d_work, int n_work, const DevCtl *ctl, int kstep,
-                                int prefetch, bool nt, int waves, hipStream_t s)
+hipError_t launch_variant(const DevInst *d_inst, const WorkItem *d_work, int n_work, int cols, const DevCtl *ctl,
+                          int kstep, int kflip, const FusedShape &f, hipStream_t s)
 {
-#define TK_VARIANT(PD, NT, W)                                                                  \
-    if (prefetch == PD && nt == NT && waves == W)                                              \
-        return launch_fused_as<Pol<PD, NT, W>>(d_inst, d_work, n_work, ctl, kstep, s);
+#define TK_VARIANT(PD, NT, W)                                                                              \
+    if (f.prefetch == PD && f.nt == NT && f.waves == W)                                                    \
+        return launch_as<Pol<PD, NT, W>>(d_inst, d_work, n_work, cols, ctl, kstep, kflip, f.two_step, s);
     TK_VARIANT(3, true, 1)
     TK_VARIANT(3, true, 3)
     TK_VARIANT(3, true, 4)
@@ -616,16 +818,11 @@ hipError_t launch_fused_variant(const DevInst *d_inst, const WorkItem *d_work, i
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_fused_fp64(const DevInst *d_inst, const WorkItem *d_work, int n_work, const DevCtl *ctl, int kstep,
-                             int prefetch, bool nt, int waves, hipStream_t s)
+hipError_t launch_fused(bool fp64, const DevInst *d_inst, const WorkItem *d_work, int n_work, int cols,
+                        const DevCtl *ctl, int kstep, int kflip, const FusedShape &f, hipStream_t s)
 {
-    return launch_fused_variant<PolicyF64>(d_inst, d_work, n_work, ctl, kstep, prefetch, nt, waves, s);
-}
-
-hipError_t launch_fused_fp32c(const DevInst *d_inst, const WorkItem *d_work, int n_work, const DevCtl *ctl, int kstep,
-                              int prefetch, bool nt, int waves, hipStream_t s)
-{
-    return launch_fused_variant<PolicyF32C>(d_inst, d_work, n_work, ctl, kstep, prefetch, nt, waves, s);
+    if (fp64) return launch_variant<PolicyF64>(d_inst, d_work, n_work, cols, ctl, kstep, kflip, f, s);
+    return launch_variant<PolicyF32C>(d_inst, d_work, n_work, cols, ctl, kstep, kflip, f, s);
 }
 
 }  // namespace tk

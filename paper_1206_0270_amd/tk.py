@@ -17,7 +17,7 @@ TK_OK, TK_E_INVALID, TK_E_NOMEM, TK_E_DEVICE, TK_E_STATE, TK_E_UNSTABLE, TK_E_NO
 TK_FP64, TK_FP32_COMP = 0, 1
 TK_FLAG_FORCE_DT = 1
 TK_SRC_NONE, TK_SRC_CIRCULAR_GAUSSIAN = 0, 1
-TK_KERNEL_AUTO, TK_KERNEL_TWO_PASS, TK_KERNEL_FUSED = 0, 1, 2
+TK_KERNEL_AUTO, TK_KERNEL_TWO_PASS, TK_KERNEL_FUSED, TK_KERNEL_FUSED2 = 0, 1, 2, 3
 
 _STATUS = {0: "TK_OK", 1: "TK_E_INVALID", 2: "TK_E_NOMEM", 3: "TK_E_DEVICE", 4: "TK_E_STATE",
            5: "TK_E_UNSTABLE", 6: "TK_E_NONFINITE"}

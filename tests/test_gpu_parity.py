@@ -104,7 +104,7 @@ def small_instances():
     return out
 
 
-@pytest.mark.parametrize("kernel", [tk.TK_KERNEL_FUSED, tk.TK_KERNEL_TWO_PASS])
+@pytest.mark.parametrize("kernel", [tk.TK_KERNEL_FUSED2, tk.TK_KERNEL_FUSED, tk.TK_KERNEL_TWO_PASS])
 def test_small_grids_vs_oracle(kernel):
     insts = small_instances()
     steps = 150
@@ -184,12 +184,29 @@ def test_launch_variants_bitwise(precision):
             assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
 
 
-def test_graph_replay_equals_eager_bitwise():
+@pytest.mark.parametrize("kernel,G", [(tk.TK_KERNEL_FUSED2, 20), (tk.TK_KERNEL_FUSED2, 7), (tk.TK_KERNEL_FUSED, 20)])
+def test_graph_replay_equals_eager_bitwise(kernel, G):
+    # an odd block size ends each replay with a one-step launch and flips the
+    # state buffer an odd number of times per replay
     insts = small_instances()
-    eager = gpu_run(insts, 70, graph=0)
-    graph = gpu_run(insts, 70, graph=20, chunks=[25, 20, 5, 20])
+    eager = gpu_run(insts, 70, kernel=kernel, graph=0)
+    graph = gpu_run(insts, 70, kernel=kernel, graph=G, chunks=[25, 20, 5, 20])
     for (a, b) in zip(eager, graph):
         assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+
+
+@pytest.mark.parametrize("precision", [tk.TK_FP64, tk.TK_FP32_COMP])
+@pytest.mark.parametrize("steps", [40, 41])
+def test_two_step_kernel_equals_one_step_bitwise(precision, steps):
+    # two time levels per pass change where u^{n+1} lives (registers instead
+    # of HBM), never the arithmetic; waveform samples of the middle level
+    # included (extract_every = 3)
+    insts = small_instances()
+    one = gpu_run(insts, steps, kernel=tk.TK_KERNEL_FUSED, precision=precision)
+    for pf in (3, 1):
+        two = gpu_run(insts, steps, kernel=tk.TK_KERNEL_FUSED2, prefetch=pf, precision=precision)
+        for (a, b) in zip(one, two):
+            assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
 
 
 def test_checkpoint_resume_bitwise():
