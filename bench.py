@@ -116,7 +116,8 @@ def main():
                          "two_pass: half-step array through HBM")
     ap.add_argument("--prefetch", type=int, default=3, choices=[1, 3])
     ap.add_argument("--no-nt", action="store_true", help="plain (not non-temporal) stores")
-    ap.add_argument("--waves", type=int, default=0, choices=[0, 3, 4])
+    ap.add_argument("--waves", type=int, default=None, choices=[0, 3, 4],
+                    help="occupancy target of the fused kernels (default: the library's choice)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="instead of the stepper, run a plain device copy of this many GiB "
@@ -158,8 +159,9 @@ def main():
     two_step = args.kernel == "fused2"
     if two_step and (args.steps % 2 or args.warmup % 2 or args.graph_steps % 2):
         raise SystemExit("--kernel fused2 times whole two-step launches: use even --steps, --warmup, --graph-steps")
+    waves = st.get_tuning()["waves_per_simd"] if args.waves is None else args.waves
     st.set_tuning(kernel=kern, rows_per_tile=args.rows, graph_steps=args.graph_steps,
-                  prefetch_rows=args.prefetch, nt_stores=not args.no_nt, waves_per_simd=args.waves)
+                  prefetch_rows=args.prefetch, nt_stores=not args.no_nt, waves_per_simd=waves)
     for k, inst in enumerate(insts):
         st.set_fields(k, *W.initial_data(inst))
     print(f"# workload {args.workload}: {len(insts)} instances, {points} points, "
@@ -181,14 +183,17 @@ def main():
           file=sys.stderr, flush=True)
     elapsed = max(wall, gpu_ms / 1e3)
     value = points * args.steps / elapsed
-    # one launch reads the state once and writes it once, for one step (or
-    # two with the two-step kernel): algorithmic bytes per launch = bytes
-    # per point update x points
-    launches = args.steps // 2 if two_step else args.steps
+    # Roofline of the dominant kernel: algorithmic bytes per point update
+    # (read u^n once, write u^{n+1} once: 64 B in FP64) x the point updates
+    # one launch performs (points x steps per launch), over the launch time.
+    # The two-step kernel performs two updates per launch while it reads and
+    # writes the state once, so it moves half the algorithmic bytes.
+    spl = 2 if two_step else 1
+    launches = args.steps // spl
     launch_s = gpu_ms / 1e3 / launches
     bpu = BYTES_PER_UPDATE[args.precision]
-    achieved = points * bpu / launch_s / 1e9
-    kname = (kernel_name(args.precision, args.prefetch, not args.no_nt, args.waves, two_step)
+    achieved = points * spl * bpu / launch_s / 1e9
+    kname = (kernel_name(args.precision, args.prefetch, not args.no_nt, waves, two_step)
              if args.kernel != "two_pass" else "k_two_pass_half + k_two_pass_full")
     traffic = traffic_entry(kname, args.workload)
     st.close()
@@ -210,12 +215,13 @@ def main():
                    "precision": args.precision, "kernel": args.kernel,
                    "graph_steps": args.graph_steps, "rows_per_tile": args.rows,
                    "prefetch_rows": args.prefetch, "nt_stores": not args.no_nt,
-                   "waves_per_simd": args.waves},
+                   "waves_per_simd": waves},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": kname,
-                     "algorithmic_bytes_per_launch": points * bpu,
-                     "steps_per_launch": 2 if two_step else 1,
+                     "algorithmic_bytes_per_launch": points * spl * bpu,
+                     "steps_per_launch": spl,
+                     "state_bytes_moved_per_launch": points * bpu,
                      "avg_launch_ms": launch_s * 1e3},
     }
     if not args.no_cpu_baseline:

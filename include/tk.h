@@ -124,9 +124,10 @@ typedef struct {
     int prefetch_rows; /* fused kernel: u^n rows in flight per wave, 1 or 3 (0 = 3) */
     int flags;         /* TK_TUNE_* */
     int waves_per_simd;/* fused kernel: register budget for 3 or 4 waves per SIMD
-                          (0 = the compiler's choice); compiled combinations:
-                          prefetch 3 with non-temporal stores at 0/3/4, and
-                          prefetch 1 or 3 at 0; others give TK_E_INVALID */
+                          (0 = the compiler's choice; the FP32 default is 3);
+                          compiled combinations: prefetch 3 with non-temporal
+                          stores at 0/3/4, and prefetch 1 or 3 at 0; others
+                          give TK_E_INVALID */
 } tk_tuning;
 
 /* Set up the grids of n_inst instances (tortoise inversion, radial and

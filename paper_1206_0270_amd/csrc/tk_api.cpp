@@ -34,6 +34,7 @@ struct tk_ctx {
     std::vector<DevInst> hdev;         // host mirror of the device descriptors
     std::vector<std::vector<Radial>> hrad;   // host copies of the coefficient tables
     std::vector<std::vector<Angular>> hang;
+    std::vector<std::vector<AngularF>> hangf;
     long long step = 0;
     int cur = 0;  // state buffer holding u^step (mirror of the device control block)
     tk_tuning tuning{TK_KERNEL_AUTO, 0, 0, 3, TK_TUNE_NT_STORES, 0};
@@ -149,6 +150,8 @@ void layout(tk_ctx *c)
         off = align_up(off + (size_t)(2 * d.n_r - 1) * sizeof(Radial), A);
         h.off_ang = off;
         off = align_up(off + (size_t)d.n_theta * sizeof(Angular), A);
+        h.off_angf = off;
+        off = align_up(off + (size_t)d.n_theta * sizeof(AngularF), A);
         size_t ubytes = c->prec == TK_FP64 ? pts * 32 : pts * 16;
         size_t cbytes = c->prec == TK_FP64 ? 0 : pts * 8;
         for (int b = 0; b < 2; ++b) {
@@ -193,6 +196,7 @@ DevInst make_dev(const tk_ctx *c, const HostInst &h)
     D.half = ws + h.off_half;
     D.rad = (const Radial *)(ws + h.off_rad);
     D.ang = (const Angular *)(ws + h.off_ang);
+    D.angf = (const AngularF *)(ws + h.off_angf);
     D.wave = (double *)(ws + h.off_wave);
     D.src_kind = h.src.kind;
     D.src_amp = h.src.amplitude;
@@ -339,6 +343,8 @@ tk_status tk_init_grid(const tk_instance_desc *inst, int n_inst, tk_precision pr
     tk_ctx *c = new (std::nothrow) tk_ctx();
     if (!c) return fail(nullptr, TK_E_NOMEM, "host allocation failed");
     c->prec = prec;
+    // FP32: the two-step kernel fits three waves per SIMD
+    c->tuning.waves_per_simd = prec == TK_FP32_COMP ? 3 : 0;
     c->stream = (hipStream_t)hip_stream;
     c->inst.resize(n_inst);
     for (int k = 0; k < n_inst; ++k) {
@@ -403,21 +409,30 @@ tk_status tk_bind_workspace(tk_ctx *c, void *dev_ptr, size_t bytes)
     c->hdev.resize(c->inst.size());
     c->hrad.resize(c->inst.size());
     c->hang.resize(c->inst.size());
+    c->hangf.resize(c->inst.size());
     for (size_t k = 0; k < c->inst.size() && st == TK_OK; ++k) {
         HostInst &h = c->inst[k];
         std::vector<Radial> &rad = c->hrad[k];
         std::vector<Angular> &ang = c->hang[k];
+        std::vector<AngularF> &angf = c->hangf[k];
         rad.resize(2 * h.desc.n_r - 1);
         ang.resize(h.desc.n_theta);
+        angf.resize(h.desc.n_theta);
         fill_radial(h, rad.data());
         fill_angular(h, ang.data());
         fill_source(h, rad.data(), ang.data());
+        for (int j = 0; j < h.desc.n_theta; ++j)
+            angf[j] = AngularF{(float)ang[j].sa, (float)ang[j].sn2, (float)ang[j].kcs, (float)ang[j].V2,
+                               (float)ang[j].cot_h, 0.0f, 0.0f, 0.0f};
         c->hdev[k] = make_dev(c, h);
         hipError_t e = hipMemcpyAsync(c->ws + h.off_rad, rad.data(), rad.size() * sizeof(Radial),
                                       hipMemcpyHostToDevice, c->stream);
         if (e == hipSuccess)
             e = hipMemcpyAsync(c->ws + h.off_ang, ang.data(), ang.size() * sizeof(Angular), hipMemcpyHostToDevice,
                                c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(c->ws + h.off_angf, angf.data(), angf.size() * sizeof(AngularF),
+                               hipMemcpyHostToDevice, c->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
         if (e != hipSuccess) st = fail(c, TK_E_DEVICE, std::string("table upload: ") + hipGetErrorString(e));
     }

@@ -198,36 +198,100 @@ __device__ __forceinline__ float inv_sqrt(float x)
     return fmaf(y, fmaf(-hx * y, y, 0.5f), y);
 }
 
-// Radial factors a fused-kernel lane keeps for its node or half node; the
-// rest of the table is rebuilt from them: rho^2 = rho*rho, a^2 Delta =
-// a2 * Dl, the cos-part of Im ct = kct * Dl with kct = -2 s a.
+// ---------------------------------------------------------------------------
+// Fused-kernel form of the same arithmetic, arranged as chains of fused
+// multiply-adds.  The angular part of S_Pi,
+//   cthth (Phi_thth + cot Phi_th) ~ A2f (P+ - 2 P0 + P-) + A1f (P+ - P-),
+//   A2f = cthth / dtheta^2, A1f = cthth cot / (2 dtheta),
+// becomes a weight per row: (A2f + A1f) on row j+1, (A2f - A1f) on row j-1
+// and -2 A2f on row j (folded into c0).  The averages on rows j+-1 are
+// half the sum of two values; the 1/2 goes into the weights (Ap, Am), and
+// 1/h into b and d.
+// ---------------------------------------------------------------------------
+
+// Radial factors of one node or half node, premultiplied by the grid
+// constants they appear with: rho^2, rho/h, Re ct, Im ct at cos = 0, K
+// (b' = K sin^2 W sig), c1/h, D2h = Delta/(2 dtheta^2), c0 (all before the
+// 1/Sigma-hat^2 factor W).  Every other Delta-dependent term is D2h times a
+// row factor.
 template <typename T>
-struct RadV {
-    T rho, Dl, ct_re, ct_im0, K, c1_re, c1_im, c0_re, c0_im;
+struct RadF {
+    T rho2, rho_h, ct_re, ct_im0, K, c1h_re, c1h_im, D2h, c0_re, c0_im;
 };
-constexpr int kRadVals = 9;
+constexpr int kRadF = 10;  // read as 5 pairs
+
+// Uniform factors of a row: sa, kcs, V2 (a^2 Delta sin^2, kct Delta cos,
+// Delta V divided by D2h), sin^2, and cot dtheta / 2.
+template <typename T>
+struct AngF {
+    T sa, sn2, kcs, V2, kc;
+};
+
+// Coefficients of the fused bracket at one point: bh = b/h, dh = d/h, ct,
+// c0a = c0 - 2 A2f, and the row weights Ap, Am = (A2f +- A1f)/2.
+template <typename T>
+struct CoefF {
+    T bh, Ap, Am;
+    cx<T> ct, c0a, dh;
+};
 
 template <typename T>
-struct AngV {
-    T sn2, cs, cot, V;
-};
-
-template <typename T>
-__device__ __forceinline__ Coef<T> coef_lean(const RadV<T> &R, const AngV<T> &A, T a2, T kct)
+__device__ __forceinline__ CoefF<T> coef_fused(const RadF<T> &R, const AngF<T> &A)
 {
-    Coef<T> c;
-    const T Sh2 = R.rho * R.rho - (a2 * R.Dl) * A.sn2;
+    CoefF<T> c;
+    const T Sh2 = fma(-R.D2h, A.sa, R.rho2);
     const T sig = inv_sqrt(Sh2);
     const T W = sig * sig;
-    c.b = R.rho * sig;
-    c.cthth = R.Dl * W;
-    c.cth = c.cthth * A.cot;
-    c.ct = mkc(W * R.ct_re, W * (R.ct_im0 + (kct * R.Dl) * A.cs));
-    const cx<T> c1 = mkc(W * R.c1_re, W * R.c1_im);
-    c.c0 = mkc(W * (R.c0_re - R.Dl * A.V), W * R.c0_im);
-    const T bp = R.K * A.sn2 * W * sig;
-    c.d = mkc(c.b * bp + c.b * c.ct.re - c1.re, c.b * c.ct.im - c1.im);
+    c.bh = R.rho_h * sig;
+    const T A2 = R.D2h * W;  // A2f / 2
+    const T A1 = A2 * A.kc;  // A1f / 2
+    c.Ap = A2 + A1;
+    c.Am = A2 - A1;
+    const T cti = fma(R.D2h, A.kcs, R.ct_im0);
+    c.ct = mkc(W * R.ct_re, W * cti);
+    c.c0a = mkc(fma(T(-4), A2, W * fma(-R.D2h, A.V2, R.c0_re)), W * R.c0_im);
+    // d/h = (b (b' + ct) - c1) / h; b' + Re ct = W (K sin^2 sig + ct_re)
+    const T t = fma(R.K * A.sn2, sig, R.ct_re);
+    c.dh = mkc(W * fma(c.bh, t, -R.c1h_re), W * fma(c.bh, cti, -R.c1h_im));
     return c;
+}
+
+// Bracket D du / h - S at a point: pm, pp = the two values whose average is
+// Phi on rows j-1, j+1; ph0, pi0 = averaged fields on row j; du = the
+// difference across the cell; F = source (zero off its window).
+template <typename T>
+__device__ __forceinline__ Q4<T> bracket_fused(const CoefF<T> &c, cx<T> pm, cx<T> pp, cx<T> ph0, cx<T> pi0,
+                                               const Q4<T> &du, cx<T> F)
+{
+    // S_Pi = ct pi0 + c0a ph0 + Ap pp + Am pm + F
+    const T sre = fma(c.ct.re, pi0.re,
+                      fma(-c.ct.im, pi0.im,
+                          fma(c.c0a.re, ph0.re, fma(-c.c0a.im, ph0.im, fma(c.Ap, pp.re, fma(c.Am, pm.re, F.re))))));
+    const T sim = fma(c.ct.re, pi0.im,
+                      fma(c.ct.im, pi0.re,
+                          fma(c.c0a.re, ph0.im, fma(c.c0a.im, ph0.re, fma(c.Ap, pp.im, fma(c.Am, pm.im, F.im))))));
+    Q4<T> br;
+    br.phi = mkc(fma(c.bh, du.phi.re, -pi0.re), fma(c.bh, du.phi.im, -pi0.im));
+    br.pi = mkc(fma(c.dh.re, du.phi.re, fma(-c.dh.im, du.phi.im, fma(-c.bh, du.pi.re, -sre))),
+                fma(c.dh.re, du.phi.im, fma(c.dh.im, du.phi.re, fma(-c.bh, du.pi.im, -sim))));
+    return br;
+}
+
+// base - fac * br
+template <typename T>
+__device__ __forceinline__ Q4<T> lw_update(const Q4<T> &base, T fac, const Q4<T> &br)
+{
+    return Q4<T>{mkc(fma(-fac, br.phi.re, base.phi.re), fma(-fac, br.phi.im, base.phi.im)),
+                 mkc(fma(-fac, br.pi.re, base.pi.re), fma(-fac, br.pi.im, base.pi.im))};
+}
+
+// a + w (b - a) componentwise (the average of a and b for w = 1/2, given d = b - a)
+template <typename T>
+__device__ __forceinline__ Q4<T> mid_from(const Q4<T> &a, const Q4<T> &d)
+{
+    const T h = T(0.5);
+    return Q4<T>{mkc(fma(h, d.phi.re, a.phi.re), fma(h, d.phi.im, a.phi.im)),
+                 mkc(fma(h, d.pi.re, a.pi.re), fma(h, d.pi.im, a.pi.im))};
 }
 
 // The bracket of Eqs. (3)/(4) at a point: D du / h - S with

@@ -37,10 +37,19 @@ static_assert(sizeof(Radial) == 128, "Radial must stay 128 bytes");
 struct alignas(16) Angular {
     double sn2, cs, cot, V;  // sin^2, cos, cot, (m + s cos)^2/sin^2 - s
     double theta;
-    double srcg;  // g_theta(theta - pi/2) of the particle source (0 off its window)
+    double srcg;   // g_theta(theta - pi/2) of the particle source (0 off its window)
+    // The same, scaled for the fused kernels' radial factor D2h = Delta /
+    // (2 dtheta^2): a^2 Delta sin^2 = D2h sa, kct Delta cos = D2h kcs,
+    // Delta V = D2h V2; and cot dtheta / 2.
+    double cot_h, sa, kcs, V2;
     double pad1, pad2;
 };
-static_assert(sizeof(Angular) == 64, "Angular must stay 64 bytes");
+static_assert(sizeof(Angular) == 96, "Angular must stay 96 bytes");
+
+// The fused kernels' angular factors in float (FP32 form).
+struct alignas(16) AngularF {
+    float sa, sn2, kcs, V2, cot_h, pad1, pad2, pad3;
+};
 
 // One instance as the kernels see it (device memory, read-only in kernels).
 struct alignas(16) DevInst {
@@ -57,6 +66,7 @@ struct alignas(16) DevInst {
     void *half;  // two-pass kernel's half-step array (FP64, n_theta x pitch)
     const Radial *rad;     // [2 n_r - 1]
     const Angular *ang;    // [n_theta]
+    const AngularF *angf;  // [n_theta]
     double *wave;          // [wave_cap][n_theta][2]
     // source
     int src_kind, pad1, pad2, pad3;
@@ -84,7 +94,7 @@ struct HostInst {
     double h, dth, rp, rm;
     double src_Omega, src_rstar_p;
     int i_obs, pitch, wave_cap;
-    size_t off_u[2], off_c[2], off_half, off_rad, off_ang, off_wave;  // workspace offsets
+    size_t off_u[2], off_c[2], off_half, off_rad, off_ang, off_angf, off_wave;  // workspace offsets
     long long wave_drained;  // samples already handed out
 };
 

@@ -254,13 +254,13 @@ struct Lane {
     const DevInst *I;
     const void *u, *uc;  // u^n values (and bf16 terms)
     void *un, *unc;      // u^{n+1}
-    T *rad;              // this lane's radial factors in LDS: [2][kRadVals] with stride 64
+    T *rad;              // this lane's radial factors in LDS: [2 nodes][kRadF/2 pairs] with a stride of 64 pairs
     int c, p, nt;
     bool cin, hv, icol;
     bool ov;              // this lane's column is one the work item writes
     bool near_h, near_n;  // half node / node lies on the source window
     double gh, gn;        // tabulated A g_r there
-    T a2, kct, dt, inv_h, inv_dth2, inv_2dth;
+    T dt;
 };
 
 template <class P>
@@ -283,19 +283,33 @@ __device__ __forceinline__ St<typename P::T> load_row(const Lane<P> &L, int row)
     return v;
 }
 
+// LDS layout of the radial factors: for node k (0 = half node, 1 = node)
+// and pair p, lane l reads the two values at ((k kRadF/2 + p) 64 + l) 2.
 template <class P>
-__device__ __forceinline__ RadV<typename P::T> rad_of(const Lane<P> &L, int which)
-{
-    const typename P::T *b = L.rad + which * kRadVals * 64;
-    return RadV<typename P::T>{b[0], b[64], b[128], b[192], b[256], b[320], b[384], b[448], b[512]};
-}
-
-template <class P>
-__device__ __forceinline__ AngV<typename P::T> ang_of(const Angular &A)
+__device__ __forceinline__ RadF<typename P::T> radf_of(const Lane<P> &L, int k)
 {
     using T = typename P::T;
-    return AngV<T>{(T)A.sn2, (T)A.cs, (T)A.cot, (T)A.V};
+    typedef T T2 __attribute__((ext_vector_type(2)));
+    const T2 *b = (const T2 *)L.rad + k * (kRadF / 2) * 64;
+    const T2 v0 = b[0], v1 = b[64], v2 = b[128], v3 = b[192], v4 = b[256];
+    return RadF<T>{v0.x, v0.y, v1.x, v1.y, v2.x, v2.y, v3.x, v3.y, v4.x, v4.y};
 }
+
+// Uniform angular factors of a row (scalar loads; floats for FP32).
+template <class P>
+__device__ __forceinline__ AngF<typename P::T> angf_of(const DevInst &I, int row)
+{
+    if constexpr (!P::kComp) {
+        const TK_CONST Angular *A = cload_ptr(I.ang) + row;
+        return AngF<double>{A->sa, A->sn2, A->kcs, A->V2, A->cot_h};
+    } else {
+        const TK_CONST AngularF *A = cload_ptr(I.angf) + row;
+        return AngF<float>{A->sa, A->sn2, A->kcs, A->V2, A->cot_h};
+    }
+}
+
+// g_theta of the particle source on a row (0 off its window)
+__device__ __forceinline__ double src_theta(const DevInst &I, int row) { return (cload_ptr(I.ang) + row)->srcg; }
 
 template <class P>
 __device__ __forceinline__ double value_of(const St<typename P::T> &v, int k)
@@ -388,21 +402,24 @@ __device__ __forceinline__ Q4<typename P::T> half_row(const Lane<P> &L, const Le
     const cx<T> nm = shfl_down1(UM.phi), np = shfl_down1(UP.phi);
     const Q4<T> n0 = shfl_down1(U0);
     if (!L.hv) return zero_q4<T>();
-    const Q4<T> bar = half_sum(n0, U0);
-    const Angular A = load_entry(cload_ptr(I.ang) + (r));
-    const Coef<T> cf = coef_lean(rad_of(L, 0), ang_of<P>(A), L.a2, L.kct);
+    const Q4<T> du = n0 - U0;
+    const Q4<T> bar = mid_from(U0, du);
+    const CoefF<T> cf = coef_fused(radf_of(L, 0), angf_of<P>(I, r));
     const T fac = T(0.5) * L.dt;
     if constexpr (!P::kComp) {
-        const cd F = L.near_h ? source_value(L.gh, A.srcg, lv.eh) : mk(0, 0);
-        return lw_point(cf, bar, avg(nm, UM.phi), bar.phi, avg(np, UP.phi), bar.pi, n0 - U0, fac, L.inv_h,
-                        L.inv_dth2, L.inv_2dth, F);
+        // F is exactly zero off the source window (g_r = 0 there)
+        const cd F = source_value(L.gh, src_theta(I, r), lv.eh);
+        return lw_update(bar, fac, bracket_fused(cf, nm + UM.phi, np + UP.phi, bar.phi, bar.pi, du, F));
     } else {
-        Q4<T> h = lw_point(cf, bar, avg(nm, UM.phi), bar.phi, avg(np, UP.phi), bar.pi, n0 - U0, fac, L.inv_h,
-                           L.inv_dth2, L.inv_2dth, mkc(T(0), T(0)));
-        if (L.near_h && A.srcg != 0.0) {  // FP64 source increment (dt/2) F
-            const cd F = source_value(L.gh, A.srcg, lv.eh);
-            const double f64 = 0.5 * I.dt;
-            h.pi = mkc((T)((double)h.pi.re + f64 * F.re), (T)((double)h.pi.im + f64 * F.im));
+        Q4<T> h = lw_update(bar, fac, bracket_fused(cf, nm + UM.phi, np + UP.phi, bar.phi, bar.pi, du,
+                                                    mkc(T(0), T(0))));
+        if (L.near_h) {  // FP64 source increment (dt/2) F
+            const double gj = src_theta(I, r);
+            if (gj != 0.0) {
+                const cd F = source_value(L.gh, gj, lv.eh);
+                const double f64 = 0.5 * I.dt;
+                h.pi = mkc((T)((double)h.pi.re + f64 * F.re), (T)((double)h.pi.im + f64 * F.im));
+            }
         }
         return h;
     }
@@ -431,21 +448,20 @@ __device__ __forceinline__ St<typename P::T> out_row(const Lane<P> &L, const Lev
     res.f = zero_q4<T>();
     res.c = zero_q4<T>();
     if (!L.icol) return res;
-    const Q4<T> til = half_sum(H0, l0);
-    const Angular A = load_entry(cload_ptr(I.ang) + (o));
-    const Coef<T> cf = coef_lean(rad_of(L, 1), ang_of<P>(A), L.a2, L.kct);
+    const Q4<T> du = H0 - l0;
+    const Q4<T> til = mid_from(l0, du);
+    const CoefF<T> cf = coef_fused(radf_of(L, 1), angf_of<P>(I, o));
     if constexpr (!P::kComp) {
-        const cd F = L.near_n ? source_value(L.gn, A.srcg, lv.ef) : mk(0, 0);
-        res.f = lw_point(cf, Uo.f, avg(HM.phi, lm), til.phi, avg(HP.phi, lp), til.pi, H0 - l0, L.dt, L.inv_h,
-                         L.inv_dth2, L.inv_2dth, F);
+        const cd F = source_value(L.gn, src_theta(I, o), lv.ef);
+        res.f = lw_update(Uo.f, L.dt, bracket_fused(cf, HM.phi + lm, HP.phi + lp, til.phi, til.pi, du, F));
     } else {
-        const Q4<T> br = lw_bracket(cf, avg(HM.phi, lm), til.phi, avg(HP.phi, lp), til.pi, H0 - l0, L.inv_h,
-                                    L.inv_dth2, L.inv_2dth, mkc(T(0), T(0)));
+        const Q4<T> br = bracket_fused(cf, HM.phi + lm, HP.phi + lp, til.phi, til.pi, du, mkc(T(0), T(0)));
         const T *bp = &br.phi.re, *fp = &Uo.f.phi.re, *cp = &Uo.c.phi.re;
         T *rf = &res.f.phi.re, *rc = &res.c.phi.re;
-        if (L.near_n && A.srcg != 0.0) {
+        const double gj = L.near_n ? src_theta(I, o) : 0.0;
+        if (gj != 0.0) {
             // FP64 accumulation where the source injects: u + c - dt [.] + dt F
-            const cd F = source_value(L.gn, A.srcg, lv.ef);
+            const cd F = source_value(L.gn, gj, lv.ef);
             const double add[4] = {0.0, 0.0, I.dt * F.re, I.dt * F.im};
             for (int k = 0; k < 4; ++k) {
                 const double v = ((double)fp[k] + (double)cp[k]) + (double)(-L.dt * bp[k]) + add[k];
@@ -453,7 +469,7 @@ __device__ __forceinline__ St<typename P::T> out_row(const Lane<P> &L, const Lev
                 rc[k] = (T)(v - (double)rf[k]);
             }
         } else {
-            for (int k = 0; k < 4; ++k) two_sum(fp[k], -L.dt * bp[k] + cp[k], rf[k], rc[k]);
+            for (int k = 0; k < 4; ++k) two_sum(fp[k], fma(-L.dt, bp[k], cp[k]), rf[k], rc[k]);
         }
         // the Kahan term is kept at its stored precision from here on, so
         // that a value used on chip equals the value a later step reloads
@@ -659,21 +675,25 @@ __device__ __forceinline__ void init_lane(Lane<P> &L, const DevInst &I, const Wo
     L.hv = L.c >= 0 && L.c <= nr - 2;
     L.icol = L.c >= 1 && L.c <= nr - 2;
     L.ov = lane >= halo && lane < halo + cols && L.c < nr;
-    L.a2 = (T)I.a2;
-    L.kct = (T)I.kct;
     L.dt = (T)I.dt;
-    L.inv_h = (T)I.inv_h;
-    L.inv_dth2 = (T)I.inv_dth2;
-    L.inv_2dth = (T)I.inv_2dth;
     L.rad = rad;
     const Radial Rh = load_entry(gload_ptr(I.rad) + (L.hv ? 2 * L.c + 1 : 0));
     const Radial Rn = load_entry(gload_ptr(I.rad) + (L.icol ? 2 * L.c : 0));
-    const double vh[kRadVals] = {Rh.rho, Rh.Dl, Rh.ct_re, Rh.ct_im0, Rh.K, Rh.c1_re, Rh.c1_im, Rh.c0_re, Rh.c0_im};
-    const double vn[kRadVals] = {Rn.rho, Rn.Dl, Rn.ct_re, Rn.ct_im0, Rn.K, Rn.c1_re, Rn.c1_im, Rn.c0_re, Rn.c0_im};
+    typedef T T2 __attribute__((ext_vector_type(2)));
+    T2 *slot = (T2 *)L.rad;
 #pragma unroll
-    for (int k = 0; k < kRadVals; ++k) {
-        L.rad[k * 64] = (T)vh[k];
-        L.rad[(kRadVals + k) * 64] = (T)vn[k];
+    for (int k = 0; k < 2; ++k) {
+        const Radial &R = k == 0 ? Rh : Rn;
+        const double v[kRadF] = {R.rho2, R.rho * I.inv_h,   R.ct_re,           R.ct_im0,
+                                 R.K,    R.c1_re * I.inv_h, R.c1_im * I.inv_h, 0.5 * R.Dl * I.inv_dth2,
+                                 R.c0_re, R.c0_im};
+#pragma unroll
+        for (int p = 0; p < kRadF / 2; ++p) {
+            T2 x;
+            x.x = (T)v[2 * p];
+            x.y = (T)v[2 * p + 1];
+            slot[(k * (kRadF / 2) + p) * 64] = x;
+        }
     }
     L.gh = L.hv ? Rh.srcg : 0.0;
     L.gn = L.icol ? Rn.srcg : 0.0;
@@ -692,7 +712,7 @@ __global__ void __launch_bounds__(64 * kFusedWavesPerBlock) __attribute__((amdgp
             const DevCtl *__restrict__ ctl, int kstep, int kflip)
 {
     using T = typename P::T;
-    __shared__ T s_rad[kFusedWavesPerBlock][2 * kRadVals * 64];
+    __shared__ T s_rad[kFusedWavesPerBlock][2 * kRadF * 64];
     const int lane = (int)(threadIdx.x & 63);
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int w = (int)blockIdx.x * kFusedWavesPerBlock + wv;
@@ -701,7 +721,7 @@ __global__ void __launch_bounds__(64 * kFusedWavesPerBlock) __attribute__((amdgp
     const DevInst &I = insts[it.inst];
     const long long n = ctl->step + kstep;
     Lane<P> L;
-    init_lane(L, I, it, lane, 1, cols, (int)((ctl->cur + kflip) & 1), &s_rad[wv][lane]);
+    init_lane(L, I, it, lane, 1, cols, (int)((ctl->cur + kflip) & 1), &s_rad[wv][2 * lane]);
     const Level lv = make_level(I, n);
 
     const int nt = I.n_theta;
@@ -750,7 +770,7 @@ __global__ void __launch_bounds__(64 * kFusedWavesPerBlock) __attribute__((amdgp
              const DevCtl *__restrict__ ctl, int kstep, int kflip)
 {
     using T = typename P::T;
-    __shared__ T s_rad[kFusedWavesPerBlock][2 * kRadVals * 64];
+    __shared__ T s_rad[kFusedWavesPerBlock][2 * kRadF * 64];
     const int lane = (int)(threadIdx.x & 63);
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int w = (int)blockIdx.x * kFusedWavesPerBlock + wv;
@@ -759,7 +779,7 @@ __global__ void __launch_bounds__(64 * kFusedWavesPerBlock) __attribute__((amdgp
     const DevInst &I = insts[it.inst];
     const long long n = ctl->step + kstep;
     Lane<P> L;
-    init_lane(L, I, it, lane, 2, kFused2Cols, (int)((ctl->cur + kflip) & 1), &s_rad[wv][lane]);
+    init_lane(L, I, it, lane, 2, kFused2Cols, (int)((ctl->cur + kflip) & 1), &s_rad[wv][2 * lane]);
     const Level l1 = make_level(I, n), l2 = make_level(I, n + 1);
     const int nt = I.n_theta;  // >= 5: the six head iterations all exist
 

@@ -123,7 +123,7 @@ void fill_angular(const HostInst &hi, Angular *ang)
         Angular &A = ang[j];
         double th = j * hi.dth;
         A.theta = th;
-        A.srcg = A.pad1 = A.pad2 = 0.0;
+        A.srcg = A.cot_h = A.sa = A.kcs = A.V2 = A.pad1 = A.pad2 = 0.0;
         if (j == 0 || j == d.n_theta - 1) {  // coefficients never used on the poles
             A.sn2 = A.cs = A.cot = A.V = 0.0;
             continue;
@@ -132,8 +132,13 @@ void fill_angular(const HostInst &hi, Angular *ang)
         A.sn2 = sn * sn;
         A.cs = cs;
         A.cot = cs / sn;
+        A.cot_h = A.cot * hi.dth * 0.5;
+        const double q = 2.0 * hi.dth * hi.dth;  // 1 / (Delta-factor scale)
         double w = d.m + d.s * cs;
         A.V = w * w / A.sn2 - d.s;
+        A.sa = q * d.a * d.a * A.sn2;
+        A.kcs = q * (-2.0 * d.s * d.a) * cs;
+        A.V2 = q * A.V;
     }
 }
 
