@@ -110,6 +110,9 @@ def main():
     ap.add_argument("--workload", default="batched")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32c"])
     ap.add_argument("--graph-steps", type=int, default=100)
+    ap.add_argument("--tune", default="auto", choices=["auto", "manual"],
+                    help="auto: the library's autotuner picks the launch shape before timing; "
+                         "manual: the shape given by --kernel/--rows/--prefetch/--no-nt/--waves")
     ap.add_argument("--rows", type=int, default=0)
     ap.add_argument("--kernel", default="fused2", choices=["fused2", "fused", "two_pass"],
                     help="fused2: two time steps per pass (needs --rows 0); fused: one step per pass; "
@@ -154,16 +157,27 @@ def main():
     insts, desc = workload(args.workload)
     prec = tk.TK_FP64 if args.precision == "fp64" else tk.TK_FP32_COMP
     points = W.points(insts)
+    if args.steps % 2 or args.warmup % 2 or args.graph_steps % 2:
+        raise SystemExit("the two-step kernel is timed in whole launches: use even --steps, --warmup, --graph-steps")
     st = tk.Stepper(insts, precision=prec)
-    kern = {"fused2": tk.TK_KERNEL_FUSED2, "fused": tk.TK_KERNEL_FUSED, "two_pass": tk.TK_KERNEL_TWO_PASS}[args.kernel]
-    two_step = args.kernel == "fused2"
-    if two_step and (args.steps % 2 or args.warmup % 2 or args.graph_steps % 2):
-        raise SystemExit("--kernel fused2 times whole two-step launches: use even --steps, --warmup, --graph-steps")
-    waves = st.get_tuning()["waves_per_simd"] if args.waves is None else args.waves
-    st.set_tuning(kernel=kern, rows_per_tile=args.rows, graph_steps=args.graph_steps,
-                  prefetch_rows=args.prefetch, nt_stores=not args.no_nt, waves_per_simd=waves)
     for k, inst in enumerate(insts):
         st.set_fields(k, *W.initial_data(inst))
+    if args.tune == "auto":
+        tune_ms, tried = st.autotune(warmup=2, steps=6)
+        t = st.get_tuning()
+        print(f"# autotune: {tried} launch shapes, best {tune_ms:.4f} ms/step: {t}", file=sys.stderr, flush=True)
+        t["graph_steps"] = args.graph_steps
+        st.set_tuning(**t)
+    else:
+        kern = {"fused2": tk.TK_KERNEL_FUSED2, "fused": tk.TK_KERNEL_FUSED,
+                "two_pass": tk.TK_KERNEL_TWO_PASS}[args.kernel]
+        waves = st.get_tuning()["waves_per_simd"] if args.waves is None else args.waves
+        st.set_tuning(kernel=kern, rows_per_tile=args.rows, graph_steps=args.graph_steps,
+                      prefetch_rows=args.prefetch, nt_stores=not args.no_nt, waves_per_simd=waves)
+    t = st.get_tuning()
+    kernel = {tk.TK_KERNEL_FUSED2: "fused2", tk.TK_KERNEL_FUSED: "fused",
+              tk.TK_KERNEL_TWO_PASS: "two_pass"}[t["kernel"]]
+    two_step = kernel == "fused2"
     print(f"# workload {args.workload}: {len(insts)} instances, {points} points, "
           f"{st.workspace_bytes / 2**30:.2f} GiB workspace", file=sys.stderr, flush=True)
     st.step(args.warmup)
@@ -193,8 +207,8 @@ def main():
     launch_s = gpu_ms / 1e3 / launches
     bpu = BYTES_PER_UPDATE[args.precision]
     achieved = points * spl * bpu / launch_s / 1e9
-    kname = (kernel_name(args.precision, args.prefetch, not args.no_nt, waves, two_step)
-             if args.kernel != "two_pass" else "k_two_pass_half + k_two_pass_full")
+    kname = (kernel_name(args.precision, t["prefetch_rows"], t["nt_stores"], t["waves_per_simd"], two_step)
+             if kernel != "two_pass" else "k_two_pass_half + k_two_pass_full")
     traffic = traffic_entry(kname, args.workload)
     st.close()
 
@@ -212,10 +226,10 @@ def main():
         "dtype": "f64" if args.precision == "fp64" else "f32+bf16comp",
         "data": "synthetic",
         "config": {"workload": desc, "instances": len(insts), "points": points,
-                   "precision": args.precision, "kernel": args.kernel,
-                   "graph_steps": args.graph_steps, "rows_per_tile": args.rows,
-                   "prefetch_rows": args.prefetch, "nt_stores": not args.no_nt,
-                   "waves_per_simd": waves},
+                   "precision": args.precision, "kernel": kernel, "tuning": args.tune,
+                   "graph_steps": t["graph_steps"], "rows_per_tile": t["rows_per_tile"],
+                   "prefetch_rows": t["prefetch_rows"], "nt_stores": t["nt_stores"],
+                   "waves_per_simd": t["waves_per_simd"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": kname,

@@ -183,6 +183,21 @@ tk_status tk_set_step(tk_ctx *ctx, long step);
 tk_status tk_set_tuning(tk_ctx *ctx, const tk_tuning *t);
 tk_status tk_get_tuning(const tk_ctx *ctx, tk_tuning *t);
 
+/* Autotuner: time every compiled launch shape (kernel, u^n prefetch depth,
+ * store kind, occupancy target; for the one-step kernel also rows per tile
+ * 0, 64 and 16) on this context's own instances and keep the fastest;
+ * graph_steps stays as it was.  Each
+ * candidate runs `warmup` untimed and then `steps` timed steps (both
+ * rounded up to even), timed with HIP events on the context's stream.  The
+ * state, the step counter and the waveform rings are copied to a temporary
+ * device allocation (hipMalloc; freed before return) and restored
+ * afterwards, so the simulation is left as it was found.  Synchronous; not
+ * for use during stream capture.  On success *best_ms_per_step and
+ * *n_tried (each may be NULL) receive the winner's time per step and the
+ * number of shapes timed.  TK_E_NOMEM if the temporary copy cannot be
+ * allocated. */
+tk_status tk_autotune(tk_ctx *ctx, int warmup, int steps, double *best_ms_per_step, int *n_tried);
+
 /* Wait for all work enqueued by the context. */
 tk_status tk_synchronize(tk_ctx *ctx);
 

@@ -742,6 +742,115 @@ tk_status tk_get_tuning(const tk_ctx *c, tk_tuning *t)
     return TK_OK;
 }
 
+tk_status tk_autotune(tk_ctx *c, int warmup, int steps, double *best_ms_per_step, int *n_tried)
+{
+    if (!c) return TK_E_INVALID;
+    if (!c->ws) return fail(c, TK_E_STATE, "no workspace bound");
+    if (warmup < 0 || warmup > 100000 || steps < 1 || steps > 100000)
+        return fail(c, TK_E_INVALID, "warmup must be in [0, 1e5] and steps in [1, 1e5]");
+    warmup += warmup & 1;
+    steps += steps & 1;
+    TK_HIP(c, hipStreamSynchronize(c->stream));
+
+    // what a run changes: the current state, the waveform rings, the control block
+    struct Span {
+        size_t off, bytes, save;
+    };
+    std::vector<Span> spans;
+    size_t total = 0;
+    auto add = [&](size_t off, size_t bytes) {
+        spans.push_back(Span{off, bytes, total});
+        total += align_up(bytes, 256);
+    };
+    for (const HostInst &h : c->inst) {
+        const size_t pts = (size_t)h.desc.n_theta * h.pitch;
+        add(h.off_u[c->cur], c->prec == TK_FP64 ? pts * 32 : pts * 16);
+        if (c->prec != TK_FP64) add(h.off_c[c->cur], pts * 8);
+        add(h.off_wave, (size_t)h.wave_cap * h.desc.n_theta * 16);
+    }
+    add(c->off_ctl, sizeof(DevCtl));
+    char *save = nullptr;
+    if (hipMalloc(&save, total) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, TK_E_NOMEM, "autotune: no device memory for the state copy");
+    }
+    hipError_t e = hipSuccess;
+    for (const Span &sp : spans)
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(save + sp.save, c->ws + sp.off, sp.bytes, hipMemcpyDeviceToDevice, c->stream);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+
+    const tk_tuning keep = c->tuning;
+    const long long step0 = c->step;
+    const int cur0 = c->cur;
+    drop_graph(c);
+    // candidates: every compiled fused shape with the two-step kernel (whole
+    // strips) and the one-step kernel (whole strips, or chunks of rows, which
+    // give a small workload more waves), and the two-pass kernel (FP64)
+    const int shapes[][3] = {{3, 1, 0}, {3, 1, 3}, {3, 1, 4}, {3, 0, 0}, {1, 1, 0}, {1, 0, 0}};
+    std::vector<tk_tuning> cand;
+    for (const auto &sh : shapes)
+        cand.push_back(tk_tuning{TK_KERNEL_FUSED2, 0, 0, sh[0], sh[1] ? TK_TUNE_NT_STORES : 0, sh[2]});
+    for (int rows : {0, 64, 16})
+        for (const auto &sh : shapes)
+            cand.push_back(tk_tuning{TK_KERNEL_FUSED, rows, 0, sh[0], sh[1] ? TK_TUNE_NT_STORES : 0, sh[2]});
+    if (c->prec == TK_FP64) cand.push_back(tk_tuning{TK_KERNEL_TWO_PASS, 0, 0, 3, TK_TUNE_NT_STORES, 0});
+
+    tk_status st = e == hipSuccess ? TK_OK : fail(c, TK_E_DEVICE, std::string("autotune setup: ") + hipGetErrorString(e));
+    double best = 1e300;
+    tk_tuning best_t = keep;
+    int tried = 0;
+    for (const tk_tuning &t : cand) {
+        if (st != TK_OK) break;
+        c->tuning = t;
+        const int kernel = resolve_kernel(c);
+        if (kernel != TK_KERNEL_TWO_PASS) st = ensure_work(c, kernel);
+        int flips = 0;
+        if (st == TK_OK && warmup > 0) st = enqueue_steps(c, kernel, warmup, &flips);
+        if (st == TK_OK && (e = hipEventRecord(e0, c->stream)) != hipSuccess)
+            st = fail(c, TK_E_DEVICE, std::string("autotune event: ") + hipGetErrorString(e));
+        if (st == TK_OK) st = enqueue_steps(c, kernel, steps, &flips);
+        if (st == TK_OK && (e = hipEventRecord(e1, c->stream)) != hipSuccess)
+            st = fail(c, TK_E_DEVICE, std::string("autotune event: ") + hipGetErrorString(e));
+        float ms = 0.0f;
+        if (st == TK_OK && ((e = hipEventSynchronize(e1)) != hipSuccess || (e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess))
+            st = fail(c, TK_E_DEVICE, std::string("autotune timing: ") + hipGetErrorString(e));
+        if (st != TK_OK) break;
+        ++tried;
+        if (ms / steps < best) {
+            best = ms / steps;
+            best_t = t;
+        }
+    }
+    // restore the simulation as it was
+    hipError_t er = hipStreamSynchronize(c->stream);
+    for (const Span &sp : spans)
+        if (er == hipSuccess)
+            er = hipMemcpyAsync(c->ws + sp.off, save + sp.save, sp.bytes, hipMemcpyDeviceToDevice, c->stream);
+    if (er == hipSuccess) er = hipStreamSynchronize(c->stream);
+    (void)hipFree(save);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    c->step = step0;
+    c->cur = cur0;
+    if (er != hipSuccess && st == TK_OK) st = fail(c, TK_E_DEVICE, std::string("autotune restore: ") + hipGetErrorString(er));
+    if (st != TK_OK) {
+        c->tuning = keep;
+        return st;
+    }
+    best_t.graph_steps = keep.graph_steps;
+    c->tuning = best_t;
+    if (resolve_kernel(c) != TK_KERNEL_TWO_PASS) {
+        st = ensure_work(c, resolve_kernel(c));
+        if (st != TK_OK) return st;
+    }
+    if (best_ms_per_step) *best_ms_per_step = best;
+    if (n_tried) *n_tried = tried;
+    return TK_OK;
+}
+
 tk_status tk_synchronize(tk_ctx *c)
 {
     if (!c) return TK_E_INVALID;

@@ -24,7 +24,7 @@ _STATUS = {0: "TK_OK", 1: "TK_E_INVALID", 2: "TK_E_NOMEM", 3: "TK_E_DEVICE", 4: 
 
 EXPORTS = ["tk_abi_version", "tk_init_grid", "tk_workspace_bytes", "tk_bind_workspace",
            "tk_set_fields", "tk_get_fields", "tk_set_source", "tk_step", "tk_extract",
-           "tk_get_step", "tk_set_step", "tk_set_tuning", "tk_get_tuning", "tk_synchronize",
+           "tk_get_step", "tk_set_step", "tk_set_tuning", "tk_get_tuning", "tk_autotune", "tk_synchronize",
            "tk_destroy", "tk_last_error", "tk_stable_dt"]
 
 
@@ -87,6 +87,7 @@ def load():
         "tk_set_step": (st, [vp, ctypes.c_long]),
         "tk_set_tuning": (st, [vp, ctypes.POINTER(Tuning)]),
         "tk_get_tuning": (st, [vp, ctypes.POINTER(Tuning)]),
+        "tk_autotune": (st, [vp, ctypes.c_int, ctypes.c_int, _dp, ctypes.POINTER(ctypes.c_int)]),
         "tk_synchronize": (st, [vp]),
         "tk_destroy": (st, [vp]),
         "tk_last_error": (ctypes.c_char_p, [vp]),
@@ -238,6 +239,15 @@ class Stepper:
         return dict(kernel=t.kernel, rows_per_tile=t.rows_per_tile, graph_steps=t.graph_steps,
                     prefetch_rows=t.prefetch_rows, nt_stores=bool(t.flags & TK_TUNE_NT_STORES),
                     waves_per_simd=t.waves_per_simd)
+
+    def autotune(self, warmup=2, steps=10):
+        """Time the compiled launch shapes on these instances, keep the
+        fastest; the simulation state is left as it was.  Returns
+        (ms per step of the winner, shapes tried)."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int()
+        _check(self.lib.tk_autotune(self.ctx, int(warmup), int(steps), ctypes.byref(ms), ctypes.byref(n)), self.ctx)
+        return ms.value, n.value
 
     def synchronize(self):
         _check(self.lib.tk_synchronize(self.ctx), self.ctx)

@@ -68,8 +68,9 @@ def test_unstable_dt_rejected_unless_forced():
     lib = tk.load()
     n = ctypes.c_size_t()
     assert lib.tk_workspace_bytes(ctx, ctypes.byref(n)) == tk.TK_OK and n.value > 801 * 33 * 64
-    # stepping without a bound workspace is a state error, not a crash
+    # stepping (or tuning) without a bound workspace is a state error, not a crash
     assert lib.tk_step(ctx, 1) == tk.TK_E_STATE
+    assert lib.tk_autotune(ctx, 2, 4, None, None) == tk.TK_E_STATE
     assert lib.tk_destroy(ctx) == tk.TK_OK
 
 

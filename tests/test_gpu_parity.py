@@ -230,6 +230,30 @@ def test_checkpoint_resume_bitwise():
     st2.close()
 
 
+@pytest.mark.parametrize("precision", [tk.TK_FP64, tk.TK_FP32_COMP])
+def test_autotune_leaves_the_simulation_unchanged(precision):
+    insts = small_instances()
+    ref = gpu_run(insts, 40, precision=precision)
+    st = tk.Stepper(insts, force_dt=True, precision=precision)
+    for k, inst in enumerate(insts):
+        st.set_fields(k, *W.initial_data(inst))
+    st.step(20)
+    ms, n = st.autotune(warmup=2, steps=4)
+    t = st.get_tuning()
+    say("autotune:", n, "shapes, best", f"{ms:.4f} ms/step", t)
+    assert n >= 24 and ms > 0 and st.step_index == 20
+    st.step(20)
+    for k in range(len(insts)):
+        phi, pi = st.get_fields(k)
+        wave = st.extract(k)
+        if t["kernel"] == tk.TK_KERNEL_TWO_PASS:  # another evaluation order
+            assert rel(phi, ref[k][0]) < 1e-13 and rel(pi, ref[k][1]) < 1e-13
+        else:  # every fused shape computes the same bits
+            assert np.array_equal(phi, ref[k][0]) and np.array_equal(pi, ref[k][1])
+            assert np.array_equal(wave, ref[k][2])
+    st.close()
+
+
 def test_two_pass_and_fused_agree():
     insts = small_instances()
     a = gpu_run(insts, 100, kernel=tk.TK_KERNEL_FUSED)
