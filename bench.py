@@ -171,7 +171,9 @@ def main():
     else:
         kern = {"fused2": tk.TK_KERNEL_FUSED2, "fused": tk.TK_KERNEL_FUSED,
                 "two_pass": tk.TK_KERNEL_TWO_PASS}[args.kernel]
-        waves = st.get_tuning()["waves_per_simd"] if args.waves is None else args.waves
+        waves = args.waves
+        if waves is None:  # the library's default where that shape is compiled with it
+            waves = st.get_tuning()["waves_per_simd"] if (args.prefetch == 3 and not args.no_nt) else 0
         st.set_tuning(kernel=kern, rows_per_tile=args.rows, graph_steps=args.graph_steps,
                       prefetch_rows=args.prefetch, nt_stores=not args.no_nt, waves_per_simd=waves)
     t = st.get_tuning()
