@@ -102,6 +102,115 @@ def cpu_baseline(insts, target_s=15.0, steps=20):
                        f"with OpenMP over theta rows")
 
 
+def projected_waveform(inst, wave):
+    """Waveform samples [k][theta] projected onto the s=-2 spin-weighted
+    harmonic with l = max(|m|, 2)."""
+    from paper_1206_0270_amd import workloads as W
+    import numpy as np
+    nt = inst["n_theta"]
+    th = np.arange(nt) * np.pi / (nt - 1)
+    Y = W.swsh_profile(-2, inst["m"], max(abs(inst["m"]), 2), th)
+    return wave @ (Y * 2 * np.pi * np.sin(th) * (np.pi / (nt - 1)))
+
+
+def waveform_errors(w_ref, w, floor=1e-3):
+    """Amplitude error max ||w| - |w_ref|| / |w_ref| and phase error
+    max |arg(w / w_ref)| over samples with |w_ref| >= floor * max |w_ref|."""
+    import numpy as np
+    sel = np.abs(w_ref) >= floor * np.abs(w_ref).max()
+    if not sel.any():
+        return None, None
+    amp = float(np.max(np.abs(np.abs(w[sel]) - np.abs(w_ref[sel])) / np.abs(w_ref[sel])))
+    ph = float(np.max(np.abs(np.angle(w[sel] / w_ref[sel]))))
+    return amp, ph
+
+
+def precision_study(args):
+    """The fifth workload (m = 2, 3, 4 x a = 0.5, 0.9; circular orbits at
+    r0 = 8M; 16001 x 129 on [-300, 300]M; dt = 1/500) in FP64 and in the
+    FP32-compensated form on the GPU over a window of window_M, and on a short
+    prefix against the FP64 oracle.  One JSON line."""
+    import numpy as np
+    import torch
+    from paper_1206_0270_amd import tk
+    from paper_1206_0270_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    insts = W.config5()["instances"]
+    dt = insts[0]["dt"]
+    steps = int(round(args.study_window / dt))
+    steps -= steps % 200
+    points = W.points(insts)
+    forms = {}
+    for name, prec in (("fp64", tk.TK_FP64), ("fp32c", tk.TK_FP32_COMP)):
+        st = tk.Stepper(insts, precision=prec, wave_capacity=int(args.study_window) + 64)
+        for k, inst in enumerate(insts):
+            st.set_fields(k, *W.initial_data(inst))
+        st.autotune(warmup=2, steps=6)
+        t = st.get_tuning()
+        t["graph_steps"] = 100
+        st.set_tuning(**t)
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(st.stream)
+        st.step(steps)
+        ev1.record(st.stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1)
+        waves = [projected_waveform(inst, st.extract(k, max_samples=int(args.study_window) + 64))
+                 for k, inst in enumerate(insts)]
+        st.close()
+        forms[name] = dict(updates_per_s=points * steps / (ms / 1e3), seconds=ms / 1e3, tuning=t, waves=waves)
+        print(f"# {name}: {steps} steps in {ms / 1e3:.1f} s", file=sys.stderr, flush=True)
+    K = insts[0]["extract_every"]
+    per_inst = []
+    worst = {}
+    for k, inst in enumerate(insts):
+        wa, wb = forms["fp64"]["waves"][k], forms["fp32c"]["waves"][k]
+        row = {"name": inst["name"]}
+        for T in args.study_checkpoints:
+            n = min(len(wa), int(round(T / (K * dt))))
+            amp, ph = waveform_errors(wa[:n], wb[:n])
+            row[f"T{int(T)}"] = {"amp": amp, "phase": ph}
+            if amp is not None:
+                w = worst.setdefault(int(T), [0.0, 0.0])
+                w[0], w[1] = max(w[0], amp), max(w[1], ph)
+        per_inst.append(row)
+    # short prefix against the oracle, first instance, both forms
+    import oracle
+    inst = insts[0]
+    g = oracle.Grid(M=inst["M"], a=inst["a"], s=inst["s"], m=inst["m"], n_r=inst["n_r"], n_theta=inst["n_theta"],
+                    rstar_min=inst["rstar_min"], rstar_max=inst["rstar_max"], dt=inst["dt"], i_obs=inst["i_obs"],
+                    extract_every=inst["extract_every"], source=inst.get("source"))
+    g.set_state(*W.initial_data(inst))
+    g.run(args.study_oracle_steps)
+    ophi, opi = g.get_state()
+    den = np.sqrt(np.linalg.norm(ophi) ** 2 + np.linalg.norm(opi) ** 2)
+    pref = {}
+    for name, prec in (("fp64", tk.TK_FP64), ("fp32c", tk.TK_FP32_COMP)):
+        st = tk.Stepper([inst], precision=prec)
+        st.set_fields(0, *W.initial_data(inst))
+        st.step(args.study_oracle_steps)
+        phi, pi = st.get_fields(0)
+        st.close()
+        pref[name] = float(np.sqrt(np.linalg.norm(phi - ophi) ** 2 + np.linalg.norm(pi - opi) ** 2) / den)
+    out = {
+        "metric": "waveform amplitude / phase relative error of the FP32-compensated form vs FP64; updates/s of both",
+        "workload": "6 instances m=2,3,4 x a=0.5,0.9, circular orbit r0=8M, 16001 x 129 on [-300,300]M, dt=1/500, "
+                    "waveform at r*=290M projected on the l=max(|m|,2) harmonic",
+        "window_M": steps * dt, "steps": steps, "points": points,
+        "fp64_updates_per_s": forms["fp64"]["updates_per_s"], "fp32c_updates_per_s": forms["fp32c"]["updates_per_s"],
+        "fp32c_speedup": forms["fp32c"]["updates_per_s"] / forms["fp64"]["updates_per_s"],
+        "tuning": {k: forms[k]["tuning"] for k in forms},
+        "worst_by_window": {f"T{T}": {"amp": v[0], "phase": v[1]} for T, v in worst.items()},
+        "per_instance": per_inst,
+        "oracle_prefix": {"instance": inst["name"], "steps": args.study_oracle_steps,
+                          "joint_rel_l2_vs_oracle": pref},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,6 +231,11 @@ def main():
     ap.add_argument("--waves", type=int, default=None, choices=[0, 3, 4],
                     help="occupancy target of the fused kernels (default: the library's choice)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision-study", action="store_true",
+                    help="instead of the throughput line, run the FP32-compensated vs FP64 waveform study")
+    ap.add_argument("--study-window", type=float, default=600.0, help="precision study: simulated time (M)")
+    ap.add_argument("--study-checkpoints", type=float, nargs="+", default=[300.0, 400.0, 500.0, 600.0])
+    ap.add_argument("--study-oracle-steps", type=int, default=2000)
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="instead of the stepper, run a plain device copy of this many GiB "
                          "(calibrates the HBM byte counters)")
@@ -131,6 +245,9 @@ def main():
               f"multi-GPU sharding is a design, not part of this build", file=sys.stderr)
         sys.exit(2)
 
+    if args.precision_study:
+        precision_study(args)
+        return
     import torch
     from paper_1206_0270_amd import tk
     from paper_1206_0270_amd import workloads as W

@@ -155,6 +155,7 @@ class Stepper:
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         self.instances = list(instances)
         self.n_inst = len(self.instances)
+        self.wave_capacity = wave_capacity if wave_capacity > 0 else 4096  # the library's default
         descs = (InstanceDesc * self.n_inst)(*[make_desc(i, force_dt, wave_capacity)
                                                for i in self.instances])
         with torch.cuda.device(self.device):
@@ -211,7 +212,7 @@ class Stepper:
     def extract(self, k, max_samples=1 << 20):
         nth = self.instances[k]["n_theta"]
         n = ctypes.c_long()
-        cap = int(max_samples)
+        cap = min(int(max_samples), self.wave_capacity)  # more than the ring holds is an overrun
         out = np.zeros((max(cap, 1), nth), np.complex128)
         st = self.lib.tk_extract(self.ctx, k, out.view(np.float64).ctypes.data_as(_dp), cap,
                                  ctypes.byref(n))
