@@ -171,6 +171,7 @@ template <int PD, bool NT, int W>
 struct PolicyF64 {
     using T = double;
     static constexpr bool kComp = false;
+    static constexpr bool kRadRegs = true;  // radial factors in registers (else LDS)
     static constexpr int kPD = PD;
     static constexpr bool kNT = NT;
     static constexpr int kWaves = W;
@@ -179,6 +180,7 @@ template <int PD, bool NT, int W>
 struct PolicyF32C {
     using T = float;
     static constexpr bool kComp = true;
+    static constexpr bool kRadRegs = false;
     static constexpr int kPD = PD;
     static constexpr bool kNT = NT;
     static constexpr int kWaves = W;
@@ -255,6 +257,7 @@ struct Lane {
     const void *u, *uc;  // u^n values (and bf16 terms)
     void *un, *unc;      // u^{n+1}
     T *rad;              // this lane's radial factors in LDS: [2 nodes][kRadF/2 pairs] with a stride of 64 pairs
+    RadF<T> rf[2];       // or in registers (half node, node)
     int c, p, nt;
     bool cin, hv, icol;
     bool ov;              // this lane's column is one the work item writes
@@ -289,6 +292,7 @@ template <class P>
 __device__ __forceinline__ RadF<typename P::T> radf_of(const Lane<P> &L, int k)
 {
     using T = typename P::T;
+    if constexpr (P::kRadRegs) return L.rf[k];
     typedef T T2 __attribute__((ext_vector_type(2)));
     const T2 *b = (const T2 *)L.rad + k * (kRadF / 2) * 64;
     const T2 v0 = b[0], v1 = b[64], v2 = b[128], v3 = b[192], v4 = b[256];
@@ -570,7 +574,7 @@ __device__ __forceinline__ void south(const Lane<P> &L, const Level &lv, Roll<P>
 }
 
 // Two time levels in one pass.  Level 1 is the march above without stores;
-// level 2 runs two rows behind it on the u^{n+1} rows level 1 leaves in
+// level 2 runs three rows behind it on the u^{n+1} rows level 1 leaves in
 // registers and writes u^{n+2}.  Slots are (row - 1) mod 3 for every ring.
 template <class P>
 struct Roll2 {
@@ -582,11 +586,8 @@ struct Roll2 {
     St<T> keep;          // a u^{n+2} row kept for a pole
 };
 
-// Iteration r (1 <= r <= nt+1, slot S = (r - 1) mod 3): level 1 takes u^n
-// row r+1 and forms half row r and u^{n+1} row r-1; level 2 forms half row
-// r-2 of the next step and u^{n+2} row r-3.  The pole rows of both levels
-// come from the rows next to them as in the one-step march.  With EDGE
-// false (rows 7 .. nt-2) the pole and end bookkeeping is compiled out.
+// Componentwise choice between two rows (a select of whole structs would
+// keep them in memory).
 template <typename T>
 __device__ __forceinline__ Q4<T> pick(bool c, const Q4<T> &a, const Q4<T> &b)
 {
@@ -598,20 +599,23 @@ __device__ __forceinline__ St<T> pick(bool c, const St<T> &a, const St<T> &b)
     return St<T>{pick(c, a.f, b.f), pick(c, a.c, b.c)};
 }
 
-// Iteration r (1 <= r <= nt+1, slot S = (r - 1) mod 3): level 1 takes u^n
-// row r+1 and forms half row r and u^{n+1} row r-1; level 2 forms half row
-// r-2 of the next step and u^{n+2} row r-3.  The pole rows of both levels
-// come from the rows next to them as in the one-step march.  With EDGE
-// false (rows 7 .. nt-2) the pole and end bookkeeping is compiled out.
-// Each ring slot is written from one place only, the rows that feed a pole
-// being picked by value: two pole updates of different slots under
+// Iteration r (1 <= r <= nt+2, slot S = (r - 1) mod 3).  Level 1 takes
+// u^n row r+1 and forms half row r and u^{n+1} row r-1.  Level 2, three rows
+// behind, forms half row r-3 of the next step and u^{n+2} row r-4 from
+// u^{n+1} rows made in earlier iterations only, so the two levels are
+// independent inside an iteration (the new u^{n+1} row enters the ring at
+// its end, into the slot level 2 has just finished with).  The pole rows of
+// both levels come from the rows next to them as in the one-step march.
+// With EDGE false (rows 7 .. nt-2) the pole and end bookkeeping is compiled
+// out.  Each ring slot is written from one place only, the rows that feed a
+// pole being picked by value: two pole updates of different slots under
 // different conditions would otherwise be merged by the compiler into one
 // store through a selected address, which keeps the rings in memory.
 template <class P, int S, bool EDGE>
 __device__ __forceinline__ void march2(const Lane<P> &L, const Level &l1, const Level &l2, Roll2<P> &R, int r)
 {
     constexpr int SM = (S + 2) % 3;  // rows r-1 and r-4
-    constexpr int SP = (S + 1) % 3;  // rows r+1 and r-2
+    constexpr int SP = (S + 1) % 3;  // rows r+1 and r-2 (and r-5)
     const int nt = L.nt;
     const bool even = L.I->m_even;
     // level 1: half rows r-2 (SP), r-1 (SM), r (S); u^n rows r-1 (SM), r (S), r+1 (SP)
@@ -622,25 +626,21 @@ __device__ __forceinline__ void march2(const Lane<P> &L, const Level &l1, const 
         R.H[S] = pole_half(even, R.H[SM], R.H[SP]);
     }
     if (EDGE && r == 2) R.H[SP] = pole_half(even, R.H[SM], R.H[S]);  // half row 0 from 1 (SM), 2 (S)
-    if (!EDGE || (r >= 2 && r <= nt - 1)) {  // u^{n+1} row r-1 -> V slot SM
-        R.V[SM] = out_row(L, l1, R.U[SM], R.H[SP], R.H[SM], R.H[S], r - 1);
-        sample(L, l1, r - 1, R.V[SM]);
+    const bool v_new = !EDGE || (r >= 2 && r <= nt - 1);              // u^{n+1} row r-1 this iteration
+    St<typename P::T> vn;
+    if (v_new) {
+        vn = out_row(L, l1, R.U[SM], R.H[SP], R.H[SM], R.H[S], r - 1);
+        sample(L, l1, r - 1, vn);
     }
-    if (EDGE && r == 3) {  // u^{n+1} row 0 (slot S) from rows 1 (SP) and 2 (SM)
-        R.V[S] = pole_row<P>(even, R.V[SP], R.V[SM]);
-        sample(L, l1, 0, R.V[S]);
-    }
-    // level 2: u^{n+1} rows r-3 (S), r-2 (SP), r-1 (SM); its half rows r-4 (SM), r-3 (S), r-2 (SP)
-    if (!EDGE || r >= 3) {
-        if (!EDGE || r <= nt)
-            R.G[SP] = half_row(L, l2, R.V[S].f, R.V[SP].f, R.V[SM].f, r - 2);
-        else  // r = nt+1: half row nt-1 from nt-2 (S), nt-3 (SM)
-            R.G[SP] = pole_half(even, R.G[S], R.G[SM]);
-    }
-    if (EDGE && r == 4) R.G[SM] = pole_half(even, R.G[S], R.G[SP]);  // half row 0 from 1 (S), 2 (SP)
-    if (!EDGE || (r >= 4 && r <= nt + 1)) {  // u^{n+2} row o = r-3
-        const int o = r - 3;
-        const St<typename P::T> v = out_row(L, l2, R.V[S], R.G[SM], R.G[S], R.G[SP], o);
+    // level 2: u^{n+1} rows r-4 (SM), r-3 (S), r-2 (SP); its half rows r-5 (SP), r-4 (SM), r-3 (S)
+    if (!EDGE || (r >= 4 && r <= nt + 1))
+        R.G[S] = half_row(L, l2, R.V[SM].f, R.V[S].f, R.V[SP].f, r - 3);
+    else if (r == nt + 2)  // half row nt-1 from nt-2 (SM), nt-3 (SP)
+        R.G[S] = pole_half(even, R.G[SM], R.G[SP]);
+    if (EDGE && r == 5) R.G[SP] = pole_half(even, R.G[SM], R.G[S]);  // half row 0 from 1 (SM), 2 (S)
+    if (!EDGE || (r >= 5 && r <= nt + 2)) {                          // u^{n+2} row o = r-4
+        const int o = r - 4;
+        const St<typename P::T> v = out_row(L, l2, R.V[SM], R.G[SP], R.G[SM], R.G[S], o);
         emit(L, l2, o, v);
         if (EDGE) {
             const bool pn = o == 2, ps = o == nt - 2;  // row 0 from rows 1, 2; row nt-1 from nt-2, nt-3
@@ -648,9 +648,15 @@ __device__ __forceinline__ void march2(const Lane<P> &L, const Level &l1, const 
             if (o == 1 || o == nt - 3) R.keep = v;
         }
     }
-    if (EDGE && r == nt - 1) {  // u^{n+1} row nt-1 from nt-2 (SM), nt-3 (SP), into the slot level 2 is done with
-        R.V[S] = pole_row<P>(even, R.V[SM], R.V[SP]);
-        sample(L, l1, nt - 1, R.V[S]);
+    // the new u^{n+1} rows enter the ring where level 2 is done
+    if (v_new) R.V[SM] = vn;  // row r-1 replaces row r-4
+    if (EDGE && r == 3) {     // row 0 (slot S) from rows 1 (SP) and 2 (SM)
+        R.V[S] = pole_row<P>(even, R.V[SP], R.V[SM]);
+        sample(L, l1, 0, R.V[S]);
+    }
+    if (EDGE && r == nt) {  // row nt-1 (slot SM, row nt-4 no longer needed) from nt-2 (SP) and nt-3 (S)
+        R.V[SM] = pole_row<P>(even, R.V[SP], R.V[S]);
+        sample(L, l1, nt - 1, R.V[SM]);
     }
 }
 
@@ -687,6 +693,11 @@ __device__ __forceinline__ void init_lane(Lane<P> &L, const DevInst &I, const Wo
         const double v[kRadF] = {R.rho2, R.rho * I.inv_h,   R.ct_re,           R.ct_im0,
                                  R.K,    R.c1_re * I.inv_h, R.c1_im * I.inv_h, 0.5 * R.Dl * I.inv_dth2,
                                  R.c0_re, R.c0_im};
+        if constexpr (P::kRadRegs) {
+            L.rf[k] = RadF<T>{(T)v[0], (T)v[1], (T)v[2], (T)v[3], (T)v[4],
+                              (T)v[5], (T)v[6], (T)v[7], (T)v[8], (T)v[9]};
+            continue;
+        }
 #pragma unroll
         for (int p = 0; p < kRadF / 2; ++p) {
             T2 x;
@@ -712,7 +723,7 @@ __global__ void __launch_bounds__(64 * kFusedWavesPerBlock) __attribute__((amdgp
             const DevCtl *__restrict__ ctl, int kstep, int kflip)
 {
     using T = typename P::T;
-    __shared__ T s_rad[kFusedWavesPerBlock][2 * kRadF * 64];
+    __shared__ T s_rad[kFusedWavesPerBlock][P::kRadRegs ? 2 : 2 * kRadF * 64];
     const int lane = (int)(threadIdx.x & 63);
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int w = (int)blockIdx.x * kFusedWavesPerBlock + wv;
@@ -770,7 +781,7 @@ __global__ void __launch_bounds__(64 * kFusedWavesPerBlock) __attribute__((amdgp
              const DevCtl *__restrict__ ctl, int kstep, int kflip)
 {
     using T = typename P::T;
-    __shared__ T s_rad[kFusedWavesPerBlock][2 * kRadF * 64];
+    __shared__ T s_rad[kFusedWavesPerBlock][P::kRadRegs ? 2 : 2 * kRadF * 64];
     const int lane = (int)(threadIdx.x & 63);
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int w = (int)blockIdx.x * kFusedWavesPerBlock + wv;
@@ -798,12 +809,13 @@ __global__ void __launch_bounds__(64 * kFusedWavesPerBlock) __attribute__((amdgp
         march2<P, 1, false>(L, l1, l2, R, r + 1);
         march2<P, 2, false>(L, l1, l2, R, r + 2);
     }
-    // tail: iterations r .. nt+1 (at most five)
-    if (r <= nt + 1) march2<P, 0, true>(L, l1, l2, R, r);
-    if (r + 1 <= nt + 1) march2<P, 1, true>(L, l1, l2, R, r + 1);
-    if (r + 2 <= nt + 1) march2<P, 2, true>(L, l1, l2, R, r + 2);
-    if (r + 3 <= nt + 1) march2<P, 0, true>(L, l1, l2, R, r + 3);
-    if (r + 4 <= nt + 1) march2<P, 1, true>(L, l1, l2, R, r + 4);
+    // tail: iterations r .. nt+2 (at most six)
+    if (r <= nt + 2) march2<P, 0, true>(L, l1, l2, R, r);
+    if (r + 1 <= nt + 2) march2<P, 1, true>(L, l1, l2, R, r + 1);
+    if (r + 2 <= nt + 2) march2<P, 2, true>(L, l1, l2, R, r + 2);
+    if (r + 3 <= nt + 2) march2<P, 0, true>(L, l1, l2, R, r + 3);
+    if (r + 4 <= nt + 2) march2<P, 1, true>(L, l1, l2, R, r + 4);
+    if (r + 5 <= nt + 2) march2<P, 2, true>(L, l1, l2, R, r + 5);
 }
 
 template <class P>
