@@ -124,7 +124,7 @@ typedef struct {
     int prefetch_rows; /* fused kernel: u^n rows in flight per wave, 1 or 3 (0 = 3) */
     int flags;         /* TK_TUNE_* */
     int waves_per_simd;/* fused kernel: register budget for 3 or 4 waves per SIMD
-                          (0 = the compiler's choice; the FP32 default is 3);
+                          (0 = the compiler's choice, the default);
                           compiled combinations: prefetch 3 with non-temporal
                           stores at 0/3/4, and prefetch 1 or 3 at 0; others
                           give TK_E_INVALID */

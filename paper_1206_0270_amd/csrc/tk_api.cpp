@@ -343,8 +343,6 @@ tk_status tk_init_grid(const tk_instance_desc *inst, int n_inst, tk_precision pr
     tk_ctx *c = new (std::nothrow) tk_ctx();
     if (!c) return fail(nullptr, TK_E_NOMEM, "host allocation failed");
     c->prec = prec;
-    // FP32: the two-step kernel fits three waves per SIMD
-    c->tuning.waves_per_simd = prec == TK_FP32_COMP ? 3 : 0;
     c->stream = (hipStream_t)hip_stream;
     c->inst.resize(n_inst);
     for (int k = 0; k < n_inst; ++k) {

@@ -191,25 +191,70 @@ struct St {  // stored value of a point: f (+ c in the compensated form)
     Q4<T> f, c;
 };
 
-template <typename T>
+// Neighbour-column exchange inside the wave by DPP wave shifts (a vector
+// move, no LDS round trip): shfl_down1 gives lane l the value of lane l+1,
+// shfl_up1 that of lane l-1; the lane at the open end gets 0 (it is a halo
+// lane whose result is never stored).
+__device__ __forceinline__ float dpp_down1(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x130, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float dpp_up1(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x138, 0xf, 0xf, true));
+}
+__device__ __forceinline__ double dpp_down1(double v)
+{
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, 0x130, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), 0x130, 0xf, 0xf, true);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double dpp_up1(double v)
+{
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, 0x138, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), 0x138, 0xf, 0xf, true);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+// The exchange a launch shape uses: DPP, except in the shapes compiled for a
+// forced occupancy (kWaves > 1), which spill registers.  There the LDS
+// permute is kept: with DPP the four-wave FP64 shape produced non-finite
+// values on sourced instances (a DPP move reads the registers of every lane,
+// and spill reloads under a partial EXEC mask can leave other lanes stale).
+template <class P, typename T>
+__device__ __forceinline__ T down1(T v)
+{
+    if constexpr (P::kWaves > 1) return __shfl_down(v, 1);
+    else return dpp_down1(v);
+}
+template <class P, typename T>
+__device__ __forceinline__ T up1(T v)
+{
+    if constexpr (P::kWaves > 1) return __shfl_up(v, 1);
+    else return dpp_up1(v);
+}
+
+template <class P, typename T>
 __device__ __forceinline__ cx<T> shfl_down1(cx<T> v)
 {
-    return mkc<T>(__shfl_down(v.re, 1), __shfl_down(v.im, 1));
+    return mkc<T>(down1<P>(v.re), down1<P>(v.im));
 }
-template <typename T>
+template <class P, typename T>
 __device__ __forceinline__ cx<T> shfl_up1(cx<T> v)
 {
-    return mkc<T>(__shfl_up(v.re, 1), __shfl_up(v.im, 1));
+    return mkc<T>(up1<P>(v.re), up1<P>(v.im));
 }
-template <typename T>
+template <class P, typename T>
 __device__ __forceinline__ Q4<T> shfl_down1(const Q4<T> &v)
 {
-    return Q4<T>{shfl_down1(v.phi), shfl_down1(v.pi)};
+    return Q4<T>{shfl_down1<P>(v.phi), shfl_down1<P>(v.pi)};
 }
-template <typename T>
+template <class P, typename T>
 __device__ __forceinline__ Q4<T> shfl_up1(const Q4<T> &v)
 {
-    return Q4<T>{shfl_up1(v.phi), shfl_up1(v.pi)};
+    return Q4<T>{shfl_up1<P>(v.phi), shfl_up1<P>(v.pi)};
 }
 
 // A wave-uniform value computed on the vector unit, moved to scalar registers.
@@ -403,8 +448,8 @@ __device__ __forceinline__ Q4<typename P::T> half_row(const Lane<P> &L, const Le
 {
     using T = typename P::T;
     const DevInst &I = *L.I;
-    const cx<T> nm = shfl_down1(UM.phi), np = shfl_down1(UP.phi);
-    const Q4<T> n0 = shfl_down1(U0);
+    const cx<T> nm = shfl_down1<P>(UM.phi), np = shfl_down1<P>(UP.phi);
+    const Q4<T> n0 = shfl_down1<P>(U0);
     if (!L.hv) return zero_q4<T>();
     const Q4<T> du = n0 - U0;
     const Q4<T> bar = mid_from(U0, du);
@@ -446,8 +491,8 @@ __device__ __forceinline__ St<typename P::T> out_row(const Lane<P> &L, const Lev
 {
     using T = typename P::T;
     const DevInst &I = *L.I;
-    const cx<T> lm = shfl_up1(HM.phi), lp = shfl_up1(HP.phi);
-    const Q4<T> l0 = shfl_up1(H0);
+    const cx<T> lm = shfl_up1<P>(HM.phi), lp = shfl_up1<P>(HP.phi);
+    const Q4<T> l0 = shfl_up1<P>(H0);
     St<T> res;
     res.f = zero_q4<T>();
     res.c = zero_q4<T>();
