@@ -66,8 +66,9 @@ enum {
 };
 
 /* One instance = one (a, s, m) mode on one grid.
- * Eqs. (2)-(4); the boundary conditions follow from the parity of |m|
- * (Section 2.2). */
+ * Eqs. (2)-(4); the pole conditions (Section 2.2) follow from the parity of
+ * m + s (a spin-weighted mode behaves like sin^{|m+s|} there; for the
+ * paper's s = -2 this is the parity of |m|). */
 typedef struct {
     double M, a;
     int s, m;

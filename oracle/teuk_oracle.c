@@ -33,9 +33,12 @@
  *  - S at half points/times is S evaluated on the averaged fields with the
  *    exact coefficients at the half node; the source is taken at t^n in the
  *    first step and at t^n + dt/2 in the second.
- *  - Pole conditions of Section 2.2: for even |m| d_theta X = 0 is imposed
- *    to second order, X_0 = (4X_1 - X_2)/3 (same at theta = pi); for odd |m|
- *    X = 0.  Applied to Phi and Pi on the half-step array and on u^{n+1}.
+ *  - Pole conditions of Section 2.2: where m + s is even (for the s = -2
+ *    field of the paper: even |m|) d_theta X = 0 is imposed to second order,
+ *    X_0 = (4X_1 - X_2)/3 (same at theta = pi); where m + s is odd, X = 0.
+ *    A spin-weighted mode behaves like sin^{|m+s|} at the poles, so the
+ *    parity of m + s decides.  Applied to Phi and Pi on the half-step array
+ *    and on u^{n+1}.
  *  - The point particle is the smeared Gaussian of Section 2.3 item 1:
  *    F = A exp(-i m (Omega t + phi0)) g_r(r* - r*_p) g_theta(theta - pi/2),
  *    g(xi) = exp(-xi^2 / (2 sigma^2)) / (sigma sqrt(2 pi)) for
@@ -297,12 +300,12 @@ static cplx S_pi(const or_grid *g, int q, int j, cplx phim, cplx phi0, cplx phip
     return g->ct[c] * pi0 + g->cthth[c] * d2 + g->cth[c] * d1 + g->c0[c] * phi0 + F;
 }
 
-/* Pole value from the two next interior rows (Section 2.2): for even |m|
- * d_theta X = 0 to second order, X_pole = (4 X_1 - X_2) / 3; for odd |m|
+/* Pole value from the two next interior rows (Section 2.2): for even m + s
+ * d_theta X = 0 to second order, X_pole = (4 X_1 - X_2) / 3; for odd m + s
  * X_pole = 0.  Used by the stepper and by or_rhs_column alike. */
 static cplx pole_value(const or_grid *g, cplx x1, cplx x2)
 {
-    if (abs(g->desc.m) % 2 == 0)
+    if (abs(g->desc.m + g->desc.s) % 2 == 0)
         return (4 * x1 - x2) / 3;
     return 0;
 }

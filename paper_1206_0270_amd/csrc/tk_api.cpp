@@ -176,7 +176,7 @@ DevInst make_dev(const tk_ctx *c, const HostInst &h)
     D.n_r = d.n_r;
     D.n_theta = d.n_theta;
     D.pitch = h.pitch;
-    D.m_even = (std::abs(d.m) % 2) == 0;
+    D.m_even = (std::abs(d.m + d.s) % 2) == 0;  // pole rule: parity of m + s
     D.m = d.m;
     D.i_obs = h.i_obs;
     D.extract_every = d.extract_every;

@@ -54,7 +54,7 @@ struct alignas(16) AngularF {
 // One instance as the kernels see it (device memory, read-only in kernels).
 struct alignas(16) DevInst {
     // grid
-    int n_r, n_theta, pitch, m_even;
+    int n_r, n_theta, pitch, m_even;  // m_even: m + s even (Neumann poles), else zero poles
     int m, i_obs, extract_every, wave_cap;
     double h, dth, dt, inv_h;
     double inv_dth2, inv_2dth, rstar_min, pad0;

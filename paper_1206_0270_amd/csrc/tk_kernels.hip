@@ -407,7 +407,7 @@ __device__ __forceinline__ void emit(const Lane<P> &L, const Level &lv, int row,
 }
 
 // Pole rows (Section 2.2): (4 X1 - X2) / 3 from the two rows next to the
-// pole for even |m|, zero for odd |m|.  The parity is selected per component
+// pole for even m + s, zero for odd m + s.  The parity is selected per component
 // (a select between whole structs would keep them in memory).
 template <typename T>
 __device__ __forceinline__ Q4<T> pole_half(bool even, const Q4<T> &x1, const Q4<T> &x2)

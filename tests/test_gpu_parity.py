@@ -89,18 +89,24 @@ def gpu_run(insts, steps, kernel=tk.TK_KERNEL_AUTO, rows=0, graph=0, inits=None,
 
 
 def small_instances():
+    # ragged sizes (none a multiple of a strip width), 5 to 33 rows, a from 0
+    # to 0.99, even and odd m + s (both pole rules), m = 0, spin weights
+    # -2, -1, +1, +2, with and without a source
     rng = W.rng_for(99)
     out = []
-    for (n_r, n_th, a, m, src) in [(101, 9, 0.0, 2, None), (130, 17, 0.9, 2, "s"),
-                                   (77, 11, 0.6, 3, None), (200, 13, 0.3, -1, "s"),
-                                   (63, 5, 0.99, 8, None), (125, 33, 0.5, 4, "s")]:
+    for (n_r, n_th, a, m, src, s) in [(101, 9, 0.0, 2, None, -2), (130, 17, 0.9, 2, "s", -2),
+                                      (77, 11, 0.6, 3, None, -2), (200, 13, 0.3, -1, "s", -2),
+                                      (63, 5, 0.99, 8, None, -2), (125, 33, 0.5, 4, "s", -2),
+                                      (96, 7, 0.5, 0, None, -2), (70, 9, 0.8, 1, "s", -1),
+                                      (88, 11, 0.3, 2, None, 2), (75, 13, 0.6, -2, None, 1)]:
         init = None if src else dict(center=2.0, width=3.0,
-                                     amps={max(abs(m), 2): complex(rng.standard_normal(), rng.standard_normal())})
+                                     amps={max(abs(m), abs(s), 2): complex(rng.standard_normal(),
+                                                                            rng.standard_normal())})
         source = dict(r0=6.0 + 3 * rng.uniform(), phase0=float(rng.uniform(0, 6.28)),
                       sigma_r_cells=2.0, sigma_th_cells=2.0, window_sigmas=6.0) if src else None
-        out.append(W.instance(a=a, m=m, n_r=n_r, n_theta=n_th, rstar_min=-20.0, rstar_max=25.0,
+        out.append(W.instance(a=a, s=s, m=m, n_r=n_r, n_theta=n_th, rstar_min=-20.0, rstar_max=25.0,
                               rstar_obs=20.0, extract_every=3, init=init, source=source,
-                              name=f"small.{n_r}x{n_th}.a{a}.m{m}"))
+                              name=f"small.{n_r}x{n_th}.a{a}.m{m}.s{s}"))
     return out
 
 
@@ -139,6 +145,20 @@ def test_third_workload_sourced_prefix():
     ref = oracle_run(inst, steps)
     assert np.linalg.norm(ref[0]) > 0
     check_parity(inst, steps, got, ref)
+
+
+def test_fifth_workload_prefix():
+    # 16001 x 129, sourced, at the size and launch shape of the precision study
+    inst = W.config5()["instances"][0]
+    steps = 200
+    say("fifth workload 16001x129 sourced, steps", steps)
+    got, = gpu_run([inst], steps, graph=100)
+    ref = oracle_run(inst, steps)
+    check_parity(inst, steps, got, ref)
+    c, = gpu_run([inst], steps, graph=100, precision=tk.TK_FP32_COMP)
+    e = joint_rel(c[0], c[1], ref[0], ref[1])
+    say("  FP32C joint rel L2 vs oracle", f"{e:.2e}")
+    assert e < 1e-5
 
 
 def test_batched_uneven_workload_vs_oracle():

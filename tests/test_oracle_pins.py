@@ -284,7 +284,7 @@ def test_thread_count_bitwise():
 
 def _theta_profile(s, m):
     th = sp.Symbol("th")
-    if abs(m) % 2 == 0:
+    if abs(m + s) % 2 == 0:  # regular at the poles with zero slope, else zero there
         expr = (1 + sp.cos(th)) ** 2 * (1 + sp.Rational(3, 10) * sp.cos(th)
                                         + sp.Rational(1, 5) * sp.I * sp.cos(th) ** 2)
     else:
@@ -350,7 +350,7 @@ def _mms_error(M, a, s, m, n_r, n_th, steps, T, kind="f64"):
     return np.max(np.abs(phi - exact)) / np.max(np.abs(exact))
 
 
-def mms_check(a, m, kind="f64", levels=((201, 17), (401, 33), (801, 65))):
+def mms_check(a, m, kind="f64", levels=((201, 17), (401, 33), (801, 65)), s=-2):
     # h, dtheta and dt halved together; Eqs. (3)-(4) are second order, so the
     # error must drop by ~4 per level (the even-m pole extrapolation is still
     # pre-asymptotic at 9 theta points, hence the levels start at 17).
@@ -358,7 +358,7 @@ def mms_check(a, m, kind="f64", levels=((201, 17), (401, 33), (801, 65))):
     errs = []
     for k, (n_r, n_th) in enumerate(levels):
         steps = 64 * (n_r - 1) // 200
-        errs.append(_mms_error(1.0, a, -2, m, n_r, n_th, steps, T, kind=kind))
+        errs.append(_mms_error(1.0, a, s, m, n_r, n_th, steps, T, kind=kind))
     ratios = [errs[i] / errs[i + 1] for i in range(len(errs) - 1)]
     assert errs[-1] < 0.05 * (201.0 / levels[-1][0]) ** 2, errs
     if len(ratios) > 1:
@@ -369,6 +369,12 @@ def mms_check(a, m, kind="f64", levels=((201, 17), (401, 33), (801, 65))):
 @pytest.mark.parametrize("a,m", [(0.9, 2), (0.6, 3), (0.3, -1), (0.0, 2)])
 def test_mms_second_order(a, m):
     mms_check(a, m)
+
+
+@pytest.mark.parametrize("a,m,s", [(0.7, 1, -1), (0.5, 0, 0), (0.8, 2, 2), (0.4, -2, 1)])
+def test_mms_second_order_other_spin_weights(a, m, s):
+    # the pole rule follows the parity of m + s (odd for the first and last)
+    mms_check(a, m, s=s)
 
 
 # ---------------------------------------------------------------------------
