@@ -211,6 +211,83 @@ def precision_study(args):
     print(json.dumps(out), flush=True)
 
 
+def richardson_study(args):
+    """Section 2.3 item 3 / Section 5.1 footnote on the GPU: one sourced Kerr
+    mode at three resolutions (grid spacings and time step halved), the
+    projected waveforms extrapolated by the library, and the error estimate
+    from the two extrapolants over the window in which only outgoing
+    radiation reaches the observer.  One JSON line."""
+    import numpy as np
+    import torch
+    from paper_1206_0270_amd import tk
+    from paper_1206_0270_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    n_r = int(round(300.0 / args.rich_h)) + 1
+    base = W.instance(a=0.9, m=2, n_r=n_r, n_theta=args.rich_nth, rstar_min=-60.0, rstar_max=240.0,
+                      rstar_obs=180.0, name="kerr a=0.9 m=2 sourced",
+                      source=dict(r0=10.0, phase0=0.7, sigma_r_cells=args.rich_sigma_r / args.rich_h,
+                                  sigma_th_cells=args.rich_sigma_th))
+    fam = W.richardson_family(base)
+    T = args.rich_window
+    waves, runs = [], []
+    total_upd, total_s = 0, 0.0
+    for inst in fam:
+        steps = int(round(T / inst["dt"]))
+        steps -= steps % 2
+        st = tk.Stepper([inst], wave_capacity=int(T) + 64)
+        st.set_fields(0, *W.initial_data(inst))
+        st.autotune(warmup=2, steps=6)
+        t = st.get_tuning()
+        t["graph_steps"] = 100
+        st.set_tuning(**t)
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(st.stream)
+        st.step(steps)
+        ev1.record(st.stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1)
+        waves.append(projected_waveform(inst, st.extract(0, max_samples=int(T) + 64)))
+        st.close()
+        upd = inst["n_r"] * inst["n_theta"] * steps
+        total_upd += upd
+        total_s += ms / 1e3
+        runs.append(dict(n_r=inst["n_r"], n_theta=inst["n_theta"], dt=inst["dt"], steps=steps,
+                         updates_per_s=upd / (ms / 1e3), kernel=t["kernel"], rows_per_tile=t["rows_per_tile"]))
+    n = min(len(w) for w in waves)
+    ext, est = tk.richardson(*[w[:n] for w in waves])
+    dt_s = fam[0]["extract_every"] * fam[0]["dt"]
+    times = (np.arange(n) + 1) * dt_s
+    # outgoing-only window at the observer: from the arrival of the direct
+    # signal to the return of its reflection from the outer boundary
+    r_obs, r_b, r_src = base["rstar_obs"], base["rstar_max"], 10.0
+    t0, t1 = r_obs - r_src, 2 * r_b - r_obs - r_src
+    win = (times >= t0) & (times <= t1) & (np.abs(ext) >= 1e-3 * np.abs(ext).max())
+    r12 = (4 * waves[1][:n] - waves[0][:n]) / 3  # the coarse pair's extrapolant
+    out = {
+        "metric": "Richardson-extrapolated waveform: error estimate from two extrapolants (Section 5.1)",
+        "workload": f"Kerr a=0.9, s=-2, m=2, circular orbit r0=10M (source widths {args.rich_sigma_r} M in r*, "
+                    f"{args.rich_sigma_th} coarse theta cells); "
+                    f"r* in [-60,240]M, observer 180M; coarse h = {args.rich_h} M, {args.rich_nth} theta rows; "
+                    f"three levels halving h, dtheta and dt",
+        "window_M": [t0, t1],
+        "levels": runs,
+        "gpu_updates_per_s_all_levels": total_upd / total_s,
+        "estimate_max_in_window": float(np.max(est[win])),
+        "estimate_median_in_window": float(np.median(est[win])),
+        "amplitude_estimate_max": float(np.max(np.abs(np.abs(ext[win]) - np.abs(r12[win])) / np.abs(ext[win]))),
+        "phase_estimate_max": float(np.max(np.abs(np.angle(ext[win] / r12[win])))),
+        "finest_vs_extrapolated_max": float(np.max(np.abs(waves[2][:n][win] - ext[win]) / np.abs(ext[win]))),
+        # self-convergence factor |w1 - w2| / |w2 - w3|: 4 for a second-order result
+        "convergence_factor_median": float(np.median(np.abs(waves[0][:n][win] - waves[1][:n][win]) /
+                                                     np.abs(waves[1][:n][win] - waves[2][:n][win]))),
+        "samples_in_window": int(win.sum()),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -236,6 +313,13 @@ def main():
     ap.add_argument("--study-window", type=float, default=600.0, help="precision study: simulated time (M)")
     ap.add_argument("--study-checkpoints", type=float, nargs="+", default=[300.0, 400.0, 500.0, 600.0])
     ap.add_argument("--study-oracle-steps", type=int, default=2000)
+    ap.add_argument("--richardson", action="store_true",
+                    help="instead of the throughput line, run the three-resolution Richardson study")
+    ap.add_argument("--rich-window", type=float, default=330.0, help="Richardson study: simulated time (M)")
+    ap.add_argument("--rich-h", type=float, default=0.04, help="Richardson study: coarse r* spacing (M)")
+    ap.add_argument("--rich-nth", type=int, default=33, help="Richardson study: coarse theta rows")
+    ap.add_argument("--rich-sigma-r", type=float, default=0.5, help="Richardson study: source width in r* (M)")
+    ap.add_argument("--rich-sigma-th", type=float, default=4.0, help="Richardson study: source width, coarse theta cells")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="instead of the stepper, run a plain device copy of this many GiB "
                          "(calibrates the HBM byte counters)")
@@ -247,6 +331,9 @@ def main():
 
     if args.precision_study:
         precision_study(args)
+        return
+    if args.richardson:
+        richardson_study(args)
         return
     import torch
     from paper_1206_0270_amd import tk

@@ -213,6 +213,20 @@ const char *tk_last_error(const tk_ctx *ctx);
  * TK_E_UNSTABLE check). */
 tk_status tk_stable_dt(const tk_instance_desc *inst, double *dt_max);
 
+/* Richardson extrapolation of second-order results (Section 2.3, item 3)
+ * and its error estimate from two extrapolants (Section 5.1, footnote).
+ * w1, w2, w3: n complex values each ([k][re, im], host memory, caller-owned)
+ * of the same quantity computed with the grid spacings and time step scaled
+ * by 1, 1/2, 1/4 (for waveforms: the same sample times and observer).  With
+ * q = 2^order:
+ *   R12 = (q w2 - w1) / (q - 1),  R23 = (q w3 - w2) / (q - 1);
+ * extrap[k] = R23[k]; err[k] = |R23[k] - R12[k]| / |R23[k]| (the absolute
+ * difference where R23[k] = 0).  extrap and err may be NULL.  A host
+ * computation, O(n); TK_E_INVALID for n < 0, order < 1 or a NULL input, and
+ * TK_E_NONFINITE if an input value is not finite. */
+tk_status tk_richardson(const double *w1, const double *w2, const double *w3, long n, int order, double *extrap,
+                        double *err);
+
 int tk_abi_version(void);
 
 #ifdef __cplusplus

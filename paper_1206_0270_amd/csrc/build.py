@@ -16,7 +16,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 HIP_SOURCES = ["tk_kernels.hip"]
-HOST_SOURCES = ["tk_setup.cpp", "tk_api.cpp"]
+HOST_SOURCES = ["tk_setup.cpp", "tk_api.cpp", "tk_post.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wextra", "-Wno-unused-parameter",
           "-I" + os.path.join(ROOT, "include")]

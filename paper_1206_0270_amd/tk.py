@@ -25,7 +25,7 @@ _STATUS = {0: "TK_OK", 1: "TK_E_INVALID", 2: "TK_E_NOMEM", 3: "TK_E_DEVICE", 4: 
 EXPORTS = ["tk_abi_version", "tk_init_grid", "tk_workspace_bytes", "tk_bind_workspace",
            "tk_set_fields", "tk_get_fields", "tk_set_source", "tk_step", "tk_extract",
            "tk_get_step", "tk_set_step", "tk_set_tuning", "tk_get_tuning", "tk_autotune", "tk_synchronize",
-           "tk_destroy", "tk_last_error", "tk_stable_dt"]
+           "tk_destroy", "tk_last_error", "tk_stable_dt", "tk_richardson"]
 
 
 class TkError(RuntimeError):
@@ -92,6 +92,7 @@ def load():
         "tk_destroy": (st, [vp]),
         "tk_last_error": (ctypes.c_char_p, [vp]),
         "tk_stable_dt": (st, [ctypes.POINTER(InstanceDesc), _dp]),
+        "tk_richardson": (st, [_dp, _dp, _dp, ctypes.c_long, ctypes.c_int, _dp, _dp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -139,6 +140,22 @@ def stable_dt(inst):
     out = ctypes.c_double()
     _check(load().tk_stable_dt(ctypes.byref(make_desc(inst)), ctypes.byref(out)))
     return out.value
+
+
+def richardson(w1, w2, w3, order=2):
+    """Richardson extrapolant of three results at spacings 1, 1/2, 1/4 and
+    the error estimate from two extrapolants (tk_richardson).  Returns
+    (extrapolated array, relative error array), shaped like the inputs."""
+    arrs = [np.ascontiguousarray(w, dtype=np.complex128) for w in (w1, w2, w3)]
+    if not (arrs[0].shape == arrs[1].shape == arrs[2].shape):
+        raise ValueError("the three results must have one shape")
+    n = arrs[0].size
+    ext = np.zeros(arrs[0].shape, np.complex128)
+    err = np.zeros(arrs[0].shape, np.float64)
+    ptr = [a.view(np.float64).ctypes.data_as(_dp) for a in arrs]
+    _check(load().tk_richardson(ptr[0], ptr[1], ptr[2], n, int(order), ext.view(np.float64).ctypes.data_as(_dp),
+                                err.ctypes.data_as(_dp)))
+    return ext, err
 
 
 class Stepper:

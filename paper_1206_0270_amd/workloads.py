@@ -108,6 +108,46 @@ def instance(M=1.0, a=0.0, s=-2, m=2, n_r=801, n_theta=33, rstar_min=-100.0,
                 source=source, init=init, name=name)
 
 
+def refine(inst, k):
+    """The same physical problem with the grid spacings h, dtheta and the
+    time step divided by 2^k: n - 1 intervals become 2^k (n - 1), the waveform
+    is sampled at the same times, and the source keeps its physical widths
+    (its widths are given in cells).  Coarse nodes stay nodes of the refined
+    grid, so results compare at the coarse points."""
+    f = 2 ** k
+    out = dict(inst)
+    out["n_r"] = (inst["n_r"] - 1) * f + 1
+    out["n_theta"] = (inst["n_theta"] - 1) * f + 1
+    out["dt"] = inst["dt"] / f
+    out["extract_every"] = inst["extract_every"] * f
+    h = (inst["rstar_max"] - inst["rstar_min"]) / (out["n_r"] - 1)
+    out["i_obs"] = int(math.floor((inst["rstar_obs"] - inst["rstar_min"]) / h + 0.5))
+    if inst.get("source"):
+        src = dict(inst["source"])
+        src["sigma_r_cells"] = src.get("sigma_r_cells", 2.0) * f
+        src["sigma_th_cells"] = src.get("sigma_th_cells", 2.0) * f
+        out["source"] = src
+    out["name"] = f"{inst.get('name', '')}/r{f}"
+    return out
+
+
+def richardson_family(inst, levels=3):
+    """refine(inst, k) for k = 0 .. levels-1, with the base time step lowered
+    (if needed) so that every level satisfies its own step rule: the
+    angular part of the rule scales like dtheta^(4/3), faster than the
+    halving of dt.  The base step is 1/N M, so the halvings are exact."""
+    h = (inst["rstar_max"] - inst["rstar_min"]) / (inst["n_r"] - 1)
+    dt = inst["dt"]
+    for k in range(levels):
+        f = 2 ** k
+        dt = min(dt, f * stable_dt(inst["a"], inst["m"], inst["s"], h / f, (inst["n_theta"] - 1) * f + 1,
+                                   M=inst["M"]))
+    base = dict(inst)
+    base["dt"] = 1.0 / math.ceil(1.0 / dt - 1e-9)
+    base["extract_every"] = max(1, int(round(inst["extract_every"] * inst["dt"] / base["dt"])))
+    return [refine(base, k) for k in range(levels)]
+
+
 def initial_data(inst):
     """(phi, pi) complex arrays of shape (n_theta, n_r) for an instance.
 

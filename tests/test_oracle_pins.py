@@ -293,7 +293,7 @@ def _theta_profile(s, m):
     return fns
 
 
-def _mms_error(M, a, s, m, n_r, n_th, steps, T, kind="f64"):
+def _mms_error(M, a, s, m, n_r, n_th, steps, T, kind="f64", fields=False):
     rmin, rmax = -20.0, 30.0
     dt = T / steps
     g = oracle.Grid(M=M, a=a, s=s, m=m, n_r=n_r, n_theta=n_th, rstar_min=rmin,
@@ -347,6 +347,8 @@ def _mms_error(M, a, s, m, n_r, n_th, steps, T, kind="f64"):
     phi, _ = g.get_state()
     fT = fderivs(T, rs_q[node][None, :])[0]
     exact = Th[0][:, None] * fT
+    if fields:
+        return phi, exact
     return np.max(np.abs(phi - exact)) / np.max(np.abs(exact))
 
 
