@@ -288,6 +288,81 @@ def richardson_study(args):
     print(json.dumps(out), flush=True)
 
 
+def segments_study(args):
+    """Section 4's temporal decomposition on one GPU: one sourced mode run
+    for T in one context, against the same T split into segments that start
+    `overlap` earlier, advance together as one batch and are patched.  Time
+    to solution of both and the patched waveform against the long run after
+    the switch-on burst.  One JSON line."""
+    import numpy as np
+    import torch
+    from paper_1206_0270_amd import segments as SEG
+    from paper_1206_0270_amd import tk
+    from paper_1206_0270_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    inst = W.instance(a=0.9, m=2, n_r=8001, n_theta=33, rstar_min=-20.0, rstar_max=1980.0, rstar_obs=40.0,
+                      source=dict(r0=10.0, phase0=0.7), name="kerr a=0.9 m=2 r0=10")
+    T, n, ov = args.seg_total, args.seg_count, args.seg_overlap
+    segs, info = SEG.plan(inst, T, n, ov)
+    K, dt = inst["extract_every"], inst["dt"]
+
+    def timed(insts, steps):
+        st = tk.Stepper(insts, wave_capacity=steps // K + 64)
+        for k, i in enumerate(insts):
+            st.set_fields(k, *W.initial_data(i))
+        st.autotune(warmup=2, steps=6)
+        t = st.get_tuning()
+        t["graph_steps"] = 100
+        st.set_tuning(**t)
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(st.stream)
+        st.step(steps)
+        ev1.record(st.stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1)
+        eq = insts[0]["n_theta"] // 2
+        waves = [st.extract(k, max_samples=steps // K + 64)[:, eq] for k in range(len(insts))]
+        st.close()
+        return ms / 1e3, waves, t
+
+    n_total = n * info["samples_per_segment"]
+    t_long, (w_long,), tune_long = timed([inst], n_total * K)
+    t_seg, waves, tune_seg = timed(segs, info["steps"])
+    p = SEG.patch(waves, info)
+    n_L = info["samples_per_segment"]
+    # compare where the long run has settled too: intervals starting after
+    # one overlap (the long run switched its source on at t = 0)
+    k0 = int(np.ceil(info["overlap"] / info["L"] - 1e-9))
+    per_seg = [float(np.max(np.abs(p[k * n_L:(k + 1) * n_L] - w_long[k * n_L:(k + 1) * n_L])) /
+                     np.max(np.abs(w_long[k * n_L:(k + 1) * n_L]))) for k in range(k0, n)]
+    err = max(per_seg)
+    amp_long = [float(np.max(np.abs(w_long[k * n_L:(k + 1) * n_L]))) for k in range(n)]
+    amp_patch = [float(np.max(np.abs(p[k * n_L:(k + 1) * n_L]))) for k in range(n)]
+    pts = inst["n_r"] * inst["n_theta"]
+    out = {
+        "metric": "temporal segments (Section 4) on one GPU: time to solution of a long waveform, one run vs "
+                  "batched segments, and the patched waveform's agreement with the long run",
+        "workload": f"Kerr a=0.9, s=-2, m=2, circular orbit r0=10M; 8001 x 33 on [-20,1980]M, observer 40M "
+                    f"(equator row); T = {n_total * K * dt:.0f}M",
+        "segments": n, "segment_M": info["L"], "overlap_M": info["overlap"],
+        "long_run": {"seconds": t_long, "steps": n_total * K, "updates_per_s": pts * n_total * K / t_long,
+                     "tuning": tune_long},
+        "batched_segments": {"seconds": t_seg, "steps": info["steps"], "instances": n,
+                             "updates_per_s": pts * n * info["steps"] / t_seg, "tuning": tune_seg},
+        "time_to_solution_speedup": t_long / t_seg,
+        "work_ratio": n * info["steps"] / (n_total * K),
+        "compared_from_M": k0 * info["L"],
+        "patched_vs_long_max_rel_err": err,
+        "patched_vs_long_rel_err_by_segment": per_seg,
+        "long_run_max_amplitude_by_segment": amp_long,
+        "patched_max_amplitude_by_segment": amp_patch,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -320,6 +395,11 @@ def main():
     ap.add_argument("--rich-nth", type=int, default=33, help="Richardson study: coarse theta rows")
     ap.add_argument("--rich-sigma-r", type=float, default=0.5, help="Richardson study: source width in r* (M)")
     ap.add_argument("--rich-sigma-th", type=float, default=4.0, help="Richardson study: source width, coarse theta cells")
+    ap.add_argument("--segments", action="store_true",
+                    help="instead of the throughput line, run the temporal-segments study")
+    ap.add_argument("--seg-total", type=float, default=3600.0, help="segments study: length of the long run (M)")
+    ap.add_argument("--seg-count", type=int, default=36, help="segments study: number of segments")
+    ap.add_argument("--seg-overlap", type=float, default=300.0, help="segments study: overlap per segment (M)")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="instead of the stepper, run a plain device copy of this many GiB "
                          "(calibrates the HBM byte counters)")
@@ -334,6 +414,9 @@ def main():
         return
     if args.richardson:
         richardson_study(args)
+        return
+    if args.segments:
+        segments_study(args)
         return
     import torch
     from paper_1206_0270_amd import tk

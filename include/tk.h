@@ -87,7 +87,7 @@ typedef enum {
 } tk_source_kind;
 
 /* Smeared point particle (Section 2.3, item 1): the Pi equation gets
- *   F = amplitude * exp(-i m (Omega t + phase0)) * g_r(r* - r*(r0)) * g_th(theta - pi/2)
+ *   F = amplitude * exp(-i m (Omega (t + t0) + phase0)) * g_r(r* - r*(r0)) * g_th(theta - pi/2)
  * with g(xi) = exp(-xi^2/(2 sigma^2)) / (sigma sqrt(2 pi)) for
  * |xi| <= window_sigmas * sigma and 0 beyond; sigma_r = sigma_r_cells * h,
  * sigma_th = sigma_th_cells * dtheta; Omega = sqrt(M)/(r0^{3/2} + a sqrt(M))
@@ -98,6 +98,8 @@ typedef struct {
     int kind;
     double r0, amplitude, phase0;
     double sigma_r_cells, sigma_th_cells, window_sigmas;
+    double t0; /* time along the orbit at step 0: a segment of a long run
+                  (Section 4's temporal decomposition) starts at t0 */
 } tk_source_desc;
 
 /* Kernel choice and launch shape (the only per-architecture tuning the

@@ -211,6 +211,7 @@ typedef struct {
     int src_kind;
     double src_r0, src_amp, src_phase0;
     double src_sigma_r_cells, src_sigma_th_cells, src_window_sigmas;
+    double src_t0; /* time along the orbit at step 0 (a segment's start) */
 } or_desc;
 
 typedef struct {
@@ -278,7 +279,7 @@ static cplx source_at(const or_grid *g, real t, real rstar, real th)
     real gt = gauss_window(th - PI_R / 2, (real)d->src_sigma_th_cells * g->dth, (real)d->src_window_sigmas);
     if (gt == 0)
         return 0;
-    real phase = -(real)d->m * (g->src_Omega * t + (real)d->src_phase0);
+    real phase = -(real)d->m * (g->src_Omega * (t + (real)d->src_t0) + (real)d->src_phase0);
     return (real)d->src_amp * gr * gt * (cos(phase) + IU * sin(phase));
 }
 

@@ -206,6 +206,7 @@ DevInst make_dev(const tk_ctx *c, const HostInst &h)
     D.src_sig_r = h.src.sigma_r_cells * h.h;
     D.src_sig_th = h.src.sigma_th_cells * h.dth;
     D.src_win = h.src.window_sigmas;
+    D.src_t0 = h.src.t0;
     D.a2 = d.a * d.a;
     D.kct = -2.0 * d.s * d.a;
     return D;
@@ -585,7 +586,7 @@ tk_status tk_set_source(tk_ctx *c, int inst, const tk_source_desc *src)
     if (s.kind == TK_SRC_CIRCULAR_GAUSSIAN) {
         if (!(s.r0 > h.rp) || !std::isfinite(s.r0)) return fail(c, TK_E_INVALID, "r0 must lie outside the horizon");
         if (!(s.sigma_r_cells > 0) || !(s.sigma_th_cells > 0) || !(s.window_sigmas > 0) ||
-            !std::isfinite(s.amplitude) || !std::isfinite(s.phase0))
+            !std::isfinite(s.amplitude) || !std::isfinite(s.phase0) || !std::isfinite(s.t0))
             return fail(c, TK_E_INVALID, "source widths, window, amplitude and phase must be positive/finite");
         Om = orbit_frequency(h.desc.M, h.desc.a, s.r0);
         rsp = tortoise_of_x(h.desc.M, h.desc.a, s.r0 - h.rp);

@@ -321,10 +321,10 @@ __device__ __forceinline__ Q4<T> lw_point(const Coef<T> &c, const Q4<T> &base, c
     return Q4<T>{base.phi - fac * br.phi, base.pi - fac * br.pi};
 }
 
-// Time factor of the smeared particle source, exp(-i m (Omega t + phase0)).
+// Time factor of the smeared particle source, exp(-i m (Omega (t + t0) + phase0)).
 __device__ __forceinline__ cd source_phase(const DevInst &I, double t)
 {
-    const double ph = -(double)I.m * (I.src_Omega * t + I.src_phase0);
+    const double ph = -(double)I.m * (I.src_Omega * (t + I.src_t0) + I.src_phase0);
     return mk(cos(ph), sin(ph));
 }
 

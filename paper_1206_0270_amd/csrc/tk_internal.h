@@ -71,7 +71,7 @@ struct alignas(16) DevInst {
     // source
     int src_kind, pad1, pad2, pad3;
     double src_amp, src_phase0, src_Omega, src_rstar_p;
-    double src_sig_r, src_sig_th, src_win, pad4;
+    double src_sig_r, src_sig_th, src_win, src_t0;
     double a2, kct, pad5, pad6;  // a^2 and -2 s a (to rebuild a^2 Delta and Im ct's cos part)
 };
 
