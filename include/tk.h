@@ -212,7 +212,7 @@ tk_status tk_destroy(tk_ctx *ctx);
 const char *tk_last_error(const tk_ctx *ctx);
 
 /* Largest stable dt of the scheme for one description (same rule as the
- * TK_E_UNSTABLE check). */
+ * TK_E_UNSTABLE check); the description's own dt is not used. */
 tk_status tk_stable_dt(const tk_instance_desc *inst, double *dt_max);
 
 /* Richardson extrapolation of second-order results (Section 2.3, item 3)

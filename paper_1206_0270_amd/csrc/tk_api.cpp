@@ -331,9 +331,11 @@ const char *tk_last_error(const tk_ctx *ctx) { return ctx ? ctx->err.c_str() : g
 tk_status tk_stable_dt(const tk_instance_desc *inst, double *dt_max)
 {
     if (!inst || !dt_max) return fail(nullptr, TK_E_INVALID, "null argument");
-    std::string v = validate(*inst);
+    tk_instance_desc d = *inst;
+    if (!(d.dt > 0) || !std::isfinite(d.dt)) d.dt = 1.0;  // the step itself is what is asked for
+    std::string v = validate(d);
     if (!v.empty()) return fail(nullptr, TK_E_INVALID, v);
-    *dt_max = stable_dt_bound(*inst);
+    *dt_max = stable_dt_bound(d);
     return TK_OK;
 }
 

@@ -106,3 +106,47 @@ def test_tuning_validation():
     ok = tk.Tuning(tk.TK_KERNEL_FUSED2, 0, 100, 1, tk.TK_TUNE_NT_STORES, 0)
     assert lib.tk_set_tuning(ctx, ctypes.byref(ok)) == tk.TK_OK
     lib.tk_destroy(ctx)
+
+
+C_PROGRAM = r"""
+#include "tk.h"
+#include <stdio.h>
+int main(void)
+{
+    tk_instance_desc d = {1.0, 0.5, -2, 2, 101, 9, -20.0, 25.0, 0.0, 20.0, 3, 0, 0};
+    double dt = 0.0, w[6] = {1, 0, 2, 0, 3, 0}, e[2], err[1];
+    tk_ctx *ctx = NULL;
+    size_t bytes = 0;
+    if (tk_abi_version() != TK_ABI_VERSION) return 1;
+    if (tk_stable_dt(&d, &dt) != TK_OK || !(dt > 0)) return 2;
+    d.dt = dt;
+    if (tk_init_grid(&d, 1, TK_FP64, NULL, &ctx) != TK_OK) return 3;
+    if (tk_workspace_bytes(ctx, &bytes) != TK_OK || bytes == 0) return 4;
+    if (tk_step(ctx, 1) != TK_E_STATE) return 5; /* no workspace bound yet */
+    if (tk_destroy(ctx) != TK_OK) return 6;
+    if (tk_richardson(w, w + 2, w + 4, 1, 2, e, err) != TK_OK) return 7;
+    printf("%.17g %.17g\n", dt, e[0]);
+    return 0;
+}
+"""
+
+
+def test_abi_from_plain_c(tmp_path):
+    # the header is C, and a C program links libtk.so and calls it (host-side
+    # entry points only: no device here)
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "abi.c"
+    src.write_text(C_PROGRAM)
+    exe = tmp_path / "abi"
+    lib_dir = os.path.dirname(tk.LIB_PATH)
+    subprocess.run([gcc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-I", os.path.join(ROOT, "include"),
+                    str(src), "-o", str(exe), "-L", lib_dir, "-ltk", "-Wl,-rpath," + lib_dir], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
+    dt = float(out[0])
+    same = W.instance(a=0.5, m=2, n_r=101, n_theta=9, rstar_min=-20.0, rstar_max=25.0, rstar_obs=20.0)
+    assert dt == tk.stable_dt(same)
+    assert float(out[1]) == pytest.approx(10.0 / 3.0)
