@@ -288,6 +288,92 @@ def richardson_study(args):
     print(json.dumps(out), flush=True)
 
 
+def source_study(args):
+    """Section 2.3 item 1 on the GPU: one Kerr mode driven by the same
+    circular orbit with three representations of the point particle (the
+    two-cell Gaussian, the step delta and the linear delta), each at three
+    resolutions halving h, dtheta and dt (the Gaussian keeps its width in
+    cells, so all three tend to the point particle).  Per form and level the
+    projected waveform's distance, over the outgoing-only window, to the
+    Richardson extrapolant of the linear delta; the observed convergence
+    factor; and how far each form's own extrapolant lies from that limit.
+    The three forms of a level advance together in one batch.  One JSON line."""
+    import numpy as np
+    import torch
+    from paper_1206_0270_amd import tk
+    from paper_1206_0270_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    n_r = int(round(300.0 / args.src_h)) + 1
+    shapes = ("gaussian", "step_delta", "linear_delta")
+    fams = []
+    for shape in shapes:
+        base = W.instance(a=0.9, m=2, n_r=n_r, n_theta=args.src_nth, rstar_min=-60.0, rstar_max=240.0,
+                          rstar_obs=180.0, name=f"kerr a=0.9 m=2 {shape}",
+                          source=dict(r0=10.0, phase0=0.7, shape=shape))
+        fams.append(W.richardson_family(base, 3, point_limit=True))
+    T = args.src_window
+    waves = {sh: [] for sh in shapes}
+    runs = []
+    for lev in range(3):
+        insts = [f[lev] for f in fams]
+        steps = int(round(T / insts[0]["dt"]))
+        steps -= steps % 2
+        st = tk.Stepper(insts, wave_capacity=int(T) + 64)
+        for k, inst in enumerate(insts):
+            st.set_fields(k, *W.initial_data(inst))
+        st.autotune(warmup=2, steps=6)
+        t = st.get_tuning()
+        t["graph_steps"] = 100
+        st.set_tuning(**t)
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(st.stream)
+        st.step(steps)
+        ev1.record(st.stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1)
+        for k, sh in enumerate(shapes):
+            waves[sh].append(projected_waveform(insts[k], st.extract(k, max_samples=int(T) + 64)))
+        st.close()
+        upd = 3 * insts[0]["n_r"] * insts[0]["n_theta"] * steps
+        runs.append(dict(n_r=insts[0]["n_r"], n_theta=insts[0]["n_theta"], dt=insts[0]["dt"], steps=steps,
+                         updates_per_s=upd / (ms / 1e3), kernel=t["kernel"]))
+        print(f"# level {lev}: {insts[0]['n_r']} x {insts[0]['n_theta']}, {steps} steps x 3 forms in "
+              f"{ms / 1e3:.1f} s", file=sys.stderr, flush=True)
+    n = min(len(w) for ws in waves.values() for w in ws)
+    ext = {sh: tk.richardson(*[w[:n] for w in waves[sh]])[0] for sh in shapes}
+    ref = ext["linear_delta"]
+    dt_s = fams[0][0]["extract_every"] * fams[0][0]["dt"]
+    times = (np.arange(n) + 1) * dt_s
+    t0, t1 = 180.0 - 10.0, 2 * 240.0 - 180.0 - 10.0  # direct signal .. its outer-boundary reflection
+    win = (times >= t0) & (times <= t1) & (np.abs(ref) >= 1e-3 * np.abs(ref).max())
+    nrm = lambda x: float(np.linalg.norm(x[:n][win]))
+    forms = {}
+    for sh in shapes:
+        w = waves[sh]
+        forms[sh] = {
+            "rel_l2_vs_limit_by_level": [nrm(wl[:n] - ref) / nrm(ref) for wl in w],
+            "convergence_factor": nrm(w[0][:n] - w[1][:n]) / nrm(w[1][:n] - w[2][:n]),
+            "own_extrapolant_vs_limit": nrm(ext[sh] - ref) / nrm(ref),
+        }
+    out = {
+        "metric": "point-particle representations (Section 2.3 item 1): waveform error vs the point-particle "
+                  "limit at three resolutions",
+        "workload": f"Kerr a=0.9, s=-2, m=2, circular orbit r0=10M; r* in [-60,240]M, observer 180M; coarse h = "
+                    f"{args.src_h} M, {args.src_nth} theta rows; three levels halving h, dtheta and dt; "
+                    f"limit = Richardson extrapolant of the linear delta",
+        "window_M": [t0, t1], "samples_in_window": int(win.sum()),
+        "levels": runs,
+        "forms": forms,
+        "gaussian_over_linear_error_by_level": [forms["gaussian"]["rel_l2_vs_limit_by_level"][k] /
+                                                forms["linear_delta"]["rel_l2_vs_limit_by_level"][k]
+                                                for k in range(3)],
+    }
+    print(json.dumps(out), flush=True)
+
+
 def segments_study(args):
     """Section 4's temporal decomposition on one GPU: one sourced mode run
     for T in one context, against the same T split into segments that start
@@ -395,6 +481,11 @@ def main():
     ap.add_argument("--rich-nth", type=int, default=33, help="Richardson study: coarse theta rows")
     ap.add_argument("--rich-sigma-r", type=float, default=0.5, help="Richardson study: source width in r* (M)")
     ap.add_argument("--rich-sigma-th", type=float, default=4.0, help="Richardson study: source width, coarse theta cells")
+    ap.add_argument("--source-study", action="store_true",
+                    help="compare the Gaussian and the two discrete-delta particles under refinement")
+    ap.add_argument("--src-window", type=float, default=330.0, help="source study: simulated time (M)")
+    ap.add_argument("--src-h", type=float, default=0.08, help="source study: coarse r* spacing (M)")
+    ap.add_argument("--src-nth", type=int, default=33, help="source study: coarse theta rows")
     ap.add_argument("--segments", action="store_true",
                     help="instead of the throughput line, run the temporal-segments study")
     ap.add_argument("--seg-total", type=float, default=3600.0, help="segments study: length of the long run (M)")
@@ -417,6 +508,9 @@ def main():
         return
     if args.segments:
         segments_study(args)
+        return
+    if args.source_study:
+        source_study(args)
         return
     import torch
     from paper_1206_0270_amd import tk

@@ -83,7 +83,9 @@ typedef struct {
 
 typedef enum {
     TK_SRC_NONE = 0,
-    TK_SRC_CIRCULAR_GAUSSIAN = 1
+    TK_SRC_CIRCULAR_GAUSSIAN = 1,
+    TK_SRC_CIRCULAR_STEP_DELTA = 2,
+    TK_SRC_CIRCULAR_LINEAR_DELTA = 3
 } tk_source_kind;
 
 /* Smeared point particle (Section 2.3, item 1): the Pi equation gets
@@ -93,7 +95,22 @@ typedef enum {
  * sigma_th = sigma_th_cells * dtheta; Omega = sqrt(M)/(r0^{3/2} + a sqrt(M))
  * (prograde circular equatorial orbit).  Evaluated in FP64 in every
  * precision mode, at t^n in the first Lax-Wendroff step and t^n + dt/2 in
- * the second. */
+ * the second.
+ *
+ * Discrete-delta forms (Section 2.3, item 1: the finite-difference
+ * derivative of a step function laid on the grid) replace g_r and g_th by
+ * grid functions d(x - x_p) of unit sum times the spacing D (D = h in r*,
+ * where nodes and half nodes each form a grid of spacing h; D = dtheta in
+ * theta); sigma_*_cells and window_sigmas are then ignored:
+ *   TK_SRC_CIRCULAR_STEP_DELTA: the centred difference of the sampled
+ *     Heaviside step, d(x) = [H(x + D - x_p) - H(x - D - x_p)] / (2D) with
+ *     H(0) = 1/2: 1/(2D) on the two grid points around x_p, or 1/(4D),
+ *     1/(2D), 1/(4D) when x_p is on a grid point (within 1e-9 D, so that a
+ *     particle on the equator sits on the row theta = pi/2 of an odd
+ *     N_theta grid whatever the rounding of j dtheta);
+ *   TK_SRC_CIRCULAR_LINEAR_DELTA: the difference of the step that rises
+ *     linearly over one cell, d(x) = max(0, 1 - |x - x_p|/D) / D, exact on
+ *     constants and linear functions (zeroth and first moments). */
 typedef struct {
     int kind;
     double r0, amplitude, phase0;

@@ -135,6 +135,10 @@ def get_threads(kind="f64"):
     return _lib(kind).or_get_threads()
 
 
+# source shapes: the smeared Gaussian and the two discrete delta functions
+SOURCE_SHAPES = {"gaussian": 1, "step_delta": 2, "linear_delta": 3}
+
+
 class Grid:
     """One oracle instance: a grid, its coefficient planes and the state."""
 
@@ -151,7 +155,7 @@ class Grid:
         d.rstar_min, d.rstar_max, d.dt = rstar_min, rstar_max, dt
         d.i_obs, d.extract_every = int(i_obs), int(extract_every)
         if source is not None:
-            d.src_kind = 1
+            d.src_kind = SOURCE_SHAPES[source.get("shape", "gaussian")]
             d.src_r0 = source["r0"]
             d.src_amp = source.get("amplitude", 1.0)
             d.src_phase0 = source.get("phase0", 0.0)

@@ -44,7 +44,10 @@
  *    g(xi) = exp(-xi^2 / (2 sigma^2)) / (sigma sqrt(2 pi)) for
  *    |xi| <= window*sigma and 0 outside; Omega is the prograde circular
  *    equatorial Kerr orbital frequency sqrt(M) / (r0^{3/2} + a sqrt(M)).
- *    F enters the Pi equation additively.
+ *    F enters the Pi equation additively.  In place of g_r and g_theta the
+ *    source may take the discrete delta functions that item 1 describes as
+ *    the finite-difference derivative of a step function on the grid (kinds
+ *    2 and 3 below).
  */
 #include <stdlib.h>
 #include <string.h>
@@ -267,17 +270,49 @@ static real gauss_window(real xi, real sig, real win)
     return exp(-xi * xi / (2 * sig * sig)) / (sig * sqrt(2 * PI_R));
 }
 
+/* Discrete delta functions (Section 2.3, item 1): a step function laid on
+ * the grid, differenced.  Kind 2 takes the sharp Heaviside step H, with the
+ * value 1/2 at the jump (a point within 1e-9 of a cell of it counts as on
+ * it), and its centred difference over the neighbours x +- dx.  Kind 3 takes
+ * the step that rises linearly over the cell below xp and its difference
+ * over one cell. */
+static real heaviside(real y, real dx)
+{
+    if (y > (real)1e-9 * dx)
+        return 1;
+    if (y < -(real)1e-9 * dx)
+        return 0;
+    return (real)0.5;
+}
+
+static real ramp_step(real y, real dx)
+{
+    real v = y / dx + 1;
+    return v <= 0 ? 0 : (v >= 1 ? 1 : v);
+}
+
+static real discrete_delta(int kind, real x, real xp, real dx)
+{
+    if (kind == 2)
+        return (heaviside(x + dx - xp, dx) - heaviside(x - dx - xp, dx)) / (2 * dx);
+    return (ramp_step(x - xp, dx) - ramp_step(x - dx - xp, dx)) / dx;
+}
+
 /* Synthetic particle source F(t, r*, theta). */
 static cplx source_at(const or_grid *g, real t, real rstar, real th)
 {
     const or_desc *d = &g->desc;
-    if (d->src_kind != 1)
+    real gr, gt;
+    if (d->src_kind == 1) {
+        gr = gauss_window(rstar - g->src_rstar_p, (real)d->src_sigma_r_cells * g->h, (real)d->src_window_sigmas);
+        gt = gauss_window(th - PI_R / 2, (real)d->src_sigma_th_cells * g->dth, (real)d->src_window_sigmas);
+    } else if (d->src_kind == 2 || d->src_kind == 3) {
+        gr = discrete_delta(d->src_kind, rstar, g->src_rstar_p, g->h);
+        gt = discrete_delta(d->src_kind, th, PI_R / 2, g->dth);
+    } else {
         return 0;
-    real gr = gauss_window(rstar - g->src_rstar_p, (real)d->src_sigma_r_cells * g->h, (real)d->src_window_sigmas);
-    if (gr == 0)
-        return 0;
-    real gt = gauss_window(th - PI_R / 2, (real)d->src_sigma_th_cells * g->dth, (real)d->src_window_sigmas);
-    if (gt == 0)
+    }
+    if (gr == 0 || gt == 0)
         return 0;
     real phase = -(real)d->m * (g->src_Omega * (t + (real)d->src_t0) + (real)d->src_phase0);
     return (real)d->src_amp * gr * gt * (cos(phase) + IU * sin(phase));
@@ -529,7 +564,7 @@ void *or_grid_new(const or_desc *d)
             g->c0[o] = c.c0;
         }
     }
-    if (d->src_kind == 1) {
+    if (d->src_kind >= 1 && d->src_kind <= 3) {
         g->src_rstar_p = tortoise_x(&g->k, (real)d->src_r0 - g->k.rp);
         real sm = sqrt((real)d->M);
         g->src_Omega = sm / (pow((real)d->src_r0, (real)1.5) + (real)d->a * sm);

@@ -585,11 +585,15 @@ tk_status tk_set_source(tk_ctx *c, int inst, const tk_source_desc *src)
     HostInst &h = c->inst[inst];
     tk_source_desc s = *src;
     double Om = 0.0, rsp = 0.0;
-    if (s.kind == TK_SRC_CIRCULAR_GAUSSIAN) {
+    if (s.kind == TK_SRC_CIRCULAR_GAUSSIAN || s.kind == TK_SRC_CIRCULAR_STEP_DELTA ||
+        s.kind == TK_SRC_CIRCULAR_LINEAR_DELTA) {
         if (!(s.r0 > h.rp) || !std::isfinite(s.r0)) return fail(c, TK_E_INVALID, "r0 must lie outside the horizon");
-        if (!(s.sigma_r_cells > 0) || !(s.sigma_th_cells > 0) || !(s.window_sigmas > 0) ||
-            !std::isfinite(s.amplitude) || !std::isfinite(s.phase0) || !std::isfinite(s.t0))
-            return fail(c, TK_E_INVALID, "source widths, window, amplitude and phase must be positive/finite");
+        if (!std::isfinite(s.amplitude) || !std::isfinite(s.phase0) || !std::isfinite(s.t0))
+            return fail(c, TK_E_INVALID, "source amplitude, phase and t0 must be finite");
+        if (s.kind == TK_SRC_CIRCULAR_GAUSSIAN &&
+            (!(s.sigma_r_cells > 0) || !(s.sigma_th_cells > 0) || !(s.window_sigmas > 0) ||
+             !std::isfinite(s.sigma_r_cells) || !std::isfinite(s.sigma_th_cells) || !std::isfinite(s.window_sigmas)))
+            return fail(c, TK_E_INVALID, "source widths and window must be positive and finite");
         Om = orbit_frequency(h.desc.M, h.desc.a, s.r0);
         rsp = tortoise_of_x(h.desc.M, h.desc.a, s.r0 - h.rp);
     } else if (s.kind != TK_SRC_NONE) {

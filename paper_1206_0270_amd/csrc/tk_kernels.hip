@@ -284,7 +284,7 @@ struct Level {
 __device__ __forceinline__ Level make_level(const DevInst &I, long long n)
 {
     Level v;
-    if (I.src_kind == TK_SRC_CIRCULAR_GAUSSIAN) {
+    if (I.src_kind != TK_SRC_NONE) {
         v.eh = uniform(source_phase(I, (double)n * I.dt));
         v.ef = uniform(source_phase(I, (double)n * I.dt + 0.5 * I.dt));
     } else {

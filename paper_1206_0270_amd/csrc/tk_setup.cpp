@@ -150,15 +150,38 @@ double gauss_cut(double xi, double sig, double win)
 }
 }  // namespace
 
+// Discrete delta of spacing dx around xp at a grid point x (the two forms of
+// tk_source_kind): with u = |x - xp| / dx, the linear form is the hat
+// (1 - u)/dx on u < 1; the step form is 1/(2dx) inside one cell of xp and
+// 1/(4dx) at exactly one cell (the step's midpoint value), a point within
+// 1e-9 of a cell boundary counting as on it.
+static double discrete_delta(int kind, double x, double xp, double dx)
+{
+    constexpr double tol = 1e-9;
+    const double u = std::fabs(x - xp) / dx;
+    if (kind == TK_SRC_CIRCULAR_LINEAR_DELTA) return u < 1.0 ? (1.0 - u) / dx : 0.0;
+    if (u < 1.0 - tol) return 0.5 / dx;
+    if (u <= 1.0 + tol) return 0.25 / dx;
+    return 0.0;
+}
+
 void fill_source(const HostInst &hi, Radial *rad, Angular *ang)
 {
     const tk_instance_desc &d = hi.desc;
-    const bool on = hi.src.kind == TK_SRC_CIRCULAR_GAUSSIAN;
-    const double sig_r = hi.src.sigma_r_cells * hi.h, sig_t = hi.src.sigma_th_cells * hi.dth;
-    for (int q = 0; q < 2 * d.n_r - 1; ++q)
-        rad[q].srcg = on ? hi.src.amplitude * gauss_cut(rad[q].rstar - hi.src_rstar_p, sig_r, hi.src.window_sigmas) : 0.0;
-    for (int j = 0; j < d.n_theta; ++j)
-        ang[j].srcg = on ? gauss_cut(ang[j].theta - M_PI / 2, sig_t, hi.src.window_sigmas) : 0.0;
+    const int kind = hi.src.kind;
+    const double A = hi.src.amplitude;
+    if (kind == TK_SRC_CIRCULAR_GAUSSIAN) {
+        const double sig_r = hi.src.sigma_r_cells * hi.h, sig_t = hi.src.sigma_th_cells * hi.dth;
+        for (int q = 0; q < 2 * d.n_r - 1; ++q)
+            rad[q].srcg = A * gauss_cut(rad[q].rstar - hi.src_rstar_p, sig_r, hi.src.window_sigmas);
+        for (int j = 0; j < d.n_theta; ++j) ang[j].srcg = gauss_cut(ang[j].theta - M_PI / 2, sig_t, hi.src.window_sigmas);
+    } else if (kind == TK_SRC_CIRCULAR_STEP_DELTA || kind == TK_SRC_CIRCULAR_LINEAR_DELTA) {
+        for (int q = 0; q < 2 * d.n_r - 1; ++q) rad[q].srcg = A * discrete_delta(kind, rad[q].rstar, hi.src_rstar_p, hi.h);
+        for (int j = 0; j < d.n_theta; ++j) ang[j].srcg = discrete_delta(kind, ang[j].theta, M_PI / 2, hi.dth);
+    } else {
+        for (int q = 0; q < 2 * d.n_r - 1; ++q) rad[q].srcg = 0.0;
+        for (int j = 0; j < d.n_theta; ++j) ang[j].srcg = 0.0;
+    }
 }
 
 // Time-step bound.  With the angular terms inside S, one Lax-Wendroff step

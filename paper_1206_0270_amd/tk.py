@@ -16,7 +16,9 @@ LIB_PATH = os.path.join(_HERE, "libtk.so")
 TK_OK, TK_E_INVALID, TK_E_NOMEM, TK_E_DEVICE, TK_E_STATE, TK_E_UNSTABLE, TK_E_NONFINITE = range(7)
 TK_FP64, TK_FP32_COMP = 0, 1
 TK_FLAG_FORCE_DT = 1
-TK_SRC_NONE, TK_SRC_CIRCULAR_GAUSSIAN = 0, 1
+TK_SRC_NONE, TK_SRC_CIRCULAR_GAUSSIAN, TK_SRC_CIRCULAR_STEP_DELTA, TK_SRC_CIRCULAR_LINEAR_DELTA = 0, 1, 2, 3
+SOURCE_KINDS = {"gaussian": TK_SRC_CIRCULAR_GAUSSIAN, "step_delta": TK_SRC_CIRCULAR_STEP_DELTA,
+                "linear_delta": TK_SRC_CIRCULAR_LINEAR_DELTA}
 TK_KERNEL_AUTO, TK_KERNEL_TWO_PASS, TK_KERNEL_FUSED, TK_KERNEL_FUSED2 = 0, 1, 2, 3
 
 _STATUS = {0: "TK_OK", 1: "TK_E_INVALID", 2: "TK_E_NOMEM", 3: "TK_E_DEVICE", 4: "TK_E_STATE",
@@ -127,7 +129,7 @@ def make_source(src):
     if src is None:
         s.kind = TK_SRC_NONE
         return s
-    s.kind = TK_SRC_CIRCULAR_GAUSSIAN
+    s.kind = SOURCE_KINDS[src.get("shape", "gaussian")]
     s.r0 = src["r0"]
     s.amplitude = src.get("amplitude", 1.0)
     s.phase0 = src.get("phase0", 0.0)

@@ -108,12 +108,14 @@ def instance(M=1.0, a=0.0, s=-2, m=2, n_r=801, n_theta=33, rstar_min=-100.0,
                 source=source, init=init, name=name)
 
 
-def refine(inst, k):
+def refine(inst, k, point_limit=False):
     """The same physical problem with the grid spacings h, dtheta and the
     time step divided by 2^k: n - 1 intervals become 2^k (n - 1), the waveform
     is sampled at the same times, and the source keeps its physical widths
     (its widths are given in cells).  Coarse nodes stay nodes of the refined
-    grid, so results compare at the coarse points."""
+    grid, so results compare at the coarse points.  With point_limit the
+    Gaussian keeps its width in cells instead, so that refinement tends to the
+    point particle (the discrete deltas are one cell wide at every level)."""
     f = 2 ** k
     out = dict(inst)
     out["n_r"] = (inst["n_r"] - 1) * f + 1
@@ -122,7 +124,7 @@ def refine(inst, k):
     out["extract_every"] = inst["extract_every"] * f
     h = (inst["rstar_max"] - inst["rstar_min"]) / (out["n_r"] - 1)
     out["i_obs"] = int(math.floor((inst["rstar_obs"] - inst["rstar_min"]) / h + 0.5))
-    if inst.get("source"):
+    if inst.get("source") and not point_limit:
         src = dict(inst["source"])
         src["sigma_r_cells"] = src.get("sigma_r_cells", 2.0) * f
         src["sigma_th_cells"] = src.get("sigma_th_cells", 2.0) * f
@@ -131,7 +133,7 @@ def refine(inst, k):
     return out
 
 
-def richardson_family(inst, levels=3):
+def richardson_family(inst, levels=3, point_limit=False):
     """refine(inst, k) for k = 0 .. levels-1, with the base time step lowered
     (if needed) so that every level satisfies its own step rule: the
     angular part of the rule scales like dtheta^(4/3), faster than the
@@ -145,7 +147,7 @@ def richardson_family(inst, levels=3):
     base = dict(inst)
     base["dt"] = 1.0 / math.ceil(1.0 / dt - 1e-9)
     base["extract_every"] = max(1, int(round(inst["extract_every"] * inst["dt"] / base["dt"])))
-    return [refine(base, k) for k in range(levels)]
+    return [refine(base, k, point_limit) for k in range(levels)]
 
 
 def initial_data(inst):

@@ -1,5 +1,5 @@
 // Test driver: prints the library's host-side setup values (inverse tortoise
-// coordinate, radial and angular tables) so that tests/test_host_setup.py can
+// coordinate, radial and angular tables, source tables) so that tests/test_host_setup.py can
 // compare them with closed forms and with the oracle.  Built with g++ by the
 // test; links the library's own tk_setup.cpp.
 #include <cmath>
@@ -41,5 +41,17 @@ int main(int argc, char **argv)
     for (int j = 0; j < d.n_theta; ++j)
         printf("A %d %.17g %.17g %.17g %.17g %.17g\n", j, ang[j].theta, ang[j].sn2, ang[j].cs, ang[j].cot, ang[j].V);
     printf("B %.17g\n", tk::stable_dt_bound(d));
+    if (argc >= 11) {  // source tables: kind, r0 (amplitude 1, widths 2 cells, window 6 sigma)
+        h.src.kind = atoi(argv[9]);
+        h.src.r0 = atof(argv[10]);
+        h.src.amplitude = 1.0;
+        h.src.sigma_r_cells = h.src.sigma_th_cells = 2.0;
+        h.src.window_sigmas = 6.0;
+        h.src_rstar_p = tk::tortoise_of_x(d.M, d.a, h.src.r0 - h.rp);
+        tk::fill_source(h, rad.data(), ang.data());
+        printf("P %.17g\n", h.src_rstar_p);
+        for (size_t k = 0; k < rad.size(); ++k) printf("S %zu %.17g %.17g\n", k, rad[k].rstar, rad[k].srcg);
+        for (int j = 0; j < d.n_theta; ++j) printf("T %d %.17g %.17g\n", j, ang[j].theta, ang[j].srcg);
+    }
     return 0;
 }

@@ -1,6 +1,7 @@
 """The oracle's pins are sharp enough: each plausible mistake planted in a
 copy of the oracle source (a dropped term, a wrong sign, a wrong index or
-time level, a first-order pole condition) makes at least one pin fail.
+time level, a first-order pole condition, a misplaced or mis-scaled discrete
+delta) makes at least one pin fail.
 
 Each mutant is compiled from an edited copy of oracle/teuk_oracle.c into a
 temporary library; the committed oracle is never modified.
@@ -14,6 +15,7 @@ import oracle
 from oracle import build as orbuild
 
 import test_oracle_pins as PINS
+import test_source_shapes as SHAPES
 
 # (name, original text (must occur exactly once), replacement, pins to run)
 MUTANTS = [
@@ -38,6 +40,17 @@ MUTANTS = [
     ("c1 misses 2 r Delta", "2 * s * (r - M) * rho + 2 * r * Delta + 2 * IU", "2 * s * (r - M) * rho + 2 * IU",
      ["mms_odd"]),
     ("tortoise: r- weight with the wrong sign", "val -= k->Am * log(", "val += k->Am * log(", ["tortoise"]),
+    ("step delta: value 1 at the jump", "        return 0;\n    return (real)0.5;", "        return 0;\n    return 1;",
+     ["delta_theta"]),
+    ("step delta: forward difference",
+     "(heaviside(x + dx - xp, dx) - heaviside(x - dx - xp, dx)) / (2 * dx)",
+     "(heaviside(x + dx - xp, dx) - heaviside(x - xp, dx)) / dx", ["delta_step"]),
+    ("linear delta: ramp over the cell above the particle", "real v = y / dx + 1;", "real v = y / dx;",
+     ["delta_linear"]),
+    ("radial delta on half the spacing", "discrete_delta(d->src_kind, rstar, g->src_rstar_p, g->h);",
+     "discrete_delta(d->src_kind, rstar, g->src_rstar_p, g->h / 2);", ["delta_linear", "delta_step"]),
+    ("theta delta takes the radial spacing", "discrete_delta(d->src_kind, th, PI_R / 2, g->dth);",
+     "discrete_delta(d->src_kind, th, PI_R / 2, g->h);", ["delta_theta"]),
 ]
 
 
@@ -60,6 +73,15 @@ def run_pin(name, kind):
         PINS.principal_part_check(kind=kind)
     elif name == "source":
         PINS.source_consistency_check(kind=kind)
+    elif name == "delta_linear":
+        for q0 in (0, 1):
+            SHAPES.linear_delta_check(9.01, q0, kind=kind)
+    elif name == "delta_step":
+        for q0 in (0, 1):
+            SHAPES.step_delta_check(q0, kind=kind)
+    elif name == "delta_theta":
+        for case in SHAPES.THETA_CASES:
+            SHAPES.theta_delta_check(*case, kind=kind)
     else:
         raise KeyError(name)
 
@@ -71,7 +93,7 @@ def src_text():
 
 
 def test_unmutated_source_passes_the_detectors(src_text):
-    for pin in ("mms_even", "mms_odd", "eig", "tortoise", "source"):
+    for pin in ("mms_even", "mms_odd", "eig", "tortoise", "source", "delta_linear", "delta_step", "delta_theta"):
         run_pin(pin, "f64")
 
 
