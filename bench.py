@@ -459,15 +459,13 @@ def main():
     ap.add_argument("--graph-steps", type=int, default=100)
     ap.add_argument("--tune", default="auto", choices=["auto", "manual"],
                     help="auto: the library's autotuner picks the launch shape before timing; "
-                         "manual: the shape given by --kernel/--rows/--prefetch/--no-nt/--waves")
+                         "manual: the shape given by --kernel/--rows/--prefetch/--no-nt")
     ap.add_argument("--rows", type=int, default=0)
     ap.add_argument("--kernel", default="fused2", choices=["fused2", "fused", "two_pass"],
                     help="fused2: two time steps per pass (needs --rows 0); fused: one step per pass; "
                          "two_pass: half-step array through HBM")
     ap.add_argument("--prefetch", type=int, default=3, choices=[1, 3])
     ap.add_argument("--no-nt", action="store_true", help="plain (not non-temporal) stores")
-    ap.add_argument("--waves", type=int, default=None, choices=[0, 3, 4],
-                    help="occupancy target of the fused kernels (default: the library's choice)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision-study", action="store_true",
                     help="instead of the throughput line, run the FP32-compensated vs FP64 waveform study")
@@ -552,11 +550,8 @@ def main():
     else:
         kern = {"fused2": tk.TK_KERNEL_FUSED2, "fused": tk.TK_KERNEL_FUSED,
                 "two_pass": tk.TK_KERNEL_TWO_PASS}[args.kernel]
-        waves = args.waves
-        if waves is None:  # the library's default where that shape is compiled with it
-            waves = st.get_tuning()["waves_per_simd"] if (args.prefetch == 3 and not args.no_nt) else 0
         st.set_tuning(kernel=kern, rows_per_tile=args.rows, graph_steps=args.graph_steps,
-                      prefetch_rows=args.prefetch, nt_stores=not args.no_nt, waves_per_simd=waves)
+                      prefetch_rows=args.prefetch, nt_stores=not args.no_nt)
     t = st.get_tuning()
     kernel = {tk.TK_KERNEL_FUSED2: "fused2", tk.TK_KERNEL_FUSED: "fused",
               tk.TK_KERNEL_TWO_PASS: "two_pass"}[t["kernel"]]

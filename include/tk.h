@@ -143,11 +143,11 @@ typedef struct {
     int graph_steps;   /* steps per captured HIP graph (0 = no graphs)        */
     int prefetch_rows; /* fused kernel: u^n rows in flight per wave, 1 or 3 (0 = 3) */
     int flags;         /* TK_TUNE_* */
-    int waves_per_simd;/* fused kernel: register budget for 3 or 4 waves per SIMD
-                          (0 = the compiler's choice, the default);
-                          compiled combinations: prefetch 3 with non-temporal
-                          stores at 0/3/4, and prefetch 1 or 3 at 0; others
-                          give TK_E_INVALID */
+    int waves_per_simd;/* fused kernel: forced occupancy; must be 0 (the
+                          compiler's register budget).  Budgets for 3 or 4
+                          waves per SIMD spilled registers and never ran
+                          faster, so they are not compiled: other values give
+                          TK_E_INVALID */
 } tk_tuning;
 
 /* Set up the grids of n_inst instances (tortoise inversion, radial and

@@ -727,9 +727,10 @@ tk_status tk_set_tuning(tk_ctx *c, const tk_tuning *t)
     {
         const int pf = t->prefetch_rows == 0 ? 3 : t->prefetch_rows;
         const bool nt = (t->flags & TK_TUNE_NT_STORES) != 0;
-        const int w = t->waves_per_simd;
-        const bool compiled = (pf == 3 && nt && (w == 0 || w == 3 || w == 4)) || (w == 0);
-        if (!compiled) return fail(c, TK_E_INVALID, "launch variant not compiled (waves_per_simd needs prefetch 3 + NT)");
+        (void)pf;
+        (void)nt;
+        if (t->waves_per_simd != 0)
+            return fail(c, TK_E_INVALID, "waves_per_simd must be 0 (forced-occupancy shapes are not compiled)");
     }
     c->tuning = *t;
     if (c->tuning.prefetch_rows == 0) c->tuning.prefetch_rows = 3;
@@ -794,7 +795,7 @@ tk_status tk_autotune(tk_ctx *c, int warmup, int steps, double *best_ms_per_step
     // candidates: every compiled fused shape with the two-step kernel (whole
     // strips) and the one-step kernel (whole strips, or chunks of rows, which
     // give a small workload more waves), and the two-pass kernel (FP64)
-    const int shapes[][3] = {{3, 1, 0}, {3, 1, 3}, {3, 1, 4}, {3, 0, 0}, {1, 1, 0}, {1, 0, 0}};
+    const int shapes[][3] = {{3, 1, 0}, {3, 0, 0}, {1, 1, 0}, {1, 0, 0}};
     std::vector<tk_tuning> cand;
     for (const auto &sh : shapes)
         cand.push_back(tk_tuning{TK_KERNEL_FUSED2, 0, 0, sh[0], sh[1] ? TK_TUNE_NT_STORES : 0, sh[2]});

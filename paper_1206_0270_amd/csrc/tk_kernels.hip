@@ -166,12 +166,16 @@ namespace {
 
 // Arithmetic / storage policy, prefetch depth (u^n rows in flight per wave:
 // 1 or 3), non-temporal stores, and the occupancy the register allocator
-// must reach (waves per SIMD; 1 leaves the choice to the compiler).
+// must reach (waves per SIMD; 1 leaves the choice to the compiler, the only
+// value compiled: higher targets spill registers, never ran faster, and a
+// spill reload can leave the registers of inactive lanes stale, which the
+// cross-lane column exchange then reads).
 template <int PD, bool NT, int W>
 struct PolicyF64 {
     using T = double;
     static constexpr bool kComp = false;
     static constexpr bool kRadRegs = true;  // radial factors in registers (else LDS)
+    static constexpr bool kMaskHalo = false;  // lanes off the grid load and compute unmasked
     static constexpr int kPD = PD;
     static constexpr bool kNT = NT;
     static constexpr int kWaves = W;
@@ -181,6 +185,7 @@ struct PolicyF32C {
     using T = float;
     static constexpr bool kComp = true;
     static constexpr bool kRadRegs = false;
+    static constexpr bool kMaskHalo = true;  // measured faster with them masked
     static constexpr int kPD = PD;
     static constexpr bool kNT = NT;
     static constexpr int kWaves = W;
@@ -193,47 +198,40 @@ struct St {  // stored value of a point: f (+ c in the compensated form)
 
 // Neighbour-column exchange inside the wave by DPP wave shifts (a vector
 // move, no LDS round trip): shfl_down1 gives lane l the value of lane l+1,
-// shfl_up1 that of lane l-1; the lane at the open end gets 0 (it is a halo
-// lane whose result is never stored).
-__device__ __forceinline__ float dpp_down1(float v)
+// shfl_up1 that of lane l-1; the lane at the open end gets 0 (bound_ctrl; it
+// is a halo lane whose result is never stored).  Every row and bank is
+// enabled and bound_ctrl supplies the one lane without a source, so no lane
+// keeps an old value: the move takes none, and the destination needs no
+// initialisation.
+template <int CTRL>
+__device__ __forceinline__ int dpp_shift(int v)
 {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x130, 0xf, 0xf, true));
+    return __builtin_amdgcn_mov_dpp(v, CTRL, 0xf, 0xf, true);
 }
-__device__ __forceinline__ float dpp_up1(float v)
+constexpr int kWaveShl1 = 0x130, kWaveShr1 = 0x138;  // wave_shl:1, wave_shr:1
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v)
 {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x138, 0xf, 0xf, true));
+    return __builtin_bit_cast(float, dpp_shift<CTRL>(__builtin_bit_cast(int, v)));
 }
-__device__ __forceinline__ double dpp_down1(double v)
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v)
 {
     const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, 0x130, 0xf, 0xf, true);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), 0x130, 0xf, 0xf, true);
-    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
-}
-__device__ __forceinline__ double dpp_up1(double v)
-{
-    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, 0x138, 0xf, 0xf, true);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), 0x138, 0xf, 0xf, true);
+    const int lo = dpp_shift<CTRL>((int)(unsigned)b);
+    const int hi = dpp_shift<CTRL>((int)(unsigned)(b >> 32));
     return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
 }
 
-// The exchange a launch shape uses: DPP, except in the shapes compiled for a
-// forced occupancy (kWaves > 1), which spill registers.  There the LDS
-// permute is kept: with DPP the four-wave FP64 shape produced non-finite
-// values on sourced instances (a DPP move reads the registers of every lane,
-// and spill reloads under a partial EXEC mask can leave other lanes stale).
 template <class P, typename T>
 __device__ __forceinline__ T down1(T v)
 {
-    if constexpr (P::kWaves > 1) return __shfl_down(v, 1);
-    else return dpp_down1(v);
+    return dpp_move<kWaveShl1>(v);
 }
 template <class P, typename T>
 __device__ __forceinline__ T up1(T v)
 {
-    if constexpr (P::kWaves > 1) return __shfl_up(v, 1);
-    else return dpp_up1(v);
+    return dpp_move<kWaveShr1>(v);
 }
 
 template <class P, typename T>
@@ -304,7 +302,8 @@ struct Lane {
     T *rad;              // this lane's radial factors in LDS: [2 nodes][kRadF/2 pairs] with a stride of 64 pairs
     RadF<T> rf[2];       // or in registers (half node, node)
     int c, p, nt;
-    bool cin, hv, icol;
+    int cl;  // c clamped into the grid: the column this lane reads
+    bool hv, icol;
     bool ov;              // this lane's column is one the work item writes
     bool near_h, near_n;  // half node / node lies on the source window
     double gh, gn;        // tabulated A g_r there
@@ -316,10 +315,14 @@ __device__ __forceinline__ St<typename P::T> load_row(const Lane<P> &L, int row)
 {
     using T = typename P::T;
     St<T> v;
-    v.f = zero_q4<T>();
-    v.c = zero_q4<T>();
-    if (!L.cin) return v;
-    const size_t o = (size_t)row * L.p + L.c;
+    if constexpr (P::kMaskHalo) {
+        if (L.cl != L.c) {
+            v.f = zero_q4<T>();
+            v.c = zero_q4<T>();
+            return v;
+        }
+    }
+    const size_t o = (size_t)row * L.p + L.cl;
     if constexpr (!P::kComp) {
         v.f = ld_p4((const double4 *)L.u + o);
     } else {
@@ -359,6 +362,28 @@ __device__ __forceinline__ AngF<typename P::T> angf_of(const DevInst &I, int row
 
 // g_theta of the particle source on a row (0 off its window)
 __device__ __forceinline__ double src_theta(const DevInst &I, int row) { return (cload_ptr(I.ang) + row)->srcg; }
+
+// The bracket's source argument off the source: -0 makes its innermost
+// multiply-add a plain multiply.
+template <typename T>
+__device__ __forceinline__ cx<T> no_source()
+{
+    return mkc(T(-0.0), T(-0.0));
+}
+
+// FP64 form: the source enters the bracket D du / h - S as -F, only on rows
+// whose theta factor is non-zero.  The test is on the table entry's bits, a
+// wave-uniform scalar comparison, so rows off the window (and instances
+// without a source) skip the work; g_r = 0 makes F zero in the other lanes.
+__device__ __forceinline__ void add_source(double gq, const DevInst &I, int row, cd e, Q4<double> &br)
+{
+    const unsigned long long bits = *(const TK_CONST unsigned long long *)&(cload_ptr(I.ang) + row)->srcg;
+    if (bits != 0ull) {
+        asm volatile("");  // keeps this a branch: selects would do the work on every row
+        const cd F = source_value(gq, __builtin_bit_cast(double, bits), e);
+        br.pi = mkc(br.pi.re - F.re, br.pi.im - F.im);
+    }
+}
 
 template <class P>
 __device__ __forceinline__ double value_of(const St<typename P::T> &v, int k)
@@ -450,15 +475,19 @@ __device__ __forceinline__ Q4<typename P::T> half_row(const Lane<P> &L, const Le
     const DevInst &I = *L.I;
     const cx<T> nm = shfl_down1<P>(UM.phi), np = shfl_down1<P>(UP.phi);
     const Q4<T> n0 = shfl_down1<P>(U0);
-    if (!L.hv) return zero_q4<T>();
+    // lanes without a half node (c = n_r - 1 and off the grid) feed only
+    // out_row lanes that do not update: computing them unmasked (FP64) or
+    // returning zero (FP32C) gives the same stored results
+    if constexpr (P::kMaskHalo)
+        if (!L.hv) return zero_q4<T>();
     const Q4<T> du = n0 - U0;
     const Q4<T> bar = mid_from(U0, du);
     const CoefF<T> cf = coef_fused(radf_of(L, 0), angf_of<P>(I, r));
     const T fac = T(0.5) * L.dt;
     if constexpr (!P::kComp) {
-        // F is exactly zero off the source window (g_r = 0 there)
-        const cd F = source_value(L.gh, src_theta(I, r), lv.eh);
-        return lw_update(bar, fac, bracket_fused(cf, nm + UM.phi, np + UP.phi, bar.phi, bar.pi, du, F));
+        Q4<T> br = bracket_fused(cf, nm + UM.phi, np + UP.phi, bar.phi, bar.pi, du, no_source<T>());
+        add_source(L.gh, I, r, lv.eh, br);
+        return lw_update(bar, fac, br);
     } else {
         Q4<T> h = lw_update(bar, fac, bracket_fused(cf, nm + UM.phi, np + UP.phi, bar.phi, bar.pi, du,
                                                     mkc(T(0), T(0))));
@@ -501,8 +530,9 @@ __device__ __forceinline__ St<typename P::T> out_row(const Lane<P> &L, const Lev
     const Q4<T> til = mid_from(l0, du);
     const CoefF<T> cf = coef_fused(radf_of(L, 1), angf_of<P>(I, o));
     if constexpr (!P::kComp) {
-        const cd F = source_value(L.gn, src_theta(I, o), lv.ef);
-        res.f = lw_update(Uo.f, L.dt, bracket_fused(cf, HM.phi + lm, HP.phi + lp, til.phi, til.pi, du, F));
+        Q4<T> br = bracket_fused(cf, HM.phi + lm, HP.phi + lp, til.phi, til.pi, du, no_source<T>());
+        add_source(L.gn, I, o, lv.ef, br);
+        res.f = lw_update(Uo.f, L.dt, br);
     } else {
         const Q4<T> br = bracket_fused(cf, HM.phi + lm, HP.phi + lp, til.phi, til.pi, du, mkc(T(0), T(0)));
         const T *bp = &br.phi.re, *fp = &Uo.f.phi.re, *cp = &Uo.c.phi.re;
@@ -722,7 +752,11 @@ __device__ __forceinline__ void init_lane(Lane<P> &L, const DevInst &I, const Wo
     L.nt = I.n_theta;
     const int nr = I.n_r;
     L.c = it.i0 - halo + lane;
-    L.cin = L.c >= 0 && L.c < nr;
+    // a lane off the grid reads the nearest column (or zero, P::kMaskHalo):
+    // what it computes reaches only results that are never stored (halo
+    // lanes, and the boundary columns, which out_row sets to zero), so lanes
+    // can load and compute without masks
+    L.cl = L.c < 0 ? 0 : (L.c >= nr ? nr - 1 : L.c);
     L.hv = L.c >= 0 && L.c <= nr - 2;
     L.icol = L.c >= 1 && L.c <= nr - 2;
     L.ov = lane >= halo && lane < halo + cols && L.c < nr;
@@ -886,8 +920,6 @@ hipError_t launch_variant(const DevInst *d_inst, const WorkItem *d_work, int n_w
     if (f.prefetch == PD && f.nt == NT && f.waves == W)                                                    \
         return launch_as<Pol<PD, NT, W>>(d_inst, d_work, n_work, cols, ctl, kstep, kflip, f.two_step, s);
     TK_VARIANT(3, true, 1)
-    TK_VARIANT(3, true, 3)
-    TK_VARIANT(3, true, 4)
     TK_VARIANT(3, false, 1)
     TK_VARIANT(1, true, 1)
     TK_VARIANT(1, false, 1)

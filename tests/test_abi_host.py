@@ -94,6 +94,8 @@ def test_tuning_validation():
     for bad in (tk.Tuning(7, 0, 0, 0, 0, 0), tk.Tuning(tk.TK_KERNEL_FUSED, 2, 0, 0, 0, 0),
                 tk.Tuning(tk.TK_KERNEL_FUSED, 0, 0, 2, 0, 0), tk.Tuning(tk.TK_KERNEL_FUSED, 0, 0, 3, 8, 0),
                 tk.Tuning(tk.TK_KERNEL_FUSED, 0, 0, 1, 1, 4), tk.Tuning(tk.TK_KERNEL_FUSED2, 8, 0, 3, 1, 0),
+                tk.Tuning(tk.TK_KERNEL_FUSED, 0, 0, 3, tk.TK_TUNE_NT_STORES, 4),
+                tk.Tuning(tk.TK_KERNEL_FUSED2, 0, 0, 3, tk.TK_TUNE_NT_STORES, 3),
                 tk.Tuning(4, 0, 0, 3, 1, 0)):
         assert lib.tk_set_tuning(ctx, ctypes.byref(bad)) == tk.TK_E_INVALID
     ok = tk.Tuning(tk.TK_KERNEL_TWO_PASS, 8, 50, 1, tk.TK_TUNE_NT_STORES, 0)
@@ -101,7 +103,7 @@ def test_tuning_validation():
     got = tk.Tuning()
     assert lib.tk_get_tuning(ctx, ctypes.byref(got)) == tk.TK_OK
     assert (got.kernel, got.rows_per_tile, got.graph_steps, got.prefetch_rows, got.flags) == (1, 8, 50, 1, 1)
-    ok = tk.Tuning(tk.TK_KERNEL_FUSED, 0, 0, 3, tk.TK_TUNE_NT_STORES, 4)
+    ok = tk.Tuning(tk.TK_KERNEL_FUSED, 0, 0, 3, 0, 0)
     assert lib.tk_set_tuning(ctx, ctypes.byref(ok)) == tk.TK_OK
     ok = tk.Tuning(tk.TK_KERNEL_FUSED2, 0, 100, 1, tk.TK_TUNE_NT_STORES, 0)
     assert lib.tk_set_tuning(ctx, ctypes.byref(ok)) == tk.TK_OK

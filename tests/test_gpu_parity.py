@@ -198,11 +198,9 @@ def test_launch_variants_bitwise(precision):
     # prefetch depth and store kind change scheduling only, never arithmetic
     insts = small_instances()
     base = gpu_run(insts, 40, prefetch=3, precision=precision)
-    # (forced-occupancy shapes spill registers and exchange columns through
-    # LDS instead of DPP; rows 7 with four waves once went non-finite)
-    for pf, nt, rows, w in [(1, False, 0, 0), (3, False, 0, 0), (1, True, 5, 0), (3, True, 0, 3), (3, True, 7, 4),
-                            (3, True, 0, 4), (3, True, 64, 3)]:
-        other = gpu_run(insts, 40, prefetch=pf, nt=nt, rows=rows, waves=w, precision=precision)
+    for pf, nt, rows in [(1, False, 0), (3, False, 0), (1, True, 0), (1, True, 5), (3, True, 7), (3, False, 64),
+                         (1, False, 16)]:
+        other = gpu_run(insts, 40, prefetch=pf, nt=nt, rows=rows, precision=precision)
         for (a, b) in zip(base, other):
             assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
 
@@ -264,7 +262,7 @@ def test_autotune_leaves_the_simulation_unchanged(precision):
     ms, n = st.autotune(warmup=2, steps=4)
     t = st.get_tuning()
     say("autotune:", n, "shapes, best", f"{ms:.4f} ms/step", t)
-    assert n >= 24 and ms > 0 and st.step_index == 20
+    assert n >= 16 and ms > 0 and st.step_index == 20
     st.step(20)
     for k in range(len(insts)):
         phi, pi = st.get_fields(k)
