@@ -388,7 +388,7 @@ def segments_study(args):
 
     torch.cuda.set_device(0)
     inst = W.instance(a=0.9, m=2, n_r=8001, n_theta=33, rstar_min=-20.0, rstar_max=1980.0, rstar_obs=40.0,
-                      source=dict(r0=10.0, phase0=0.7), name="kerr a=0.9 m=2 r0=10")
+                      source=dict(r0=10.0, phase0=0.7, ramp=args.seg_ramp), name="kerr a=0.9 m=2 r0=10")
     T, n, ov = args.seg_total, args.seg_count, args.seg_overlap
     segs, info = SEG.plan(inst, T, n, ov)
     K, dt = inst["extract_every"], inst["dt"]
@@ -432,8 +432,9 @@ def segments_study(args):
         "metric": "temporal segments (Section 4) on one GPU: time to solution of a long waveform, one run vs "
                   "batched segments, and the patched waveform's agreement with the long run",
         "workload": f"Kerr a=0.9, s=-2, m=2, circular orbit r0=10M; 8001 x 33 on [-20,1980]M, observer 40M "
-                    f"(equator row); T = {n_total * K * dt:.0f}M",
-        "segments": n, "segment_M": info["L"], "overlap_M": info["overlap"],
+                    f"(equator row); T = {n_total * K * dt:.0f}M; every run switches its source on over "
+                    f"{args.seg_ramp}M",
+        "segments": n, "segment_M": info["L"], "overlap_M": info["overlap"], "ramp_M": args.seg_ramp,
         "long_run": {"seconds": t_long, "steps": n_total * K, "updates_per_s": pts * n_total * K / t_long,
                      "tuning": tune_long},
         "batched_segments": {"seconds": t_seg, "steps": info["steps"], "instances": n,
@@ -489,6 +490,8 @@ def main():
     ap.add_argument("--seg-total", type=float, default=3600.0, help="segments study: length of the long run (M)")
     ap.add_argument("--seg-count", type=int, default=36, help="segments study: number of segments")
     ap.add_argument("--seg-overlap", type=float, default=300.0, help="segments study: overlap per segment (M)")
+    ap.add_argument("--seg-ramp", type=float, default=0.0,
+                    help="segments study: switch-on time of the source in every run (M; 0 = abrupt)")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="instead of the stepper, run a plain device copy of this many GiB "
                          "(calibrates the HBM byte counters)")

@@ -117,6 +117,14 @@ typedef struct {
     double sigma_r_cells, sigma_th_cells, window_sigmas;
     double t0; /* time along the orbit at step 0: a segment of a long run
                   (Section 4's temporal decomposition) starts at t0 */
+    double ramp; /* switch-on time T_on (M; 0 = the full source from step
+                    0): F is multiplied by s(t / T_on), t = n dt the time
+                    since step 0 and s the smooth step
+                    e^{-1/x} / (e^{-1/x} + e^{-1/(1-x)}) on 0 < x < 1 (0
+                    below, 1 above), every derivative of which vanishes at
+                    both ends, so that a run started from zero fields leaves
+                    no persistent junk (Section 4's known techniques for the
+                    junk burst of each segment) */
 } tk_source_desc;
 
 /* Kernel choice and launch shape (the only per-architecture tuning the

@@ -36,6 +36,7 @@ class OrDesc(ctypes.Structure):
         ("src_sigma_th_cells", ctypes.c_double),
         ("src_window_sigmas", ctypes.c_double),
         ("src_t0", ctypes.c_double),
+        ("src_ramp", ctypes.c_double),
     ]
 
 
@@ -163,6 +164,7 @@ class Grid:
             d.src_sigma_th_cells = source.get("sigma_th_cells", 2.0)
             d.src_window_sigmas = source.get("window_sigmas", 6.0)
             d.src_t0 = source.get("t0", 0.0)
+            d.src_ramp = source.get("ramp", 0.0)
         self.desc = d
         self.n_r, self.n_theta = n_r, n_theta
         self.h = (rstar_max - rstar_min) / (n_r - 1)

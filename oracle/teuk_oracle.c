@@ -210,11 +210,13 @@ typedef struct {
     double rstar_min, rstar_max, dt;
     int i_obs;         /* extraction column (r* index) */
     int extract_every; /* steps between waveform samples; 0 = none */
-    /* synthetic particle source; kind 0 = none, 1 = Gaussian circular orbit */
+    /* synthetic particle source; kind 0 = none, 1 = Gaussian circular orbit,
+       2 / 3 = the step / linear discrete delta */
     int src_kind;
     double src_r0, src_amp, src_phase0;
     double src_sigma_r_cells, src_sigma_th_cells, src_window_sigmas;
-    double src_t0; /* time along the orbit at step 0 (a segment's start) */
+    double src_t0;   /* time along the orbit at step 0 (a segment's start) */
+    double src_ramp; /* switch-on time of the source (0 = none) */
 } or_desc;
 
 typedef struct {
@@ -298,7 +300,20 @@ static real discrete_delta(int kind, real x, real xp, real dx)
     return (ramp_step(x - xp, dx) - ramp_step(x - dx - xp, dx)) / dx;
 }
 
-/* Synthetic particle source F(t, r*, theta). */
+/* Smooth switch-on of the source (the remedy for the junk of a run that
+ * starts with the source at full strength, Section 4): the step
+ *   s(x) = f(x) / (f(x) + f(1 - x)),  f(x) = exp(-1/x) for x > 0, 0 else,
+ * which is 0 for x <= 0, 1 for x >= 1 and has every derivative zero at both
+ * ends. */
+static real bump_tail(real x) { return x > 0 ? exp(-1 / x) : 0; }
+
+static real switch_on(real x)
+{
+    real a = bump_tail(x), b = bump_tail(1 - x);
+    return a / (a + b);
+}
+
+/* Synthetic particle source F(t, r*, theta), t the time since step 0. */
 static cplx source_at(const or_grid *g, real t, real rstar, real th)
 {
     const or_desc *d = &g->desc;
@@ -315,7 +330,8 @@ static cplx source_at(const or_grid *g, real t, real rstar, real th)
     if (gr == 0 || gt == 0)
         return 0;
     real phase = -(real)d->m * (g->src_Omega * (t + (real)d->src_t0) + (real)d->src_phase0);
-    return (real)d->src_amp * gr * gt * (cos(phase) + IU * sin(phase));
+    real w = d->src_ramp > 0 ? switch_on(t / (real)d->src_ramp) : 1;
+    return (real)d->src_amp * w * gr * gt * (cos(phase) + IU * sin(phase));
 }
 
 /* ------------------------------------------------------------------ */

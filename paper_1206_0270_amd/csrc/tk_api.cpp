@@ -207,6 +207,7 @@ DevInst make_dev(const tk_ctx *c, const HostInst &h)
     D.src_sig_th = h.src.sigma_th_cells * h.dth;
     D.src_win = h.src.window_sigmas;
     D.src_t0 = h.src.t0;
+    D.src_ramp_inv = h.src.ramp > 0.0 ? 1.0 / h.src.ramp : 0.0;
     D.a2 = d.a * d.a;
     D.kct = -2.0 * d.s * d.a;
     return D;
@@ -590,6 +591,8 @@ tk_status tk_set_source(tk_ctx *c, int inst, const tk_source_desc *src)
         if (!(s.r0 > h.rp) || !std::isfinite(s.r0)) return fail(c, TK_E_INVALID, "r0 must lie outside the horizon");
         if (!std::isfinite(s.amplitude) || !std::isfinite(s.phase0) || !std::isfinite(s.t0))
             return fail(c, TK_E_INVALID, "source amplitude, phase and t0 must be finite");
+        if (!(s.ramp >= 0.0) || !std::isfinite(s.ramp))
+            return fail(c, TK_E_INVALID, "source ramp must be finite and >= 0");
         if (s.kind == TK_SRC_CIRCULAR_GAUSSIAN &&
             (!(s.sigma_r_cells > 0) || !(s.sigma_th_cells > 0) || !(s.window_sigmas > 0) ||
              !std::isfinite(s.sigma_r_cells) || !std::isfinite(s.sigma_th_cells) || !std::isfinite(s.window_sigmas)))

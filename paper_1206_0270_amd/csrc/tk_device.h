@@ -321,11 +321,22 @@ __device__ __forceinline__ Q4<T> lw_point(const Coef<T> &c, const Q4<T> &base, c
     return Q4<T>{base.phi - fac * br.phi, base.pi - fac * br.pi};
 }
 
-// Time factor of the smeared particle source, exp(-i m (Omega (t + t0) + phase0)).
+// Smooth switch-on s(x): 0 for x <= 0, 1 for x >= 1, and
+// e^{-1/x} / (e^{-1/x} + e^{-1/(1-x)}) = 1 / (1 + e^{1/x - 1/(1-x)}) between.
+__device__ __forceinline__ double switch_on(double x)
+{
+    if (x <= 0.0) return 0.0;
+    if (x >= 1.0) return 1.0;
+    return 1.0 / (1.0 + exp(1.0 / x - 1.0 / (1.0 - x)));
+}
+
+// Time factor of the particle source at time t since step 0:
+// s(t / T_on) exp(-i m (Omega (t + t0) + phase0)).
 __device__ __forceinline__ cd source_phase(const DevInst &I, double t)
 {
     const double ph = -(double)I.m * (I.src_Omega * (t + I.src_t0) + I.src_phase0);
-    return mk(cos(ph), sin(ph));
+    const double w = I.src_ramp_inv > 0.0 ? switch_on(t * I.src_ramp_inv) : 1.0;
+    return mk(w * cos(ph), w * sin(ph));
 }
 
 // F(t, r*_q, theta_j) = [A g_r(q)] g_theta(j) exp(-i m (Omega t + phase0));

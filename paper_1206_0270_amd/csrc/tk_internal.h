@@ -72,7 +72,8 @@ struct alignas(16) DevInst {
     int src_kind, pad1, pad2, pad3;
     double src_amp, src_phase0, src_Omega, src_rstar_p;
     double src_sig_r, src_sig_th, src_win, src_t0;
-    double a2, kct, pad5, pad6;  // a^2 and -2 s a (to rebuild a^2 Delta and Im ct's cos part)
+    double a2, kct;        // a^2 and -2 s a (to rebuild a^2 Delta and Im ct's cos part)
+    double src_ramp_inv, pad6;  // 1 / T_on of the source's switch-on (0: none)
 };
 
 // Fused-kernel work item: a block of columns [i0, i0 + width) x rows [j0, j1)

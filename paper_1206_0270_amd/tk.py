@@ -50,7 +50,7 @@ class SourceDesc(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("r0", ctypes.c_double), ("amplitude", ctypes.c_double),
                 ("phase0", ctypes.c_double), ("sigma_r_cells", ctypes.c_double),
                 ("sigma_th_cells", ctypes.c_double), ("window_sigmas", ctypes.c_double),
-                ("t0", ctypes.c_double)]
+                ("t0", ctypes.c_double), ("ramp", ctypes.c_double)]
 
 
 TK_TUNE_NT_STORES = 1
@@ -137,6 +137,7 @@ def make_source(src):
     s.sigma_th_cells = src.get("sigma_th_cells", 2.0)
     s.window_sigmas = src.get("window_sigmas", 6.0)
     s.t0 = src.get("t0", 0.0)
+    s.ramp = src.get("ramp", 0.0)
     return s
 
 

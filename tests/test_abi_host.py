@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layout_matches_header():
     # the ctypes mirrors must have the C sizes (x86-64 ABI)
     assert ctypes.sizeof(tk.InstanceDesc) == 80
-    assert ctypes.sizeof(tk.SourceDesc) == 64
+    assert ctypes.sizeof(tk.SourceDesc) == 72
     assert ctypes.sizeof(tk.Tuning) == 24
 
 

@@ -15,6 +15,7 @@ import oracle
 from oracle import build as orbuild
 
 import test_oracle_pins as PINS
+import test_segments as SEGS
 import test_source_shapes as SHAPES
 
 # (name, original text (must occur exactly once), replacement, pins to run)
@@ -51,6 +52,10 @@ MUTANTS = [
      "discrete_delta(d->src_kind, rstar, g->src_rstar_p, g->h / 2);", ["delta_linear", "delta_step"]),
     ("theta delta takes the radial spacing", "discrete_delta(d->src_kind, th, PI_R / 2, g->dth);",
      "discrete_delta(d->src_kind, th, PI_R / 2, g->h);", ["delta_theta"]),
+    ("switch-on not mirrored", "real a = bump_tail(x), b = bump_tail(1 - x);",
+     "real a = bump_tail(x), b = bump_tail(x);", ["switch_on"]),
+    ("switch-on counted from the orbit's origin", "switch_on(t / (real)d->src_ramp)",
+     "switch_on((t + (real)d->src_t0) / (real)d->src_ramp)", ["switch_on"]),
 ]
 
 
@@ -79,6 +84,8 @@ def run_pin(name, kind):
     elif name == "delta_step":
         for q0 in (0, 1):
             SHAPES.step_delta_check(q0, kind=kind)
+    elif name == "switch_on":
+        SEGS.switch_on_check(kind=kind)
     elif name == "delta_theta":
         for case in SHAPES.THETA_CASES:
             SHAPES.theta_delta_check(*case, kind=kind)
@@ -93,7 +100,8 @@ def src_text():
 
 
 def test_unmutated_source_passes_the_detectors(src_text):
-    for pin in ("mms_even", "mms_odd", "eig", "tortoise", "source", "delta_linear", "delta_step", "delta_theta"):
+    for pin in ("mms_even", "mms_odd", "eig", "tortoise", "source", "delta_linear", "delta_step", "delta_theta",
+                "switch_on"):
         run_pin(pin, "f64")
 
 

@@ -49,6 +49,42 @@ def test_source_time_origin_continues_a_run():
     assert np.max(np.abs(c.get_state()[0] - pa)) > 1e-3 * np.max(np.abs(pa))
 
 
+def _switch_on(g, t, T_on, rstar, theta):
+    """The oracle's ramp factor at time t: F with the ramp over F without."""
+    return g.source_value(t, rstar, theta) / g.unramped.source_value(t, rstar, theta)
+
+
+def switch_on_check(kind="f64"):
+    """F(t) = s(t / T_on) F_full(t), t the time since step 0 whatever the
+    orbit's time origin t0: s vanishes for t <= 0 with every derivative
+    (flat: below any power of t near 0), is 1 from T_on on, 1/2 at the
+    midpoint, and s(x) + s(1 - x) = 1 (the step is built symmetric); between,
+    it rises monotonically."""
+    T_on = 40.0
+    inst = _inst(source=dict(r0=7.0, phase0=0.3, t0=15.0, ramp=T_on))
+    g = _grid(inst, kind)
+    g.unramped = _grid(_inst(source=dict(r0=7.0, phase0=0.3, t0=15.0)), kind)
+    rs, _ = g.radial()
+    xp = oracle.tortoise(1.0, 0.7, 7.0 - (1 + np.sqrt(1 - 0.49)))
+    r = rs[int(np.argmin(np.abs(rs - xp)))]
+    th = np.pi / 2
+    s = lambda x: _switch_on(g, x * T_on, T_on, r, th)
+    assert g.source_value(-1.0, r, th) == 0 and g.source_value(0.0, r, th) == 0
+    assert abs(s(1.0) - 1) < 1e-15 and abs(s(1.7) - 1) < 1e-15 and abs(s(0.5) - 0.5) < 1e-14
+    for x in (0.05, 0.2, 0.37, 0.8):
+        assert abs(s(x) + s(1 - x) - 1) < 1e-13
+        assert abs(s(x).imag) < 1e-13
+    xs = np.linspace(0.01, 0.99, 99)
+    v = np.array([s(x).real for x in xs])
+    assert np.all(np.diff(v) >= 0) and np.all(np.diff(v[10:-10]) > 0)  # it reaches 1.0 in double near x = 1
+    for k in (2, 4, 8):  # flat at the start: s(x) / x^k -> 0
+        assert s(0.02).real / 0.02 ** k < 1e-3
+
+
+def test_source_switch_on_shape():
+    switch_on_check()
+
+
 def test_plan_and_patch_bookkeeping():
     inst = _inst()
     segs, info = SEG.plan(inst, t_total=30.0, n_seg=3, overlap=4.0)
@@ -106,7 +142,7 @@ def test_oracle_segments_reproduce_the_long_run_after_the_overlap():
 def test_batched_gpu_segments_match_the_oracle_segments():
     import test_gpu_parity as GP
     from paper_1206_0270_amd import tk
-    inst = _inst()
+    inst = _inst(source=dict(r0=7.0, phase0=0.3, ramp=4.0))  # each segment switches its source on smoothly
     segs, info = SEG.plan(inst, 30.0, 4, 6.0)
     res = GP.gpu_run(segs, info["steps"])  # one batched context, every segment one instance
     gp, op = [], []

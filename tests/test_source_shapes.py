@@ -199,10 +199,10 @@ def test_point_source_forms_converge_to_one_limit():
 def _delta_instances():
     rng = W.rng_for(4242)
     out = []
-    for (n_r, n_th, a, m, shape) in [(130, 17, 0.9, 2, "linear_delta"), (101, 9, 0.0, 2, "step_delta"),
-                                     (77, 16, 0.6, 3, "linear_delta"), (200, 13, 0.3, -1, "step_delta"),
-                                     (125, 33, 0.99, 4, "linear_delta")]:
-        src = dict(r0=6.0 + 3 * rng.uniform(), phase0=float(rng.uniform(0, 6.28)), shape=shape)
+    for (n_r, n_th, a, m, shape, ramp) in [(130, 17, 0.9, 2, "linear_delta", 0.0), (101, 9, 0.0, 2, "step_delta", 3.0),
+                                           (77, 16, 0.6, 3, "linear_delta", 0.0), (200, 13, 0.3, -1, "step_delta", 0.0),
+                                           (125, 33, 0.99, 4, "linear_delta", 2.5), (90, 11, 0.5, 2, "gaussian", 4.0)]:
+        src = dict(r0=6.0 + 3 * rng.uniform(), phase0=float(rng.uniform(0, 6.28)), shape=shape, ramp=ramp)
         out.append(W.instance(a=a, s=-2, m=m, n_r=n_r, n_theta=n_th, rstar_min=-20.0, rstar_max=25.0,
                               rstar_obs=20.0, extract_every=3, source=src,
                               name=f"delta.{shape}.{n_r}x{n_th}.a{a}.m{m}"))
