@@ -137,6 +137,8 @@ def precision_study(args):
 
     torch.cuda.set_device(0)
     insts = W.config5()["instances"]
+    if args.study_ramp > 0:  # every source switched on smoothly over study_ramp
+        insts = [dict(i, source=dict(i["source"], ramp=args.study_ramp)) for i in insts]
     dt = insts[0]["dt"]
     steps = int(round(args.study_window / dt))
     steps -= steps % 200
@@ -198,7 +200,9 @@ def precision_study(args):
     out = {
         "metric": "waveform amplitude / phase relative error of the FP32-compensated form vs FP64; updates/s of both",
         "workload": "6 instances m=2,3,4 x a=0.5,0.9, circular orbit r0=8M, 16001 x 129 on [-300,300]M, dt=1/500, "
-                    "waveform at r*=290M projected on the l=max(|m|,2) harmonic",
+                    "waveform at r*=290M projected on the l=max(|m|,2) harmonic"
+                    + (f"; sources switched on over {args.study_ramp}M" if args.study_ramp > 0 else ""),
+        "ramp_M": args.study_ramp,
         "window_M": steps * dt, "steps": steps, "points": points,
         "fp64_updates_per_s": forms["fp64"]["updates_per_s"], "fp32c_updates_per_s": forms["fp32c"]["updates_per_s"],
         "fp32c_speedup": forms["fp32c"]["updates_per_s"] / forms["fp64"]["updates_per_s"],
@@ -473,6 +477,8 @@ def main():
     ap.add_argument("--study-window", type=float, default=600.0, help="precision study: simulated time (M)")
     ap.add_argument("--study-checkpoints", type=float, nargs="+", default=[300.0, 400.0, 500.0, 600.0])
     ap.add_argument("--study-oracle-steps", type=int, default=2000)
+    ap.add_argument("--study-ramp", type=float, default=0.0,
+                    help="precision study: switch-on time of the sources (M; 0 = abrupt)")
     ap.add_argument("--richardson", action="store_true",
                     help="instead of the throughput line, run the three-resolution Richardson study")
     ap.add_argument("--rich-window", type=float, default=330.0, help="Richardson study: simulated time (M)")
