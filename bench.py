@@ -466,7 +466,7 @@ def main():
                     help="auto: the library's autotuner picks the launch shape before timing; "
                          "manual: the shape given by --kernel/--rows/--prefetch/--no-nt")
     ap.add_argument("--rows", type=int, default=0)
-    ap.add_argument("--kernel", default="fused2", choices=["fused2", "fused", "two_pass"],
+    ap.add_argument("--kernel", default="fused2", choices=["fused2", "fused", "two_pass", "tiled"],
                     help="fused2: two time steps per pass (needs --rows 0); fused: one step per pass; "
                          "two_pass: half-step array through HBM")
     ap.add_argument("--prefetch", type=int, default=3, choices=[1, 3])
@@ -558,12 +558,12 @@ def main():
         st.set_tuning(**t)
     else:
         kern = {"fused2": tk.TK_KERNEL_FUSED2, "fused": tk.TK_KERNEL_FUSED,
-                "two_pass": tk.TK_KERNEL_TWO_PASS}[args.kernel]
+                "two_pass": tk.TK_KERNEL_TWO_PASS, "tiled": tk.TK_KERNEL_TILED}[args.kernel]
         st.set_tuning(kernel=kern, rows_per_tile=args.rows, graph_steps=args.graph_steps,
                       prefetch_rows=args.prefetch, nt_stores=not args.no_nt)
     t = st.get_tuning()
     kernel = {tk.TK_KERNEL_FUSED2: "fused2", tk.TK_KERNEL_FUSED: "fused",
-              tk.TK_KERNEL_TWO_PASS: "two_pass"}[t["kernel"]]
+              tk.TK_KERNEL_TWO_PASS: "two_pass", tk.TK_KERNEL_TILED: "tiled"}[t["kernel"]]
     two_step = kernel == "fused2"
     print(f"# workload {args.workload}: {len(insts)} instances, {points} points, "
           f"{st.workspace_bytes / 2**30:.2f} GiB workspace", file=sys.stderr, flush=True)
@@ -594,8 +594,13 @@ def main():
     launch_s = gpu_ms / 1e3 / launches
     bpu = BYTES_PER_UPDATE[args.precision]
     achieved = points * spl * bpu / launch_s / 1e9
-    kname = (kernel_name(args.precision, t["prefetch_rows"], t["nt_stores"], t["waves_per_simd"], two_step)
-             if kernel != "two_pass" else "k_two_pass_half + k_two_pass_full")
+    if kernel == "two_pass":
+        kname = "k_two_pass_half + k_two_pass_full"
+    elif kernel == "tiled":  # tile capacity: rows_per_tile + 2
+        kname = (f"k_tiled<{KERNEL_POLICY[args.precision]}<1, {'true' if t['nt_stores'] else 'false'}, 1>, "
+                 f"{t['rows_per_tile'] + 2}>")
+    else:
+        kname = kernel_name(args.precision, t["prefetch_rows"], t["nt_stores"], t["waves_per_simd"], two_step)
     traffic = traffic_entry(kname, args.workload)
     st.close()
 

@@ -134,10 +134,15 @@ typedef enum {
                                fused forms only) */
     TK_KERNEL_TWO_PASS = 1, /* half-step array through HBM, one thread per point */
     TK_KERNEL_FUSED = 2,    /* both stages in one pass, theta-marching columns   */
-    TK_KERNEL_FUSED2 = 3    /* two time steps per pass over whole column strips:
+    TK_KERNEL_FUSED2 = 3,   /* two time steps per pass over whole column strips:
                                u^n read and u^{n+2} written once, u^{n+1} kept
                                on chip (an odd step count ends with one FUSED
                                step); results are bitwise those of FUSED */
+    TK_KERNEL_TILED = 4     /* one step on tiles of rows_per_tile (4 or 8) rows
+                               by 62 columns, one block of four waves per tile
+                               with its rows staged in LDS: for grids too small
+                               to give the marching kernels enough waves;
+                               results are bitwise those of FUSED */
 } tk_kernel;
 
 enum {

@@ -244,6 +244,9 @@ hipError_t launch_one(tk_ctx *c, int kernel, int steps, int kstep, int kflip)
         return launch_two_pass(di, (const int2 *)(c->ws + c->off_blocks), (int)c->blocks.size(), ctl, kstep, kflip,
                                c->stream);
     const WorkItem *wk = (const WorkItem *)(c->ws + c->off_work);
+    if (kernel == TK_KERNEL_TILED)
+        return launch_tiled(c->prec == TK_FP64, di, wk, (int)c->work.size(), c->tuning.rows_per_tile, ctl, kstep,
+                            kflip, (c->tuning.flags & TK_TUNE_NT_STORES) != 0, c->stream);
     FusedShape f;
     f.prefetch = c->tuning.prefetch_rows == 1 ? 1 : 3;
     f.nt = (c->tuning.flags & TK_TUNE_NT_STORES) != 0;
@@ -715,8 +718,10 @@ tk_status tk_set_step(tk_ctx *c, long step)
 tk_status tk_set_tuning(tk_ctx *c, const tk_tuning *t)
 {
     if (!c || !t) return TK_E_INVALID;
-    if (t->kernel < TK_KERNEL_AUTO || t->kernel > TK_KERNEL_FUSED2)
+    if (t->kernel < TK_KERNEL_AUTO || t->kernel > TK_KERNEL_TILED)
         return fail(c, TK_E_INVALID, "unknown kernel");
+    if (t->kernel == TK_KERNEL_TILED && t->rows_per_tile != 4 && t->rows_per_tile != 8)
+        return fail(c, TK_E_INVALID, "the tiled kernel takes rows_per_tile 4 or 8");
     if (t->kernel == TK_KERNEL_FUSED2 && t->rows_per_tile != 0)
         return fail(c, TK_E_INVALID, "the two-step kernel marches whole strips: rows_per_tile must be 0");
     if (t->kernel == TK_KERNEL_TWO_PASS && c->prec != TK_FP64)
@@ -797,7 +802,8 @@ tk_status tk_autotune(tk_ctx *c, int warmup, int steps, double *best_ms_per_step
     drop_graph(c);
     // candidates: every compiled fused shape with the two-step kernel (whole
     // strips) and the one-step kernel (whole strips, or chunks of rows, which
-    // give a small workload more waves), and the two-pass kernel (FP64)
+    // give a small workload more waves), the tiled kernel (short tiles for
+    // small grids), and the two-pass kernel (FP64)
     const int shapes[][3] = {{3, 1, 0}, {3, 0, 0}, {1, 1, 0}, {1, 0, 0}};
     std::vector<tk_tuning> cand;
     for (const auto &sh : shapes)
@@ -805,6 +811,8 @@ tk_status tk_autotune(tk_ctx *c, int warmup, int steps, double *best_ms_per_step
     for (int rows : {0, 64, 16})
         for (const auto &sh : shapes)
             cand.push_back(tk_tuning{TK_KERNEL_FUSED, rows, 0, sh[0], sh[1] ? TK_TUNE_NT_STORES : 0, sh[2]});
+    for (int rows : {8, 4})
+        for (int ntf : {(int)TK_TUNE_NT_STORES, 0}) cand.push_back(tk_tuning{TK_KERNEL_TILED, rows, 0, 3, ntf, 0});
     if (c->prec == TK_FP64) cand.push_back(tk_tuning{TK_KERNEL_TWO_PASS, 0, 0, 3, TK_TUNE_NT_STORES, 0});
 
     tk_status st = e == hipSuccess ? TK_OK : fail(c, TK_E_DEVICE, std::string("autotune setup: ") + hipGetErrorString(e));

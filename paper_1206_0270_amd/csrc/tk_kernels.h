@@ -33,6 +33,13 @@ struct FusedShape {
 hipError_t launch_fused(bool fp64, const DevInst *d_inst, const WorkItem *d_work, int n_work, int cols,
                         const DevCtl *ctl, int kstep, int kflip, const FusedShape &f, hipStream_t s);
 
+// One step on tiles: one block of kFusedWavesPerBlock waves per work item
+// (strips of kFusedCols columns split into chunks of `rows` rows, 4 or 8),
+// with the tile's u^n and half rows staged in LDS.  Bitwise the results of
+// launch_fused's one-step shapes.  hipErrorInvalidValue for other row counts.
+hipError_t launch_tiled(bool fp64, const DevInst *d_inst, const WorkItem *d_work, int n_work, int rows,
+                        const DevCtl *ctl, int kstep, int kflip, bool nt, hipStream_t s);
+
 // ctl->step += n; ctl->cur flips `flips` times
 hipError_t launch_bump(DevCtl *ctl, int n, int flips, hipStream_t s);
 

@@ -465,16 +465,16 @@ __device__ __forceinline__ St<typename P::T> pole_row(bool even, const St<typena
     return o;
 }
 
-// Eq. (3) at half row r: u^n rows r-1 (UM), r (U0), r+1 (UP) of this column;
-// the column to the right comes by lane shuffles.
+// Eq. (3) at half row r: u^n rows r-1 (UM), r (U0), r+1 (UP) of this column
+// and nm, n0, np of the column to the right (Phi only on rows r -+ 1).
 template <class P>
-__device__ __forceinline__ Q4<typename P::T> half_row(const Lane<P> &L, const Level &lv, const Q4<typename P::T> &UM,
-                                                      const Q4<typename P::T> &U0, const Q4<typename P::T> &UP, int r)
+__device__ __forceinline__ Q4<typename P::T> half_core(const Lane<P> &L, const Level &lv, const Q4<typename P::T> &UM,
+                                                       const Q4<typename P::T> &U0, const Q4<typename P::T> &UP,
+                                                       cx<typename P::T> nm, const Q4<typename P::T> &n0,
+                                                       cx<typename P::T> np, int r)
 {
     using T = typename P::T;
     const DevInst &I = *L.I;
-    const cx<T> nm = shfl_down1<P>(UM.phi), np = shfl_down1<P>(UP.phi);
-    const Q4<T> n0 = shfl_down1<P>(U0);
     // lanes without a half node (c = n_r - 1 and off the grid) feed only
     // out_row lanes that do not update: computing them unmasked (FP64) or
     // returning zero (FP32C) gives the same stored results
@@ -503,6 +503,14 @@ __device__ __forceinline__ Q4<typename P::T> half_row(const Lane<P> &L, const Le
     }
 }
 
+// The same with the column to the right taken by lane shuffles.
+template <class P>
+__device__ __forceinline__ Q4<typename P::T> half_row(const Lane<P> &L, const Level &lv, const Q4<typename P::T> &UM,
+                                                      const Q4<typename P::T> &U0, const Q4<typename P::T> &UP, int r)
+{
+    return half_core(L, lv, UM, U0, UP, shfl_down1<P>(UM.phi), shfl_down1<P>(U0), shfl_down1<P>(UP.phi), r);
+}
+
 // exact sum a + b = s + e (two-sum)
 __device__ __forceinline__ void two_sum(float a, float b, float &s, float &e)
 {
@@ -512,16 +520,16 @@ __device__ __forceinline__ void two_sum(float a, float b, float &s, float &e)
 }
 
 // Eq. (4) at output row o: u^n row o (Uo), half rows o-1 (HM), o (H0), o+1
-// (HP) of this column (at c+1/2); the column at c-1/2 comes by lane shuffles.
+// (HP) of this column (at c+1/2) and lm, l0, lp of the column at c-1/2 (Phi
+// only on rows o -+ 1).
 template <class P>
-__device__ __forceinline__ St<typename P::T> out_row(const Lane<P> &L, const Level &lv, const St<typename P::T> &Uo,
-                                                     const Q4<typename P::T> &HM, const Q4<typename P::T> &H0,
-                                                     const Q4<typename P::T> &HP, int o)
+__device__ __forceinline__ St<typename P::T> out_core(const Lane<P> &L, const Level &lv, const St<typename P::T> &Uo,
+                                                      const Q4<typename P::T> &HM, const Q4<typename P::T> &H0,
+                                                      const Q4<typename P::T> &HP, cx<typename P::T> lm,
+                                                      const Q4<typename P::T> &l0, cx<typename P::T> lp, int o)
 {
     using T = typename P::T;
     const DevInst &I = *L.I;
-    const cx<T> lm = shfl_up1<P>(HM.phi), lp = shfl_up1<P>(HP.phi);
-    const Q4<T> l0 = shfl_up1<P>(H0);
     St<T> res;
     res.f = zero_q4<T>();
     res.c = zero_q4<T>();
@@ -555,6 +563,15 @@ __device__ __forceinline__ St<typename P::T> out_row(const Lane<P> &L, const Lev
         for (int k = 0; k < 4; ++k) rc[k] = bf16_round(rc[k]);
     }
     return res;
+}
+
+// The same with the column at c-1/2 taken by lane shuffles.
+template <class P>
+__device__ __forceinline__ St<typename P::T> out_row(const Lane<P> &L, const Level &lv, const St<typename P::T> &Uo,
+                                                     const Q4<typename P::T> &HM, const Q4<typename P::T> &H0,
+                                                     const Q4<typename P::T> &HP, int o)
+{
+    return out_core(L, lv, Uo, HM, H0, HP, shfl_up1<P>(HM.phi), shfl_up1<P>(H0), shfl_up1<P>(HP.phi), o);
 }
 
 template <class P>
@@ -740,7 +757,7 @@ __device__ __forceinline__ void march2(const Lane<P> &L, const Level &l1, const 
 // lane's radial factors (half node, node) go to its LDS slots.
 template <class P>
 __device__ __forceinline__ void init_lane(Lane<P> &L, const DevInst &I, const WorkItem &it, int lane, int halo,
-                                          int cols, int buf, typename P::T *rad)
+                                          int cols, int buf, typename P::T *rad, bool load_rad = true)
 {
     using T = typename P::T;
     L.I = &I;
@@ -762,6 +779,7 @@ __device__ __forceinline__ void init_lane(Lane<P> &L, const DevInst &I, const Wo
     L.ov = lane >= halo && lane < halo + cols && L.c < nr;
     L.dt = (T)I.dt;
     L.rad = rad;
+    if (!load_rad) return;  // the radial factors come from another wave (tiled kernel)
     const Radial Rh = load_entry(gload_ptr(I.rad) + (L.hv ? 2 * L.c + 1 : 0));
     const Radial Rn = load_entry(gload_ptr(I.rad) + (L.icol ? 2 * L.c : 0));
     typedef T T2 __attribute__((ext_vector_type(2)));
@@ -851,6 +869,168 @@ __global__ void __launch_bounds__(64 * kFusedWavesPerBlock) __attribute__((amdgp
     }
 }
 
+namespace {
+
+// LDS staging of the tiled kernel: a stored point as one 4-vector (f) or two
+// (f, c in the compensated form), a half point as one.
+template <typename T>
+struct Vec4Of;
+template <>
+struct Vec4Of<double> {
+    using type = dvec4;
+};
+template <>
+struct Vec4Of<float> {
+    using type = fvec4;
+};
+
+template <class P>
+__device__ __forceinline__ void lds_put(typename Vec4Of<typename P::T>::type *s, int idx, const St<typename P::T> &v)
+{
+    using V = typename Vec4Of<typename P::T>::type;
+    constexpr int KV = P::kComp ? 2 : 1;
+    s[idx * KV] = V{v.f.phi.re, v.f.phi.im, v.f.pi.re, v.f.pi.im};
+    if constexpr (P::kComp) s[idx * KV + 1] = V{v.c.phi.re, v.c.phi.im, v.c.pi.re, v.c.pi.im};
+}
+
+template <class P>
+__device__ __forceinline__ St<typename P::T> lds_get(const typename Vec4Of<typename P::T>::type *s, int idx)
+{
+    using T = typename P::T;
+    constexpr int KV = P::kComp ? 2 : 1;
+    St<T> v;
+    const auto a = s[idx * KV];
+    v.f = Q4<T>{mkc(a.x, a.y), mkc(a.z, a.w)};
+    if constexpr (P::kComp) {
+        const auto b = s[idx * KV + 1];
+        v.c = Q4<T>{mkc(b.x, b.y), mkc(b.z, b.w)};
+    } else {
+        v.c = zero_q4<T>();
+    }
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ void lds_put_half(typename Vec4Of<T>::type *s, int idx, const Q4<T> &v)
+{
+    s[idx] = typename Vec4Of<T>::type{v.phi.re, v.phi.im, v.pi.re, v.pi.im};
+}
+
+template <typename T>
+__device__ __forceinline__ Q4<T> lds_get_half(const typename Vec4Of<T>::type *s, int idx)
+{
+    const auto a = s[idx];
+    return Q4<T>{mkc(a.x, a.y), mkc(a.z, a.w)};
+}
+
+}  // namespace
+
+// One step on a tile: the output rows [j0, j1) (at most TRC) of a strip of
+// kFusedCols columns, by a block of four waves.  The u^n rows j0-2 .. j1+1
+// are staged in LDS (one row per wave at a time), the half rows j0-1 .. j1
+// are formed in parallel and kept in LDS, then the output rows, and the pole
+// rows last.  A lane's neighbour columns are read from LDS instead of being
+// shuffled; every point is computed by the same row functions as in the
+// marching kernels, so the results are theirs bit for bit.  Many short tiles
+// instead of a few long marches: the shape for grids too small to give the
+// marching kernels enough waves.  One work item per block, every wave takes
+// part in every barrier.
+template <class P, int TRC>
+__global__ void __launch_bounds__(64 * kFusedWavesPerBlock)
+    k_tiled(const DevInst *__restrict__ insts, const WorkItem *__restrict__ work, const DevCtl *__restrict__ ctl,
+            int kstep, int kflip)
+{
+    using T = typename P::T;
+    using V = typename Vec4Of<T>::type;
+    constexpr int NW = kFusedWavesPerBlock;
+    constexpr int KV = P::kComp ? 2 : 1;
+    // the block's four waves share one strip: its radial factors are loaded
+    // once, by wave 0, and passed on through LDS (FP64: the register copies
+    // and the source factors; FP32C: its LDS slots and the source factors)
+    __shared__ T s_rad[P::kRadRegs ? 2 : 2 * kRadF * 64];
+    __shared__ double s_share[(P::kRadRegs ? 2 * kRadF + 2 : 2) * 64];
+    __shared__ V s_u[(TRC + 4) * 64 * KV];  // u^n rows a_lo .. a_hi
+    __shared__ V s_h[(TRC + 2) * 64];       // half rows h_lo .. h_hi
+    __shared__ V s_p[4 * 64 * KV];          // output rows 1, 2 and nt-2, nt-3 for the poles
+    const int lane = (int)(threadIdx.x & 63);
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const WorkItem it = work[blockIdx.x];
+    const DevInst &I = insts[it.inst];
+    const long long n = ctl->step + kstep;
+    Lane<P> L;
+    const bool lead = wv == 0;
+    init_lane(L, I, it, lane, 1, kFusedCols, (int)((ctl->cur + kflip) & 1), &s_rad[2 * lane], lead);
+    constexpr int NF = P::kRadRegs ? 2 * kRadF : 0;  // factor values passed on in s_share
+    if (lead) {
+        if constexpr (P::kRadRegs) {
+            const T *f = &L.rf[0].rho2;
+            for (int k = 0; k < kRadF; ++k) s_share[k * 64 + lane] = (double)f[k];
+            f = &L.rf[1].rho2;
+            for (int k = 0; k < kRadF; ++k) s_share[(kRadF + k) * 64 + lane] = (double)f[k];
+        }
+        s_share[NF * 64 + lane] = L.gh;
+        s_share[(NF + 1) * 64 + lane] = L.gn;
+    }
+    const Level lv = make_level(I, n);
+    const int nt = I.n_theta;
+    const bool even = I.m_even;
+    const int j0 = it.j0, j1 = it.j1;
+    const bool north = j0 == 0, southp = j1 == nt;
+    const int a_lo = max(0, j0 - 2), a_hi = min(nt - 1, j1 + 1);  // u^n rows staged
+    const int h_lo = max(1, j0 - 1), h_hi = min(nt - 2, j1);      // half rows formed
+    const int o_lo = max(1, j0), o_hi = min(nt - 2, j1 - 1);      // output rows formed
+    // neighbour lanes; the lanes at the two ends read their own values, which
+    // only reach halo results that are never stored
+    const int lr = lane < 63 ? lane + 1 : lane, ll = lane > 0 ? lane - 1 : lane;
+
+    for (int row = a_lo + wv; row <= a_hi; row += NW) lds_put<P>(s_u, (row - a_lo) * 64 + lane, load_row(L, row));
+    __syncthreads();
+    if (!lead) {
+        if constexpr (P::kRadRegs) {
+            T *f = &L.rf[0].rho2;
+            for (int k = 0; k < kRadF; ++k) f[k] = (T)s_share[k * 64 + lane];
+            f = &L.rf[1].rho2;
+            for (int k = 0; k < kRadF; ++k) f[k] = (T)s_share[(kRadF + k) * 64 + lane];
+        }
+        L.gh = s_share[NF * 64 + lane];
+        L.gn = s_share[(NF + 1) * 64 + lane];
+        L.near_h = L.gh != 0.0;
+        L.near_n = L.gn != 0.0;
+    }
+    for (int r = h_lo + wv; r <= h_hi; r += NW) {
+        const int k = (r - a_lo) * 64;
+        const Q4<T> UM = lds_get<P>(s_u, k - 64 + lane).f, U0 = lds_get<P>(s_u, k + lane).f;
+        const Q4<T> UP = lds_get<P>(s_u, k + 64 + lane).f;
+        const cx<T> nm = lds_get<P>(s_u, k - 64 + lr).f.phi, np = lds_get<P>(s_u, k + 64 + lr).f.phi;
+        const Q4<T> n0 = lds_get<P>(s_u, k + lr).f;
+        lds_put_half(s_h, (r - h_lo) * 64 + lane, half_core(L, lv, UM, U0, UP, nm, n0, np, r));
+    }
+    __syncthreads();
+    // half row `row` of lane l, the pole rows from the rows next to them
+    auto half_at = [&](int row, int l) -> Q4<T> {
+        if (row == 0) return pole_half(even, lds_get_half<T>(s_h, (1 - h_lo) * 64 + l),
+                                       lds_get_half<T>(s_h, (2 - h_lo) * 64 + l));
+        if (row == nt - 1) return pole_half(even, lds_get_half<T>(s_h, (nt - 2 - h_lo) * 64 + l),
+                                            lds_get_half<T>(s_h, (nt - 3 - h_lo) * 64 + l));
+        return lds_get_half<T>(s_h, (row - h_lo) * 64 + l);
+    };
+    for (int o = o_lo + wv; o <= o_hi; o += NW) {
+        const St<T> Uo = lds_get<P>(s_u, (o - a_lo) * 64 + lane);
+        const Q4<T> HM = half_at(o - 1, lane), H0 = half_at(o, lane), HP = half_at(o + 1, lane);
+        const cx<T> lm = half_at(o - 1, ll).phi, lp = half_at(o + 1, ll).phi;
+        const Q4<T> l0 = half_at(o, ll);
+        const St<T> v = out_core(L, lv, Uo, HM, H0, HP, lm, l0, lp, o);
+        emit(L, lv, o, v);
+        if (north && o <= 2) lds_put<P>(s_p, (o - 1) * 64 + lane, v);
+        if (southp && o >= nt - 3) lds_put<P>(s_p, (2 + (nt - 2 - o)) * 64 + lane, v);
+    }
+    __syncthreads();
+    if (north && wv == 0)
+        emit(L, lv, 0, pole_row<P>(even, lds_get<P>(s_p, lane), lds_get<P>(s_p, 64 + lane)));
+    if (southp && wv == NW - 1)
+        emit(L, lv, nt - 1, pole_row<P>(even, lds_get<P>(s_p, 128 + lane), lds_get<P>(s_p, 192 + lane)));
+}
+
 // Two steps (n -> n+2) in one pass over whole column strips: u^n is read
 // and u^{n+2} written once; u^{n+1} exists only in registers (and in the
 // waveform ring when sampled).
@@ -924,6 +1104,38 @@ hipError_t launch_variant(const DevInst *d_inst, const WorkItem *d_work, int n_w
     TK_VARIANT(1, true, 1)
     TK_VARIANT(1, false, 1)
 #undef TK_VARIANT
+    return hipErrorInvalidValue;
+}
+
+namespace {
+
+template <template <int, bool, int> class Pol, int TRC>
+hipError_t launch_tiled_as(const DevInst *d_inst, const WorkItem *d_work, int n_work, const DevCtl *ctl, int kstep,
+                           int kflip, bool nt, hipStream_t s)
+{
+    if (n_work <= 0) return hipSuccess;
+    if (nt)
+        hipLaunchKernelGGL((k_tiled<Pol<1, true, 1>, TRC>), dim3(n_work), dim3(64 * kFusedWavesPerBlock), 0, s, d_inst,
+                           d_work, ctl, kstep, kflip);
+    else
+        hipLaunchKernelGGL((k_tiled<Pol<1, false, 1>, TRC>), dim3(n_work), dim3(64 * kFusedWavesPerBlock), 0, s,
+                           d_inst, d_work, ctl, kstep, kflip);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_tiled(bool fp64, const DevInst *d_inst, const WorkItem *d_work, int n_work, int rows,
+                        const DevCtl *ctl, int kstep, int kflip, bool nt, hipStream_t s)
+{
+    // a work item has at most rows + 2 rows (the last chunk absorbs a rest
+    // of one or two)
+    if (rows == 4)
+        return fp64 ? launch_tiled_as<PolicyF64, 6>(d_inst, d_work, n_work, ctl, kstep, kflip, nt, s)
+                    : launch_tiled_as<PolicyF32C, 6>(d_inst, d_work, n_work, ctl, kstep, kflip, nt, s);
+    if (rows == 8)
+        return fp64 ? launch_tiled_as<PolicyF64, 10>(d_inst, d_work, n_work, ctl, kstep, kflip, nt, s)
+                    : launch_tiled_as<PolicyF32C, 10>(d_inst, d_work, n_work, ctl, kstep, kflip, nt, s);
     return hipErrorInvalidValue;
 }
 

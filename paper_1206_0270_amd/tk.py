@@ -19,7 +19,7 @@ TK_FLAG_FORCE_DT = 1
 TK_SRC_NONE, TK_SRC_CIRCULAR_GAUSSIAN, TK_SRC_CIRCULAR_STEP_DELTA, TK_SRC_CIRCULAR_LINEAR_DELTA = 0, 1, 2, 3
 SOURCE_KINDS = {"gaussian": TK_SRC_CIRCULAR_GAUSSIAN, "step_delta": TK_SRC_CIRCULAR_STEP_DELTA,
                 "linear_delta": TK_SRC_CIRCULAR_LINEAR_DELTA}
-TK_KERNEL_AUTO, TK_KERNEL_TWO_PASS, TK_KERNEL_FUSED, TK_KERNEL_FUSED2 = 0, 1, 2, 3
+TK_KERNEL_AUTO, TK_KERNEL_TWO_PASS, TK_KERNEL_FUSED, TK_KERNEL_FUSED2, TK_KERNEL_TILED = 0, 1, 2, 3, 4
 
 _STATUS = {0: "TK_OK", 1: "TK_E_INVALID", 2: "TK_E_NOMEM", 3: "TK_E_DEVICE", 4: "TK_E_STATE",
            5: "TK_E_UNSTABLE", 6: "TK_E_NONFINITE"}

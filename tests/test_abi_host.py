@@ -96,7 +96,8 @@ def test_tuning_validation():
                 tk.Tuning(tk.TK_KERNEL_FUSED, 0, 0, 1, 1, 4), tk.Tuning(tk.TK_KERNEL_FUSED2, 8, 0, 3, 1, 0),
                 tk.Tuning(tk.TK_KERNEL_FUSED, 0, 0, 3, tk.TK_TUNE_NT_STORES, 4),
                 tk.Tuning(tk.TK_KERNEL_FUSED2, 0, 0, 3, tk.TK_TUNE_NT_STORES, 3),
-                tk.Tuning(4, 0, 0, 3, 1, 0)):
+                tk.Tuning(tk.TK_KERNEL_TILED, 0, 0, 3, 1, 0), tk.Tuning(tk.TK_KERNEL_TILED, 6, 0, 3, 1, 0),
+                tk.Tuning(5, 0, 0, 3, 1, 0)):
         assert lib.tk_set_tuning(ctx, ctypes.byref(bad)) == tk.TK_E_INVALID
     ok = tk.Tuning(tk.TK_KERNEL_TWO_PASS, 8, 50, 1, tk.TK_TUNE_NT_STORES, 0)
     assert lib.tk_set_tuning(ctx, ctypes.byref(ok)) == tk.TK_OK
@@ -107,6 +108,9 @@ def test_tuning_validation():
     assert lib.tk_set_tuning(ctx, ctypes.byref(ok)) == tk.TK_OK
     ok = tk.Tuning(tk.TK_KERNEL_FUSED2, 0, 100, 1, tk.TK_TUNE_NT_STORES, 0)
     assert lib.tk_set_tuning(ctx, ctypes.byref(ok)) == tk.TK_OK
+    for rows in (4, 8):
+        ok = tk.Tuning(tk.TK_KERNEL_TILED, rows, 100, 3, 0, 0)
+        assert lib.tk_set_tuning(ctx, ctypes.byref(ok)) == tk.TK_OK
     lib.tk_destroy(ctx)
 
 

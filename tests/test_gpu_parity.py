@@ -110,12 +110,12 @@ def small_instances():
     return out
 
 
-@pytest.mark.parametrize("kernel", [tk.TK_KERNEL_FUSED2, tk.TK_KERNEL_FUSED, tk.TK_KERNEL_TWO_PASS])
+@pytest.mark.parametrize("kernel", [tk.TK_KERNEL_FUSED2, tk.TK_KERNEL_FUSED, tk.TK_KERNEL_TWO_PASS, tk.TK_KERNEL_TILED])
 def test_small_grids_vs_oracle(kernel):
     insts = small_instances()
     steps = 150
     say("small grids", [i["name"] for i in insts], "kernel", kernel)
-    res = gpu_run(insts, steps, kernel=kernel)
+    res = gpu_run(insts, steps, kernel=kernel, rows=4 if kernel == tk.TK_KERNEL_TILED else 0)
     for inst, got in zip(insts, res):
         check_parity(inst, steps, got, oracle_run(inst, steps))
 
@@ -205,13 +205,27 @@ def test_launch_variants_bitwise(precision):
             assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
 
 
-@pytest.mark.parametrize("kernel,G", [(tk.TK_KERNEL_FUSED2, 20), (tk.TK_KERNEL_FUSED2, 7), (tk.TK_KERNEL_FUSED, 20)])
+@pytest.mark.parametrize("precision", [tk.TK_FP64, tk.TK_FP32_COMP])
+@pytest.mark.parametrize("rows,nt", [(4, True), (8, False), (8, True)])
+def test_tiled_kernel_equals_marching_bitwise(precision, rows, nt):
+    # tiles of 4 or 8 rows (the last chunk up to two more) staged in LDS
+    # compute every point with the marching kernels' row functions
+    insts = small_instances()
+    base = gpu_run(insts, 40, precision=precision)
+    other = gpu_run(insts, 40, kernel=tk.TK_KERNEL_TILED, rows=rows, nt=nt, precision=precision)
+    for (a, b) in zip(base, other):
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+
+
+@pytest.mark.parametrize("kernel,G", [(tk.TK_KERNEL_FUSED2, 20), (tk.TK_KERNEL_FUSED2, 7), (tk.TK_KERNEL_FUSED, 20),
+                                      (tk.TK_KERNEL_TILED, 20)])
 def test_graph_replay_equals_eager_bitwise(kernel, G):
     # an odd block size ends each replay with a one-step launch and flips the
     # state buffer an odd number of times per replay
     insts = small_instances()
-    eager = gpu_run(insts, 70, kernel=kernel, graph=0)
-    graph = gpu_run(insts, 70, kernel=kernel, graph=G, chunks=[25, 20, 5, 20])
+    rows = 8 if kernel == tk.TK_KERNEL_TILED else 0
+    eager = gpu_run(insts, 70, kernel=kernel, rows=rows, graph=0)
+    graph = gpu_run(insts, 70, kernel=kernel, rows=rows, graph=G, chunks=[25, 20, 5, 20])
     for (a, b) in zip(eager, graph):
         assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
 
