@@ -210,13 +210,13 @@ def _delta_instances():
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("kernel", ["FUSED2", "FUSED", "TWO_PASS"])
-def test_delta_sources_gpu_vs_oracle(kernel):
+@pytest.mark.parametrize("kernel,rows", [("FUSED2", 0), ("FUSED", 0), ("TWO_PASS", 0), ("TILED", 8)])
+def test_delta_sources_gpu_vs_oracle(kernel, rows):
     import test_gpu_parity as GP
     from paper_1206_0270_amd import tk
     insts = _delta_instances()
     steps = 120
-    res = GP.gpu_run(insts, steps, kernel=getattr(tk, "TK_KERNEL_" + kernel))
+    res = GP.gpu_run(insts, steps, kernel=getattr(tk, "TK_KERNEL_" + kernel), rows=rows)
     for inst, got in zip(insts, res):
         GP.check_parity(inst, steps, got, GP.oracle_run(inst, steps))
 
