@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define TK_ABI_VERSION 1
+#define TK_ABI_VERSION 2
 
 typedef struct tk_ctx tk_ctx;
 

@@ -25,7 +25,7 @@ def test_library_exports_every_declared_symbol():
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(tk.EXPORTS)
-    assert lib.tk_abi_version() == 1
+    assert lib.tk_abi_version() == 2
 
 
 def test_struct_layout_matches_header():

@@ -1,7 +1,8 @@
 """Host code under AddressSanitizer and UndefinedBehaviorSanitizer: the C
-oracle (small grids, every source kind, the switch-on, both pole rules) and
-the library's host setup (coefficient and source tables, tortoise inversion,
-step rule).  Compiled with gcc / g++ here; no GPU."""
+oracle (small grids, every source kind, the switch-on, both pole rules), the
+library's host setup (coefficient and source tables, tortoise inversion,
+step rule), and the library's host entry points driven from C.  Compiled
+with gcc / g++ here; no GPU."""
 import os
 import subprocess
 
@@ -42,3 +43,31 @@ def test_host_setup_under_sanitizers(args):
     r = _run([exe] + args)
     assert r.returncode == 0 and "runtime error" not in r.stderr and "ERROR: AddressSanitizer" not in r.stderr, \
         r.stderr[-2000:]
+
+
+def test_host_library_entry_points_under_sanitizers():
+    # the library's host code (C ABI, validation, work lists, layout, post-
+    # processing) rebuilt with the sanitizers and driven from C without a
+    # device; the kernels' object is linked as built
+    kobj = os.path.join(BUILD, "tk_kernels.hip.o")
+    if not os.path.exists(kobj):
+        pytest.skip("build the library first (its kernels' object is linked here)")
+    out = os.path.join(BUILD, "san")
+    os.makedirs(out, exist_ok=True)
+    csrc = os.path.join(ROOT, "paper_1206_0270_amd", "csrc")
+    inc = ["-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-I" + os.path.join(ROOT, "include")]
+    objs = []
+    for f in ("tk_api", "tk_setup", "tk_post"):
+        o = os.path.join(out, f + ".o")
+        subprocess.run(["g++", "-std=c++17", "-fPIC", *SAN, *inc, "-c", os.path.join(csrc, f + ".cpp"), "-o", o],
+                       check=True)
+        objs.append(o)
+    lib = os.path.join(out, "libtk.so")
+    subprocess.run(["g++", "-shared", "-fsanitize=address,undefined", *objs, kobj, "-L/opt/rocm/lib", "-lamdhip64",
+                    "-Wl,-rpath,/opt/rocm/lib", "-o", lib], check=True)
+    exe = os.path.join(out, "abi_driver")
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-Werror", *SAN, *inc,
+                    os.path.join(ROOT, "tests", "abi_sanitize_driver.c"), "-o", exe, "-L" + out, "-ltk",
+                    "-Wl,-rpath," + out, "-lm"], check=True)
+    r = _run([exe])
+    assert r.returncode == 0 and r.stdout.strip() == "ok", r.stdout + r.stderr[-3000:]
