@@ -44,6 +44,10 @@ def workload(name):
     elif name == "single":
         insts = W.config2()["instances"]
         desc = "single instance: Kerr a=0.9, s=-2, m=2, 8001 x 129 on [-300,300]M, Gaussian data"
+    elif name == "precision":
+        insts = W.config5()["instances"]
+        desc = ("precision-study workload: 6 instances m=2,3,4 x a=0.5,0.9, circular orbits r0=8M, "
+                "16001 x 129 on [-300,300]M")
     else:
         raise SystemExit(f"unknown workload {name}")
     return insts, desc
@@ -459,7 +463,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--warmup", type=int, default=30)
-    ap.add_argument("--workload", default="batched")
+    ap.add_argument("--workload", default="batched", choices=["batched", "single", "precision"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32c"])
     ap.add_argument("--graph-steps", type=int, default=100)
     ap.add_argument("--tune", default="auto", choices=["auto", "manual"],

@@ -134,10 +134,11 @@ typedef enum {
                                fused forms only) */
     TK_KERNEL_TWO_PASS = 1, /* half-step array through HBM, one thread per point */
     TK_KERNEL_FUSED = 2,    /* both stages in one pass, theta-marching columns   */
-    TK_KERNEL_FUSED2 = 3,   /* two time steps per pass over whole column strips:
-                               u^n read and u^{n+2} written once, u^{n+1} kept
-                               on chip (an odd step count ends with one FUSED
-                               step); results are bitwise those of FUSED */
+    TK_KERNEL_FUSED2 = 3,   /* two time steps per pass over column strips (whole,
+                               or chunks of rows_per_tile rows): u^n read and
+                               u^{n+2} written once, u^{n+1} kept on chip (an
+                               odd step count ends with one FUSED step);
+                               results are bitwise those of FUSED */
     TK_KERNEL_TILED = 4     /* one step on tiles of rows_per_tile (4 or 8) rows
                                by 62 columns, one block of four waves per tile
                                with its rows staged in LDS: for grids too small
@@ -151,8 +152,9 @@ enum {
 
 typedef struct {
     int kernel;        /* tk_kernel */
-    int rows_per_tile; /* fused kernel: theta rows per work item (0 = all;
-                          FUSED2 needs 0)                                     */
+    int rows_per_tile; /* fused kernels: theta rows per work item (0 = all;
+                          FUSED2: 0 or >= 4, its chunks recompute the u^{n+1}
+                          rows of a two-row halo; TILED: 4 or 8)              */
     int graph_steps;   /* steps per captured HIP graph (0 = no graphs)        */
     int prefetch_rows; /* fused kernel: u^n rows in flight per wave, 1 or 3 (0 = 3) */
     int flags;         /* TK_TUNE_* */

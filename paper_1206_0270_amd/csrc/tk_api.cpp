@@ -97,16 +97,18 @@ std::string validate(const tk_instance_desc &d)
 
 // Fused work list: strips of `cols` output columns x chunks of rows,
 // longest first (waves are dispatched roughly in order).
-void build_work(tk_ctx *c, int rows, int cols)
+void build_work(tk_ctx *c, int rows, int cols, int min_rows)
 {
     c->work.clear();
     for (size_t k = 0; k < c->inst.size(); ++k) {
         const tk_instance_desc &d = c->inst[k].desc;
-        int rc = rows > 0 ? std::max(rows, 3) : d.n_theta;
+        int rc = rows > 0 ? std::max(rows, min_rows) : d.n_theta;
         for (int j0 = 0; j0 < d.n_theta; j0 += rc) {
             int j1 = std::min(d.n_theta, j0 + rc);
-            // keep a pole chunk at least 3 rows (pole extrapolation needs rows 1, 2)
-            if (d.n_theta - j1 > 0 && d.n_theta - j1 < 3) j1 = d.n_theta;
+            // keep a pole chunk at least min_rows rows (the one-step pole
+            // extrapolation needs rows 1, 2; a two-step chunk keeps four rows
+            // from a pole it does not hold)
+            if (d.n_theta - j1 > 0 && d.n_theta - j1 < min_rows) j1 = d.n_theta;
             for (int i0 = 0; i0 < d.n_r; i0 += cols) c->work.push_back(WorkItem{(int)k, i0, j0, j1});
             if (j1 == d.n_theta) break;
         }
@@ -120,12 +122,12 @@ void build_work(tk_ctx *c, int rows, int cols)
 size_t work_capacity(const tk_ctx *c)
 {
     // upper bound over the shapes: chunks of 3 rows of kFusedCols-wide
-    // strips, or whole kFused2Cols-wide strips
+    // strips, or chunks of 4 rows of kFused2Cols-wide strips
     size_t n = 0;
     for (const HostInst &h : c->inst) {
         size_t strips = (h.desc.n_r + kFusedCols - 1) / kFusedCols;
         size_t strips2 = (h.desc.n_r + kFused2Cols - 1) / kFused2Cols;
-        n += std::max(strips * ((h.desc.n_theta + 2) / 3 + 1), strips2);
+        n += std::max(strips * ((h.desc.n_theta + 2) / 3 + 1), strips2 * ((h.desc.n_theta + 3) / 4 + 1));
     }
     return n;
 }
@@ -226,7 +228,7 @@ tk_status ensure_work(tk_ctx *c, int kernel)
     const int rows = c->tuning.rows_per_tile;
     const int cols = kernel == TK_KERNEL_FUSED2 ? kFused2Cols : kFusedCols;
     if (!c->work.empty() && c->work_rows == rows && c->work_cols == cols) return TK_OK;
-    build_work(c, rows, cols);
+    build_work(c, rows, cols, kernel == TK_KERNEL_FUSED2 ? 4 : 3);
     if (c->work.size() > c->work_cap) return fail(c, TK_E_STATE, "work list exceeds its reserved area");
     TK_HIP(c, hipMemcpyAsync(c->ws + c->off_work, c->work.data(), c->work.size() * sizeof(WorkItem),
                              hipMemcpyHostToDevice, c->stream));
@@ -252,6 +254,7 @@ hipError_t launch_one(tk_ctx *c, int kernel, int steps, int kstep, int kflip)
     f.nt = (c->tuning.flags & TK_TUNE_NT_STORES) != 0;
     f.waves = c->tuning.waves_per_simd == 0 ? 1 : c->tuning.waves_per_simd;
     f.two_step = steps == 2;
+    f.chunked = c->tuning.rows_per_tile > 0;
     return launch_fused(c->prec == TK_FP64, di, wk, (int)c->work.size(), c->work_cols, ctl, kstep, kflip, f,
                         c->stream);
 }
@@ -722,8 +725,8 @@ tk_status tk_set_tuning(tk_ctx *c, const tk_tuning *t)
         return fail(c, TK_E_INVALID, "unknown kernel");
     if (t->kernel == TK_KERNEL_TILED && t->rows_per_tile != 4 && t->rows_per_tile != 8)
         return fail(c, TK_E_INVALID, "the tiled kernel takes rows_per_tile 4 or 8");
-    if (t->kernel == TK_KERNEL_FUSED2 && t->rows_per_tile != 0)
-        return fail(c, TK_E_INVALID, "the two-step kernel marches whole strips: rows_per_tile must be 0");
+    if (t->kernel == TK_KERNEL_FUSED2 && t->rows_per_tile != 0 && t->rows_per_tile < 4)
+        return fail(c, TK_E_INVALID, "the two-step kernel takes whole strips (rows_per_tile 0) or chunks of >= 4 rows");
     if (t->kernel == TK_KERNEL_TWO_PASS && c->prec != TK_FP64)
         return fail(c, TK_E_INVALID, "the two-pass kernel is FP64 only");
     if (t->rows_per_tile < 0 || (t->rows_per_tile > 0 && t->rows_per_tile < 3))
@@ -806,8 +809,9 @@ tk_status tk_autotune(tk_ctx *c, int warmup, int steps, double *best_ms_per_step
     // small grids), and the two-pass kernel (FP64)
     const int shapes[][3] = {{3, 1, 0}, {3, 0, 0}, {1, 1, 0}, {1, 0, 0}};
     std::vector<tk_tuning> cand;
-    for (const auto &sh : shapes)
-        cand.push_back(tk_tuning{TK_KERNEL_FUSED2, 0, 0, sh[0], sh[1] ? TK_TUNE_NT_STORES : 0, sh[2]});
+    for (int rows : {0, 32, 16})
+        for (const auto &sh : shapes)
+            cand.push_back(tk_tuning{TK_KERNEL_FUSED2, rows, 0, sh[0], sh[1] ? TK_TUNE_NT_STORES : 0, sh[2]});
     for (int rows : {0, 64, 16})
         for (const auto &sh : shapes)
             cand.push_back(tk_tuning{TK_KERNEL_FUSED, rows, 0, sh[0], sh[1] ? TK_TUNE_NT_STORES : 0, sh[2]});

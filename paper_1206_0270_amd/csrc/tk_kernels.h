@@ -22,6 +22,7 @@ struct FusedShape {
     bool nt;
     int waves;
     bool two_step;
+    bool chunked;  // two steps on chunks of rows (k_fused2c) rather than whole strips
 };
 
 // Fused step(s): both Lax-Wendroff stages in one pass over theta-marching

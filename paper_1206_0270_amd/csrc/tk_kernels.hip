@@ -752,6 +752,93 @@ __device__ __forceinline__ void march2(const Lane<P> &L, const Level &l1, const 
     }
 }
 
+// Rows a chunk [j0, j1) of the two-step kernel works on.  It writes u^{n+2}
+// rows [j0, j1); level 2 needs the u^{n+1} rows j0-2 .. j1+1 and level 1
+// recomputes them, from the half rows j0-3 .. j1+2 and the u^n rows
+// j0-4 .. j1+3.  A chunk that holds a pole runs the pole bookkeeping of the
+// whole-strip march; the others keep four rows from either pole, so that
+// they never need a pole row.  Iteration r forms level 1's half row r and
+// u^{n+1} row r-1, and level 2's half row r-3 and u^{n+2} row r-4.
+struct Chunk2 {
+    int nt;
+    bool north, south;
+    int r_lo, r_hi;  // iterations
+    int h1_hi;       // last level-1 half row from the stencil
+    int v_lo, v_hi;  // level-1 rows (u^{n+1}) from the stencil
+    int g_lo, g_hi;  // level-2 half rows from the stencil
+    int o_lo, o_hi;  // level-2 rows (u^{n+2}) written from the stencil
+};
+
+__device__ __forceinline__ Chunk2 chunk2_of(int nt, int j0, int j1)
+{
+    Chunk2 B;
+    B.nt = nt;
+    B.north = j0 == 0;
+    B.south = j1 == nt;
+    B.r_lo = B.north ? 1 : j0 - 3;
+    B.h1_hi = B.south ? nt - 2 : j1 + 2;
+    B.v_lo = B.north ? 1 : j0 - 2;
+    B.v_hi = B.south ? nt - 2 : j1 + 1;
+    B.g_lo = B.north ? 1 : j0 - 1;
+    B.g_hi = B.south ? nt - 2 : j1;
+    B.o_lo = B.north ? 1 : j0;
+    B.o_hi = B.south ? nt - 2 : j1 - 1;
+    B.r_hi = B.o_hi + 4;
+    return B;
+}
+
+// One iteration of the two-step march on a chunk (slot S = (r - r_lo) mod
+// 3); the whole-strip march2 with the chunk's bounds.  With EDGE false (all
+// bounds inside, no pole event) the checks are compiled out.  u^{n+1} rows
+// are sampled for the waveform only on the chunk's own rows, so that halo
+// rows computed by two chunks are written once.
+template <class P, int S, bool EDGE>
+__device__ __forceinline__ void march2c(const Lane<P> &L, const Level &l1, const Level &l2, Roll2<P> &R, int r,
+                                        const Chunk2 &B)
+{
+    constexpr int SM = (S + 2) % 3;
+    constexpr int SP = (S + 1) % 3;
+    const int nt = B.nt;
+    const bool even = L.I->m_even;
+    if (!EDGE || r <= B.h1_hi) {
+        advance_rows<P, S>(L, R, r, B.h1_hi + 1);
+        R.H[S] = half_row<P>(L, l1, R.U[SM].f, R.U[S].f, R.U[SP].f, r);
+    } else if (B.south && r == nt - 1) {
+        R.H[S] = pole_half(even, R.H[SM], R.H[SP]);
+    }
+    if (EDGE && B.north && r == 2) R.H[SP] = pole_half(even, R.H[SM], R.H[S]);
+    const bool v_new = !EDGE || (r - 1 >= B.v_lo && r - 1 <= B.v_hi);
+    St<typename P::T> vn;
+    if (v_new) {
+        vn = out_row<P>(L, l1, R.U[SM], R.H[SP], R.H[SM], R.H[S], r - 1);
+        if (!EDGE || (r - 1 >= B.o_lo && r - 1 <= B.o_hi)) sample(L, l1, r - 1, vn);
+    }
+    if (!EDGE || (r - 3 >= B.g_lo && r - 3 <= B.g_hi))
+        R.G[S] = half_row<P>(L, l2, R.V[SM].f, R.V[S].f, R.V[SP].f, r - 3);
+    else if (B.south && r == nt + 2)
+        R.G[S] = pole_half(even, R.G[SM], R.G[SP]);
+    if (EDGE && B.north && r == 5) R.G[SP] = pole_half(even, R.G[SM], R.G[S]);
+    if (!EDGE || (r - 4 >= B.o_lo && r - 4 <= B.o_hi)) {
+        const int o = r - 4;
+        const St<typename P::T> v = out_row<P>(L, l2, R.V[SM], R.G[SP], R.G[SM], R.G[S], o);
+        emit(L, l2, o, v);
+        if (EDGE) {
+            const bool pn = B.north && o == 2, ps = B.south && o == nt - 2;
+            if (pn || ps) emit(L, l2, pn ? 0 : nt - 1, pole_row<P>(even, pick(pn, R.keep, v), pick(pn, v, R.keep)));
+            if ((B.north && o == 1) || (B.south && o == nt - 3)) R.keep = v;
+        }
+    }
+    if (v_new) R.V[SM] = vn;
+    if (EDGE && B.north && r == 3) {
+        R.V[S] = pole_row<P>(even, R.V[SP], R.V[SM]);
+        sample(L, l1, 0, R.V[S]);
+    }
+    if (EDGE && B.south && r == nt) {
+        R.V[SM] = pole_row<P>(even, R.V[SP], R.V[S]);
+        sample(L, l1, nt - 1, R.V[SM]);
+    }
+}
+
 // Lane set-up shared by the fused kernels: lane `lane` holds r* column
 // i0 - halo + lane and the work item writes lanes halo .. halo+cols-1; the
 // lane's radial factors (half node, node) go to its LDS slots.
@@ -1077,13 +1164,63 @@ __global__ void __launch_bounds__(64 * kFusedWavesPerBlock) __attribute__((amdgp
     if (r + 5 <= nt + 2) march2<P, 2, true>(L, l1, l2, R, r + 5);
 }
 
+// The two-step kernel on chunks of rows (for workloads whose whole strips
+// give too few waves): the same march as k_fused2 over the iterations of
+// the chunk, level 1 recomputing the u^{n+1} rows of the halo.  Bitwise the
+// results of k_fused2 and k_fused.
+template <class P>
+__global__ void __launch_bounds__(64 * kFusedWavesPerBlock) __attribute__((amdgpu_waves_per_eu(P::kWaves, 8)))
+    k_fused2c(const DevInst *__restrict__ insts, const WorkItem *__restrict__ work, int n_work,
+              const DevCtl *__restrict__ ctl, int kstep, int kflip)
+{
+    using T = typename P::T;
+    __shared__ T s_rad[kFusedWavesPerBlock][P::kRadRegs ? 2 : 2 * kRadF * 64];
+    const int lane = (int)(threadIdx.x & 63);
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int w = (int)blockIdx.x * kFusedWavesPerBlock + wv;
+    if (w >= n_work) return;  // whole wave leaves together; no block barriers below
+    const WorkItem it = work[w];
+    const DevInst &I = insts[it.inst];
+    const long long n = ctl->step + kstep;
+    Lane<P> L;
+    init_lane(L, I, it, lane, 2, kFused2Cols, (int)((ctl->cur + kflip) & 1), &s_rad[wv][2 * lane]);
+    const Level l1 = make_level(I, n), l2 = make_level(I, n + 1);
+    const Chunk2 B = chunk2_of(I.n_theta, it.j0, it.j1);
+    // every check holds from iteration steady_lo on and through steady_hi
+    const int steady_lo = B.north ? 7 : B.r_lo + 7;
+    const int steady_hi = B.south ? B.nt - 2 : it.j1;
+
+    Roll2<P> R;
+    prologue_rows(L, R, B.r_lo, B.h1_hi + 1);
+    R.keep = zero_st<P>();
+    int r = B.r_lo;
+    for (; r < steady_lo && r <= B.r_hi; r += 3) {
+        march2c<P, 0, true>(L, l1, l2, R, r, B);
+        if (r + 1 <= B.r_hi) march2c<P, 1, true>(L, l1, l2, R, r + 1, B);
+        if (r + 2 <= B.r_hi) march2c<P, 2, true>(L, l1, l2, R, r + 2, B);
+    }
+    for (; r + 2 <= steady_hi; r += 3) {
+        march2c<P, 0, false>(L, l1, l2, R, r, B);
+        march2c<P, 1, false>(L, l1, l2, R, r + 1, B);
+        march2c<P, 2, false>(L, l1, l2, R, r + 2, B);
+    }
+    for (; r <= B.r_hi; r += 3) {
+        march2c<P, 0, true>(L, l1, l2, R, r, B);
+        if (r + 1 <= B.r_hi) march2c<P, 1, true>(L, l1, l2, R, r + 1, B);
+        if (r + 2 <= B.r_hi) march2c<P, 2, true>(L, l1, l2, R, r + 2, B);
+    }
+}
+
 template <class P>
 hipError_t launch_as(const DevInst *d_inst, const WorkItem *d_work, int n_work, int cols, const DevCtl *ctl, int kstep,
-                     int kflip, bool two_step, hipStream_t s)
+                     int kflip, bool two_step, bool chunked, hipStream_t s)
 {
     if (n_work <= 0) return hipSuccess;
     const int blocks = (n_work + kFusedWavesPerBlock - 1) / kFusedWavesPerBlock;
-    if (two_step)
+    if (two_step && chunked)
+        hipLaunchKernelGGL(k_fused2c<P>, dim3(blocks), dim3(64 * kFusedWavesPerBlock), 0, s, d_inst, d_work, n_work,
+                           ctl, kstep, kflip);
+    else if (two_step)
         hipLaunchKernelGGL(k_fused2<P>, dim3(blocks), dim3(64 * kFusedWavesPerBlock), 0, s, d_inst, d_work, n_work,
                            ctl, kstep, kflip);
     else
@@ -1098,7 +1235,7 @@ hipError_t launch_variant(const DevInst *d_inst, const WorkItem *d_work, int n_w
 {
 #define TK_VARIANT(PD, NT, W)                                                                              \
     if (f.prefetch == PD && f.nt == NT && f.waves == W)                                                    \
-        return launch_as<Pol<PD, NT, W>>(d_inst, d_work, n_work, cols, ctl, kstep, kflip, f.two_step, s);
+        return launch_as<Pol<PD, NT, W>>(d_inst, d_work, n_work, cols, ctl, kstep, kflip, f.two_step, f.chunked, s);
     TK_VARIANT(3, true, 1)
     TK_VARIANT(3, false, 1)
     TK_VARIANT(1, true, 1)

@@ -93,7 +93,7 @@ def test_tuning_validation():
     lib = tk.load()
     for bad in (tk.Tuning(7, 0, 0, 0, 0, 0), tk.Tuning(tk.TK_KERNEL_FUSED, 2, 0, 0, 0, 0),
                 tk.Tuning(tk.TK_KERNEL_FUSED, 0, 0, 2, 0, 0), tk.Tuning(tk.TK_KERNEL_FUSED, 0, 0, 3, 8, 0),
-                tk.Tuning(tk.TK_KERNEL_FUSED, 0, 0, 1, 1, 4), tk.Tuning(tk.TK_KERNEL_FUSED2, 8, 0, 3, 1, 0),
+                tk.Tuning(tk.TK_KERNEL_FUSED, 0, 0, 1, 1, 4), tk.Tuning(tk.TK_KERNEL_FUSED2, 3, 0, 3, 1, 0),
                 tk.Tuning(tk.TK_KERNEL_FUSED, 0, 0, 3, tk.TK_TUNE_NT_STORES, 4),
                 tk.Tuning(tk.TK_KERNEL_FUSED2, 0, 0, 3, tk.TK_TUNE_NT_STORES, 3),
                 tk.Tuning(tk.TK_KERNEL_TILED, 0, 0, 3, 1, 0), tk.Tuning(tk.TK_KERNEL_TILED, 6, 0, 3, 1, 0),
@@ -110,6 +110,9 @@ def test_tuning_validation():
     assert lib.tk_set_tuning(ctx, ctypes.byref(ok)) == tk.TK_OK
     for rows in (4, 8):
         ok = tk.Tuning(tk.TK_KERNEL_TILED, rows, 100, 3, 0, 0)
+        assert lib.tk_set_tuning(ctx, ctypes.byref(ok)) == tk.TK_OK
+    for rows in (4, 16):
+        ok = tk.Tuning(tk.TK_KERNEL_FUSED2, rows, 100, 1, 0, 0)
         assert lib.tk_set_tuning(ctx, ctypes.byref(ok)) == tk.TK_OK
     lib.tk_destroy(ctx)
 

@@ -206,6 +206,19 @@ def test_launch_variants_bitwise(precision):
 
 
 @pytest.mark.parametrize("precision", [tk.TK_FP64, tk.TK_FP32_COMP])
+@pytest.mark.parametrize("rows,steps", [(4, 40), (5, 41), (7, 40), (16, 40)])
+def test_two_step_chunks_bitwise(precision, rows, steps):
+    # the two-step kernel on chunks of rows (level 1 recomputing a two-row
+    # halo of u^{n+1}; an odd count ends with one one-step launch on the same
+    # work list) against the whole-strip two-step kernel
+    insts = small_instances()
+    base = gpu_run(insts, steps, precision=precision)
+    other = gpu_run(insts, steps, kernel=tk.TK_KERNEL_FUSED2, rows=rows, precision=precision)
+    for (a, b) in zip(base, other):
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+
+
+@pytest.mark.parametrize("precision", [tk.TK_FP64, tk.TK_FP32_COMP])
 @pytest.mark.parametrize("rows,nt", [(4, True), (8, False), (8, True)])
 def test_tiled_kernel_equals_marching_bitwise(precision, rows, nt):
     # tiles of 4 or 8 rows (the last chunk up to two more) staged in LDS
@@ -217,13 +230,13 @@ def test_tiled_kernel_equals_marching_bitwise(precision, rows, nt):
         assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
 
 
-@pytest.mark.parametrize("kernel,G", [(tk.TK_KERNEL_FUSED2, 20), (tk.TK_KERNEL_FUSED2, 7), (tk.TK_KERNEL_FUSED, 20),
-                                      (tk.TK_KERNEL_TILED, 20)])
-def test_graph_replay_equals_eager_bitwise(kernel, G):
+@pytest.mark.parametrize("kernel,G,rows", [(tk.TK_KERNEL_FUSED2, 20, 0), (tk.TK_KERNEL_FUSED2, 7, 0),
+                                           (tk.TK_KERNEL_FUSED, 20, 0), (tk.TK_KERNEL_TILED, 20, 8),
+                                           (tk.TK_KERNEL_FUSED2, 7, 5)])
+def test_graph_replay_equals_eager_bitwise(kernel, G, rows):
     # an odd block size ends each replay with a one-step launch and flips the
     # state buffer an odd number of times per replay
     insts = small_instances()
-    rows = 8 if kernel == tk.TK_KERNEL_TILED else 0
     eager = gpu_run(insts, 70, kernel=kernel, rows=rows, graph=0)
     graph = gpu_run(insts, 70, kernel=kernel, rows=rows, graph=G, chunks=[25, 20, 5, 20])
     for (a, b) in zip(eager, graph):
