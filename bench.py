@@ -53,10 +53,10 @@ def workload(name):
     return insts, desc
 
 
-def kernel_name(prec, prefetch, nt, waves, two_step=False):
+def kernel_name(prec, prefetch, nt, waves, two_step=False, chunked=False):
     """The fused kernel variant as rocprofv3 names it (template arguments:
     prefetch depth, non-temporal stores, occupancy target)."""
-    k = "k_fused2" if two_step else "k_fused"
+    k = ("k_fused2c" if chunked else "k_fused2") if two_step else "k_fused"
     return f"{k}<{KERNEL_POLICY[prec]}<{prefetch}, {'true' if nt else 'false'}, {waves or 1}>>"
 
 
@@ -604,7 +604,8 @@ def main():
         kname = (f"k_tiled<{KERNEL_POLICY[args.precision]}<1, {'true' if t['nt_stores'] else 'false'}, 1>, "
                  f"{t['rows_per_tile'] + 2}>")
     else:
-        kname = kernel_name(args.precision, t["prefetch_rows"], t["nt_stores"], t["waves_per_simd"], two_step)
+        kname = kernel_name(args.precision, t["prefetch_rows"], t["nt_stores"], t["waves_per_simd"], two_step,
+                            t["rows_per_tile"] > 0)
     traffic = traffic_entry(kname, args.workload)
     st.close()
 
