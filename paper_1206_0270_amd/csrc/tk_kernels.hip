@@ -147,14 +147,20 @@ hipError_t launch_bump(DevCtl *ctl, int n, int flips, hipStream_t s)
 // One wavefront per work item: 64 lanes hold r* columns i0-1 .. i0+62 and
 // write the 62 columns i0 .. i0+61; the wave marches over the theta rows of
 // its chunk.  At row r it reads u^n row r+1 once (coalesced, prefetched one
-// row ahead), takes the neighbour column u^n_{i+1} by lane shuffles, forms
-// the half-step value at (i+1/2, r) (Eq. (3)), takes u^{n+1/2}_{i-1/2} by
-// another shuffle and forms u^{n+1} at row r-1 (Eq. (4)).  The half-step
-// array never leaves registers; u^n is read once and u^{n+1} written once.
-// Rolling rows live in three register slots indexed by row mod 3 (every
-// index is a compile-time constant inside each unrolled phase).  The lane's
-// radial factors (node and half node) sit in LDS for the whole march; the
-// angular ones are uniform per row.
+// or three rows ahead), takes the neighbour column u^n_{i+1} by a DPP lane
+// shift, forms the half-step value at (i+1/2, r) (Eq. (3)), takes
+// u^{n+1/2}_{i-1/2} by another shift and forms u^{n+1} at row r-1
+// (Eq. (4)).  The half-step array never leaves registers; u^n is read once
+// and u^{n+1} written once.  Rolling rows live in three register slots
+// indexed by row mod 3 (every index is a compile-time constant inside each
+// unrolled phase).  The lane's radial factors (node and half node) are kept
+// for the whole march, in registers in FP64 and in LDS in FP32; the angular
+// ones are uniform per row.  The two-step kernels (k_fused2 on whole strips,
+// k_fused2c on chunks of rows) run a second march three rows behind the
+// first on the u^{n+1} rows it leaves in registers; the tiled kernel
+// (k_tiled) stages short tiles in LDS instead of marching.  All of them
+// compute every point with the same row functions, so their results agree
+// bit for bit.
 //
 // FP32-compensated form: each value is stored as f (FP32) + c (bf16 Kahan
 // term).  The stencil runs in FP32 on f; Eq. (4)'s time update is added to
