@@ -219,8 +219,9 @@ tk_status tk_set_tuning(tk_ctx *ctx, const tk_tuning *t);
 tk_status tk_get_tuning(const tk_ctx *ctx, tk_tuning *t);
 
 /* Autotuner: time every compiled launch shape (kernel, u^n prefetch depth,
- * store kind, occupancy target; for the one-step kernel also rows per tile
- * 0, 64 and 16) on this context's own instances and keep the fastest;
+ * store kind; rows per tile 0, 32 and 16 for the two-step kernel, 0, 64 and
+ * 16 for the one-step kernel, 8 and 4 for the tiled kernel) on this
+ * context's own instances and keep the fastest;
  * graph_steps stays as it was.  Each
  * candidate runs `warmup` untimed and then `steps` timed steps (both
  * rounded up to even), timed with HIP events on the context's stream.  The

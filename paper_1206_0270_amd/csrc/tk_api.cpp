@@ -803,10 +803,10 @@ tk_status tk_autotune(tk_ctx *c, int warmup, int steps, double *best_ms_per_step
     const long long step0 = c->step;
     const int cur0 = c->cur;
     drop_graph(c);
-    // candidates: every compiled fused shape with the two-step kernel (whole
-    // strips) and the one-step kernel (whole strips, or chunks of rows, which
-    // give a small workload more waves), the tiled kernel (short tiles for
-    // small grids), and the two-pass kernel (FP64)
+    // candidates: every compiled fused shape with the two-step and the
+    // one-step kernels (whole strips, or chunks of rows, which give a small
+    // workload more waves), the tiled kernel (short tiles for small grids),
+    // and the two-pass kernel (FP64)
     const int shapes[][3] = {{3, 1, 0}, {3, 0, 0}, {1, 1, 0}, {1, 0, 0}};
     std::vector<tk_tuning> cand;
     for (int rows : {0, 32, 16})

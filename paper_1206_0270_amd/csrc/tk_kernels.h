@@ -15,8 +15,9 @@ hipError_t launch_two_pass(const DevInst *d_inst, const int2 *d_blocks, int n_bl
                            int kflip, hipStream_t s);
 
 // Launch shape of the fused kernels: u^n rows in flight per wave (1 or 3),
-// non-temporal stores, occupancy target per SIMD (1 = compiler's choice, 3,
-// 4), and one or two time steps per pass.
+// non-temporal stores, occupancy target per SIMD (1 = the compiler's choice,
+// the only one compiled), one or two time steps per pass, and for two steps
+// whole strips or chunks of rows.
 struct FusedShape {
     int prefetch;
     bool nt;
