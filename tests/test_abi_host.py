@@ -159,3 +159,21 @@ def test_abi_from_plain_c(tmp_path):
     same = W.instance(a=0.5, m=2, n_r=101, n_theta=9, rstar_min=-20.0, rstar_max=25.0, rstar_obs=20.0)
     assert dt == tk.stable_dt(same)
     assert float(out[1]) == pytest.approx(10.0 / 3.0)
+
+
+def test_binding_refuses_without_the_library(monkeypatch, tmp_path):
+    # no CPU fallback: without libtk.so the binding raises instead of
+    # computing anything
+    monkeypatch.setattr(tk, "_lib", None)
+    monkeypatch.setattr(tk, "LIB_PATH", str(tmp_path / "libtk.so"))
+    with pytest.raises(RuntimeError, match="missing"):
+        tk.load()
+
+
+def test_stepper_refuses_without_a_device():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a HIP device is visible here")
+    inst = W.config1()["instances"][0]
+    with pytest.raises(RuntimeError, match="no HIP device"):
+        tk.Stepper([inst])
