@@ -77,7 +77,7 @@ def traffic_entry(name, wl):
         return None
 
 
-def cpu_baseline(insts, target_s=15.0, steps=40):
+def cpu_baseline(insts, target_s=15.0, steps=70):
     """The oracle as it stands, timed on this host on a bounded sample of the
     same workload: instances in workload order, `steps` steps each, until
     about target_s seconds of stepping (grid setup excluded)."""
