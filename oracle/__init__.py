@@ -37,6 +37,7 @@ class OrDesc(ctypes.Structure):
         ("src_window_sigmas", ctypes.c_double),
         ("src_t0", ctypes.c_double),
         ("src_ramp", ctypes.c_double),
+        ("layer_R", ctypes.c_double),
     ]
 
 
@@ -84,6 +85,12 @@ def _lib(kind="f64"):
         lib.or_rhs_column.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, _dp, _dp]
         lib.or_get_coeff_column.restype = None
         lib.or_get_coeff_column.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp]
+        lib.or_layer_map.restype = None
+        lib.or_layer_map.argtypes = [ctypes.c_double] * 3 + [_dp]
+        lib.or_layer_coeffs.restype = None
+        lib.or_layer_coeffs.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_double, _dp]
         lib.or_source_value.restype = None
         lib.or_source_value.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
                                         ctypes.c_double, _dp]
@@ -124,6 +131,24 @@ def coeffs(M, a, s, m, x, theta, kind="f64"):
                 r=out[12], Delta=out[13])
 
 
+def layer_map(R, S, rho, kind="f64"):
+    """Hyperboloidal layer map at grid position rho: (r*, rho', H, rho'')."""
+    out = np.zeros(4)
+    _lib(kind).or_layer_map(R, S, rho, _ptr(out))
+    return tuple(out)
+
+
+def layer_coeffs(M, a, s, m, R, S, rho, theta, kind="f64"):
+    """Coefficients of the layer system at grid position rho and theta: dict
+    with bo, bi (outgoing / ingoing speeds), cthth, cth, fw, complex ct, c0,
+    d, and r, Delta."""
+    out = np.zeros(13)
+    _lib(kind).or_layer_coeffs(M, a, s, m, R, S, rho, theta, _ptr(out))
+    return dict(bo=out[0], bi=out[1], cthth=out[2], cth=out[3], fw=out[4],
+                ct=complex(out[5], out[6]), c0=complex(out[7], out[8]),
+                d=complex(out[9], out[10]), r=out[11], Delta=out[12])
+
+
 def orbit_omega(M, a, r0):
     return _lib().or_orbit_omega(M, a, r0)
 
@@ -145,7 +170,7 @@ class Grid:
 
     def __init__(self, M=1.0, a=0.0, s=-2, m=2, n_r=101, n_theta=17,
                  rstar_min=-50.0, rstar_max=50.0, dt=0.1, i_obs=None,
-                 extract_every=0, source=None, kind="f64"):
+                 extract_every=0, source=None, layer_R=0.0, kind="f64"):
         self.kind = kind
         self.lib = _lib(kind)
         if i_obs is None:
@@ -155,6 +180,7 @@ class Grid:
         d.n_r, d.n_theta = n_r, n_theta
         d.rstar_min, d.rstar_max, d.dt = rstar_min, rstar_max, dt
         d.i_obs, d.extract_every = int(i_obs), int(extract_every)
+        d.layer_R = layer_R
         if source is not None:
             d.src_kind = SOURCE_SHAPES[source.get("shape", "gaussian")]
             d.src_r0 = source["r0"]
@@ -236,11 +262,11 @@ class Grid:
         return out
 
     def coeff_column(self, q):
-        out = np.zeros((self.n_theta, 10))
+        out = np.zeros((self.n_theta, 12))
         self.lib.or_get_coeff_column(self._h, int(q), _ptr(out))
         return dict(b=out[:, 0], cthth=out[:, 1], cth=out[:, 2],
                     ct=out[:, 3] + 1j * out[:, 4], c0=out[:, 5] + 1j * out[:, 6],
-                    d=out[:, 7] + 1j * out[:, 8])
+                    d=out[:, 7] + 1j * out[:, 8], bi=out[:, 9], fw=out[:, 10])
 
     def source_value(self, t, rstar, theta):
         out = np.zeros(2)

@@ -48,6 +48,12 @@
  *    source may take the discrete delta functions that item 1 describes as
  *    the finite-difference derivative of a step function on the grid (kinds
  *    2 and 3 below).
+ *  - Hyperboloidal layer (Section 2.3, item 2): beyond rho = R the grid
+ *    coordinate rho is compactified, r* = rho / Omega(rho), so that the last
+ *    node rho = S is future null infinity, and the time is tau = t - h(r*)
+ *    with h' = 1 - d rho / d r*.  The evolved pair there is (Phi, Pi~) with
+ *    Pi~ = Pi / (1 - h' b); the last node is an outflow boundary, filled by
+ *    linear extrapolation.  The transformed system is derived below.
  */
 #include <stdlib.h>
 #include <string.h>
@@ -199,6 +205,101 @@ static coeffs point_coeffs(const kerr_bg *k, int s, int m, real x, real th)
 }
 
 /* ------------------------------------------------------------------ */
+/* Hyperboloidal layer                                                  */
+/* ------------------------------------------------------------------ */
+
+/* Compactifying layer on rho in [R, S] (0 < R < S):
+ *   r*(rho) = rho / Omega(rho),  Omega = 1 - ((rho - R)/(S - R))^4,
+ * equal to rho for rho <= R, so r* runs to infinity as rho -> S.  With
+ *   rho' = d rho / d r* = Omega^2 / (Omega - rho Omega'),
+ *   H    = d h / d r*   = 1 - rho'        (tau = t - h(r*)),
+ *   rho'' = d rho' / d rho,
+ * outgoing rays keep unit speed in rho.  out = r*, rho', H, rho''. */
+typedef struct {
+    real rstar, rhop, H, rhopp;
+} layer_map;
+
+static layer_map layer_map_at(real R, real S, real rho)
+{
+    layer_map L;
+    if (rho <= R) {
+        L.rstar = rho;
+        L.rhop = 1;
+        L.H = 0;
+        L.rhopp = 0;
+        return L;
+    }
+    real L4 = S - R, xi = (rho - R) / L4;
+    real Om = 1 - xi * xi * xi * xi;
+    real Om1 = -4 * xi * xi * xi / L4;
+    real Om2 = -12 * xi * xi / (L4 * L4);
+    real q = Om - rho * Om1; /* d q / d rho = -rho Om2 */
+    L.rstar = rho / Om;
+    L.rhop = Om * Om / q;
+    L.H = 1 - L.rhop;
+    L.rhopp = (2 * Om * Om1 * q + Om * Om * rho * Om2) / (q * q);
+    return L;
+}
+
+/* Coefficients of the first-order system in the layer.  Changing to
+ * (tau, rho) turns d_t into d_tau and d_{r*} into -H d_tau + rho' d_rho.
+ * With w = 1 - H b, v = 1 + H b, the Phi equation Phi_t + b Phi_{r*} = Pi
+ * becomes w Phi_tau + b rho' Phi_rho = Pi, and the Pi equation
+ * (1 + H b) Pi_tau - b rho' Pi_rho - d H Phi_tau + d rho' Phi_rho = S_Pi.
+ * Eliminating Phi_tau (H b + w = 1) and writing Pi = w Pi~:
+ *   Phi_tau + (b rho'/w) Phi_rho = Pi~
+ *   Pi~_tau - (b rho'/v) Pi~_rho + (d rho'/(w^2 v)) Phi_rho
+ *       = [ct w + d H + b rho' w_rho] Pi~ / (w v)
+ *         + [cthth (Phi_thth + cot Phi_th) + c0 Phi + F] / (w v),
+ * with b rho' w_rho = b^2 rho' rho'' - b H b'.  So the layer has separate
+ * outgoing and ingoing speeds bo = b rho'/w and bi = b rho'/v, and
+ * d~ = d rho'/(w^2 v), ct~ = (ct w + d H + b^2 rho' rho'' - b H b')/(w v),
+ * and cthth, cth, c0 and F scaled by fw = 1/(w v).  For the spin s = -2
+ * field every one of them stays finite as rho -> S: w ~ rho' there and
+ * c1 - ct, d, c0, cthth all fall off like 1/r^2.  Near S, 1 - b is far
+ * below rounding of b, so w is formed as rho' b + (1 - b) with
+ * 1 - b = -a^2 Delta sin^2 / (Sh (Sh + rho)). */
+typedef struct {
+    real bo, bi, cthth, cth, fw;
+    cplx ct, c0, d;
+} lcoeffs;
+
+static lcoeffs layer_coeffs(const kerr_bg *k, int s, int m, real x, real th, const layer_map *L)
+{
+    coeffs c = point_coeffs(k, s, m, x, th);
+    lcoeffs o;
+    if (L->H == 0 && L->rhop == 1) {
+        o.bo = o.bi = c.b;
+        o.cthth = c.cthth;
+        o.cth = c.cth;
+        o.fw = 1;
+        o.ct = c.ct;
+        o.c0 = c.c0;
+        o.d = c.d;
+        return o;
+    }
+    real a = k->a;
+    real r = k->rp + x;
+    real Delta = x * (x + k->rp - k->rm);
+    real rho = r * r + a * a;
+    real sn = sin(th);
+    real Sh = sqrt(rho * rho - a * a * Delta * sn * sn);
+    real one_minus_b = -a * a * Delta * sn * sn / (Sh * (Sh + rho));
+    real w = L->rhop * c.b + one_minus_b;
+    real v = 1 + L->H * c.b;
+    real wv = w * v;
+    o.bo = c.b * L->rhop / w;
+    o.bi = c.b * L->rhop / v;
+    o.d = c.d * L->rhop / (w * wv);
+    o.ct = (c.ct * w + c.d * L->H + c.b * c.b * L->rhop * L->rhopp - c.b * L->H * c.bp) / wv;
+    o.fw = 1 / wv;
+    o.cthth = c.cthth / wv;
+    o.cth = c.cth / wv;
+    o.c0 = c.c0 / wv;
+    return o;
+}
+
+/* ------------------------------------------------------------------ */
 /* Grid, state, source                                                  */
 /* ------------------------------------------------------------------ */
 
@@ -217,6 +318,9 @@ typedef struct {
     double src_sigma_r_cells, src_sigma_th_cells, src_window_sigmas;
     double src_t0;   /* time along the orbit at step 0 (a segment's start) */
     double src_ramp; /* switch-on time of the source (0 = none) */
+    /* hyperboloidal layer: 0 = none; else the layer starts at rho = layer_R
+       and rstar_max is the grid position S of future null infinity */
+    double layer_R;
 } or_desc;
 
 typedef struct {
@@ -226,9 +330,12 @@ typedef struct {
     real h, dth, dt;
     /* radial positions: index q = 2i (node i) or 2i+1 (half node i+1/2) */
     real *rstar, *x; /* [2*nr-1] */
-    /* coefficient planes [q][j] */
-    real *b, *cthth, *cth;
+    /* coefficient planes [q][j]; b is the outgoing speed (Phi row) and bi
+       the ingoing one (Pi row), equal outside a hyperboloidal layer; fw
+       scales the source (1 outside a layer) */
+    real *b, *bi, *fw, *cthth, *cth;
     cplx *d, *ct, *c0;
+    int layer; /* hyperboloidal layer on: the last node is future null infinity */
     /* state u^n = (Phi, Pi), [j][i]; half-step array [j][i] (i <-> i+1/2) */
     cplx *phi, *pi, *hphi, *hpi, *nphi, *npi;
     long step;
@@ -249,6 +356,8 @@ static void free_grid(or_grid *g)
     free(g->rstar);
     free(g->x);
     free(g->b);
+    free(g->bi);
+    free(g->fw);
     free(g->cthth);
     free(g->cth);
     free(g->d);
@@ -349,7 +458,7 @@ static cplx S_pi(const or_grid *g, int q, int j, cplx phim, cplx phi0, cplx phip
     size_t c = QIDX(g, q, j);
     cplx d2 = (phip - 2 * phi0 + phim) / (g->dth * g->dth);
     cplx d1 = (phip - phim) / (2 * g->dth);
-    return g->ct[c] * pi0 + g->cthth[c] * d2 + g->cth[c] * d1 + g->c0[c] * phi0 + F;
+    return g->ct[c] * pi0 + g->cthth[c] * d2 + g->cth[c] * d1 + g->c0[c] * phi0 + g->fw[c] * F;
 }
 
 /* Pole value from the two next interior rows (Section 2.2): for even m + s
@@ -403,7 +512,7 @@ static void lw_step(or_grid *g, const double *F_half, const double *F_node)
             cplx s_phi = pib;
             cplx s_pi = S_pi(g, q, j, phb[0], phb[1], phb[2], pib, F);
             cplx adv_phi = g->b[c] * dphi / h;
-            cplx adv_pi = (g->d[c] * dphi - g->b[c] * dpi) / h;
+            cplx adv_pi = (g->d[c] * dphi - g->bi[c] * dpi) / h;
             g->hphi[IDX(g, j, i)] = phb[1] - dt / 2 * (adv_phi - s_phi);
             g->hpi[IDX(g, j, i)] = pib - dt / 2 * (adv_pi - s_pi);
         }
@@ -433,17 +542,25 @@ static void lw_step(or_grid *g, const double *F_half, const double *F_node)
             cplx s_phi = pit;
             cplx s_pi = S_pi(g, q, j, pht[0], pht[1], pht[2], pit, F);
             cplx adv_phi = g->b[c] * dphi / h;
-            cplx adv_pi = (g->d[c] * dphi - g->b[c] * dpi) / h;
+            cplx adv_pi = (g->d[c] * dphi - g->bi[c] * dpi) / h;
             g->nphi[IDX(g, j, i)] = g->phi[IDX(g, j, i)] - dt * (adv_phi - s_phi);
             g->npi[IDX(g, j, i)] = g->pi[IDX(g, j, i)] - dt * (adv_pi - s_pi);
         }
     }
-    /* Radial boundaries: Phi = Pi = 0 at i = 0 and i = nr-1. */
+    /* Radial boundaries: Phi = Pi = 0 at i = 0 and i = nr-1.  With a
+     * hyperboloidal layer the last node is future null infinity, where no
+     * characteristic enters: it takes the linear extrapolation
+     * X_{nr-1} = 2 X_{nr-2} - X_{nr-3} of the new interior values. */
     for (int j = 0; j < nth; ++j) {
         g->nphi[IDX(g, j, 0)] = 0;
         g->npi[IDX(g, j, 0)] = 0;
-        g->nphi[IDX(g, j, nr - 1)] = 0;
-        g->npi[IDX(g, j, nr - 1)] = 0;
+        if (g->layer) {
+            g->nphi[IDX(g, j, nr - 1)] = 2 * g->nphi[IDX(g, j, nr - 2)] - g->nphi[IDX(g, j, nr - 3)];
+            g->npi[IDX(g, j, nr - 1)] = 2 * g->npi[IDX(g, j, nr - 2)] - g->npi[IDX(g, j, nr - 3)];
+        } else {
+            g->nphi[IDX(g, j, nr - 1)] = 0;
+            g->npi[IDX(g, j, nr - 1)] = 0;
+        }
     }
     pole_bc_rows(g, g->nphi, nr);
     pole_bc_rows(g, g->npi, nr);
@@ -529,6 +646,8 @@ void *or_grid_new(const or_desc *d)
     if (!d || d->n_r < 5 || d->n_theta < 5 || !(d->M > 0) || !(fabs(d->a) < d->M) || !(d->rstar_max > d->rstar_min) ||
         !(d->dt > 0) || d->i_obs < 0 || d->i_obs >= d->n_r)
         return NULL;
+    if (d->layer_R != 0 && !(d->layer_R > 0 && d->layer_R > d->rstar_min && d->layer_R < d->rstar_max && d->s == -2))
+        return NULL;
     or_grid *g = (or_grid *)calloc(1, sizeof(or_grid));
     if (!g)
         return NULL;
@@ -545,6 +664,8 @@ void *or_grid_new(const or_desc *d)
     g->rstar = (real *)malloc(nq * sizeof(real));
     g->x = (real *)malloc(nq * sizeof(real));
     g->b = (real *)calloc(nqp, sizeof(real));
+    g->bi = (real *)calloc(nqp, sizeof(real));
+    g->fw = (real *)calloc(nqp, sizeof(real));
     g->cthth = (real *)calloc(nqp, sizeof(real));
     g->cth = (real *)calloc(nqp, sizeof(real));
     g->d = (cplx *)calloc(nqp, sizeof(cplx));
@@ -556,23 +677,38 @@ void *or_grid_new(const or_desc *d)
     g->hpi = (cplx *)calloc(npt, sizeof(cplx));
     g->nphi = (cplx *)calloc(npt, sizeof(cplx));
     g->npi = (cplx *)calloc(npt, sizeof(cplx));
-    if (!g->rstar || !g->x || !g->b || !g->cthth || !g->cth || !g->d || !g->ct || !g->c0 || !g->phi || !g->pi ||
+    if (!g->rstar || !g->x || !g->b || !g->bi || !g->fw || !g->cthth || !g->cth || !g->d || !g->ct || !g->c0 || !g->phi || !g->pi ||
         !g->hphi || !g->hpi || !g->nphi || !g->npi) {
         free_grid(g);
         return NULL;
     }
-    /* Nodes r*_i = r*_min + i h, half nodes r*_min + (i + 1/2) h. */
+    /* Nodes r*_i = r*_min + i h, half nodes r*_min + (i + 1/2) h.  With a
+     * layer these are the grid positions rho, and r* = rho / Omega(rho)
+     * beyond R; the last node is future null infinity (r* infinite), where
+     * no coefficient is used. */
+    g->layer = d->layer_R != 0;
+    size_t nq_used = g->layer ? nq - 1 : nq;
     for (size_t q = 0; q < nq; ++q) {
-        g->rstar[q] = (real)d->rstar_min + (real)q * g->h / 2;
+        real rho = (real)d->rstar_min + (real)q * g->h / 2;
+        if (q >= nq_used) {
+            g->rstar[q] = INFINITY;
+            g->x[q] = INFINITY;
+            continue;
+        }
+        g->rstar[q] = g->layer ? layer_map_at((real)d->layer_R, (real)d->rstar_max, rho).rstar : rho;
         g->x[q] = x_of_rstar(&g->k, g->rstar[q]);
     }
     /* Coefficients at every interior theta row (never on the poles). */
 #pragma omp parallel for schedule(static)
-    for (size_t q = 0; q < nq; ++q) {
+    for (size_t q = 0; q < nq_used; ++q) {
+        real rho = (real)d->rstar_min + (real)q * g->h / 2;
+        layer_map L = layer_map_at(g->layer ? (real)d->layer_R : INFINITY, (real)d->rstar_max, rho);
         for (int j = 1; j < g->nth - 1; ++j) {
-            coeffs c = point_coeffs(&g->k, d->s, d->m, g->x[q], j * g->dth);
+            lcoeffs c = layer_coeffs(&g->k, d->s, d->m, g->x[q], j * g->dth, &L);
             size_t o = QIDX(g, q, j);
-            g->b[o] = c.b;
+            g->b[o] = c.bo;
+            g->bi[o] = c.bi;
+            g->fw[o] = c.fw;
             g->cthth[o] = c.cthth;
             g->cth[o] = c.cth;
             g->d[o] = c.d;
@@ -678,13 +814,14 @@ void or_rhs_column(void *hd, int q, const double *phi_col, const double *pi_col,
 }
 
 /* Coefficient planes at radial position q for all theta rows:
- * out[nth][10] = b, cthth, cth, ct.re, ct.im, c0.re, c0.im, d.re, d.im, 0 */
+ * out[nth][12] = b, cthth, cth, ct.re, ct.im, c0.re, c0.im, d.re, d.im,
+ *                bi, fw, 0 */
 void or_get_coeff_column(void *hd, int q, double *out)
 {
     or_grid *g = (or_grid *)hd;
     for (int j = 0; j < g->nth; ++j) {
         size_t c = QIDX(g, q, j);
-        double *o = out + 10 * j;
+        double *o = out + 12 * j;
         o[0] = (double)g->b[c];
         o[1] = (double)g->cthth[c];
         o[2] = (double)g->cth[c];
@@ -694,8 +831,44 @@ void or_get_coeff_column(void *hd, int q, double *out)
         o[6] = (double)cimag(g->c0[c]);
         o[7] = (double)creal(g->d[c]);
         o[8] = (double)cimag(g->d[c]);
-        o[9] = 0;
+        o[9] = (double)g->bi[c];
+        o[10] = (double)g->fw[c];
+        o[11] = 0;
     }
+}
+
+/* Layer map at grid position rho: out = r*, rho', H, rho''. */
+void or_layer_map(double R, double S, double rho, double *out)
+{
+    layer_map L = layer_map_at(R, S, rho);
+    out[0] = (double)L.rstar;
+    out[1] = (double)L.rhop;
+    out[2] = (double)L.H;
+    out[3] = (double)L.rhopp;
+}
+
+/* Layer coefficients at grid position rho (R < rho < S) and theta:
+ * out[13] = bo, bi, cthth, cth, fw, ct.re, ct.im, c0.re, c0.im, d.re, d.im,
+ *           r, Delta.  Outside the layer they are the plain coefficients. */
+void or_layer_coeffs(double M, double a, int s, int m, double R, double S, double rho, double th, double *out)
+{
+    kerr_bg k = make_bg(M, a);
+    layer_map L = layer_map_at(R, S, rho);
+    real x = x_of_rstar(&k, L.rstar);
+    lcoeffs c = layer_coeffs(&k, s, m, x, th, &L);
+    out[0] = (double)c.bo;
+    out[1] = (double)c.bi;
+    out[2] = (double)c.cthth;
+    out[3] = (double)c.cth;
+    out[4] = (double)c.fw;
+    out[5] = (double)creal(c.ct);
+    out[6] = (double)cimag(c.ct);
+    out[7] = (double)creal(c.c0);
+    out[8] = (double)cimag(c.c0);
+    out[9] = (double)creal(c.d);
+    out[10] = (double)cimag(c.d);
+    out[11] = (double)(k.rp + x);
+    out[12] = (double)(x * (x + k.rp - k.rm));
 }
 
 /* Synthetic source value at (t, r*, theta) (for tests of the source). */

@@ -1,12 +1,13 @@
 /* Test driver: the oracle compiled together with this file under AddressSanitizer
  * and UndefinedBehaviorSanitizer (tests/test_sanitizers.py).  It runs small
  * grids with every source kind, with and without the switch-on, both pole
- * rules, and reads back the state and the waveform. */
+ * rules, with and without a hyperboloidal layer, and reads back the state and
+ * the waveform. */
 #include "../oracle/teuk_oracle.c"
 
 #include <stdio.h>
 
-static int run_case(double a, int s, int m, int n_r, int n_theta, int kind, double ramp)
+static int run_case(double a, int s, int m, int n_r, int n_theta, int kind, double ramp, double layer_R)
 {
     or_desc d;
     memset(&d, 0, sizeof d);
@@ -30,6 +31,8 @@ static int run_case(double a, int s, int m, int n_r, int n_theta, int kind, doub
     d.src_window_sigmas = 6.0;
     d.src_t0 = 3.0;
     d.src_ramp = ramp;
+    d.layer_R = layer_R;
+    if (layer_R != 0) d.i_obs = n_r - 1;  /* read the waveform at null infinity */
     void *g = or_grid_new(&d);
     if (!g) return 1;
     size_t npt = (size_t)n_r * n_theta;
@@ -55,9 +58,10 @@ int main(void)
 {
     int bad = 0;
     for (int kind = 0; kind <= 3; ++kind) {
-        bad |= run_case(0.9, -2, 2, 41, 9, kind, 0.0);
-        bad |= run_case(0.6, -2, 3, 37, 10, kind, 0.5);
-        bad |= run_case(0.0, 1, -2, 30, 7, kind, 0.0);
+        bad |= run_case(0.9, -2, 2, 41, 9, kind, 0.0, 0.0);
+        bad |= run_case(0.6, -2, 3, 37, 10, kind, 0.5, 0.0);
+        bad |= run_case(0.0, 1, -2, 30, 7, kind, 0.0, 0.0);
+        bad |= run_case(0.7, -2, 2, 43, 9, kind, 0.3, 20.0);  /* hyperboloidal layer on [20, 30] */
     }
     printf("%s\n", bad ? "FAILED" : "ok");
     return bad;

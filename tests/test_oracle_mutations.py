@@ -14,6 +14,7 @@ import pytest
 import oracle
 from oracle import build as orbuild
 
+import test_layer as LAYER
 import test_oracle_pins as PINS
 import test_segments as SEGS
 import test_source_shapes as SHAPES
@@ -30,8 +31,8 @@ MUTANTS = [
      ["mms_even", "principal"]),
     ("cot term sign", "c.cth = c.cthth * cs / sn;", "c.cth = -c.cthth * cs / sn;", ["eig"]),
     ("first-order pole condition", "return (4 * x1 - x2) / 3;", "return x1;", ["eig", "mms_even"]),
-    ("advection sign on Pi", "cplx adv_pi = (g->d[c] * dphi - g->b[c] * dpi) / h;\n            g->hphi",
-     "cplx adv_pi = (g->d[c] * dphi + g->b[c] * dpi) / h;\n            g->hphi", ["mms_even"]),
+    ("advection sign on Pi", "cplx adv_pi = (g->d[c] * dphi - g->bi[c] * dpi) / h;\n            g->hphi",
+     "cplx adv_pi = (g->d[c] * dphi + g->bi[c] * dpi) / h;\n            g->hphi", ["mms_even"]),
     ("source at t^n in the second step", "F = source_at(g, th_half, g->rstar[q], th);",
      "F = source_at(g, tn, g->rstar[q], th);", ["source"]),
     ("forcing of Eq. (4) taken one node off",
@@ -56,6 +57,13 @@ MUTANTS = [
      "real a = bump_tail(x), b = bump_tail(x);", ["switch_on"]),
     ("switch-on counted from the orbit's origin", "switch_on(t / (real)d->src_ramp)",
      "switch_on((t + (real)d->src_t0) / (real)d->src_ramp)", ["switch_on"]),
+    ("layer ct drops the d H term", "o.ct = (c.ct * w + c.d * L->H + c.b", "o.ct = (c.ct * w + c.b", ["layer_eq"]),
+    ("layer ingoing speed over w", "o.bi = c.b * L->rhop / v;", "o.bi = c.b * L->rhop / w;", ["layer_eq"]),
+    ("layer w without 1 - b", "real w = L->rhop * c.b + one_minus_b;", "real w = L->rhop * c.b;", ["layer_eq"]),
+    ("layer rho'' sign", "L.rhopp = (2 * Om * Om1 * q + Om * Om * rho * Om2)",
+     "L.rhopp = (2 * Om * Om1 * q - Om * Om * rho * Om2)", ["layer_map"]),
+    ("scri node held at zero", "g->nphi[IDX(g, j, nr - 1)] = 2 * g->nphi[IDX(g, j, nr - 2)] - g->nphi[IDX(g, j, nr - 3)];",
+     "g->nphi[IDX(g, j, nr - 1)] = 0;", ["layer_dyn"]),
 ]
 
 
@@ -86,6 +94,14 @@ def run_pin(name, kind):
             SHAPES.step_delta_check(q0, kind=kind)
     elif name == "switch_on":
         SEGS.switch_on_check(kind=kind)
+    elif name == "layer_eq":
+        LAYER.eq1_check(0.9, 2, kind=kind)
+    elif name == "layer_map":
+        for rho in LAYER.MAP_POINTS:
+            LAYER.map_check(rho, kind=kind)
+    elif name == "layer_dyn":
+        LAYER.interior_check(0.5, 2, kind=kind)
+        LAYER.decay_check(kind=kind)
     elif name == "delta_theta":
         for case in SHAPES.THETA_CASES:
             SHAPES.theta_delta_check(*case, kind=kind)
@@ -101,7 +117,7 @@ def src_text():
 
 def test_unmutated_source_passes_the_detectors(src_text):
     for pin in ("mms_even", "mms_odd", "eig", "tortoise", "source", "delta_linear", "delta_step", "delta_theta",
-                "switch_on"):
+                "switch_on", "layer_eq", "layer_map", "layer_dyn"):
         run_pin(pin, "f64")
 
 
