@@ -296,6 +296,86 @@ def richardson_study(args):
     print(json.dumps(out), flush=True)
 
 
+def layer_study(args):
+    """Section 2.3 item 2 on the GPU: a Kerr mode (a = 0.9, m = 2) driven by a
+    circular orbit at r0 = 10M (switched on over 100M) on three domains with
+    the same h, dtheta and dt: [-300, 100]M ending in a hyperboloidal layer on
+    [R, 100]M whose last node is null infinity; the same domain closed by the
+    Dirichlet wall; and [-300, 700]M, long enough that nothing returns from
+    its wall within the window.  The projected waveform at r* = 50M of the two
+    short domains against the long one's, over the window after the direct
+    signal arrives; the waveform at null infinity beside it; and the step
+    rate of the layer's two-pass kernels.  One JSON line."""
+    import numpy as np
+    import torch
+    from paper_1206_0270_amd import tk
+    from paper_1206_0270_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    h, nth, T, R = args.layer_h, args.layer_nth, args.layer_window, args.layer_start
+    src = dict(r0=10.0, phase0=0.7, ramp=100.0)
+
+    def mk(rmax, layer, obs, name):
+        return W.instance(a=0.9, m=2, n_r=int(round((rmax + 300.0) / h)) + 1, n_theta=nth, rstar_min=-300.0,
+                          rstar_max=rmax, rstar_obs=obs, layer_start=layer, source=src, name=name)
+
+    cases = {"layer": [mk(100.0, R, 50.0, "layer r*=50"), mk(100.0, R, 100.0, "layer scri")],
+             "wall": [mk(100.0, 0.0, 50.0, "wall r*=50")],
+             "long": [mk(700.0, 0.0, 50.0, "long r*=50")]}
+    dt = min(i["dt"] for c in cases.values() for i in c)
+    out = {}
+    for key, insts in cases.items():
+        for i in insts:
+            i["dt"] = dt
+            i["extract_every"] = max(1, int(round(1.0 / dt)))
+        steps = int(round(T / dt))
+        steps -= steps % 2
+        cap = int(T) + 64
+        st = tk.Stepper(insts, wave_capacity=cap)
+        if key != "layer":
+            st.autotune(warmup=2, steps=6)
+        t = st.get_tuning()
+        t["graph_steps"] = 100
+        st.set_tuning(**t)
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(st.stream)
+        st.step(steps)
+        ev1.record(st.stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1)
+        pts = sum(i["n_r"] * i["n_theta"] for i in insts)
+        out[key] = dict(waves=[projected_waveform(i, st.extract(k, max_samples=cap)) for k, i in enumerate(insts)],
+                        updates_per_s=pts * steps / (ms / 1e3), ms_per_step=ms / steps, points=pts, steps=steps,
+                        kernel=t["kernel"])
+        st.close()
+        print(f"# {key}: {pts} points, {steps} steps in {ms / 1e3:.2f} s", file=sys.stderr, flush=True)
+    n = min(len(out[k]["waves"][0]) for k in out)
+    times = (np.arange(n) + 1) * cases["long"][0]["extract_every"] * dt
+    w_long = out["long"]["waves"][0][:n]
+    win = times >= args.layer_from
+    scale = np.abs(w_long[win]).max()
+    diff = {k: float(np.abs(out[k]["waves"][0][:n][win] - w_long[win]).max() / scale) for k in ("layer", "wall")}
+    w_scri = out["layer"]["waves"][1][:n]
+    tail = times >= T - 100.0
+    lay_bytes = 160.0  # two-pass: u^n read twice, half array written and read, u^{n+1} written (32 B each)
+    ups = out["layer"]["updates_per_s"]
+    res = {
+        "metric": "hyperboloidal layer: waveform at r*=50M against a domain 7x longer; step rate of its kernels",
+        "workload": f"a=0.9 m=2, circular orbit r0=10M switched on over 100M; h={h}M, {nth} theta rows, dt={dt:.6g}; "
+                    f"layer [-300,100]M with R={R}M vs wall [-300,100]M vs long [-300,700]M; window {T}M",
+        "max_rel_diff_vs_long": {"layer": diff["layer"], "wall": diff["wall"], "from_t": args.layer_from},
+        "scri_over_r50_amplitude_last_100M": float(np.abs(w_scri[tail]).mean() / np.abs(w_long[tail]).mean()),
+        "updates_per_s": {k: out[k]["updates_per_s"] for k in out},
+        "layer_kernels": {"ms_per_step": out["layer"]["ms_per_step"], "points": out["layer"]["points"],
+                          "bytes_per_update": lay_bytes, "achieved_GBps": ups * lay_bytes / 1e9,
+                          "frac_of_8TBps": ups * lay_bytes / 8e12},
+        "kernels": {k: out[k]["kernel"] for k in out},
+    }
+    print(json.dumps(res), flush=True)
+
+
 def source_study(args):
     """Section 2.3 item 1 on the GPU: one Kerr mode driven by the same
     circular orbit with three representations of the point particle (the
@@ -502,6 +582,14 @@ def main():
     ap.add_argument("--seg-overlap", type=float, default=300.0, help="segments study: overlap per segment (M)")
     ap.add_argument("--seg-ramp", type=float, default=0.0,
                     help="segments study: switch-on time of the source in every run (M; 0 = abrupt)")
+    ap.add_argument("--layer-study", action="store_true",
+                    help="hyperboloidal layer vs a wall and a long domain, and the layer kernels' step rate")
+    ap.add_argument("--layer-h", type=float, default=0.075, help="layer study: r* spacing (M)")
+    ap.add_argument("--layer-nth", type=int, default=65, help="layer study: theta rows")
+    ap.add_argument("--layer-window", type=float, default=600.0, help="layer study: simulated time (M)")
+    ap.add_argument("--layer-start", type=float, default=60.0, help="layer study: R, where the layer begins (M)")
+    ap.add_argument("--layer-from", type=float, default=150.0,
+                    help="layer study: compare waveforms from this time on (M)")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="instead of the stepper, run a plain device copy of this many GiB "
                          "(calibrates the HBM byte counters)")
@@ -522,6 +610,9 @@ def main():
         return
     if args.source_study:
         source_study(args)
+        return
+    if args.layer_study:
+        layer_study(args)
         return
     import torch
     from paper_1206_0270_amd import tk

@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define TK_ABI_VERSION 2
+#define TK_ABI_VERSION 3
 
 typedef struct tk_ctx tk_ctx;
 
@@ -79,6 +79,21 @@ typedef struct {
     int extract_every;    /* steps between waveform samples; 0 = no sampling  */
     int wave_capacity;    /* device ring size in samples (0 -> 4096)          */
     int flags;            /* TK_FLAG_* */
+    /* Hyperboloidal outer layer (Section 2.3, item 2); 0 = none.  Otherwise
+     * the nodes rho_i = rstar_min + i h are grid positions: r* = rho up to
+     * rho = layer_start = R, and beyond it r* = rho / Omega(rho) with
+     * Omega = 1 - ((rho - R) / (rstar_max - R))^4, so the last node
+     * (rho = rstar_max) is future null infinity.  There the time is
+     * tau = t - h(r*) with h' = H = 1 - d rho / d r* (tau = t below R), and
+     * the second field is Pi~ = Pi / (1 - H b) (Pi below R): tk_set_fields
+     * and tk_get_fields exchange (Phi, Pi~).  The last node takes the linear
+     * extrapolation of the two nodes before it (no characteristic enters
+     * there), so rstar_obs = rstar_max samples the waveform at null
+     * infinity.  Requires s = -2 (whose Phi has a finite limit there),
+     * TK_FP64, max(0, rstar_min) < R, R + 2h <= rstar_max, and a particle
+     * source confined to rho < R.  A context with a layered instance steps
+     * every instance with the layer's two-pass kernels. */
+    double layer_start;
 } tk_instance_desc;
 
 typedef enum {

@@ -1,6 +1,6 @@
 """Build libtk.so (the HIP library) in-tree for gfx950.
 
-hipcc compiles the kernels (tk_kernels.hip) and the host C++ (setup, C ABI)
+hipcc compiles the kernels (tk_kernels.hip, tk_layer.hip) and the host C++ (setup, C ABI)
 and links them into paper_1206_0270_amd/libtk.so.  Objects go to _build/.
 """
 import os
@@ -15,7 +15,7 @@ BUILD = os.path.join(ROOT, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-HIP_SOURCES = ["tk_kernels.hip"]
+HIP_SOURCES = ["tk_kernels.hip", "tk_layer.hip"]
 HOST_SOURCES = ["tk_setup.cpp", "tk_api.cpp", "tk_post.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wextra", "-Wno-unused-parameter",

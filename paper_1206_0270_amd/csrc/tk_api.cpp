@@ -13,6 +13,7 @@
 
 #include "tk_internal.h"
 #include "tk_kernels.h"
+#include "tk_layer_launch.h"
 
 using namespace tk;
 
@@ -35,6 +36,11 @@ struct tk_ctx {
     std::vector<std::vector<Radial>> hrad;   // host copies of the coefficient tables
     std::vector<std::vector<Angular>> hang;
     std::vector<std::vector<AngularF>> hangf;
+    // hyperboloidal layer: any instance with one makes the context step with
+    // the layer's two-pass kernels
+    bool layered = false;
+    size_t off_linst = 0;              // LayerInst per instance
+    std::vector<size_t> off_lay;       // LayerTab table per instance (layered ones)
     long long step = 0;
     int cur = 0;  // state buffer holding u^step (mirror of the device control block)
     tk_tuning tuning{TK_KERNEL_AUTO, 0, 0, 3, TK_TUNE_NT_STORES, 0};
@@ -92,6 +98,13 @@ std::string validate(const tk_instance_desc &d)
         std::snprintf(b, sizeof b, "rstar_obs %.17g outside the grid", d.rstar_obs);
         return b;
     }
+    if (d.layer_start != 0.0) {
+        const double R = d.layer_start;
+        if (!std::isfinite(R) || !(R > 0.0) || !(R > d.rstar_min))
+            return "layer_start must be finite, positive and above rstar_min";
+        if (!(d.rstar_max - R >= 2.0 * h)) return "the layer needs at least two cells before rstar_max";
+        if (d.s != -2) return "the hyperboloidal layer is for the s = -2 field";
+    }
     return "";
 }
 
@@ -145,6 +158,14 @@ void layout(tk_ctx *c)
     c->off_work = off;
     c->work_cap = work_capacity(c);
     off = align_up(off + c->work_cap * sizeof(WorkItem), A);
+    c->off_linst = off;
+    off = align_up(off + c->inst.size() * sizeof(LayerInst), A);
+    c->off_lay.assign(c->inst.size(), 0);
+    for (size_t k = 0; k < c->inst.size(); ++k) {
+        if (c->inst[k].desc.layer_start == 0.0) continue;
+        c->off_lay[k] = off;
+        off = align_up(off + (size_t)(2 * c->inst[k].desc.n_r - 1) * sizeof(LayerTab), A);
+    }
     for (HostInst &h : c->inst) {
         const tk_instance_desc &d = h.desc;
         size_t pts = (size_t)d.n_theta * h.pitch;
@@ -217,6 +238,7 @@ DevInst make_dev(const tk_ctx *c, const HostInst &h)
 
 int resolve_kernel(const tk_ctx *c)
 {
+    if (c->layered) return TK_KERNEL_TWO_PASS;  // the layer's two-pass kernels
     int k = c->tuning.kernel;
     if (k == TK_KERNEL_AUTO) k = c->tuning.rows_per_tile == 0 ? TK_KERNEL_FUSED2 : TK_KERNEL_FUSED;
     if (c->prec != TK_FP64 && k == TK_KERNEL_TWO_PASS) k = TK_KERNEL_FUSED;
@@ -242,6 +264,9 @@ hipError_t launch_one(tk_ctx *c, int kernel, int steps, int kstep, int kflip)
 {
     const DevInst *di = (const DevInst *)(c->ws + c->off_inst);
     const DevCtl *ctl = (const DevCtl *)(c->ws + c->off_ctl);
+    if (kernel == TK_KERNEL_TWO_PASS && c->layered)
+        return launch_layer(di, (const LayerInst *)(c->ws + c->off_linst), (const int2 *)(c->ws + c->off_blocks),
+                            (int)c->blocks.size(), ctl, kstep, kflip, c->stream);
     if (kernel == TK_KERNEL_TWO_PASS)
         return launch_two_pass(di, (const int2 *)(c->ws + c->off_blocks), (int)c->blocks.size(), ctl, kstep, kflip,
                                c->stream);
@@ -389,6 +414,11 @@ tk_status tk_init_grid(const tk_instance_desc *inst, int n_inst, tk_precision pr
         delete c;
         return fail(nullptr, TK_E_INVALID, "too many points");
     }
+    for (int k = 0; k < n_inst; ++k) c->layered = c->layered || inst[k].layer_start != 0.0;
+    if (c->layered && prec != TK_FP64) {
+        delete c;
+        return fail(nullptr, TK_E_INVALID, "the hyperboloidal layer is FP64 only");
+    }
     layout(c);
     *out = c;
     return TK_OK;
@@ -441,8 +471,26 @@ tk_status tk_bind_workspace(tk_ctx *c, void *dev_ptr, size_t bytes)
         if (e == hipSuccess)
             e = hipMemcpyAsync(c->ws + h.off_angf, angf.data(), angf.size() * sizeof(AngularF),
                                hipMemcpyHostToDevice, c->stream);
+        std::vector<LayerTab> lay;
+        if (e == hipSuccess && h.desc.layer_start != 0.0) {
+            lay.resize(2 * h.desc.n_r - 1);
+            fill_layer(h, lay.data());
+            e = hipMemcpyAsync(c->ws + c->off_lay[k], lay.data(), lay.size() * sizeof(LayerTab),
+                               hipMemcpyHostToDevice, c->stream);
+        }
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
         if (e != hipSuccess) st = fail(c, TK_E_DEVICE, std::string("table upload: ") + hipGetErrorString(e));
+    }
+    if (st == TK_OK) {
+        std::vector<LayerInst> li(c->inst.size());
+        for (size_t k = 0; k < c->inst.size(); ++k) {
+            const bool on = c->inst[k].desc.layer_start != 0.0;
+            li[k] = LayerInst{on ? (const LayerTab *)(c->ws + c->off_lay[k]) : nullptr, on ? 1 : 0};
+        }
+        hipError_t e = hipMemcpyAsync(c->ws + c->off_linst, li.data(), li.size() * sizeof(LayerInst),
+                                      hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) st = fail(c, TK_E_DEVICE, std::string("layer upload: ") + hipGetErrorString(e));
     }
     if (st == TK_OK) {
         // zero everything after the tables: fields, compensation, half array, rings, control
@@ -605,6 +653,11 @@ tk_status tk_set_source(tk_ctx *c, int inst, const tk_source_desc *src)
             return fail(c, TK_E_INVALID, "source widths and window must be positive and finite");
         Om = orbit_frequency(h.desc.M, h.desc.a, s.r0);
         rsp = tortoise_of_x(h.desc.M, h.desc.a, s.r0 - h.rp);
+        if (h.desc.layer_start != 0.0) {
+            const double reach = s.kind == TK_SRC_CIRCULAR_GAUSSIAN ? s.window_sigmas * s.sigma_r_cells * h.h : 2.0 * h.h;
+            if (!(rsp + reach < h.desc.layer_start))
+                return fail(c, TK_E_INVALID, "the source must lie below the hyperboloidal layer");
+        }
     } else if (s.kind != TK_SRC_NONE) {
         return fail(c, TK_E_INVALID, "unknown source kind");
     }
@@ -729,6 +782,8 @@ tk_status tk_set_tuning(tk_ctx *c, const tk_tuning *t)
         return fail(c, TK_E_INVALID, "the two-step kernel takes whole strips (rows_per_tile 0) or chunks of >= 4 rows");
     if (t->kernel == TK_KERNEL_TWO_PASS && c->prec != TK_FP64)
         return fail(c, TK_E_INVALID, "the two-pass kernel is FP64 only");
+    if (c->layered && t->kernel != TK_KERNEL_AUTO && t->kernel != TK_KERNEL_TWO_PASS)
+        return fail(c, TK_E_INVALID, "a context with a hyperboloidal layer steps with the layer's two-pass kernels");
     if (t->rows_per_tile < 0 || (t->rows_per_tile > 0 && t->rows_per_tile < 3))
         return fail(c, TK_E_INVALID, "rows_per_tile must be 0 or >= 3");
     if (t->graph_steps < 0 || t->graph_steps > 100000) return fail(c, TK_E_INVALID, "graph_steps out of range");
@@ -818,6 +873,7 @@ tk_status tk_autotune(tk_ctx *c, int warmup, int steps, double *best_ms_per_step
     for (int rows : {8, 4})
         for (int ntf : {(int)TK_TUNE_NT_STORES, 0}) cand.push_back(tk_tuning{TK_KERNEL_TILED, rows, 0, 3, ntf, 0});
     if (c->prec == TK_FP64) cand.push_back(tk_tuning{TK_KERNEL_TWO_PASS, 0, 0, 3, TK_TUNE_NT_STORES, 0});
+    if (c->layered) cand.assign(1, tk_tuning{TK_KERNEL_TWO_PASS, 0, 0, 3, TK_TUNE_NT_STORES, 0});
 
     tk_status st = e == hipSuccess ? TK_OK : fail(c, TK_E_DEVICE, std::string("autotune setup: ") + hipGetErrorString(e));
     double best = 1e300;

@@ -10,6 +10,7 @@
 #include <limits>
 
 #include "tk_internal.h"
+#include "tk_layer.h"
 
 namespace tk {
 
@@ -82,13 +83,63 @@ double orbit_frequency(double M, double a, double r0)
     return sm / (std::pow(r0, 1.5) + a * sm);
 }
 
+// Hyperboloidal layer map (Section 2.3, item 2) on [R, S]: with
+// xi = (rho - R)/(S - R) and Omega = 1 - xi^4, r* = rho / Omega; rho' =
+// d rho / d r* = Omega^2 / q with q = Omega - rho Omega' (so that
+// d q / d rho = -rho Omega''), H = 1 - rho', and rho'' = d rho' / d rho =
+// (2 Omega Omega' q + Omega^2 rho Omega'') / q^2.
+void layer_map(double R, double S, double rho, double *rstar, double *rhop, double *H, double *rhopp)
+{
+    if (!(rho > R)) {
+        *rstar = rho;
+        *rhop = 1.0;
+        *H = 0.0;
+        *rhopp = 0.0;
+        return;
+    }
+    const double L = S - R, xi = (rho - R) / L, xi2 = xi * xi;
+    const double Om = 1.0 - xi2 * xi2;
+    const double dOm = -4.0 * xi2 * xi / L, d2Om = -12.0 * xi2 / (L * L);
+    const double q = Om - rho * dOm;
+    *rstar = rho / Om;
+    *rhop = Om * Om / q;
+    *H = 1.0 - *rhop;
+    *rhopp = (2.0 * Om * dOm * q + Om * Om * rho * d2Om) / (q * q);
+}
+
+void fill_layer(const HostInst &hi, LayerTab *tab)
+{
+    const tk_instance_desc &d = hi.desc;
+    const int nq = 2 * d.n_r - 1;
+    for (int q = 0; q < nq; ++q) {
+        LayerTab &T = tab[q];
+        T.pad = 0.0;
+        if (q == nq - 1) {  // null infinity: never read (the node is extrapolated)
+            T.rhop = T.H = T.rhopp = 0.0;
+            continue;
+        }
+        double rs;
+        layer_map(d.layer_start, d.rstar_max, d.rstar_min + (double)q * hi.h / 2.0, &rs, &T.rhop, &T.H, &T.rhopp);
+    }
+}
+
 void fill_radial(const HostInst &hi, Radial *rad)
 {
     const tk_instance_desc &d = hi.desc;
     const double M = d.M, a = d.a, s = d.s, m = d.m;
     const int nq = 2 * d.n_r - 1;
+    const bool layer = d.layer_start != 0.0;
     for (int q = 0; q < nq; ++q) {
         double rs = d.rstar_min + (double)q * hi.h / 2.0;
+        if (layer && q == nq - 1) {  // null infinity: no coefficient is read there
+            rad[q] = Radial{};
+            rad[q].rstar = INFINITY;
+            continue;
+        }
+        if (layer) {
+            double rhop, H, rhopp;
+            layer_map(d.layer_start, d.rstar_max, rs, &rs, &rhop, &H, &rhopp);
+        }
         double x = x_of_tortoise(M, a, rs);
         double r = hi.rp + x;
         double Dl = x * (x + (hi.rp - hi.rm));  // Delta = (r - r+)(r - r-)

@@ -43,7 +43,7 @@ class InstanceDesc(ctypes.Structure):
                 ("rstar_min", ctypes.c_double), ("rstar_max", ctypes.c_double),
                 ("dt", ctypes.c_double), ("rstar_obs", ctypes.c_double),
                 ("extract_every", ctypes.c_int), ("wave_capacity", ctypes.c_int),
-                ("flags", ctypes.c_int)]
+                ("flags", ctypes.c_int), ("layer_start", ctypes.c_double)]
 
 
 class SourceDesc(ctypes.Structure):
@@ -121,6 +121,7 @@ def make_desc(inst, force_dt=False, wave_capacity=0):
     d.extract_every = inst.get("extract_every", 0) or 0
     d.wave_capacity = wave_capacity
     d.flags = TK_FLAG_FORCE_DT if force_dt else 0
+    d.layer_start = inst.get("layer_start", 0.0) or 0.0
     return d
 
 

@@ -92,20 +92,23 @@ def stable_dt(a, m, s, h, n_theta, growth=0.01, M=1.0):
 
 def instance(M=1.0, a=0.0, s=-2, m=2, n_r=801, n_theta=33, rstar_min=-100.0,
              rstar_max=100.0, dt=None, rstar_obs=None, extract_every=None,
-             source=None, init=None, name=""):
-    """Plain dict describing one (a, s, m) mode on one grid."""
+             source=None, init=None, name="", layer_start=0.0):
+    """Plain dict describing one (a, s, m) mode on one grid.  With
+    layer_start = R > 0 the grid ends in a hyperboloidal layer on
+    [R, rstar_max] whose last node is future null infinity (rstar_obs
+    defaults to that node)."""
     h = (rstar_max - rstar_min) / (n_r - 1)
     if dt is None:
         dt = stable_dt(a, m, s, h, n_theta, M=M)
     if rstar_obs is None:
-        rstar_obs = rstar_max - 10.0
+        rstar_obs = rstar_max if layer_start else rstar_max - 10.0
     if extract_every is None:
         extract_every = max(1, int(round(1.0 / dt)))
     return dict(M=M, a=a, s=s, m=m, n_r=n_r, n_theta=n_theta,
                 rstar_min=rstar_min, rstar_max=rstar_max, dt=dt,
                 rstar_obs=rstar_obs, extract_every=extract_every,
                 i_obs=int(math.floor((rstar_obs - rstar_min) / h + 0.5)),
-                source=source, init=init, name=name)
+                source=source, init=init, name=name, layer_start=layer_start)
 
 
 def refine(inst, k, point_limit=False):

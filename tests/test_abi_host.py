@@ -25,12 +25,12 @@ def test_library_exports_every_declared_symbol():
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(tk.EXPORTS)
-    assert lib.tk_abi_version() == 2
+    assert lib.tk_abi_version() == 3
 
 
 def test_struct_layout_matches_header():
     # the ctypes mirrors must have the C sizes (x86-64 ABI)
-    assert ctypes.sizeof(tk.InstanceDesc) == 80
+    assert ctypes.sizeof(tk.InstanceDesc) == 88
     assert ctypes.sizeof(tk.SourceDesc) == 72
     assert ctypes.sizeof(tk.Tuning) == 24
 
@@ -122,7 +122,7 @@ C_PROGRAM = r"""
 #include <stdio.h>
 int main(void)
 {
-    tk_instance_desc d = {1.0, 0.5, -2, 2, 101, 9, -20.0, 25.0, 0.0, 20.0, 3, 0, 0};
+    tk_instance_desc d = {1.0, 0.5, -2, 2, 101, 9, -20.0, 25.0, 0.0, 20.0, 3, 0, 0, 0.0};
     double dt = 0.0, w[6] = {1, 0, 2, 0, 3, 0}, e[2], err[1];
     tk_ctx *ctx = NULL;
     size_t bytes = 0;
@@ -177,3 +177,23 @@ def test_stepper_refuses_without_a_device():
     inst = W.config1()["instances"][0]
     with pytest.raises(RuntimeError, match="no HIP device"):
         tk.Stepper([inst])
+
+
+def test_layer_descriptions_are_validated():
+    """Hyperboloidal layer: accepted on the s = -2 field in FP64 with the
+    layer inside the grid; every other description is refused at init."""
+    base = W.instance(a=0.5, m=2, n_r=201, n_theta=17, rstar_min=-40.0, rstar_max=50.0, layer_start=30.0)
+    assert base["i_obs"] == 200  # the waveform is read at null infinity by default
+    lib = tk.load()
+    st, ctx = _init([tk.make_desc(base)])
+    assert st == tk.TK_OK
+    lib.tk_destroy(ctx)
+    for change in (dict(layer_start=50.0), dict(layer_start=49.9), dict(layer_start=-10.0),
+                   dict(layer_start=float("nan")), dict(s=-1)):
+        inst = dict(base)
+        inst.update(change)
+        st, ctx = _init([tk.make_desc(inst)])
+        assert st == tk.TK_E_INVALID, change
+    arr = (tk.InstanceDesc * 1)(tk.make_desc(base))
+    ctx = ctypes.c_void_p()
+    assert lib.tk_init_grid(arr, 1, tk.TK_FP32_COMP, None, ctypes.byref(ctx)) == tk.TK_E_INVALID

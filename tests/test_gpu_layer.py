@@ -1,0 +1,137 @@
+"""GPU parity of the hyperboloidal layer (Section 2.3, item 2) against the
+oracle's layer, through the C ABI.
+
+Same bar as the other FP64 parity tests: the state (Phi, Pi~) jointly within
+relative L2 1e-12, each field and the waveform read at null infinity within
+max(1e-12, 4 e_ld) (e_ld: the FP64 oracle's distance to its long-double
+build on the same run).  Contexts mix layered and plain instances, ragged
+sizes, both pole rules, sourced and source-free runs.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1206_0270_amd import tk
+from paper_1206_0270_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def oracle_run(inst, steps, kind="f64"):
+    g = oracle.Grid(M=inst["M"], a=inst["a"], s=inst["s"], m=inst["m"], n_r=inst["n_r"],
+                    n_theta=inst["n_theta"], rstar_min=inst["rstar_min"], rstar_max=inst["rstar_max"],
+                    dt=inst["dt"], i_obs=inst["i_obs"], extract_every=inst["extract_every"],
+                    source=inst.get("source"), layer_R=inst.get("layer_start", 0.0), kind=kind)
+    g.set_state(*W.initial_data(inst))
+    g.run(steps)
+    phi, pi = g.get_state()
+    return phi, pi, g.waveform()
+
+
+def check(inst, steps, got, ref):
+    phi, pi, wave = got
+    ophi, opi, owave = ref
+    num = np.sqrt(np.linalg.norm(phi - ophi) ** 2 + np.linalg.norm(pi - opi) ** 2)
+    den = np.sqrt(np.linalg.norm(ophi) ** 2 + np.linalg.norm(opi) ** 2)
+    e = dict(joint=num / den, phi=rel(phi, ophi), pi=rel(pi, opi), wave=rel(wave, owave))
+    say(inst["name"], {k: f"{v:.2e}" for k, v in e.items()})
+    assert wave.shape == owave.shape and owave.size > 0
+    assert e["joint"] <= TOL, e
+    if max(e["phi"], e["pi"], e["wave"]) > TOL:
+        lphi, lpi, lwave = oracle_run(inst, steps, kind="ld")
+        floor = dict(phi=rel(ophi, lphi), pi=rel(opi, lpi), wave=rel(owave, lwave))
+        say("  oracle double vs long double:", {k: f"{v:.2e}" for k, v in floor.items()})
+        for k in ("phi", "pi", "wave"):
+            assert e[k] <= max(TOL, 4 * floor[k]), (k, e[k], floor[k])
+
+
+def gpu_run(insts, steps, graph=0, chunks=None):
+    st = tk.Stepper(insts, force_dt=False)
+    st.set_tuning(kernel=tk.TK_KERNEL_AUTO, graph_steps=graph)
+    for k, inst in enumerate(insts):
+        st.set_fields(k, *W.initial_data(inst))
+    for n in (chunks or [steps]):
+        st.step(n)
+    out = [st.get_fields(k) + (st.extract(k),) for k in range(len(insts))]
+    st.close()
+    return out
+
+
+def layered_instances():
+    rng = W.rng_for(1206)
+    out = []
+    for (n_r, n_th, a, m, src, R, S, lay) in [(201, 17, 0.5, 2, False, 30.0, 50.0, True),
+                                              (163, 13, 0.9, 3, True, 25.0, 40.0, True),
+                                              (150, 9, 0.0, 2, False, 20.0, 45.0, True),
+                                              (130, 11, 0.7, -2, True, 0.0, 30.0, False),
+                                              (97, 7, 0.3, 4, False, 10.0, 30.0, True)]:
+        init = None if src else dict(center=2.0, width=3.0,
+                                     amps={max(abs(m), 2): complex(rng.standard_normal(), rng.standard_normal())})
+        source = dict(r0=6.0 + 3 * rng.uniform(), phase0=float(rng.uniform(0, 6.28)), sigma_r_cells=2.0,
+                      sigma_th_cells=2.0, window_sigmas=6.0, ramp=5.0) if src else None
+        h = (S + 40.0) / (n_r - 1)
+        dt = W.stable_dt(a, m, -2, h, n_th)
+        out.append(W.instance(a=a, m=m, n_r=n_r, n_theta=n_th, rstar_min=-40.0, rstar_max=S, dt=dt,
+                              rstar_obs=S if lay else S - 5.0, extract_every=3, init=init, source=source,
+                              layer_start=R if lay else 0.0,
+                              name=f"layer.{n_r}x{n_th}.a{a}.m{m}.R{R}.S{S}"))
+    return out
+
+
+def test_layer_small_grids_vs_oracle():
+    insts = layered_instances()
+    steps = 400
+    say("layered contexts", [i["name"] for i in insts])
+    res = gpu_run(insts, steps)
+    for inst, got in zip(insts, res):
+        check(inst, steps, got, oracle_run(inst, steps))
+
+
+def test_layer_graph_and_chunks_bitwise():
+    insts = layered_instances()[:3]
+    a = gpu_run(insts, 250)
+    b = gpu_run(insts, 250, graph=40, chunks=[7, 120, 123])
+    for x, y in zip(a, b):
+        for u, v in zip(x, y):
+            assert np.array_equal(u, v)
+
+
+def test_layer_second_workload_size():
+    """8001 x 129 on [-300, 300] with a layer on [250, 300]: the second
+    workload's grid, read at null infinity; 300 steps against the oracle."""
+    inst = W.instance(a=0.9, m=2, n_r=8001, n_theta=129, rstar_min=-300.0, rstar_max=300.0,
+                      layer_start=250.0, extract_every=20,
+                      init=dict(center=240.0, width=4.0, amps={2: 1.0 + 0.5j}), name="layer.8001x129.a0.9")
+    steps = 300
+    say(inst["name"], "steps", steps)
+    got, = gpu_run([inst], steps, graph=100)
+    check(inst, steps, got, oracle_run(inst, steps))
+
+
+def test_layer_rejections():
+    inst = layered_instances()[0]
+    with pytest.raises(tk.TkError):
+        tk.Stepper([inst], precision=tk.TK_FP32_COMP)
+    st = tk.Stepper([inst])
+    try:
+        with pytest.raises(tk.TkError):
+            st.set_tuning(kernel=tk.TK_KERNEL_FUSED2)
+        with pytest.raises(tk.TkError):   # the particle inside the layer
+            st.set_source(0, dict(r0=35.0))
+        st.set_source(0, dict(r0=8.0))
+    finally:
+        st.close()

@@ -48,10 +48,10 @@ def test_host_setup_under_sanitizers(args):
 def test_host_library_entry_points_under_sanitizers():
     # the library's host code (C ABI, validation, work lists, layout, post-
     # processing) rebuilt with the sanitizers and driven from C without a
-    # device; the kernels' object is linked as built
-    kobj = os.path.join(BUILD, "tk_kernels.hip.o")
-    if not os.path.exists(kobj):
-        pytest.skip("build the library first (its kernels' object is linked here)")
+    # device; the kernels' objects are linked as built
+    kobjs = [os.path.join(BUILD, k) for k in ("tk_kernels.hip.o", "tk_layer.hip.o")]
+    if not all(os.path.exists(k) for k in kobjs):
+        pytest.skip("build the library first (its kernels' objects are linked here)")
     out = os.path.join(BUILD, "san")
     os.makedirs(out, exist_ok=True)
     csrc = os.path.join(ROOT, "paper_1206_0270_amd", "csrc")
@@ -63,7 +63,7 @@ def test_host_library_entry_points_under_sanitizers():
                        check=True)
         objs.append(o)
     lib = os.path.join(out, "libtk.so")
-    subprocess.run(["g++", "-shared", "-fsanitize=address,undefined", *objs, kobj, "-L/opt/rocm/lib", "-lamdhip64",
+    subprocess.run(["g++", "-shared", "-fsanitize=address,undefined", *objs, *kobjs, "-L/opt/rocm/lib", "-lamdhip64",
                     "-Wl,-rpath,/opt/rocm/lib", "-o", lib], check=True)
     exe = os.path.join(out, "abi_driver")
     subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-Werror", *SAN, *inc,
