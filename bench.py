@@ -296,6 +296,46 @@ def richardson_study(args):
     print(json.dumps(out), flush=True)
 
 
+def layer_throughput(args):
+    """Step rate of the layer's two-pass kernels on a batch that fills the
+    GPU: the fifth workload's six modes (m = 2, 3, 4 x a = 0.5, 0.9; 16001 x 129
+    on [-300, 300]M), each ending in a layer on [250, 300]M, sourced."""
+    import torch
+    from paper_1206_0270_amd import tk
+    from paper_1206_0270_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    thr = [W.instance(a=a, m=m, n_r=16001, n_theta=129, rstar_min=-300.0, rstar_max=300.0, layer_start=250.0,
+                      extract_every=500, source=dict(r0=8.0, phase0=0.3 * m, ramp=200.0), name=f"m{m} a{a}")
+           for m in (2, 3, 4) for a in (0.5, 0.9)]
+    dt_t = min(i["dt"] for i in thr)
+    for i in thr:
+        i["dt"] = dt_t
+    st = tk.Stepper(thr)
+    st.set_tuning(kernel=tk.TK_KERNEL_AUTO, graph_steps=100)
+    for k, i in enumerate(thr):
+        st.set_fields(k, *W.initial_data(i))
+    st.step(args.layer_warmup)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(st.stream)
+    st.step(args.layer_steps)
+    ev1.record(st.stream)
+    torch.cuda.synchronize()
+    ms_t = ev0.elapsed_time(ev1)
+    st.close()
+    pts_t = sum(i["n_r"] * i["n_theta"] for i in thr)
+    ups_t = pts_t * args.layer_steps / (ms_t / 1e3)
+    print(f"# throughput: {pts_t} points, {args.layer_steps} steps in {ms_t / 1e3:.2f} s", file=sys.stderr,
+          flush=True)
+    lay_bytes = 160.0
+    return {"workload": "6 x 16001 x 129 on [-300,300]M, layers on [250,300]M, sourced", "points": pts_t,
+            "steps": args.layer_steps, "ms_per_step": ms_t / args.layer_steps, "updates_per_s": ups_t,
+            "bytes_per_update": lay_bytes, "achieved_GBps": ups_t * lay_bytes / 1e9,
+            "frac_of_8TBps": ups_t * lay_bytes / 8e12}
+
+
 def layer_study(args):
     """Section 2.3 item 2 on the GPU: a Kerr mode (a = 0.9, m = 2) driven by a
     circular orbit at r0 = 10M (switched on over 100M) on three domains with
@@ -319,9 +359,16 @@ def layer_study(args):
         return W.instance(a=0.9, m=2, n_r=int(round((rmax + 300.0) / h)) + 1, n_theta=nth, rstar_min=-300.0,
                           rstar_max=rmax, rstar_obs=obs, layer_start=layer, source=src, name=name)
 
+    def mk2(rmax, layer, obs, name):
+        i = mk(rmax, layer, obs, name)
+        return W.instance(a=0.9, m=2, n_r=2 * (i["n_r"] - 1) + 1, n_theta=nth, rstar_min=-300.0, rstar_max=rmax,
+                          rstar_obs=obs, layer_start=layer, source=src, name=name + " h/2")
+
     cases = {"layer": [mk(100.0, R, 50.0, "layer r*=50"), mk(100.0, R, 100.0, "layer scri")],
              "wall": [mk(100.0, 0.0, 50.0, "wall r*=50")],
-             "long": [mk(700.0, 0.0, 50.0, "long r*=50")]}
+             "long": [mk(700.0, 0.0, 50.0, "long r*=50")],
+             "layer_h2": [mk2(100.0, R, 50.0, "layer r*=50")],
+             "long_h2": [mk2(700.0, 0.0, 50.0, "long r*=50")]}
     dt = min(i["dt"] for c in cases.values() for i in c)
     out = {}
     for key, insts in cases.items():
@@ -332,7 +379,7 @@ def layer_study(args):
         steps -= steps % 2
         cap = int(T) + 64
         st = tk.Stepper(insts, wave_capacity=cap)
-        if key != "layer":
+        if not key.startswith("layer"):
             st.autotune(warmup=2, steps=6)
         t = st.get_tuning()
         t["graph_steps"] = 100
@@ -357,6 +404,11 @@ def layer_study(args):
     win = times >= args.layer_from
     scale = np.abs(w_long[win]).max()
     diff = {k: float(np.abs(out[k]["waves"][0][:n][win] - w_long[win]).max() / scale) for k in ("layer", "wall")}
+    w_long2 = out["long_h2"]["waves"][0][:n]
+    diff["layer_h2"] = float(np.abs(out["layer_h2"]["waves"][0][:n][win] - w_long2[win]).max()
+                             / np.abs(w_long2[win]).max())
+
+    thr = layer_throughput(args)
     w_scri = out["layer"]["waves"][1][:n]
     tail = times >= T - 100.0
     lay_bytes = 160.0  # two-pass: u^n read twice, half array written and read, u^{n+1} written (32 B each)
@@ -365,12 +417,14 @@ def layer_study(args):
         "metric": "hyperboloidal layer: waveform at r*=50M against a domain 7x longer; step rate of its kernels",
         "workload": f"a=0.9 m=2, circular orbit r0=10M switched on over 100M; h={h}M, {nth} theta rows, dt={dt:.6g}; "
                     f"layer [-300,100]M with R={R}M vs wall [-300,100]M vs long [-300,700]M; window {T}M",
-        "max_rel_diff_vs_long": {"layer": diff["layer"], "wall": diff["wall"], "from_t": args.layer_from},
+        "max_rel_diff_vs_long": {"layer": diff["layer"], "layer_h/2": diff["layer_h2"], "wall": diff["wall"],
+                                 "from_t": args.layer_from},
         "scri_over_r50_amplitude_last_100M": float(np.abs(w_scri[tail]).mean() / np.abs(w_long[tail]).mean()),
         "updates_per_s": {k: out[k]["updates_per_s"] for k in out},
-        "layer_kernels": {"ms_per_step": out["layer"]["ms_per_step"], "points": out["layer"]["points"],
-                          "bytes_per_update": lay_bytes, "achieved_GBps": ups * lay_bytes / 1e9,
-                          "frac_of_8TBps": ups * lay_bytes / 8e12},
+        "layer_kernels_study_grid": {"ms_per_step": out["layer"]["ms_per_step"], "points": out["layer"]["points"],
+                                     "bytes_per_update": lay_bytes, "achieved_GBps": ups * lay_bytes / 1e9,
+                                     "frac_of_8TBps": ups * lay_bytes / 8e12},
+        "layer_kernels_throughput": thr,
         "kernels": {k: out[k]["kernel"] for k in out},
     }
     print(json.dumps(res), flush=True)
@@ -588,6 +642,10 @@ def main():
     ap.add_argument("--layer-nth", type=int, default=65, help="layer study: theta rows")
     ap.add_argument("--layer-window", type=float, default=600.0, help="layer study: simulated time (M)")
     ap.add_argument("--layer-start", type=float, default=60.0, help="layer study: R, where the layer begins (M)")
+    ap.add_argument("--layer-steps", type=int, default=600, help="layer study: timed steps of the throughput leg")
+    ap.add_argument("--layer-warmup", type=int, default=100, help="layer study: warm-up steps of the throughput leg")
+    ap.add_argument("--layer-throughput", action="store_true",
+                    help="only the layer study's throughput leg (one JSON line; short enough to profile)")
     ap.add_argument("--layer-from", type=float, default=150.0,
                     help="layer study: compare waveforms from this time on (M)")
     ap.add_argument("--copy-gib", type=float, default=0.0,
@@ -613,6 +671,10 @@ def main():
         return
     if args.layer_study:
         layer_study(args)
+        return
+    if args.layer_throughput:
+        print(json.dumps(dict(metric="hyperboloidal layer kernels: grid-point updates per second",
+                              **layer_throughput(args))), flush=True)
         return
     import torch
     from paper_1206_0270_amd import tk

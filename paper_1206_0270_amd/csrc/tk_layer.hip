@@ -52,17 +52,18 @@ __device__ __forceinline__ LCoef lcoef_at(const Radial &R, const Angular &A, con
     const double omb = -(R.a2D * A.sn2) / (Sh * (Sh + R.rho));
     const double w = L.rhop * c.b + omb;
     const double v = 1.0 + L.H * c.b;
-    const double wv = w * v;
-    o.bo = c.b * L.rhop / w;
-    o.bi = c.b * L.rhop / v;
-    const double dd = L.rhop / (w * wv);
+    const double fw = 1.0 / (w * v);  // the one division: 1/w = v fw, 1/v = w fw
+    const double brp = c.b * L.rhop;
+    o.bo = brp * (v * fw);
+    o.bi = brp * (w * fw);
+    const double dd = L.rhop * (v * fw) * fw;
     o.d = mk(c.d.re * dd, c.d.im * dd);
     const double g = c.b * c.b * L.rhop * L.rhopp - c.b * L.H * bp;
-    o.ct = mk((c.ct.re * w + c.d.re * L.H + g) / wv, (c.ct.im * w + c.d.im * L.H) / wv);
-    o.fw = 1.0 / wv;
-    o.cthth = c.cthth / wv;
-    o.cth = c.cth / wv;
-    o.c0 = mk(c.c0.re / wv, c.c0.im / wv);
+    o.ct = mk((c.ct.re * w + c.d.re * L.H + g) * fw, (c.ct.im * w + c.d.im * L.H) * fw);
+    o.fw = fw;
+    o.cthth = c.cthth * fw;
+    o.cth = c.cth * fw;
+    o.c0 = mk(c.c0.re * fw, c.c0.im * fw);
     return o;
 }
 
