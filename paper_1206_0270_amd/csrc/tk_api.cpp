@@ -41,6 +41,9 @@ struct tk_ctx {
     bool layered = false;
     size_t off_linst = 0;              // LayerInst per instance
     std::vector<size_t> off_lay;       // LayerTab table per instance (layered ones)
+    size_t off_lwork = 0, lwork_cap = 0;  // the layer kernels' work list area (items)
+    std::vector<WorkItem> lwork;
+    int lwork_rows = -1;               // rows per chunk it was built for
     long long step = 0;
     int cur = 0;  // state buffer holding u^step (mirror of the device control block)
     tk_tuning tuning{TK_KERNEL_AUTO, 0, 0, 3, TK_TUNE_NT_STORES, 0};
@@ -132,6 +135,30 @@ void build_work(tk_ctx *c, int rows, int cols, int min_rows)
     c->work_cols = cols;
 }
 
+// The layer kernels' work list: strips of 64 columns x chunks of `rows`
+// rows; a chunk holding a pole row keeps at least three rows.
+void build_layer_work(tk_ctx *c, int rows)
+{
+    c->lwork.clear();
+    for (size_t k = 0; k < c->inst.size(); ++k) {
+        const tk_instance_desc &d = c->inst[k].desc;
+        for (int j0 = 0; j0 < d.n_theta; j0 += rows) {
+            int j1 = std::min(d.n_theta, j0 + rows);
+            if (d.n_theta - j1 > 0 && d.n_theta - j1 < 3) j1 = d.n_theta;
+            for (int i0 = 0; i0 < d.n_r; i0 += 64) c->lwork.push_back(WorkItem{(int)k, i0, j0, j1});
+            if (j1 == d.n_theta) break;
+        }
+    }
+    c->lwork_rows = rows;
+}
+
+size_t layer_work_capacity(const tk_ctx *c)
+{
+    size_t n = 0;  // chunks of at least 3 rows
+    for (const HostInst &h : c->inst) n += (size_t)((h.desc.n_r + 63) / 64) * (h.desc.n_theta / 3 + 1);
+    return n;
+}
+
 size_t work_capacity(const tk_ctx *c)
 {
     // upper bound over the shapes: chunks of 3 rows of kFusedCols-wide
@@ -160,6 +187,9 @@ void layout(tk_ctx *c)
     off = align_up(off + c->work_cap * sizeof(WorkItem), A);
     c->off_linst = off;
     off = align_up(off + c->inst.size() * sizeof(LayerInst), A);
+    c->off_lwork = off;
+    c->lwork_cap = c->layered ? layer_work_capacity(c) : 0;
+    off = align_up(off + c->lwork_cap * sizeof(WorkItem), A);
     c->off_lay.assign(c->inst.size(), 0);
     for (size_t k = 0; k < c->inst.size(); ++k) {
         if (c->inst[k].desc.layer_start == 0.0) continue;
@@ -238,7 +268,7 @@ DevInst make_dev(const tk_ctx *c, const HostInst &h)
 
 int resolve_kernel(const tk_ctx *c)
 {
-    if (c->layered) return TK_KERNEL_TWO_PASS;  // the layer's two-pass kernels
+    if (c->layered) return TK_KERNEL_TWO_PASS;  // the layer's kernels (half pass, full pass)
     int k = c->tuning.kernel;
     if (k == TK_KERNEL_AUTO) k = c->tuning.rows_per_tile == 0 ? TK_KERNEL_FUSED2 : TK_KERNEL_FUSED;
     if (c->prec != TK_FP64 && k == TK_KERNEL_TWO_PASS) k = TK_KERNEL_FUSED;
@@ -247,6 +277,16 @@ int resolve_kernel(const tk_ctx *c)
 
 tk_status ensure_work(tk_ctx *c, int kernel)
 {
+    if (c->layered) {
+        const int rows = c->tuning.rows_per_tile > 0 ? c->tuning.rows_per_tile : kLayerRows;
+        if (!c->lwork.empty() && c->lwork_rows == rows) return TK_OK;
+        build_layer_work(c, rows);
+        if (c->lwork.size() > c->lwork_cap) return fail(c, TK_E_STATE, "layer work list exceeds its reserved area");
+        TK_HIP(c, hipMemcpyAsync(c->ws + c->off_lwork, c->lwork.data(), c->lwork.size() * sizeof(WorkItem),
+                                 hipMemcpyHostToDevice, c->stream));
+        TK_HIP(c, hipStreamSynchronize(c->stream));
+        return TK_OK;
+    }
     const int rows = c->tuning.rows_per_tile;
     const int cols = kernel == TK_KERNEL_FUSED2 ? kFused2Cols : kFusedCols;
     if (!c->work.empty() && c->work_rows == rows && c->work_cols == cols) return TK_OK;
@@ -264,9 +304,10 @@ hipError_t launch_one(tk_ctx *c, int kernel, int steps, int kstep, int kflip)
 {
     const DevInst *di = (const DevInst *)(c->ws + c->off_inst);
     const DevCtl *ctl = (const DevCtl *)(c->ws + c->off_ctl);
-    if (kernel == TK_KERNEL_TWO_PASS && c->layered)
-        return launch_layer(di, (const LayerInst *)(c->ws + c->off_linst), (const int2 *)(c->ws + c->off_blocks),
-                            (int)c->blocks.size(), ctl, kstep, kflip, c->stream);
+    if (c->layered)
+        return launch_layer(di, (const LayerInst *)(c->ws + c->off_linst), (int)c->inst.size(),
+                            (const WorkItem *)(c->ws + c->off_lwork), (int)c->lwork.size(), ctl, kstep, kflip,
+                            c->stream);
     if (kernel == TK_KERNEL_TWO_PASS)
         return launch_two_pass(di, (const int2 *)(c->ws + c->off_blocks), (int)c->blocks.size(), ctl, kstep, kflip,
                                c->stream);
@@ -683,7 +724,7 @@ tk_status tk_step(tk_ctx *c, long n_steps)
     if (!c->ws) return fail(c, TK_E_STATE, "no workspace bound");
     if (n_steps == 0) return TK_OK;
     const int kernel = resolve_kernel(c);
-    if (kernel != TK_KERNEL_TWO_PASS) {
+    if (kernel != TK_KERNEL_TWO_PASS || c->layered) {
         tk_status st = ensure_work(c, kernel);
         if (st != TK_OK) return st;
     }
@@ -800,7 +841,7 @@ tk_status tk_set_tuning(tk_ctx *c, const tk_tuning *t)
     }
     c->tuning = *t;
     if (c->tuning.prefetch_rows == 0) c->tuning.prefetch_rows = 3;
-    if (c->ws && resolve_kernel(c) != TK_KERNEL_TWO_PASS) {
+    if (c->ws && (resolve_kernel(c) != TK_KERNEL_TWO_PASS || c->layered)) {
         tk_status st = ensure_work(c, resolve_kernel(c));
         if (st != TK_OK) return st;
     }
@@ -873,7 +914,10 @@ tk_status tk_autotune(tk_ctx *c, int warmup, int steps, double *best_ms_per_step
     for (int rows : {8, 4})
         for (int ntf : {(int)TK_TUNE_NT_STORES, 0}) cand.push_back(tk_tuning{TK_KERNEL_TILED, rows, 0, 3, ntf, 0});
     if (c->prec == TK_FP64) cand.push_back(tk_tuning{TK_KERNEL_TWO_PASS, 0, 0, 3, TK_TUNE_NT_STORES, 0});
-    if (c->layered) cand.assign(1, tk_tuning{TK_KERNEL_TWO_PASS, 0, 0, 3, TK_TUNE_NT_STORES, 0});
+    if (c->layered) {  // the layer kernels: rows per chunk
+        cand.clear();
+        for (int rows : {0, 8, 32, 64}) cand.push_back(tk_tuning{TK_KERNEL_TWO_PASS, rows, 0, 3, TK_TUNE_NT_STORES, 0});
+    }
 
     tk_status st = e == hipSuccess ? TK_OK : fail(c, TK_E_DEVICE, std::string("autotune setup: ") + hipGetErrorString(e));
     double best = 1e300;
@@ -883,7 +927,7 @@ tk_status tk_autotune(tk_ctx *c, int warmup, int steps, double *best_ms_per_step
         if (st != TK_OK) break;
         c->tuning = t;
         const int kernel = resolve_kernel(c);
-        if (kernel != TK_KERNEL_TWO_PASS) st = ensure_work(c, kernel);
+        if (kernel != TK_KERNEL_TWO_PASS || c->layered) st = ensure_work(c, kernel);
         int flips = 0;
         if (st == TK_OK && warmup > 0) st = enqueue_steps(c, kernel, warmup, &flips);
         if (st == TK_OK && (e = hipEventRecord(e0, c->stream)) != hipSuccess)
@@ -919,7 +963,7 @@ tk_status tk_autotune(tk_ctx *c, int warmup, int steps, double *best_ms_per_step
     }
     best_t.graph_steps = keep.graph_steps;
     c->tuning = best_t;
-    if (resolve_kernel(c) != TK_KERNEL_TWO_PASS) {
+    if (resolve_kernel(c) != TK_KERNEL_TWO_PASS || c->layered) {
         st = ensure_work(c, resolve_kernel(c));
         if (st != TK_OK) return st;
     }

@@ -29,41 +29,45 @@ struct LCoef {
     cd ct, c0, d;
 };
 
-__device__ __forceinline__ LCoef lcoef_at(const Radial &R, const Angular &A, const LayerTab *tab, int q)
+// Coefficients of the layer system at one point from the radial record R
+// (held in registers for a whole march), the row's angular record A and the
+// position's map factors L (nullptr outside a layered instance).  1/sqrt is
+// the hardware estimate refined by Newton steps, as in the fused kernels.
+__device__ __forceinline__ LCoef lcoef_of(const Radial &R, const Angular &A, const LayerTab *L)
 {
-    const Coef<double> c = coef_at(R, A);
-    LCoef o;
-    o.bo = o.bi = c.b;
-    o.cthth = c.cthth;
-    o.cth = c.cth;
-    o.fw = 1.0;
-    o.ct = c.ct;
-    o.c0 = c.c0;
-    o.d = c.d;
-    if (tab == nullptr) return o;
-    const LayerTab L = load_entry(gload_ptr(tab) + q);
-    if (L.H == 0.0) return o;
     const double Sh2 = R.rho2 - R.a2D * A.sn2;
-    const double Sh = sqrt(Sh2);
-    const double W = 1.0 / Sh2;
-    const double bp = R.K * A.sn2 * W * sqrt(W);  // b' = d b / d r*
+    const double sig = inv_sqrt(Sh2);  // 1 / Sigma-hat
+    const double W = sig * sig;
+    const double b = R.rho * sig;
+    LCoef o;
+    o.cthth = R.Dl * W;
+    o.cth = o.cthth * A.cot;
+    o.ct = mk(W * R.ct_re, W * (R.ct_im0 + R.ct_imc * A.cs));
+    o.c0 = mk(W * (R.c0_re - R.Dl * A.V), W * R.c0_im);
+    const double bp = R.K * A.sn2 * W * sig;  // b' = d b / d r*
+    // d = -(c1 - b b' - b ct)
+    o.d = mk(b * bp + b * o.ct.re - W * R.c1_re, b * o.ct.im - W * R.c1_im);
+    o.bo = o.bi = b;
+    o.fw = 1.0;
+    if (L == nullptr || L->H == 0.0) return o;
     // w = rho' b + (1 - b), with 1 - b = -a^2 Delta sin^2 / (Sh (Sh + rho)):
     // near null infinity 1 - b is far below the rounding of b
+    const double Sh = Sh2 * sig;
     const double omb = -(R.a2D * A.sn2) / (Sh * (Sh + R.rho));
-    const double w = L.rhop * c.b + omb;
-    const double v = 1.0 + L.H * c.b;
-    const double fw = 1.0 / (w * v);  // the one division: 1/w = v fw, 1/v = w fw
-    const double brp = c.b * L.rhop;
+    const double w = L->rhop * b + omb;
+    const double v = 1.0 + L->H * b;
+    const double fw = 1.0 / (w * v);  // 1/w = v fw, 1/v = w fw
+    const double brp = b * L->rhop;
     o.bo = brp * (v * fw);
     o.bi = brp * (w * fw);
-    const double dd = L.rhop * (v * fw) * fw;
-    o.d = mk(c.d.re * dd, c.d.im * dd);
-    const double g = c.b * c.b * L.rhop * L.rhopp - c.b * L.H * bp;
-    o.ct = mk((c.ct.re * w + c.d.re * L.H + g) * fw, (c.ct.im * w + c.d.im * L.H) * fw);
+    const double dd = L->rhop * (v * fw) * fw;
+    const double g = b * b * L->rhop * L->rhopp - b * L->H * bp;
+    o.ct = mk((o.ct.re * w + o.d.re * L->H + g) * fw, (o.ct.im * w + o.d.im * L->H) * fw);
+    o.d = mk(o.d.re * dd, o.d.im * dd);
     o.fw = fw;
-    o.cthth = c.cthth * fw;
-    o.cth = c.cth * fw;
-    o.c0 = mk(c.c0.re * fw, c.c0.im * fw);
+    o.cthth *= fw;
+    o.cth *= fw;
+    o.c0 = mk(o.c0.re * fw, o.c0.im * fw);
     return o;
 }
 
@@ -81,131 +85,206 @@ __device__ __forceinline__ P4 lw_layer(const LCoef &c, const P4 &base, cd phm, c
     return P4{base.phi - fac * bphi, base.pi - fac * bpi};
 }
 
-__device__ __forceinline__ cd source_at(const DevInst &I, const Radial &R, const Angular &A, double t)
+__device__ __forceinline__ Angular angular_row(const DevInst &I, int j) { return load_entry(cload_ptr(I.ang) + j); }
+
+__device__ __forceinline__ cd source_of(const DevInst &I, double gq, const Angular &A, cd e)
 {
-    return R.srcg * A.srcg != 0.0 ? source_value(R.srcg, A.srcg, source_phase(I, t)) : mk(0, 0);
+    return gq * A.srcg != 0.0 ? source_value(gq, A.srcg, e) : mk(0, 0);
 }
 
-// Eq. (3) at half node i+1/2, row j (1 <= j <= n_theta - 2)
-__device__ P4 half_at(const DevInst &I, const LayerTab *tab, const double4 *u, int i, int j, double t)
+__device__ __forceinline__ const double4 *row_ptr(const void *base, const DevInst &I, int j)
 {
-    const int p = I.pitch;
-    const P4 a0 = ld_p4(u + (size_t)j * p + i), a1 = ld_p4(u + (size_t)j * p + i + 1);
-    const P4 am0 = ld_p4(u + (size_t)(j - 1) * p + i), am1 = ld_p4(u + (size_t)(j - 1) * p + i + 1);
-    const P4 ap0 = ld_p4(u + (size_t)(j + 1) * p + i), ap1 = ld_p4(u + (size_t)(j + 1) * p + i + 1);
-    const P4 bar = half_sum(a1, a0);
-    const cd phm = half_sum(am1, am0).phi, php = half_sum(ap1, ap0).phi;
-    const Radial R = load_entry(gload_ptr(I.rad) + (2 * i + 1));
-    const Angular A = load_entry(gload_ptr(I.ang) + j);
-    const LCoef c = lcoef_at(R, A, tab, 2 * i + 1);
-    return lw_layer(c, bar, phm, bar.phi, php, bar.pi, a1 - a0, 0.5 * I.dt, I, source_at(I, R, A, t));
+    return (const double4 *)base + (size_t)j * I.pitch;
 }
 
-// Eq. (4) at node i, row j (1 <= i <= n_r - 2, 1 <= j <= n_theta - 2)
-__device__ P4 full_at(const DevInst &I, const LayerTab *tab, const double4 *u, const double4 *hf, int i, int j,
-                      double t)
-{
-    const int p = I.pitch;
-    const P4 h0 = ld_p4(hf + (size_t)j * p + i - 1), h1 = ld_p4(hf + (size_t)j * p + i);
-    const P4 hm0 = ld_p4(hf + (size_t)(j - 1) * p + i - 1), hm1 = ld_p4(hf + (size_t)(j - 1) * p + i);
-    const P4 hp0 = ld_p4(hf + (size_t)(j + 1) * p + i - 1), hp1 = ld_p4(hf + (size_t)(j + 1) * p + i);
-    const P4 til = half_sum(h1, h0);
-    const cd phm = half_sum(hm1, hm0).phi, php = half_sum(hp1, hp0).phi;
-    const Radial R = load_entry(gload_ptr(I.rad) + (2 * i));
-    const Angular A = load_entry(gload_ptr(I.ang) + j);
-    const LCoef c = lcoef_at(R, A, tab, 2 * i);
-    const P4 un = ld_p4(u + (size_t)j * p + i);
-    return lw_layer(c, un, phm, til.phi, php, til.pi, h1 - h0, I.dt, I, source_at(I, R, A, t));
-}
-
-// u^{n+1} at the last node of a layered instance, row j (1 <= j <= n_theta - 2)
-__device__ P4 scri_at(const DevInst &I, const LayerTab *tab, const double4 *u, const double4 *hf, int j, double t)
-{
-    const int n = I.n_r;
-    const P4 a = full_at(I, tab, u, hf, n - 2, j, t), b = full_at(I, tab, u, hf, n - 3, j, t);
-    return P4{mk(2.0 * a.phi.re - b.phi.re, 2.0 * a.phi.im - b.phi.im),
-              mk(2.0 * a.pi.re - b.pi.re, 2.0 * a.pi.im - b.pi.im)};
-}
-
+// Eq. (3): one wave per work item, lane = half node i + 1/2 (i = i0 + lane),
+// marching the item's rows with u^n rows j-1, j, j+1 of columns i, i+1 in
+// registers.  A chunk that holds a pole row forms it after its rows 1, 2 (or
+// n_theta - 3, n_theta - 2) from those values; the work list keeps such
+// chunks at least three rows long.
 __global__ void __launch_bounds__(256) k_layer_half(const DevInst *__restrict__ insts,
                                                     const LayerInst *__restrict__ lays,
-                                                    const int2 *__restrict__ blocks, const DevCtl *__restrict__ ctl,
-                                                    int kstep, int kflip)
+                                                    const WorkItem *__restrict__ work, int n_work,
+                                                    const DevCtl *__restrict__ ctl, int kstep, int kflip)
 {
-    const int2 bl = blocks[blockIdx.x];
-    const DevInst &I = insts[bl.x];
-    const LayerTab *tab = lays[bl.x].on ? lays[bl.x].tab : nullptr;
+    const int w = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+    if (w >= n_work) return;
+    const WorkItem it = work[w];
+    const DevInst &I = insts[it.inst];
+    const int i = it.i0 + (int)(threadIdx.x & 63);
+    if (i >= I.n_r - 1) return;
+    const LayerTab *tab = lays[it.inst].on ? lays[it.inst].tab : nullptr;
     const long long n = ctl->step + kstep;
     const int b = (int)((ctl->cur + kflip) & 1);
-    const double4 *u = (const double4 *)I.u[b];
-    double4 *hf = (double4 *)I.half;
-    const int L = bl.y * 256 + (int)threadIdx.x;
-    const int j = L / I.n_r, i = L - j * I.n_r;
-    if (j >= I.n_theta || i >= I.n_r - 1) return;
     const double t = (double)n * I.dt;
+    const cd e = source_phase(I, t);
     const int nt = I.n_theta;
-    P4 out;
-    if (j >= 1 && j <= nt - 2) {
-        out = half_at(I, tab, u, i, j, t);
-    } else if (!I.m_even) {
-        out = zero4();
-    } else {
-        const int j1 = j == 0 ? 1 : nt - 2, j2 = j == 0 ? 2 : nt - 3;
-        out = pole_bc(half_at(I, tab, u, i, j1, t), half_at(I, tab, u, i, j2, t));
+    const int q = 2 * i + 1;
+    const Radial R = load_entry(gload_ptr(I.rad) + q);
+    LayerTab Lq;
+    if (tab) Lq = load_entry(gload_ptr(tab) + q);
+    const LayerTab *L = tab ? &Lq : nullptr;
+    double4 *hf = (double4 *)I.half;
+    const int jb = it.j0 > 1 ? it.j0 : 1, je = it.j1 < nt - 1 ? it.j1 : nt - 1;
+    P4 m0 = ld_p4(row_ptr(I.u[b], I, jb - 1) + i), m1 = ld_p4(row_ptr(I.u[b], I, jb - 1) + i + 1);
+    P4 c0 = ld_p4(row_ptr(I.u[b], I, jb) + i), c1 = ld_p4(row_ptr(I.u[b], I, jb) + i + 1);
+    P4 h1 = zero4(), h2 = zero4(), last = zero4(), before = zero4();
+    for (int j = jb; j < je; ++j) {
+        const P4 p0 = ld_p4(row_ptr(I.u[b], I, j + 1) + i), p1 = ld_p4(row_ptr(I.u[b], I, j + 1) + i + 1);
+        const Angular A = angular_row(I, j);
+        const LCoef c = lcoef_of(R, A, L);
+        const P4 bar = half_sum(c1, c0);
+        const P4 out = lw_layer(c, bar, half_sum(m1, m0).phi, bar.phi, half_sum(p1, p0).phi, bar.pi, c1 - c0,
+                                0.5 * I.dt, I, source_of(I, R.srcg, A, e));
+        st_p4(hf + (size_t)j * I.pitch + i, out);
+        if (j == 1) h1 = out;
+        if (j == 2) h2 = out;
+        before = last;
+        last = out;
+        m0 = c0;
+        m1 = c1;
+        c0 = p0;
+        c1 = p1;
     }
-    st_p4(hf + (size_t)j * I.pitch + i, out);
+    if (it.j0 == 0) st_p4(hf + i, I.m_even ? pole_bc(h1, h2) : zero4());
+    if (it.j1 == nt) st_p4(hf + (size_t)(nt - 1) * I.pitch + i, I.m_even ? pole_bc(last, before) : zero4());
 }
 
+// Eq. (4): lane = node i, marching the item's rows with the half-step rows
+// j-1, j, j+1 of half nodes i - 1/2, i + 1/2 in registers; pole rows as in
+// k_layer_half; Dirichlet at i = 0 and at the last node of a plain
+// instance.  The last node of a layered instance is left to k_layer_scri.
 __global__ void __launch_bounds__(256) k_layer_full(const DevInst *__restrict__ insts,
                                                     const LayerInst *__restrict__ lays,
-                                                    const int2 *__restrict__ blocks, const DevCtl *__restrict__ ctl,
-                                                    int kstep, int kflip)
+                                                    const WorkItem *__restrict__ work, int n_work,
+                                                    const DevCtl *__restrict__ ctl, int kstep, int kflip)
 {
-    const int2 bl = blocks[blockIdx.x];
-    const DevInst &I = insts[bl.x];
-    const LayerTab *tab = lays[bl.x].on ? lays[bl.x].tab : nullptr;
+    const int w = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+    if (w >= n_work) return;
+    const WorkItem it = work[w];
+    const DevInst &I = insts[it.inst];
+    const int i = it.i0 + (int)(threadIdx.x & 63);
+    if (i >= I.n_r) return;
+    const LayerTab *tab = lays[it.inst].on ? lays[it.inst].tab : nullptr;
+    if (i == I.n_r - 1 && tab) return;
     const long long n = ctl->step + kstep;
     const int b = (int)((ctl->cur + kflip) & 1);
-    const double4 *u = (const double4 *)I.u[b];
     double4 *un = (double4 *)I.u[b ^ 1];
-    const double4 *hf = (const double4 *)I.half;
-    const int L = bl.y * 256 + (int)threadIdx.x;
-    const int j = L / I.n_r, i = L - j * I.n_r;
-    if (j >= I.n_theta) return;
-    const double t = (double)n * I.dt + 0.5 * I.dt;
     const int nt = I.n_theta;
-    const bool scri = i == I.n_r - 1 && tab != nullptr;
-    P4 out;
-    if (i == 0 || (i == I.n_r - 1 && !scri)) {
-        out = zero4();
-    } else if (j >= 1 && j <= nt - 2) {
-        out = scri ? scri_at(I, tab, u, hf, j, t) : full_at(I, tab, u, hf, i, j, t);
-    } else if (!I.m_even) {
-        out = zero4();
-    } else {
-        const int j1 = j == 0 ? 1 : nt - 2, j2 = j == 0 ? 2 : nt - 3;
-        out = scri ? pole_bc(scri_at(I, tab, u, hf, j1, t), scri_at(I, tab, u, hf, j2, t))
-                   : pole_bc(full_at(I, tab, u, hf, i, j1, t), full_at(I, tab, u, hf, i, j2, t));
+    const bool sampling = i == I.i_obs && I.extract_every > 0 && (n + 1) % I.extract_every == 0;
+    TK_GLOBAL double *wv = nullptr;
+    if (sampling) wv = gstore_ptr(I.wave) + (size_t)(((n + 1) / I.extract_every - 1) % I.wave_cap) * nt * 2;
+    if (i == 0 || i == I.n_r - 1) {
+        for (int j = it.j0; j < it.j1; ++j) {
+            st_p4(un + (size_t)j * I.pitch + i, zero4());
+            if (sampling) wv[2 * j] = wv[2 * j + 1] = 0.0;
+        }
+        return;
     }
-    st_p4(un + (size_t)j * I.pitch + i, out);
-    if (i == I.i_obs && I.extract_every > 0 && (n + 1) % I.extract_every == 0) {
-        const long long k = (n + 1) / I.extract_every - 1;
-        TK_GLOBAL double *w = gstore_ptr(I.wave) + ((size_t)(k % I.wave_cap) * nt + j) * 2;
-        w[0] = out.phi.re;
-        w[1] = out.phi.im;
+    const double t = (double)n * I.dt + 0.5 * I.dt;
+    const cd e = source_phase(I, t);
+    const int q = 2 * i;
+    const Radial R = load_entry(gload_ptr(I.rad) + q);
+    LayerTab Lq;
+    if (tab) Lq = load_entry(gload_ptr(tab) + q);
+    const LayerTab *L = tab ? &Lq : nullptr;
+    const int jb = it.j0 > 1 ? it.j0 : 1, je = it.j1 < nt - 1 ? it.j1 : nt - 1;
+    P4 m0 = ld_p4(row_ptr(I.half, I, jb - 1) + i - 1), m1 = ld_p4(row_ptr(I.half, I, jb - 1) + i);
+    P4 c0 = ld_p4(row_ptr(I.half, I, jb) + i - 1), c1 = ld_p4(row_ptr(I.half, I, jb) + i);
+    P4 h1 = zero4(), h2 = zero4(), last = zero4(), before = zero4();
+    for (int j = jb; j < je; ++j) {
+        const P4 p0 = ld_p4(row_ptr(I.half, I, j + 1) + i - 1), p1 = ld_p4(row_ptr(I.half, I, j + 1) + i);
+        const P4 uo = ld_p4(row_ptr(I.u[b], I, j) + i);
+        const Angular A = angular_row(I, j);
+        const LCoef c = lcoef_of(R, A, L);
+        const P4 til = half_sum(c1, c0);
+        const P4 out = lw_layer(c, uo, half_sum(m1, m0).phi, til.phi, half_sum(p1, p0).phi, til.pi, c1 - c0, I.dt, I,
+                                source_of(I, R.srcg, A, e));
+        st_p4(un + (size_t)j * I.pitch + i, out);
+        if (sampling) {
+            wv[2 * j] = out.phi.re;
+            wv[2 * j + 1] = out.phi.im;
+        }
+        if (j == 1) h1 = out;
+        if (j == 2) h2 = out;
+        before = last;
+        last = out;
+        m0 = c0;
+        m1 = c1;
+        c0 = p0;
+        c1 = p1;
+    }
+    if (it.j0 == 0) {
+        const P4 o = I.m_even ? pole_bc(h1, h2) : zero4();
+        st_p4(un + i, o);
+        if (sampling) {
+            wv[0] = o.phi.re;
+            wv[1] = o.phi.im;
+        }
+    }
+    if (it.j1 == nt) {
+        const P4 o = I.m_even ? pole_bc(last, before) : zero4();
+        st_p4(un + (size_t)(nt - 1) * I.pitch + i, o);
+        if (sampling) {
+            wv[2 * (nt - 1)] = o.phi.re;
+            wv[2 * (nt - 1) + 1] = o.phi.im;
+        }
+    }
+}
+
+// The last node of each layered instance (future null infinity): the linear
+// extrapolation 2 u_{N-2} - u_{N-3} of the new values on rows 1 .. n_theta-2,
+// then the pole rows from its rows 1, 2 (n_theta-2, n_theta-3).  One block
+// per instance, threads striding over rows.
+__global__ void __launch_bounds__(256) k_layer_scri(const DevInst *__restrict__ insts,
+                                                    const LayerInst *__restrict__ lays, const DevCtl *__restrict__ ctl,
+                                                    int kstep, int kflip)
+{
+    const int k = blockIdx.x;
+    if (!lays[k].on) return;
+    const DevInst &I = insts[k];
+    const long long n = ctl->step + kstep;
+    const int b = (int)((ctl->cur + kflip) & 1);
+    double4 *un = (double4 *)I.u[b ^ 1];
+    const int nt = I.n_theta, N = I.n_r;
+    const bool sampling = I.i_obs == N - 1 && I.extract_every > 0 && (n + 1) % I.extract_every == 0;
+    TK_GLOBAL double *wv = nullptr;
+    if (sampling) wv = gstore_ptr(I.wave) + (size_t)(((n + 1) / I.extract_every - 1) % I.wave_cap) * nt * 2;
+    auto ext = [&](int j) {
+        const P4 a = ld_p4(un + (size_t)j * I.pitch + N - 2), c = ld_p4(un + (size_t)j * I.pitch + N - 3);
+        return P4{mk(2.0 * a.phi.re - c.phi.re, 2.0 * a.phi.im - c.phi.im),
+                  mk(2.0 * a.pi.re - c.pi.re, 2.0 * a.pi.im - c.pi.im)};
+    };
+    for (int j = (int)threadIdx.x; j < nt; j += (int)blockDim.x) {
+        P4 o;
+        if (j >= 1 && j <= nt - 2)
+            o = ext(j);
+        else if (!I.m_even)
+            o = zero4();
+        else
+            o = j == 0 ? pole_bc(ext(1), ext(2)) : pole_bc(ext(nt - 2), ext(nt - 3));
+        st_p4(un + (size_t)j * I.pitch + N - 1, o);
+        if (sampling) {
+            wv[2 * j] = o.phi.re;
+            wv[2 * j + 1] = o.phi.im;
+        }
     }
 }
 
 }  // namespace
 
-hipError_t launch_layer(const DevInst *d_inst, const LayerInst *d_lay, const int2 *d_blocks, int n_blocks,
+hipError_t launch_layer(const DevInst *d_inst, const LayerInst *d_lay, int n_inst, const WorkItem *d_work, int n_work,
                         const DevCtl *ctl, int kstep, int kflip, hipStream_t s)
 {
-    if (n_blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_layer_half, dim3(n_blocks), dim3(256), 0, s, d_inst, d_lay, d_blocks, ctl, kstep, kflip);
+    if (n_work <= 0) return hipSuccess;
+    const int blocks = (n_work + 3) / 4;
+    hipLaunchKernelGGL(k_layer_half, dim3(blocks), dim3(256), 0, s, d_inst, d_lay, d_work, n_work, ctl, kstep, kflip);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_layer_full, dim3(n_blocks), dim3(256), 0, s, d_inst, d_lay, d_blocks, ctl, kstep, kflip);
+    hipLaunchKernelGGL(k_layer_full, dim3(blocks), dim3(256), 0, s, d_inst, d_lay, d_work, n_work, ctl, kstep, kflip);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_layer_scri, dim3(n_inst), dim3(256), 0, s, d_inst, d_lay, ctl, kstep, kflip);
     return hipGetLastError();
 }
 

@@ -7,13 +7,19 @@
 
 namespace tk {
 
-// Two-pass step of a context holding at least one layered instance: Eq. (3)
-// into the half-step array, then Eq. (4) with the layer's coefficients
-// (separate outgoing and ingoing speeds, rescaled Pi~ equation); the last
-// node of a layered instance takes the linear extrapolation of the new
-// values at the two nodes before it.  Blocks and buffers as for
-// launch_two_pass; d_lay[k] describes instance k.
-hipError_t launch_layer(const DevInst *d_inst, const LayerInst *d_lay, const int2 *d_blocks, int n_blocks,
+// One step of a context holding at least one layered instance, in three
+// launches: Eq. (3) into the half-step array, Eq. (4), and the null-infinity
+// node of each layered instance (the linear extrapolation of the new values
+// at the two nodes before it).  The first two take one wave per work item:
+// 64 columns from i0 of instance `inst`, marching rows [j0, j1); a chunk
+// holding a pole row must be at least three rows long.  The coefficients are
+// the layer's (separate outgoing and ingoing speeds, rescaled Pi~ equation)
+// where d_lay[k] has a table, the plain ones elsewhere.  Buffers as for
+// launch_two_pass.
+hipError_t launch_layer(const DevInst *d_inst, const LayerInst *d_lay, int n_inst, const WorkItem *d_work, int n_work,
                         const DevCtl *ctl, int kstep, int kflip, hipStream_t s);
+
+// Rows per chunk of the layer kernels' work list when the tuning gives none.
+constexpr int kLayerRows = 16;
 
 }  // namespace tk

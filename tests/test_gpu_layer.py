@@ -59,11 +59,14 @@ def check(inst, steps, got, ref):
             assert e[k] <= max(TOL, 4 * floor[k]), (k, e[k], floor[k])
 
 
-def gpu_run(insts, steps, graph=0, chunks=None):
+def gpu_run(insts, steps, graph=0, chunks=None, rows=0, autotune=False):
     st = tk.Stepper(insts, force_dt=False)
-    st.set_tuning(kernel=tk.TK_KERNEL_AUTO, graph_steps=graph)
+    st.set_tuning(kernel=tk.TK_KERNEL_AUTO, graph_steps=graph, rows_per_tile=rows)
     for k, inst in enumerate(insts):
         st.set_fields(k, *W.initial_data(inst))
+    if autotune:
+        _, tried = st.autotune(warmup=2, steps=4)
+        assert tried >= 4
     for n in (chunks or [steps]):
         st.step(n)
     out = [st.get_fields(k) + (st.extract(k),) for k in range(len(insts))]
@@ -106,6 +109,23 @@ def test_layer_graph_and_chunks_bitwise():
     a = gpu_run(insts, 250)
     b = gpu_run(insts, 250, graph=40, chunks=[7, 120, 123])
     for x, y in zip(a, b):
+        for u, v in zip(x, y):
+            assert np.array_equal(u, v)
+
+
+def test_layer_row_chunks_and_autotune_bitwise():
+    """The layer kernels march chunks of rows; every chunking (3 rows, 8, 64,
+    whole columns at 16 rows default) and the autotuner's choice give the
+    same bits."""
+    insts = layered_instances()
+    ref = gpu_run(insts, 120)
+    for rows in (3, 8, 64, 200):
+        got = gpu_run(insts, 120, rows=rows)
+        for x, y in zip(ref, got):
+            for u, v in zip(x, y):
+                assert np.array_equal(u, v), rows
+    got = gpu_run(insts, 120, autotune=True)
+    for x, y in zip(ref, got):
         for u, v in zip(x, y):
             assert np.array_equal(u, v)
 
