@@ -312,9 +312,12 @@ def layer_throughput(args):
     for i in thr:
         i["dt"] = dt_t
     st = tk.Stepper(thr)
-    st.set_tuning(kernel=tk.TK_KERNEL_AUTO, graph_steps=100)
     for k, i in enumerate(thr):
         st.set_fields(k, *W.initial_data(i))
+    st.autotune(warmup=2, steps=10)
+    tuning = st.get_tuning()
+    tuning["graph_steps"] = 100
+    st.set_tuning(**tuning)
     st.step(args.layer_warmup)
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -329,10 +332,12 @@ def layer_throughput(args):
     ups_t = pts_t * args.layer_steps / (ms_t / 1e3)
     print(f"# throughput: {pts_t} points, {args.layer_steps} steps in {ms_t / 1e3:.2f} s", file=sys.stderr,
           flush=True)
-    lay_bytes = 160.0
+    # state traffic per update: one read and one write (64 B) for the single-pass kernel; the two-pass
+    # kernels also write and read the half-step array and read u^n twice (160 B)
+    lay_bytes = 160.0 if tuning["kernel"] == tk.TK_KERNEL_TWO_PASS else 64.0
     return {"workload": "6 x 16001 x 129 on [-300,300]M, layers on [250,300]M, sourced", "points": pts_t,
             "steps": args.layer_steps, "ms_per_step": ms_t / args.layer_steps, "updates_per_s": ups_t,
-            "bytes_per_update": lay_bytes, "achieved_GBps": ups_t * lay_bytes / 1e9,
+            "tuning": tuning, "bytes_per_update": lay_bytes, "achieved_GBps": ups_t * lay_bytes / 1e9,
             "frac_of_8TBps": ups_t * lay_bytes / 8e12}
 
 
@@ -411,7 +416,7 @@ def layer_study(args):
     thr = layer_throughput(args)
     w_scri = out["layer"]["waves"][1][:n]
     tail = times >= T - 100.0
-    lay_bytes = 160.0  # two-pass: u^n read twice, half array written and read, u^{n+1} written (32 B each)
+    lay_bytes = 64.0  # the single-pass layer kernel: u^n read once, u^{n+1} written once
     ups = out["layer"]["updates_per_s"]
     res = {
         "metric": "hyperboloidal layer: waveform at r*=50M against a domain 7x longer; step rate of its kernels",

@@ -43,7 +43,7 @@ struct tk_ctx {
     std::vector<size_t> off_lay;       // LayerTab table per instance (layered ones)
     size_t off_lwork = 0, lwork_cap = 0;  // the layer kernels' work list area (items)
     std::vector<WorkItem> lwork;
-    int lwork_rows = -1;               // rows per chunk it was built for
+    int lwork_rows = -1, lwork_cols = -1;  // rows per chunk and columns per strip it was built for
     long long step = 0;
     int cur = 0;  // state buffer holding u^step (mirror of the device control block)
     tk_tuning tuning{TK_KERNEL_AUTO, 0, 0, 3, TK_TUNE_NT_STORES, 0};
@@ -135,9 +135,9 @@ void build_work(tk_ctx *c, int rows, int cols, int min_rows)
     c->work_cols = cols;
 }
 
-// The layer kernels' work list: strips of 64 columns x chunks of `rows`
+// The layer kernels' work list: strips of `cols` columns x chunks of `rows`
 // rows; a chunk holding a pole row keeps at least three rows.
-void build_layer_work(tk_ctx *c, int rows)
+void build_layer_work(tk_ctx *c, int rows, int cols)
 {
     c->lwork.clear();
     for (size_t k = 0; k < c->inst.size(); ++k) {
@@ -145,17 +145,19 @@ void build_layer_work(tk_ctx *c, int rows)
         for (int j0 = 0; j0 < d.n_theta; j0 += rows) {
             int j1 = std::min(d.n_theta, j0 + rows);
             if (d.n_theta - j1 > 0 && d.n_theta - j1 < 3) j1 = d.n_theta;
-            for (int i0 = 0; i0 < d.n_r; i0 += 64) c->lwork.push_back(WorkItem{(int)k, i0, j0, j1});
+            for (int i0 = 0; i0 < d.n_r; i0 += cols) c->lwork.push_back(WorkItem{(int)k, i0, j0, j1});
             if (j1 == d.n_theta) break;
         }
     }
     c->lwork_rows = rows;
+    c->lwork_cols = cols;
 }
 
 size_t layer_work_capacity(const tk_ctx *c)
 {
     size_t n = 0;  // chunks of at least 3 rows
-    for (const HostInst &h : c->inst) n += (size_t)((h.desc.n_r + 63) / 64) * (h.desc.n_theta / 3 + 1);
+    for (const HostInst &h : c->inst)
+        n += (size_t)((h.desc.n_r + kLayerFusedCols - 1) / kLayerFusedCols) * (h.desc.n_theta / 3 + 1);
     return n;
 }
 
@@ -268,7 +270,8 @@ DevInst make_dev(const tk_ctx *c, const HostInst &h)
 
 int resolve_kernel(const tk_ctx *c)
 {
-    if (c->layered) return TK_KERNEL_TWO_PASS;  // the layer's kernels (half pass, full pass)
+    if (c->layered)  // the layer's kernels: single pass, or half pass + full pass
+        return c->tuning.kernel == TK_KERNEL_TWO_PASS ? TK_KERNEL_TWO_PASS : TK_KERNEL_FUSED;
     int k = c->tuning.kernel;
     if (k == TK_KERNEL_AUTO) k = c->tuning.rows_per_tile == 0 ? TK_KERNEL_FUSED2 : TK_KERNEL_FUSED;
     if (c->prec != TK_FP64 && k == TK_KERNEL_TWO_PASS) k = TK_KERNEL_FUSED;
@@ -279,8 +282,9 @@ tk_status ensure_work(tk_ctx *c, int kernel)
 {
     if (c->layered) {
         const int rows = c->tuning.rows_per_tile > 0 ? c->tuning.rows_per_tile : kLayerRows;
-        if (!c->lwork.empty() && c->lwork_rows == rows) return TK_OK;
-        build_layer_work(c, rows);
+        const int cols = kernel == TK_KERNEL_TWO_PASS ? kLayerCols : kLayerFusedCols;
+        if (!c->lwork.empty() && c->lwork_rows == rows && c->lwork_cols == cols) return TK_OK;
+        build_layer_work(c, rows, cols);
         if (c->lwork.size() > c->lwork_cap) return fail(c, TK_E_STATE, "layer work list exceeds its reserved area");
         TK_HIP(c, hipMemcpyAsync(c->ws + c->off_lwork, c->lwork.data(), c->lwork.size() * sizeof(WorkItem),
                                  hipMemcpyHostToDevice, c->stream));
@@ -305,9 +309,9 @@ hipError_t launch_one(tk_ctx *c, int kernel, int steps, int kstep, int kflip)
     const DevInst *di = (const DevInst *)(c->ws + c->off_inst);
     const DevCtl *ctl = (const DevCtl *)(c->ws + c->off_ctl);
     if (c->layered)
-        return launch_layer(di, (const LayerInst *)(c->ws + c->off_linst), (int)c->inst.size(),
-                            (const WorkItem *)(c->ws + c->off_lwork), (int)c->lwork.size(), ctl, kstep, kflip,
-                            c->stream);
+        return launch_layer(kernel != TK_KERNEL_TWO_PASS, di, (const LayerInst *)(c->ws + c->off_linst),
+                            (int)c->inst.size(), (const WorkItem *)(c->ws + c->off_lwork), (int)c->lwork.size(), ctl,
+                            kstep, kflip, c->stream);
     if (kernel == TK_KERNEL_TWO_PASS)
         return launch_two_pass(di, (const int2 *)(c->ws + c->off_blocks), (int)c->blocks.size(), ctl, kstep, kflip,
                                c->stream);
@@ -823,8 +827,10 @@ tk_status tk_set_tuning(tk_ctx *c, const tk_tuning *t)
         return fail(c, TK_E_INVALID, "the two-step kernel takes whole strips (rows_per_tile 0) or chunks of >= 4 rows");
     if (t->kernel == TK_KERNEL_TWO_PASS && c->prec != TK_FP64)
         return fail(c, TK_E_INVALID, "the two-pass kernel is FP64 only");
-    if (c->layered && t->kernel != TK_KERNEL_AUTO && t->kernel != TK_KERNEL_TWO_PASS)
-        return fail(c, TK_E_INVALID, "a context with a hyperboloidal layer steps with the layer's two-pass kernels");
+    if (c->layered && t->kernel != TK_KERNEL_AUTO && t->kernel != TK_KERNEL_FUSED && t->kernel != TK_KERNEL_TWO_PASS)
+        return fail(c, TK_E_INVALID,
+                    "a context with a hyperboloidal layer steps with the layer's kernels (AUTO or FUSED: one pass; "
+                    "TWO_PASS: half and full passes)");
     if (t->rows_per_tile < 0 || (t->rows_per_tile > 0 && t->rows_per_tile < 3))
         return fail(c, TK_E_INVALID, "rows_per_tile must be 0 or >= 3");
     if (t->graph_steps < 0 || t->graph_steps > 100000) return fail(c, TK_E_INVALID, "graph_steps out of range");
@@ -914,9 +920,10 @@ tk_status tk_autotune(tk_ctx *c, int warmup, int steps, double *best_ms_per_step
     for (int rows : {8, 4})
         for (int ntf : {(int)TK_TUNE_NT_STORES, 0}) cand.push_back(tk_tuning{TK_KERNEL_TILED, rows, 0, 3, ntf, 0});
     if (c->prec == TK_FP64) cand.push_back(tk_tuning{TK_KERNEL_TWO_PASS, 0, 0, 3, TK_TUNE_NT_STORES, 0});
-    if (c->layered) {  // the layer kernels: rows per chunk
+    if (c->layered) {  // the layer kernels: one pass or two, rows per chunk
         cand.clear();
-        for (int rows : {0, 8, 32, 64}) cand.push_back(tk_tuning{TK_KERNEL_TWO_PASS, rows, 0, 3, TK_TUNE_NT_STORES, 0});
+        for (int rows : {0, 8, 32, 64}) cand.push_back(tk_tuning{TK_KERNEL_FUSED, rows, 0, 3, TK_TUNE_NT_STORES, 0});
+        for (int rows : {0, 32}) cand.push_back(tk_tuning{TK_KERNEL_TWO_PASS, rows, 0, 3, TK_TUNE_NT_STORES, 0});
     }
 
     tk_status st = e == hipSuccess ? TK_OK : fail(c, TK_E_DEVICE, std::string("autotune setup: ") + hipGetErrorString(e));

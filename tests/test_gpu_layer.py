@@ -59,9 +59,9 @@ def check(inst, steps, got, ref):
             assert e[k] <= max(TOL, 4 * floor[k]), (k, e[k], floor[k])
 
 
-def gpu_run(insts, steps, graph=0, chunks=None, rows=0, autotune=False):
+def gpu_run(insts, steps, graph=0, chunks=None, rows=0, autotune=False, kernel=tk.TK_KERNEL_AUTO):
     st = tk.Stepper(insts, force_dt=False)
-    st.set_tuning(kernel=tk.TK_KERNEL_AUTO, graph_steps=graph, rows_per_tile=rows)
+    st.set_tuning(kernel=kernel, graph_steps=graph, rows_per_tile=rows)
     for k, inst in enumerate(insts):
         st.set_fields(k, *W.initial_data(inst))
     if autotune:
@@ -113,17 +113,18 @@ def test_layer_graph_and_chunks_bitwise():
             assert np.array_equal(u, v)
 
 
-def test_layer_row_chunks_and_autotune_bitwise():
-    """The layer kernels march chunks of rows; every chunking (3 rows, 8, 64,
-    whole columns at 16 rows default) and the autotuner's choice give the
-    same bits."""
+def test_layer_row_chunks_kernels_and_autotune_bitwise():
+    """The layer kernels march chunks of rows; the single-pass kernel and the
+    two-pass one, every chunking (3 rows, 8, 64, whole columns; 16 rows by
+    default) and the autotuner's choice give the same bits."""
     insts = layered_instances()
     ref = gpu_run(insts, 120)
-    for rows in (3, 8, 64, 200):
-        got = gpu_run(insts, 120, rows=rows)
-        for x, y in zip(ref, got):
-            for u, v in zip(x, y):
-                assert np.array_equal(u, v), rows
+    for kernel in (tk.TK_KERNEL_FUSED, tk.TK_KERNEL_TWO_PASS):
+        for rows in (0, 3, 8, 64, 200):
+            got = gpu_run(insts, 120, rows=rows, kernel=kernel)
+            for x, y in zip(ref, got):
+                for u, v in zip(x, y):
+                    assert np.array_equal(u, v), (kernel, rows)
     got = gpu_run(insts, 120, autotune=True)
     for x, y in zip(ref, got):
         for u, v in zip(x, y):
@@ -150,6 +151,8 @@ def test_layer_rejections():
     try:
         with pytest.raises(tk.TkError):
             st.set_tuning(kernel=tk.TK_KERNEL_FUSED2)
+        with pytest.raises(tk.TkError):
+            st.set_tuning(kernel=tk.TK_KERNEL_TILED, rows_per_tile=4)
         with pytest.raises(tk.TkError):   # the particle inside the layer
             st.set_source(0, dict(r0=35.0))
         st.set_source(0, dict(r0=8.0))
