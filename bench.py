@@ -384,8 +384,7 @@ def layer_study(args):
         steps -= steps % 2
         cap = int(T) + 64
         st = tk.Stepper(insts, wave_capacity=cap)
-        if not key.startswith("layer"):
-            st.autotune(warmup=2, steps=6)
+        st.autotune(warmup=2, steps=6)
         t = st.get_tuning()
         t["graph_steps"] = 100
         st.set_tuning(**t)

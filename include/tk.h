@@ -161,10 +161,12 @@ typedef enum {
                                results are bitwise those of FUSED */
 } tk_kernel;
 /* A context with a hyperboloidal layer (tk_instance_desc.layer_start) steps
- * with the layer's kernels: AUTO and FUSED select its single-pass kernel,
- * TWO_PASS its half-step and full-step passes (bitwise the same results);
- * rows_per_tile is then the rows each wave marches (0 = 16, else >= 3), and
- * FUSED2 and TILED are refused with TK_E_INVALID. */
+ * one step per pass.  AUTO and FUSED: FUSED on the columns whose stencil
+ * stays below the layer and the layer's single-pass kernel over the layer's
+ * columns; TWO_PASS: the layer's half-step and full-step passes over whole
+ * instances (the same results up to rounding order).  rows_per_tile is then
+ * the rows each wave marches (0 = 16, else >= 3); FUSED2 and TILED are
+ * refused with TK_E_INVALID. */
 
 enum {
     TK_TUNE_NT_STORES = 1 /* fused kernel: non-temporal stores of u^{n+1} */

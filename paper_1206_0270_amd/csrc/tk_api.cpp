@@ -135,22 +135,48 @@ void build_work(tk_ctx *c, int rows, int cols, int min_rows)
     c->work_cols = cols;
 }
 
-// The layer kernels' work list: strips of `cols` columns x chunks of `rows`
-// rows; a chunk holding a pole row keeps at least three rows.
-void build_layer_work(tk_ctx *c, int rows, int cols)
+// First output column whose stencil reaches into the layer (the half node
+// i + 1/2 beyond rho = R); n_r for an instance without a layer.
+int layer_first_column(const HostInst &h)
+{
+    const tk_instance_desc &d = h.desc;
+    if (d.layer_start == 0.0) return d.n_r;
+    int i = 0;
+    while (i < d.n_r && !(d.rstar_min + (i + 0.5) * h.h > d.layer_start)) ++i;
+    return i;
+}
+
+// Work lists of a layered context, in chunks of `rows` rows (a chunk holding
+// a pole row keeps at least three).  Split (the single-pass form): the
+// one-step fused kernel's strips of kFusedCols columns over each instance's
+// columns below its first layer column, and the layer kernel's strips of
+// kLayerFusedCols columns from there on; one-step updates read only u^n, so
+// the layer kernel, launched after the fused one, overwrites whatever part
+// of the fused kernel's last strip reaches into the layer.  Two-pass: the
+// layer kernels' strips of kLayerCols columns over whole instances.
+void build_layer_work(tk_ctx *c, int rows, bool split)
 {
     c->lwork.clear();
+    c->work.clear();
     for (size_t k = 0; k < c->inst.size(); ++k) {
         const tk_instance_desc &d = c->inst[k].desc;
+        const int iL = split ? layer_first_column(c->inst[k]) : 0;
         for (int j0 = 0; j0 < d.n_theta; j0 += rows) {
             int j1 = std::min(d.n_theta, j0 + rows);
             if (d.n_theta - j1 > 0 && d.n_theta - j1 < 3) j1 = d.n_theta;
-            for (int i0 = 0; i0 < d.n_r; i0 += cols) c->lwork.push_back(WorkItem{(int)k, i0, j0, j1});
+            if (split)
+                for (int i0 = 0; i0 < iL; i0 += kFusedCols) c->work.push_back(WorkItem{(int)k, i0, j0, j1});
+            const int step = split ? kLayerFusedCols : kLayerCols;
+            for (int i0 = iL; i0 < d.n_r; i0 += step) c->lwork.push_back(WorkItem{(int)k, i0, j0, j1});
             if (j1 == d.n_theta) break;
         }
     }
+    std::stable_sort(c->work.begin(), c->work.end(),
+                     [](const WorkItem &x, const WorkItem &y) { return (x.j1 - x.j0) > (y.j1 - y.j0); });
     c->lwork_rows = rows;
-    c->lwork_cols = cols;
+    c->lwork_cols = split ? kLayerFusedCols : kLayerCols;
+    c->work_rows = -1;  // not a list of the plain kernels' shapes
+    c->work_cols = -1;
 }
 
 size_t layer_work_capacity(const tk_ctx *c)
@@ -282,12 +308,17 @@ tk_status ensure_work(tk_ctx *c, int kernel)
 {
     if (c->layered) {
         const int rows = c->tuning.rows_per_tile > 0 ? c->tuning.rows_per_tile : kLayerRows;
-        const int cols = kernel == TK_KERNEL_TWO_PASS ? kLayerCols : kLayerFusedCols;
+        const bool split = kernel != TK_KERNEL_TWO_PASS;
+        const int cols = split ? kLayerFusedCols : kLayerCols;
         if (!c->lwork.empty() && c->lwork_rows == rows && c->lwork_cols == cols) return TK_OK;
-        build_layer_work(c, rows, cols);
-        if (c->lwork.size() > c->lwork_cap) return fail(c, TK_E_STATE, "layer work list exceeds its reserved area");
+        build_layer_work(c, rows, split);
+        if (c->lwork.size() > c->lwork_cap || c->work.size() > c->work_cap)
+            return fail(c, TK_E_STATE, "layer work list exceeds its reserved area");
         TK_HIP(c, hipMemcpyAsync(c->ws + c->off_lwork, c->lwork.data(), c->lwork.size() * sizeof(WorkItem),
                                  hipMemcpyHostToDevice, c->stream));
+        if (!c->work.empty())
+            TK_HIP(c, hipMemcpyAsync(c->ws + c->off_work, c->work.data(), c->work.size() * sizeof(WorkItem),
+                                     hipMemcpyHostToDevice, c->stream));
         TK_HIP(c, hipStreamSynchronize(c->stream));
         return TK_OK;
     }
@@ -308,10 +339,23 @@ hipError_t launch_one(tk_ctx *c, int kernel, int steps, int kstep, int kflip)
 {
     const DevInst *di = (const DevInst *)(c->ws + c->off_inst);
     const DevCtl *ctl = (const DevCtl *)(c->ws + c->off_ctl);
-    if (c->layered)
+    if (c->layered) {
+        // split: the one-step fused kernel below the layers, then the layer kernel over them
+        if (kernel != TK_KERNEL_TWO_PASS && !c->work.empty()) {
+            FusedShape f;
+            f.prefetch = c->tuning.prefetch_rows == 1 ? 1 : 3;
+            f.nt = (c->tuning.flags & TK_TUNE_NT_STORES) != 0;
+            f.waves = 1;
+            f.two_step = false;
+            f.chunked = false;
+            hipError_t e = launch_fused(true, di, (const WorkItem *)(c->ws + c->off_work), (int)c->work.size(),
+                                        kFusedCols, ctl, kstep, kflip, f, c->stream);
+            if (e != hipSuccess) return e;
+        }
         return launch_layer(kernel != TK_KERNEL_TWO_PASS, di, (const LayerInst *)(c->ws + c->off_linst),
                             (int)c->inst.size(), (const WorkItem *)(c->ws + c->off_lwork), (int)c->lwork.size(), ctl,
                             kstep, kflip, c->stream);
+    }
     if (kernel == TK_KERNEL_TWO_PASS)
         return launch_two_pass(di, (const int2 *)(c->ws + c->off_blocks), (int)c->blocks.size(), ctl, kstep, kflip,
                                c->stream);
