@@ -165,8 +165,9 @@ typedef enum {
  * stays below the layer and the layer's single-pass kernel over the layer's
  * columns; TWO_PASS: the layer's half-step and full-step passes over whole
  * instances (the same results up to rounding order).  rows_per_tile is then
- * the rows each wave marches (0 = 16, else >= 3); FUSED2 and TILED are
- * refused with TK_E_INVALID. */
+ * the chunk of rows of FUSED's work items (0 = whole columns; the layer's
+ * kernel beside it marches chunks of 8 rows), or of the two passes' (0 = 16);
+ * FUSED2 and TILED are refused with TK_E_INVALID. */
 
 enum {
     TK_TUNE_NT_STORES = 1 /* fused kernel: non-temporal stores of u^{n+1} */

@@ -146,29 +146,42 @@ int layer_first_column(const HostInst &h)
     return i;
 }
 
-// Work lists of a layered context, in chunks of `rows` rows (a chunk holding
-// a pole row keeps at least three).  Split (the single-pass form): the
+// Strips of `cols` columns from column i0s to the end of instance k (or to
+// i1), in chunks of `rows` rows (0 = whole columns); a chunk holding a pole
+// row keeps at least three rows.
+void push_strips(std::vector<WorkItem> &out, int k, const tk_instance_desc &d, int i0s, int i1, int cols, int rows)
+{
+    const int rc = rows > 0 ? rows : d.n_theta;
+    for (int j0 = 0; j0 < d.n_theta; j0 += rc) {
+        int j1 = std::min(d.n_theta, j0 + rc);
+        if (d.n_theta - j1 > 0 && d.n_theta - j1 < 3) j1 = d.n_theta;
+        for (int i0 = i0s; i0 < i1; i0 += cols) out.push_back(WorkItem{k, i0, j0, j1});
+        if (j1 == d.n_theta) break;
+    }
+}
+
+// Work lists of a layered context.  Split (the single-pass form): the
 // one-step fused kernel's strips of kFusedCols columns over each instance's
-// columns below its first layer column, and the layer kernel's strips of
-// kLayerFusedCols columns from there on; one-step updates read only u^n, so
-// the layer kernel, launched after the fused one, overwrites whatever part
-// of the fused kernel's last strip reaches into the layer.  Two-pass: the
-// layer kernels' strips of kLayerCols columns over whole instances.
+// columns below its first layer column, in chunks of `rows` rows (0 = whole
+// columns), and the layer kernel's strips of kLayerFusedCols columns from
+// there on, in chunks of kLayerSplitRows rows (the layers are a few columns
+// wide: short chunks give them waves enough); one-step updates read only
+// u^n, so the layer kernel, launched after the fused one, overwrites
+// whatever part of the fused kernel's last strip reaches into the layer.
+// Two-pass: the layer kernels' strips of kLayerCols columns over whole
+// instances in chunks of `rows` rows (0 = kLayerRows).
 void build_layer_work(tk_ctx *c, int rows, bool split)
 {
     c->lwork.clear();
     c->work.clear();
     for (size_t k = 0; k < c->inst.size(); ++k) {
         const tk_instance_desc &d = c->inst[k].desc;
-        const int iL = split ? layer_first_column(c->inst[k]) : 0;
-        for (int j0 = 0; j0 < d.n_theta; j0 += rows) {
-            int j1 = std::min(d.n_theta, j0 + rows);
-            if (d.n_theta - j1 > 0 && d.n_theta - j1 < 3) j1 = d.n_theta;
-            if (split)
-                for (int i0 = 0; i0 < iL; i0 += kFusedCols) c->work.push_back(WorkItem{(int)k, i0, j0, j1});
-            const int step = split ? kLayerFusedCols : kLayerCols;
-            for (int i0 = iL; i0 < d.n_r; i0 += step) c->lwork.push_back(WorkItem{(int)k, i0, j0, j1});
-            if (j1 == d.n_theta) break;
+        if (split) {
+            const int iL = layer_first_column(c->inst[k]);
+            push_strips(c->work, (int)k, d, 0, iL, kFusedCols, rows);
+            push_strips(c->lwork, (int)k, d, iL, d.n_r, kLayerFusedCols, kLayerSplitRows);
+        } else {
+            push_strips(c->lwork, (int)k, d, 0, d.n_r, kLayerCols, rows > 0 ? rows : kLayerRows);
         }
     }
     std::stable_sort(c->work.begin(), c->work.end(),
@@ -307,7 +320,7 @@ int resolve_kernel(const tk_ctx *c)
 tk_status ensure_work(tk_ctx *c, int kernel)
 {
     if (c->layered) {
-        const int rows = c->tuning.rows_per_tile > 0 ? c->tuning.rows_per_tile : kLayerRows;
+        const int rows = c->tuning.rows_per_tile;
         const bool split = kernel != TK_KERNEL_TWO_PASS;
         const int cols = split ? kLayerFusedCols : kLayerCols;
         if (!c->lwork.empty() && c->lwork_rows == rows && c->lwork_cols == cols) return TK_OK;

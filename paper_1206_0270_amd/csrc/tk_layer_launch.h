@@ -24,7 +24,9 @@ hipError_t launch_layer(bool fused, const DevInst *d_inst, const LayerInst *d_la
 constexpr int kLayerFusedCols = 62;
 constexpr int kLayerCols = 64;
 
-// Rows per chunk of the layer kernels' work list when the tuning gives none.
+// Rows per chunk of the two-pass layer kernels' work list when the tuning
+// gives none, and of the single-pass layer kernel's beside the fused kernel.
 constexpr int kLayerRows = 16;
+constexpr int kLayerSplitRows = 8;
 
 }  // namespace tk
