@@ -15,7 +15,9 @@ What fixes the oracle's layer, independently of it:
   * dynamics: inside rho < R a layered run agrees with a run on a domain so
     large that nothing returns from its outer boundary, the difference
     falling at second order with the grid spacing, and a layered run stays
-    bounded and decays once the pulse has left.
+    bounded and decays once the pulse has left;
+  * physics at null infinity: the Schwarzschild l = 2 ringdown read there has
+    the published quasinormal frequency.
 """
 import numpy as np
 import pytest
@@ -183,3 +185,39 @@ def test_layer_rejects_bad_descriptions():
         oracle.Grid(n_r=101, rstar_min=-50.0, rstar_max=50.0, layer_R=60.0)   # R beyond S
     with pytest.raises(ValueError):
         oracle.Grid(n_r=101, rstar_min=-50.0, rstar_max=50.0, layer_R=30.0, s=0)  # s = -2 only
+
+
+def test_ringdown_at_null_infinity_is_the_schwarzschild_qnm():
+    """Read at null infinity, the l = 2 ringdown of a Schwarzschild pulse has
+    the fundamental quasinormal frequency (tests/golden/schwarzschild_qnm_l2.json,
+    the same bar as the plain domain's pin at r* = 30M).  The fit starts 20M
+    after the peak, when the overtones have died away, and runs for 50M, before
+    the power-law tail (which decays more slowly at null infinity than at a
+    finite radius) takes over."""
+    import json
+    import os
+
+    import test_oracle_pins as PINS
+    from paper_1206_0270_amd import workloads as W
+
+    with open(os.path.join(PINS.GOLDEN, "schwarzschild_qnm_l2.json")) as f:
+        want = complex(*json.load(f)["M_omega"])
+    h, nth, dt, every = 0.125, 33, 0.025, 4
+    n_r = int(round((60.0 + 100.0) / h)) + 1
+    g = oracle.Grid(a=0.0, m=2, n_r=n_r, n_theta=nth, rstar_min=-100.0, rstar_max=60.0, dt=dt, layer_R=40.0,
+                    i_obs=n_r - 1, extract_every=every)
+    th = np.arange(nth) * np.pi / (nth - 1)
+    Y = W.swsh_profile(-2, 2, 2, th)
+    rho = -100.0 + h * np.arange(n_r)
+    phi = (np.exp(-rho ** 2 / 32.0)[None, :] * Y[:, None]).astype(np.complex128)
+    g.set_state(phi, np.zeros_like(phi))
+    g.run(int(round(160.0 / dt)))
+    c = oracle.project(g.waveform(), Y[None, :], np.pi / (nth - 1))[:, 0]
+    t = (np.arange(len(c)) + 1) * every * dt
+    assert np.max(np.abs(c.imag)) < 1e-14 * np.max(np.abs(c.real))  # real data stay real at a = 0
+    t_peak = t[np.argmax(np.abs(c))]
+    sel = (t >= t_peak + 20.0) & (t <= t_peak + 70.0)
+    om = PINS._matrix_pencil(c[sel].real, every * dt, 2)
+    om = om[np.argmax(om.real)]
+    assert abs(om.real - want.real) < 0.005 * abs(want.real), om
+    assert abs(om.imag - want.imag) < 0.02 * abs(want.imag), om
