@@ -1,10 +1,14 @@
 // Kernels of the hyperboloidal outer layer (Section 2.3, item 2).
 //
-// A context with a layered instance steps with these two-pass kernels: one
-// thread per point, Eq. (3) into the half-step array, then Eq. (4).  The
-// coefficients are the plain ones of the first-order system (the radial and
-// angular tables the other kernels read) turned into the layer's by the
-// per-position factors rho', H, rho'' of the map.  Changing to
+// A layered context steps one step per pass: by default the plain one-step
+// fused kernel below the layers and k_layer_fused (both stages in one pass,
+// DPP lane exchange) over them, or, as the alternative form, k_layer_half
+// (Eq. (3) into the half-step array) and k_layer_full (Eq. (4)) over whole
+// instances; k_layer_scri then fills the null-infinity column.  The layer
+// kernels march chunks of theta rows with their radial factors in registers.
+// Their coefficients are the plain ones of the first-order system (the
+// radial and angular tables the other kernels read) turned into the layer's
+// by the per-position factors rho', H, rho'' of the map.  Changing to
 // (tau, rho) with tau = t - h(r*), h' = H, and Pi~ = Pi / w, w = 1 - H b,
 // v = 1 + H b, the system u_tau + D~ u_rho = S~ has
 //   D~  = [[bo, 0], [d~, -bi]],  bo = b rho' / w,  bi = b rho' / v,
