@@ -143,6 +143,8 @@ def precision_study(args):
     insts = W.config5()["instances"]
     if args.study_ramp > 0:  # every source switched on smoothly over study_ramp
         insts = [dict(i, source=dict(i["source"], ramp=args.study_ramp)) for i in insts]
+    if args.study_layer > 0:  # grids ending in a layer on [study_layer, 300]M, waveform read at null infinity
+        insts = [dict(i, layer_start=args.study_layer, rstar_obs=i["rstar_max"], i_obs=i["n_r"] - 1) for i in insts]
     dt = insts[0]["dt"]
     steps = int(round(args.study_window / dt))
     steps -= steps % 200
@@ -160,7 +162,12 @@ def precision_study(args):
         ev0 = torch.cuda.Event(enable_timing=True)
         ev1 = torch.cuda.Event(enable_timing=True)
         ev0.record(st.stream)
-        st.step(steps)
+        chunk = 100000
+        for done in range(0, steps, chunk):
+            st.step(min(chunk, steps - done))
+            if steps > chunk:
+                st.synchronize()
+                print(f"# {name}: {min(done + chunk, steps)} of {steps} steps", file=sys.stderr, flush=True)
         ev1.record(st.stream)
         torch.cuda.synchronize()
         ms = ev0.elapsed_time(ev1)
@@ -188,7 +195,8 @@ def precision_study(args):
     inst = insts[0]
     g = oracle.Grid(M=inst["M"], a=inst["a"], s=inst["s"], m=inst["m"], n_r=inst["n_r"], n_theta=inst["n_theta"],
                     rstar_min=inst["rstar_min"], rstar_max=inst["rstar_max"], dt=inst["dt"], i_obs=inst["i_obs"],
-                    extract_every=inst["extract_every"], source=inst.get("source"))
+                    extract_every=inst["extract_every"], source=inst.get("source"),
+                    layer_R=inst.get("layer_start", 0.0))
     g.set_state(*W.initial_data(inst))
     g.run(args.study_oracle_steps)
     ophi, opi = g.get_state()
@@ -204,8 +212,11 @@ def precision_study(args):
     out = {
         "metric": "waveform amplitude / phase relative error of the FP32-compensated form vs FP64; updates/s of both",
         "workload": "6 instances m=2,3,4 x a=0.5,0.9, circular orbit r0=8M, 16001 x 129 on [-300,300]M, dt=1/500, "
-                    "waveform at r*=290M projected on the l=max(|m|,2) harmonic"
+                    + (f"ending in a hyperboloidal layer on [{args.study_layer},300]M, waveform at null infinity"
+                       if args.study_layer > 0 else "waveform at r*=290M")
+                    + " projected on the l=max(|m|,2) harmonic"
                     + (f"; sources switched on over {args.study_ramp}M" if args.study_ramp > 0 else ""),
+        "layer_start": args.study_layer,
         "ramp_M": args.study_ramp,
         "window_M": steps * dt, "steps": steps, "points": points,
         "fp64_updates_per_s": forms["fp64"]["updates_per_s"], "fp32c_updates_per_s": forms["fp32c"]["updates_per_s"],
@@ -621,6 +632,9 @@ def main():
     ap.add_argument("--study-oracle-steps", type=int, default=2000)
     ap.add_argument("--study-ramp", type=float, default=0.0,
                     help="precision study: switch-on time of the sources (M; 0 = abrupt)")
+    ap.add_argument("--study-layer", type=float, default=0.0,
+                    help="precision study: end the grids in a hyperboloidal layer from this r* (M) on and read the "
+                         "waveform at null infinity (0 = the plain grids, observer at 290M)")
     ap.add_argument("--richardson", action="store_true",
                     help="instead of the throughput line, run the three-resolution Richardson study")
     ap.add_argument("--rich-window", type=float, default=330.0, help="Richardson study: simulated time (M)")

@@ -90,9 +90,11 @@ typedef struct {
      * extrapolation of the two nodes before it (no characteristic enters
      * there), so rstar_obs = rstar_max samples the waveform at null
      * infinity.  Requires s = -2 (whose Phi has a finite limit there),
-     * TK_FP64, max(0, rstar_min) < R, R + 2h <= rstar_max, and a particle
-     * source confined to rho < R.  A context with a layered instance steps
-     * every instance with the layer's two-pass kernels. */
+     * max(0, rstar_min) < R, R + 2h <= rstar_max, and a particle source
+     * confined to rho < R.  In TK_FP32_COMP the columns whose stencil reaches
+     * into the layer are computed in FP64 on the stored (compensated) values.
+     * A context with a layered instance steps one step per pass (see
+     * tk_kernel). */
     double layer_start;
 } tk_instance_desc;
 

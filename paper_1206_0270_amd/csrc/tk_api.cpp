@@ -361,11 +361,12 @@ hipError_t launch_one(tk_ctx *c, int kernel, int steps, int kstep, int kflip)
             f.waves = 1;
             f.two_step = false;
             f.chunked = false;
-            hipError_t e = launch_fused(true, di, (const WorkItem *)(c->ws + c->off_work), (int)c->work.size(),
-                                        kFusedCols, ctl, kstep, kflip, f, c->stream);
+            hipError_t e = launch_fused(c->prec == TK_FP64, di, (const WorkItem *)(c->ws + c->off_work),
+                                        (int)c->work.size(), kFusedCols, ctl, kstep, kflip, f, c->stream);
             if (e != hipSuccess) return e;
         }
-        return launch_layer(kernel != TK_KERNEL_TWO_PASS, di, (const LayerInst *)(c->ws + c->off_linst),
+        return launch_layer(c->prec == TK_FP64, kernel != TK_KERNEL_TWO_PASS, di,
+                            (const LayerInst *)(c->ws + c->off_linst),
                             (int)c->inst.size(), (const WorkItem *)(c->ws + c->off_lwork), (int)c->lwork.size(), ctl,
                             kstep, kflip, c->stream);
     }
@@ -517,10 +518,6 @@ tk_status tk_init_grid(const tk_instance_desc *inst, int n_inst, tk_precision pr
         return fail(nullptr, TK_E_INVALID, "too many points");
     }
     for (int k = 0; k < n_inst; ++k) c->layered = c->layered || inst[k].layer_start != 0.0;
-    if (c->layered && prec != TK_FP64) {
-        delete c;
-        return fail(nullptr, TK_E_INVALID, "the hyperboloidal layer is FP64 only");
-    }
     layout(c);
     *out = c;
     return TK_OK;
@@ -980,7 +977,8 @@ tk_status tk_autotune(tk_ctx *c, int warmup, int steps, double *best_ms_per_step
     if (c->layered) {  // the layer kernels: one pass or two, rows per chunk
         cand.clear();
         for (int rows : {0, 8, 32, 64}) cand.push_back(tk_tuning{TK_KERNEL_FUSED, rows, 0, 3, TK_TUNE_NT_STORES, 0});
-        for (int rows : {0, 32}) cand.push_back(tk_tuning{TK_KERNEL_TWO_PASS, rows, 0, 3, TK_TUNE_NT_STORES, 0});
+        if (c->prec == TK_FP64)
+            for (int rows : {0, 32}) cand.push_back(tk_tuning{TK_KERNEL_TWO_PASS, rows, 0, 3, TK_TUNE_NT_STORES, 0});
     }
 
     tk_status st = e == hipSuccess ? TK_OK : fail(c, TK_E_DEVICE, std::string("autotune setup: ") + hipGetErrorString(e));

@@ -236,6 +236,47 @@ __global__ void __launch_bounds__(256) k_layer_full(const DevInst *__restrict__ 
     }
 }
 
+// State storage.  FP64: double4 per point.  FP32-compensated: float4 values
+// f and a ushort4 of bf16 terms c per point, the value being f + c; the
+// layer's columns are computed in FP64 on that value and stored back split
+// as f = fl32(v), c = bf16(fl32(v - f)), as the host stores fields.
+__device__ __forceinline__ float bf16_to_float(unsigned short b) { return __uint_as_float((unsigned)b << 16); }
+__device__ __forceinline__ unsigned short float_to_bf16(float x) { return __builtin_bit_cast(unsigned short, (__bf16)x); }
+
+template <bool COMP>
+__device__ __forceinline__ P4 load_state(const void *u, const void *uc, size_t o)
+{
+    if constexpr (!COMP) {
+        return ld_p4((const double4 *)u + o);
+    } else {
+        const fvec4 a = gload_ptr((const fvec4 *)u)[o];
+        const hvec4 b = gload_ptr((const hvec4 *)uc)[o];
+        return P4{mk((double)a.x + (double)bf16_to_float(b.x), (double)a.y + (double)bf16_to_float(b.y)),
+                  mk((double)a.z + (double)bf16_to_float(b.z), (double)a.w + (double)bf16_to_float(b.w))};
+    }
+}
+
+template <bool COMP>
+__device__ __forceinline__ void store_state(void *u, void *uc, size_t o, const P4 &v)
+{
+    if constexpr (!COMP) {
+        st_p4((double4 *)u + o, v);
+    } else {
+        const double x[4] = {v.phi.re, v.phi.im, v.pi.re, v.pi.im};
+        float f[4];
+        unsigned short c[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            f[q] = (float)x[q];
+            c[q] = float_to_bf16((float)(x[q] - (double)f[q]));
+        }
+        const fvec4 a = {f[0], f[1], f[2], f[3]};
+        const hvec4 b = {c[0], c[1], c[2], c[3]};
+        gstore_ptr((fvec4 *)u)[o] = a;
+        gstore_ptr((hvec4 *)uc)[o] = b;
+    }
+}
+
 // Lane exchange by DPP wave shifts (a vector move, no LDS round trip):
 // wave_shl:1 gives lane l the value of lane l+1, wave_shr:1 that of lane
 // l-1; the lane at the open end gets 0 (bound_ctrl), and it is a halo lane
@@ -267,8 +308,10 @@ __device__ __forceinline__ P4 dpp_p4(const P4 &v)
 // the half rows on either side of it.  Pole rows of the half step come from
 // its rows 1, 2 (n_theta-2, n_theta-3), as in the two-pass form, and so do
 // the pole rows of u^{n+1}.  Bitwise the results of k_layer_half +
-// k_layer_full.  Every lane runs the whole march (the shifts need their
-// source lanes); lanes off the grid read clamped columns and store nothing.
+// k_layer_full (FP64 storage).  Every lane runs the whole march (the shifts
+// need their source lanes); lanes off the grid read clamped columns and store
+// nothing.  COMP: FP32-compensated storage, FP64 arithmetic.
+template <bool COMP>
 __global__ void __launch_bounds__(256) k_layer_fused(const DevInst *__restrict__ insts,
                                                      const LayerInst *__restrict__ lays,
                                                      const WorkItem *__restrict__ work, int n_work,
@@ -292,8 +335,6 @@ __global__ void __launch_bounds__(256) k_layer_fused(const DevInst *__restrict__
     const int in = interior ? i : 1;
     const long long n = ctl->step + kstep;
     const int b = (int)((ctl->cur + kflip) & 1);
-    const double4 *u = (const double4 *)I.u[b];
-    double4 *un = (double4 *)I.u[b ^ 1];
     // the two stages' times, formed as k_layer_half and k_layer_full form them
     const double t1 = (double)n * I.dt;
     const double t2 = (double)n * I.dt + 0.5 * I.dt;
@@ -311,7 +352,7 @@ __global__ void __launch_bounds__(256) k_layer_fused(const DevInst *__restrict__
     TK_GLOBAL double *wv = nullptr;
     if (sampling) wv = gstore_ptr(I.wave) + (size_t)(((n + 1) / I.extract_every - 1) % I.wave_cap) * nt * 2;
 
-    auto ldu = [&](int j) { return ld_p4(u + (size_t)j * I.pitch + ic); };
+    auto ldu = [&](int j) { return load_state<COMP>(I.u[b], I.c[b], (size_t)j * I.pitch + ic); };
     auto right = [](const P4 &v) { return dpp_p4<kWaveShl1>(v); };  // column i + 1
     auto left = [](const P4 &v) { return dpp_p4<kWaveShr1>(v); };   // half node i - 1/2
     // Eq. (3) at half node i + 1/2, row j (1 <= j <= nt - 2), from u^n rows j-1, j, j+1 of columns i, i+1
@@ -324,7 +365,7 @@ __global__ void __launch_bounds__(256) k_layer_fused(const DevInst *__restrict__
     };
     auto store = [&](int j, const P4 &o) {
         if (interior || edge) {
-            st_p4(un + (size_t)j * I.pitch + i, o);
+            store_state<COMP>(I.u[b ^ 1], I.c[b ^ 1], (size_t)j * I.pitch + i, o);
             if (sampling) {
                 wv[2 * j] = o.phi.re;
                 wv[2 * j + 1] = o.phi.im;
@@ -388,7 +429,8 @@ __global__ void __launch_bounds__(256) k_layer_fused(const DevInst *__restrict__
 // The last node of each layered instance (future null infinity): the linear
 // extrapolation 2 u_{N-2} - u_{N-3} of the new values on rows 1 .. n_theta-2,
 // then the pole rows from its rows 1, 2 (n_theta-2, n_theta-3).  One block
-// per instance, threads striding over rows.
+// per instance, threads striding over rows.  COMP: FP32-compensated storage.
+template <bool COMP>
 __global__ void __launch_bounds__(256) k_layer_scri(const DevInst *__restrict__ insts,
                                                     const LayerInst *__restrict__ lays, const DevCtl *__restrict__ ctl,
                                                     int kstep, int kflip)
@@ -398,13 +440,14 @@ __global__ void __launch_bounds__(256) k_layer_scri(const DevInst *__restrict__ 
     const DevInst &I = insts[k];
     const long long n = ctl->step + kstep;
     const int b = (int)((ctl->cur + kflip) & 1);
-    double4 *un = (double4 *)I.u[b ^ 1];
+    void *un = I.u[b ^ 1], *unc = I.c[b ^ 1];
     const int nt = I.n_theta, N = I.n_r;
     const bool sampling = I.i_obs == N - 1 && I.extract_every > 0 && (n + 1) % I.extract_every == 0;
     TK_GLOBAL double *wv = nullptr;
     if (sampling) wv = gstore_ptr(I.wave) + (size_t)(((n + 1) / I.extract_every - 1) % I.wave_cap) * nt * 2;
     auto ext = [&](int j) {
-        const P4 a = ld_p4(un + (size_t)j * I.pitch + N - 2), c = ld_p4(un + (size_t)j * I.pitch + N - 3);
+        const P4 a = load_state<COMP>(un, unc, (size_t)j * I.pitch + N - 2);
+        const P4 c = load_state<COMP>(un, unc, (size_t)j * I.pitch + N - 3);
         return P4{mk(2.0 * a.phi.re - c.phi.re, 2.0 * a.phi.im - c.phi.im),
                   mk(2.0 * a.pi.re - c.pi.re, 2.0 * a.pi.im - c.pi.im)};
     };
@@ -416,7 +459,7 @@ __global__ void __launch_bounds__(256) k_layer_scri(const DevInst *__restrict__ 
             o = zero4();
         else
             o = j == 0 ? pole_bc(ext(1), ext(2)) : pole_bc(ext(nt - 2), ext(nt - 3));
-        st_p4(un + (size_t)j * I.pitch + N - 1, o);
+        store_state<COMP>(un, unc, (size_t)j * I.pitch + N - 1, o);
         if (sampling) {
             wv[2 * j] = o.phi.re;
             wv[2 * j + 1] = o.phi.im;
@@ -426,15 +469,20 @@ __global__ void __launch_bounds__(256) k_layer_scri(const DevInst *__restrict__ 
 
 }  // namespace
 
-hipError_t launch_layer(bool fused, const DevInst *d_inst, const LayerInst *d_lay, int n_inst, const WorkItem *d_work,
-                        int n_work, const DevCtl *ctl, int kstep, int kflip, hipStream_t s)
+hipError_t launch_layer(bool fp64, bool fused, const DevInst *d_inst, const LayerInst *d_lay, int n_inst,
+                        const WorkItem *d_work, int n_work, const DevCtl *ctl, int kstep, int kflip, hipStream_t s)
 {
     if (n_work <= 0) return hipSuccess;
+    if (!fp64 && !fused) return hipErrorInvalidValue;  // the two passes keep an FP64 half-step array
     const int blocks = (n_work + 3) / 4;
     hipError_t e;
     if (fused) {
-        hipLaunchKernelGGL(k_layer_fused, dim3(blocks), dim3(256), 0, s, d_inst, d_lay, d_work, n_work, ctl, kstep,
-                           kflip);
+        if (fp64)
+            hipLaunchKernelGGL(k_layer_fused<false>, dim3(blocks), dim3(256), 0, s, d_inst, d_lay, d_work, n_work, ctl,
+                               kstep, kflip);
+        else
+            hipLaunchKernelGGL(k_layer_fused<true>, dim3(blocks), dim3(256), 0, s, d_inst, d_lay, d_work, n_work, ctl,
+                               kstep, kflip);
         e = hipGetLastError();
     } else {
         hipLaunchKernelGGL(k_layer_half, dim3(blocks), dim3(256), 0, s, d_inst, d_lay, d_work, n_work, ctl, kstep,
@@ -446,7 +494,10 @@ hipError_t launch_layer(bool fused, const DevInst *d_inst, const LayerInst *d_la
         e = hipGetLastError();
     }
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_layer_scri, dim3(n_inst), dim3(256), 0, s, d_inst, d_lay, ctl, kstep, kflip);
+    if (fp64)
+        hipLaunchKernelGGL(k_layer_scri<false>, dim3(n_inst), dim3(256), 0, s, d_inst, d_lay, ctl, kstep, kflip);
+    else
+        hipLaunchKernelGGL(k_layer_scri<true>, dim3(n_inst), dim3(256), 0, s, d_inst, d_lay, ctl, kstep, kflip);
     return hipGetLastError();
 }
 

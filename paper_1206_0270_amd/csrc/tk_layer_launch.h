@@ -17,8 +17,11 @@ namespace tk {
 // long.  The coefficients are the layer's (separate outgoing and ingoing
 // speeds, rescaled Pi~ equation) where d_lay[k] has a table, the plain ones
 // elsewhere.  Buffers as for launch_two_pass.
-hipError_t launch_layer(bool fused, const DevInst *d_inst, const LayerInst *d_lay, int n_inst, const WorkItem *d_work,
-                        int n_work, const DevCtl *ctl, int kstep, int kflip, hipStream_t s);
+// fp64: FP64 storage, else FP32-compensated storage (single pass only; the
+// layer's columns are computed in FP64 on the stored values either way;
+// hipErrorInvalidValue for the two passes).
+hipError_t launch_layer(bool fp64, bool fused, const DevInst *d_inst, const LayerInst *d_lay, int n_inst,
+                        const WorkItem *d_work, int n_work, const DevCtl *ctl, int kstep, int kflip, hipStream_t s);
 
 // Output columns per work item of the fused and of the two-pass layer kernels.
 constexpr int kLayerFusedCols = 62;

@@ -180,8 +180,9 @@ def test_stepper_refuses_without_a_device():
 
 
 def test_layer_descriptions_are_validated():
-    """Hyperboloidal layer: accepted on the s = -2 field in FP64 with the
-    layer inside the grid; every other description is refused at init."""
+    """Hyperboloidal layer: accepted on the s = -2 field, in FP64 and in the
+    FP32-compensated form, with the layer inside the grid; every other
+    description is refused at init."""
     base = W.instance(a=0.5, m=2, n_r=201, n_theta=17, rstar_min=-40.0, rstar_max=50.0, layer_start=30.0)
     assert base["i_obs"] == 200  # the waveform is read at null infinity by default
     lib = tk.load()
@@ -196,4 +197,5 @@ def test_layer_descriptions_are_validated():
         assert st == tk.TK_E_INVALID, change
     arr = (tk.InstanceDesc * 1)(tk.make_desc(base))
     ctx = ctypes.c_void_p()
-    assert lib.tk_init_grid(arr, 1, tk.TK_FP32_COMP, None, ctypes.byref(ctx)) == tk.TK_E_INVALID
+    assert lib.tk_init_grid(arr, 1, tk.TK_FP32_COMP, None, ctypes.byref(ctx)) == tk.TK_OK
+    lib.tk_destroy(ctx)

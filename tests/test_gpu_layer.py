@@ -59,8 +59,9 @@ def check(inst, steps, got, ref):
             assert e[k] <= max(TOL, 4 * floor[k]), (k, e[k], floor[k])
 
 
-def gpu_run(insts, steps, graph=0, chunks=None, rows=0, autotune=False, kernel=tk.TK_KERNEL_AUTO):
-    st = tk.Stepper(insts, force_dt=False)
+def gpu_run(insts, steps, graph=0, chunks=None, rows=0, autotune=False, kernel=tk.TK_KERNEL_AUTO,
+            precision=tk.TK_FP64):
+    st = tk.Stepper(insts, force_dt=False, precision=precision)
     st.set_tuning(kernel=kernel, graph_steps=graph, rows_per_tile=rows)
     for k, inst in enumerate(insts):
         st.set_fields(k, *W.initial_data(inst))
@@ -151,10 +152,33 @@ def test_layer_second_workload_size():
     check(inst, steps, got, oracle_run(inst, steps))
 
 
+def test_layer_fp32c_vs_fp64():
+    """FP32-compensated storage with layers: k_fused's FP32C form below the
+    layers, the layer's columns in FP64 on the stored values.  Against the
+    FP64 run after 150 steps: the FP32C bar of the plain grids (fields within
+    relative L2 2e-5), the waveform at null infinity too; chunkings bitwise."""
+    insts = layered_instances()
+    ref = gpu_run(insts, 150)
+    got = gpu_run(insts, 150, precision=tk.TK_FP32_COMP)
+    for inst, (p64, q64, w64), (p32, q32, w32) in zip(insts, ref, got):
+        e = dict(phi=rel(p32, p64), pi=rel(q32, q64), wave=rel(w32, w64))
+        say(inst["name"], "fp32c vs fp64", {k: f"{v:.2e}" for k, v in e.items()})
+        assert max(e.values()) <= 2e-5, e
+    for rows in (3, 64):
+        again = gpu_run(insts, 150, precision=tk.TK_FP32_COMP, rows=rows)
+        for x, y in zip(got, again):
+            for u, v in zip(x, y):
+                assert np.array_equal(u, v), rows
+
+
 def test_layer_rejections():
     inst = layered_instances()[0]
-    with pytest.raises(tk.TkError):
-        tk.Stepper([inst], precision=tk.TK_FP32_COMP)
+    st = tk.Stepper([inst], precision=tk.TK_FP32_COMP)
+    try:
+        with pytest.raises(tk.TkError):   # the two passes keep an FP64 half-step array
+            st.set_tuning(kernel=tk.TK_KERNEL_TWO_PASS)
+    finally:
+        st.close()
     st = tk.Stepper([inst])
     try:
         with pytest.raises(tk.TkError):
