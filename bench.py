@@ -77,6 +77,31 @@ def traffic_entry(name, wl):
         return None
 
 
+def valu_entry(name, wl, updates_per_s):
+    """Vector-ALU issue figures of the kernel from the committed rocprofv3
+    SQ counter summary, if taken on the current kernel source: VALU busy
+    fraction, wave64 VALU instructions per point update, resident waves per
+    SIMD, and the update rate at which the VALU would be busy every cycle at
+    the clock measured under load (the issue ceiling)."""
+    path = os.path.join(ROOT, "profiles", "issue.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            data = json.load(f)
+        ent = data.get(f"{name}:{wl}")
+        if not ent or ent.get("kernel_hash") != kernel_hash():
+            return None
+        # 1024 SIMDs, 16 FP64/FP32 lanes each: a wave64 VALU instruction takes 4 cycles
+        ceiling = 1024 * ent["clock_hz"] * 64 / (4 * ent["lane_instr_per_update"])
+        return {"valu_busy": ent["valu_busy"], "lane_instr_per_update": ent["lane_instr_per_update"],
+                "waves_per_simd": ent["waves_per_simd"], "clock_hz": ent["clock_hz"],
+                "issue_ceiling_updates_per_s": ceiling, "frac_of_issue_ceiling": updates_per_s / ceiling,
+                "source": ent.get("source")}
+    except Exception:
+        return None
+
+
 def cpu_baseline(insts, target_s=15.0, steps=70):
     """The oracle as it stands, timed on this host on a bounded sample of the
     same workload: instances in workload order, `steps` steps each, until
@@ -607,7 +632,133 @@ def segments_study(args):
     print(json.dumps(out), flush=True)
 
 
-def main():
+def launch_plan(steps, graph_steps, two_step):
+    """The launches tk_step(steps) issues: replays of the captured graph of
+    graph_steps steps, then the rest directly; with the two-step kernel each
+    pair of steps is one launch and an odd count ends with one one-step
+    launch (per graph and per direct remainder).  Every graph and every
+    direct run ends with one control-block bump."""
+    if steps < 0 or graph_steps < 0:
+        raise ValueError("steps and graph_steps must be >= 0")
+
+    def split(n):
+        return (n // 2, n % 2) if two_step else (0, n)
+
+    G = graph_steps
+    replays = steps // G if G > 0 else 0
+    rest = steps - replays * G
+    g2, g1 = split(G) if G > 0 else (0, 0)
+    r2, r1 = split(rest)
+    return {"graph_replays": replays, "two_step_launches": replays * g2 + r2,
+            "one_step_launches": replays * g1 + r1, "bumps": replays + (1 if rest else 0)}
+
+
+def bench_graph_steps(steps, graph_steps, two_step):
+    """Graph block length for a timed run of `steps`: the requested length,
+    cut to the timed count so that the timed steps go through graph replays,
+    and even for the two-step kernel (whole launches)."""
+    G = min(graph_steps, steps)
+    if two_step:
+        G -= G % 2
+    return max(G, 0)
+
+
+def run_leg(args, insts, inits, precision):
+    """One timed throughput run of the stepper on `insts` in `precision`:
+    autotune (or the manual shape), graph capture, W warm-up steps, then K
+    timed steps bracketed by HIP events on the context's stream.  The timed
+    K are issued as two calls, the whole launches of the dominant kernel
+    first (even count for the two-step kernel), so its average launch time
+    is measured on its own; the second call holds the odd last step, if any."""
+    import torch
+    from paper_1206_0270_amd import tk
+
+    prec = tk.TK_FP64 if precision == "fp64" else tk.TK_FP32_COMP
+    points = sum(i["n_r"] * i["n_theta"] for i in insts)
+    st = tk.Stepper(insts, precision=prec)
+    for k, (phi, pi) in enumerate(inits):
+        st.set_fields(k, phi, pi)
+    if args.tune == "auto":
+        tune_ms, tried = st.autotune(warmup=2, steps=6)
+        t = st.get_tuning()
+        print(f"# {precision}: autotune {tried} launch shapes, best {tune_ms:.4f} ms/step: {t}", file=sys.stderr,
+              flush=True)
+    else:
+        kern = {"fused2": tk.TK_KERNEL_FUSED2, "fused": tk.TK_KERNEL_FUSED,
+                "two_pass": tk.TK_KERNEL_TWO_PASS, "tiled": tk.TK_KERNEL_TILED}[args.kernel]
+        st.set_tuning(kernel=kern, rows_per_tile=args.rows, graph_steps=0, prefetch_rows=args.prefetch,
+                      nt_stores=not args.no_nt)
+        t = st.get_tuning()
+    kernel = {tk.TK_KERNEL_FUSED2: "fused2", tk.TK_KERNEL_FUSED: "fused",
+              tk.TK_KERNEL_TWO_PASS: "two_pass", tk.TK_KERNEL_TILED: "tiled"}[t["kernel"]]
+    if t["kernel"] == tk.TK_KERNEL_AUTO:
+        kernel = "fused2" if t["rows_per_tile"] == 0 else "fused"
+    two_step = kernel == "fused2"
+    K = args.steps
+    K_main = K - (K % 2) if two_step else K
+    t["graph_steps"] = bench_graph_steps(K_main, args.graph_steps, two_step)
+    st.set_tuning(**t)
+    st.prepare(K_main)  # work list and graph capture, outside the timed region
+    print(f"# {precision}: {len(insts)} instances, {points} points, {st.workspace_bytes / 2**30:.2f} GiB workspace, "
+          f"kernel {kernel}, graph of {t['graph_steps']} steps", file=sys.stderr, flush=True)
+    st.step(args.warmup)
+    torch.cuda.synchronize()
+    stream = st.stream
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    c0 = st.counters()
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    st.step(K_main)
+    ev[1].record(stream)
+    st.step(K - K_main)
+    ev[2].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    c1 = st.counters()
+    main_ms = ev[0].elapsed_time(ev[1])
+    gpu_ms = ev[0].elapsed_time(ev[2])
+    elapsed = max(wall, gpu_ms / 1e3)
+    print(f"# {precision}: timed {K} steps: events {gpu_ms:.3f} ms, wall {wall * 1e3:.3f} ms, "
+          f"graph replays {c1['graph_launches'] - c0['graph_launches']}", file=sys.stderr, flush=True)
+    plan = launch_plan(K_main, t["graph_steps"], two_step)
+    # Roofline of the dominant kernel.  One launch reads the state u^n once
+    # and writes the new state once (32 + 32 B per point in FP64; 24 + 24 B in
+    # the FP32-compensated form), whether it advances one step or two: those
+    # are the bytes it must move.  The launch time is the first timed call's
+    # event time over its launches (its graph's control-block bump, a few
+    # microseconds, included).
+    spl = 2 if two_step else 1
+    n_launch = plan["two_step_launches"] if two_step else plan["one_step_launches"]
+    bpp = BYTES_PER_UPDATE[precision]  # per point and launch: one read and one write of the state
+    if kernel == "two_pass":
+        kname = "k_two_pass_half + k_two_pass_full"
+    elif kernel == "tiled":
+        kname = (f"k_tiled<{KERNEL_POLICY[precision]}<1, {'true' if t['nt_stores'] else 'false'}, 1>, "
+                 f"{t['rows_per_tile'] + 2}>")
+    else:
+        kname = kernel_name(precision, t["prefetch_rows"], t["nt_stores"], t["waves_per_simd"], two_step,
+                            t["rows_per_tile"] > 0)
+    roof = None
+    if n_launch > 0:
+        launch_s = main_ms / 1e3 / n_launch
+        moved = points * bpp
+        achieved = moved / launch_s / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_entry(kname, args.workload),
+                "kernel": kname, "avg_launch_ms": launch_s * 1e3, "launches_timed": n_launch,
+                "bytes_per_launch": moved, "bytes_per_point_per_launch": bpp, "updates_per_point_per_launch": spl,
+                # the same launch priced at one read and one write of the state per update (SURVEY's
+                # per-update figure): twice the bytes actually moved for the two-step kernel
+                "effective_GBps_at_per_update_bytes": points * spl * bpp / launch_s / 1e9,
+                "issue": valu_entry(kname, args.workload, points * spl / launch_s)}
+    st.close()
+    del st
+    torch.cuda.empty_cache()
+    return {"value": points * K / elapsed, "ms_per_step": elapsed * 1e3 / K, "kernel": kernel, "tuning": t,
+            "plan": plan, "graph_replays_timed": c1["graph_launches"] - c0["graph_launches"], "roofline": roof}
+
+
+def build_parser():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=300)
@@ -625,6 +776,8 @@ def main():
     ap.add_argument("--prefetch", type=int, default=3, choices=[1, 3])
     ap.add_argument("--no-nt", action="store_true", help="plain (not non-temporal) stores")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="time only --precision on --workload (no second precision, no single-mode leg)")
     ap.add_argument("--precision-study", action="store_true",
                     help="instead of the throughput line, run the FP32-compensated vs FP64 waveform study")
     ap.add_argument("--study-window", type=float, default=600.0, help="precision study: simulated time (M)")
@@ -669,7 +822,22 @@ def main():
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="instead of the stepper, run a plain device copy of this many GiB "
                          "(calibrates the HBM byte counters)")
-    args = ap.parse_args()
+    return ap
+
+
+def parse_args(argv=None):
+    """Command line of the benchmark (no device is touched)."""
+    ap = build_parser()
+    args = ap.parse_args(argv)
+    if args.steps < 1:
+        ap.error("--steps must be >= 1")
+    if args.warmup < 0 or args.graph_steps < 0:
+        ap.error("--warmup and --graph-steps must be >= 0")
+    return args
+
+
+def main(argv=None):
+    args = parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): the stepper's "
               f"multi-GPU sharding is a design, not part of this build", file=sys.stderr)
@@ -718,94 +886,54 @@ def main():
                           "GB_per_s": 2 * n / ms / 1e6}), flush=True)
         return
     insts, desc = workload(args.workload)
-    prec = tk.TK_FP64 if args.precision == "fp64" else tk.TK_FP32_COMP
+    inits = [W.initial_data(inst) for inst in insts]
     points = W.points(insts)
-    if args.steps % 2 or args.warmup % 2 or args.graph_steps % 2:
-        raise SystemExit("the two-step kernel is timed in whole launches: use even --steps, --warmup, --graph-steps")
-    st = tk.Stepper(insts, precision=prec)
-    for k, inst in enumerate(insts):
-        st.set_fields(k, *W.initial_data(inst))
-    if args.tune == "auto":
-        tune_ms, tried = st.autotune(warmup=2, steps=6)
-        t = st.get_tuning()
-        print(f"# autotune: {tried} launch shapes, best {tune_ms:.4f} ms/step: {t}", file=sys.stderr, flush=True)
-        t["graph_steps"] = args.graph_steps
-        st.set_tuning(**t)
-    else:
-        kern = {"fused2": tk.TK_KERNEL_FUSED2, "fused": tk.TK_KERNEL_FUSED,
-                "two_pass": tk.TK_KERNEL_TWO_PASS, "tiled": tk.TK_KERNEL_TILED}[args.kernel]
-        st.set_tuning(kernel=kern, rows_per_tile=args.rows, graph_steps=args.graph_steps,
-                      prefetch_rows=args.prefetch, nt_stores=not args.no_nt)
-    t = st.get_tuning()
-    kernel = {tk.TK_KERNEL_FUSED2: "fused2", tk.TK_KERNEL_FUSED: "fused",
-              tk.TK_KERNEL_TWO_PASS: "two_pass", tk.TK_KERNEL_TILED: "tiled"}[t["kernel"]]
-    two_step = kernel == "fused2"
-    print(f"# workload {args.workload}: {len(insts)} instances, {points} points, "
-          f"{st.workspace_bytes / 2**30:.2f} GiB workspace", file=sys.stderr, flush=True)
-    st.step(args.warmup)
-    torch.cuda.synchronize()
-    stream = st.stream
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    st.step(args.steps)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gpu_ms = ev0.elapsed_time(ev1)
-    print(f"# timed {args.steps} steps: events {gpu_ms:.3f} ms, wall {wall * 1e3:.3f} ms",
-          file=sys.stderr, flush=True)
-    elapsed = max(wall, gpu_ms / 1e3)
-    value = points * args.steps / elapsed
-    # Roofline of the dominant kernel: algorithmic bytes per point update
-    # (read u^n once, write u^{n+1} once: 64 B in FP64) x the point updates
-    # one launch performs (points x steps per launch), over the launch time.
-    # The two-step kernel performs two updates per launch while it reads and
-    # writes the state once, so it moves half the algorithmic bytes.
-    spl = 2 if two_step else 1
-    launches = args.steps // spl
-    launch_s = gpu_ms / 1e3 / launches
-    bpu = BYTES_PER_UPDATE[args.precision]
-    achieved = points * spl * bpu / launch_s / 1e9
-    if kernel == "two_pass":
-        kname = "k_two_pass_half + k_two_pass_full"
-    elif kernel == "tiled":  # tile capacity: rows_per_tile + 2
-        kname = (f"k_tiled<{KERNEL_POLICY[args.precision]}<1, {'true' if t['nt_stores'] else 'false'}, 1>, "
-                 f"{t['rows_per_tile'] + 2}>")
-    else:
-        kname = kernel_name(args.precision, t["prefetch_rows"], t["nt_stores"], t["waves_per_simd"], two_step,
-                            t["rows_per_tile"] > 0)
-    traffic = traffic_entry(kname, args.workload)
-    st.close()
+    main_leg = run_leg(args, insts, inits, args.precision)
+    other = "fp32c" if args.precision == "fp64" else "fp64"
+    legs = {args.precision: main_leg}
+    if not args.no_legs:
+        legs[other] = run_leg(args, insts, inits, other)
+    del inits
+    single = None
+    if not args.no_legs and args.workload != "single":
+        s_insts, s_desc = workload("single")
+        single = run_leg(args, s_insts, [W.initial_data(i) for i in s_insts], "fp64")
+        single["workload"] = s_desc
 
+    leg = main_leg
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": leg["value"],
         "unit": "grid-point updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": elapsed * 1e3 / args.steps,
+        "ms_per_step": leg["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32+bf16comp",
         "data": "synthetic",
         "config": {"workload": desc, "instances": len(insts), "points": points,
-                   "precision": args.precision, "kernel": kernel, "tuning": args.tune,
-                   "graph_steps": t["graph_steps"], "rows_per_tile": t["rows_per_tile"],
-                   "prefetch_rows": t["prefetch_rows"], "nt_stores": t["nt_stores"],
-                   "waves_per_simd": t["waves_per_simd"]},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": kname,
-                     "algorithmic_bytes_per_launch": points * spl * bpu,
-                     "steps_per_launch": spl,
-                     "state_bytes_moved_per_launch": points * bpu,
-                     "avg_launch_ms": launch_s * 1e3},
+                   "precision": args.precision, "kernel": leg["kernel"], "tuning": args.tune,
+                   "graph_steps": leg["tuning"]["graph_steps"], "rows_per_tile": leg["tuning"]["rows_per_tile"],
+                   "prefetch_rows": leg["tuning"]["prefetch_rows"], "nt_stores": leg["tuning"]["nt_stores"],
+                   "launches": leg["plan"], "graph_replays_timed": leg["graph_replays_timed"]},
+        "roofline": leg["roofline"],
     }
+    if "fp64" in legs and "fp32c" in legs:
+        f64, f32 = legs["fp64"], legs["fp32c"]
+        out["fp32c"] = {"value": f32["value"], "ms_per_step": f32["ms_per_step"], "kernel": f32["kernel"],
+                        "tuning": f32["tuning"], "roofline": f32["roofline"],
+                        "fp32c_over_fp64": f32["value"] / f64["value"]}
+    if single is not None:
+        out["fp64_single_mode"] = {"workload": single["workload"], "value": single["value"],
+                                   "ms_per_step": single["ms_per_step"], "kernel": single["kernel"],
+                                   "tuning": single["tuning"],
+                                   "note": "about 1e6 points: the state (66 MB) stays in the 256 MB Infinity "
+                                           "Cache, so no HBM roofline is claimed for it"}
+        if "fp32c" in legs:
+            out["fp32c"]["fp32c_batched_over_fp64_single_mode"] = legs["fp32c"]["value"] / single["value"]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(insts)
     print(json.dumps(out), flush=True)

@@ -21,8 +21,9 @@
  *  - Device memory: the library allocates none for the fields.  The caller
  *    queries tk_workspace_bytes, allocates that much device memory (for
  *    instance a torch tensor) and binds it with tk_bind_workspace; it stays
- *    caller-owned and must outlive the context.  The library owns only small
- *    host structures, its stream events and captured graphs.
+ *    caller-owned and must outlive the context.  The autotuner's save area
+ *    (tk_autotune_bytes) is caller-owned in the same way.  The library owns
+ *    only small host structures, its timing events and captured graphs.
  *  - Every entry point returns a tk_status; on error the context is left
  *    unchanged and tk_last_error(ctx) describes the failure.  No C++
  *    exception crosses the ABI.
@@ -39,7 +40,7 @@
 extern "C" {
 #endif
 
-#define TK_ABI_VERSION 3
+#define TK_ABI_VERSION 4
 
 typedef struct tk_ctx tk_ctx;
 
@@ -190,12 +191,17 @@ typedef struct {
                           TK_E_INVALID */
 } tk_tuning;
 
-/* Set up the grids of n_inst instances (tortoise inversion, radial and
- * angular coefficient tables, work decomposition) on the host.  No device
- * memory is touched.  hip_stream is a hipStream_t (NULL = default stream).
- * Returns TK_E_UNSTABLE if some instance's dt exceeds the stability bound of
- * the scheme with its angular terms (unless TK_FLAG_FORCE_DT), TK_E_INVALID
- * for an invalid description.  On success *out owns the context. */
+/* Set up the grids of n_inst instances on the host: the vertex-centred
+ * (r*, theta) grid of Section 2.2 with the m-mode of Eq. (2) on each, the
+ * tortoise inversion r(r*), and the radial and angular factors of the
+ * first-order system that Eqs. (3)-(4) step (Eq. (1) divided by its Psi_tt
+ * coefficient), plus the work decomposition.  No device memory is touched.
+ * inst: n_inst host descriptions (copied; caller-owned).  hip_stream is a
+ * hipStream_t; NULL is the legacy default stream, which cannot be captured,
+ * so a context on it refuses graph_steps > 0.  Returns TK_E_UNSTABLE if some
+ * instance's dt exceeds the stability bound of the scheme with its angular
+ * terms (unless TK_FLAG_FORCE_DT), TK_E_INVALID for an invalid description
+ * (the message names the instance).  On success *out owns the context. */
 tk_status tk_init_grid(const tk_instance_desc *inst, int n_inst, tk_precision prec, void *hip_stream,
                        tk_ctx **out);
 
@@ -221,15 +227,37 @@ tk_status tk_set_source(tk_ctx *ctx, int inst, const tk_source_desc *src);
 /* Advance every instance by n_steps full Lax-Wendroff steps (Eqs. (3)-(4)
  * with the Section 2.2 boundary conditions), asynchronously on the stream.
  * The state alternates between two buffers, one flip per kernel launch; the
- * context tracks which one is current. */
+ * context tracks which one is current.  With graph_steps = G > 0 (tuning)
+ * the steps go as replays of one captured HIP graph of G steps, the
+ * remainder as direct launches; TK_E_STATE if G > 0 on the NULL stream. */
 tk_status tk_step(tk_ctx *ctx, long n_steps);
 
-/* Copy the waveform samples of inst taken since the last call, oldest first,
- * to out ([sample][theta][re, im], at most max_samples samples) and drain
- * them.  Sample k holds Phi(t, r*_obs, theta_j) at t = (k+1) extract_every dt
- * after step counter 0.  Returns TK_E_STATE if more samples than the ring
- * holds were produced since the last call, TK_E_NONFINITE if a copied
- * sample is not finite. */
+/* Do ahead of time the host-side work a later tk_step(n_steps) would do
+ * first under the current tuning: upload the work list and, if
+ * graph_steps = G > 0 and n_steps >= G, capture and instantiate the graph of
+ * G steps.  Advances nothing.  Not for use during stream capture. */
+tk_status tk_prepare(tk_ctx *ctx, long n_steps);
+
+/* Launch counters of a context since tk_init_grid: graphs captured and
+ * instantiated, graph replays, and direct (eager) kernel launches issued by
+ * tk_step (autotuning is not counted). */
+typedef struct {
+    long graphs_instantiated;
+    long graph_launches;
+    long eager_launches;
+} tk_counters;
+tk_status tk_get_counters(const tk_ctx *ctx, tk_counters *out);
+
+/* Waveform extraction (Section 5.1: the waveform read from Phi near the
+ * outer boundary, at future null infinity with the layer of Section 2.3
+ * item 2).  Copies the samples of inst taken since the last call, oldest
+ * first, to out ([sample][theta][re, im] doubles, host memory, at most
+ * max_samples samples, caller-owned) and drains them; *n_samples receives
+ * the count.  Sample k holds Phi(t, r*_obs, theta_j) at
+ * t = (k+1) extract_every dt after step counter 0.  Synchronises the
+ * context's stream.  Returns TK_E_STATE if more samples than the ring holds
+ * were produced since the last call (nothing is drained), TK_E_NONFINITE if
+ * a copied sample is not finite (the samples are drained). */
 tk_status tk_extract(tk_ctx *ctx, int inst, double *out, long max_samples, long *n_samples);
 
 /* Step counter (steps taken since tk_bind_workspace or the last
@@ -246,18 +274,21 @@ tk_status tk_get_tuning(const tk_ctx *ctx, tk_tuning *t);
 /* Autotuner: time every compiled launch shape (kernel, u^n prefetch depth,
  * store kind; rows per tile 0, 32 and 16 for the two-step kernel, 0, 64 and
  * 16 for the one-step kernel, 8 and 4 for the tiled kernel) on this
- * context's own instances and keep the fastest;
- * graph_steps stays as it was.  Each
- * candidate runs `warmup` untimed and then `steps` timed steps (both
- * rounded up to even), timed with HIP events on the context's stream.  The
- * state, the step counter and the waveform rings are copied to a temporary
- * device allocation (hipMalloc; freed before return) and restored
- * afterwards, so the simulation is left as it was found.  Synchronous; not
- * for use during stream capture.  On success *best_ms_per_step and
- * *n_tried (each may be NULL) receive the winner's time per step and the
- * number of shapes timed.  TK_E_NOMEM if the temporary copy cannot be
- * allocated. */
-tk_status tk_autotune(tk_ctx *ctx, int warmup, int steps, double *best_ms_per_step, int *n_tried);
+ * context's own instances and keep the fastest; graph_steps stays as it
+ * was.  Each candidate runs `warmup` untimed and then `steps` timed steps
+ * (both rounded up to even), timed with HIP events on the context's stream.
+ * The state, the step counter and the waveform rings are copied to
+ * save_area and restored afterwards, so the simulation is left as it was
+ * found.  save_area: caller-owned device memory of at least
+ * tk_autotune_bytes bytes, 256-byte aligned, free for the duration of the
+ * call (the library allocates nothing).  Synchronous; not for use during
+ * stream capture.  On success *best_ms_per_step and *n_tried (each may be
+ * NULL) receive the winner's time per step and the number of shapes timed.
+ * TK_E_NOMEM if save_bytes is too small, TK_E_INVALID if save_area is not
+ * aligned device memory. */
+tk_status tk_autotune_bytes(const tk_ctx *ctx, size_t *bytes);
+tk_status tk_autotune(tk_ctx *ctx, int warmup, int steps, void *save_area, size_t save_bytes,
+                      double *best_ms_per_step, int *n_tried);
 
 /* Wait for all work enqueued by the context. */
 tk_status tk_synchronize(tk_ctx *ctx);

@@ -36,8 +36,9 @@ struct tk_ctx {
     std::vector<std::vector<Radial>> hrad;   // host copies of the coefficient tables
     std::vector<std::vector<Angular>> hang;
     std::vector<std::vector<AngularF>> hangf;
-    // hyperboloidal layer: any instance with one makes the context step with
-    // the layer's two-pass kernels
+    // hyperboloidal layer: any instance with one makes the context step one
+    // step per pass, split by columns (the one-step fused kernel below the
+    // layers, the layer kernel over them) or with the layer's two passes
     bool layered = false;
     size_t off_linst = 0;              // LayerInst per instance
     std::vector<size_t> off_lay;       // LayerTab table per instance (layered ones)
@@ -50,6 +51,7 @@ struct tk_ctx {
     // captured graph (steps, kernel, rows) for replay
     hipGraphExec_t gexec = nullptr;
     int g_steps = 0, g_flips = 0, g_kernel = -1, g_rows = -1, g_pf = -1, g_flags = -1, g_waves = -1;
+    tk_counters counters{0, 0, 0};
 };
 
 namespace {
@@ -452,6 +454,7 @@ tk_status ensure_graph(tk_ctx *c, int kernel, int G)
     c->g_pf = c->tuning.prefetch_rows;
     c->g_flags = c->tuning.flags;
     c->g_waves = c->tuning.waves_per_simd;
+    c->counters.graphs_instantiated += 1;
     return TK_OK;
 }
 
@@ -781,14 +784,16 @@ tk_status tk_step(tk_ctx *c, long n_steps)
     if (n_steps < 0 || n_steps > (1L << 40)) return fail(c, TK_E_INVALID, "n_steps out of range");
     if (!c->ws) return fail(c, TK_E_STATE, "no workspace bound");
     if (n_steps == 0) return TK_OK;
+    const int G = c->tuning.graph_steps;
+    if (G > 0 && c->stream == nullptr)
+        return fail(c, TK_E_STATE, "graph_steps > 0 needs a stream other than the NULL stream (it cannot be captured)");
     const int kernel = resolve_kernel(c);
     if (kernel != TK_KERNEL_TWO_PASS || c->layered) {
         tk_status st = ensure_work(c, kernel);
         if (st != TK_OK) return st;
     }
     long left = n_steps;
-    const int G = c->tuning.graph_steps;
-    if (G > 0 && c->stream != nullptr && left >= G) {
+    if (G > 0 && left >= G) {
         tk_status st = ensure_graph(c, kernel, G);
         if (st != TK_OK) return st;
         while (left >= G) {
@@ -796,6 +801,7 @@ tk_status tk_step(tk_ctx *c, long n_steps)
             left -= G;
             c->step += G;
             c->cur = (c->cur + c->g_flips) & 1;
+            c->counters.graph_launches += 1;
         }
     }
     while (left > 0) {
@@ -806,7 +812,32 @@ tk_status tk_step(tk_ctx *c, long n_steps)
         left -= chunk;
         c->step += chunk;
         c->cur = (c->cur + flips) & 1;
+        c->counters.eager_launches += flips + 1;  // the step launches and the control-block bump
     }
+    return TK_OK;
+}
+
+tk_status tk_prepare(tk_ctx *c, long n_steps)
+{
+    if (!c) return TK_E_INVALID;
+    if (n_steps < 0 || n_steps > (1L << 40)) return fail(c, TK_E_INVALID, "n_steps out of range");
+    if (!c->ws) return fail(c, TK_E_STATE, "no workspace bound");
+    const int kernel = resolve_kernel(c);
+    if (kernel != TK_KERNEL_TWO_PASS || c->layered) {
+        tk_status st = ensure_work(c, kernel);
+        if (st != TK_OK) return st;
+    }
+    const int G = c->tuning.graph_steps;
+    if (G > 0 && c->stream == nullptr)
+        return fail(c, TK_E_STATE, "graph_steps > 0 needs a stream other than the NULL stream (it cannot be captured)");
+    if (G > 0 && n_steps >= G) return ensure_graph(c, kernel, G);
+    return TK_OK;
+}
+
+tk_status tk_get_counters(const tk_ctx *c, tk_counters *out)
+{
+    if (!c || !out) return TK_E_INVALID;
+    *out = c->counters;
     return TK_OK;
 }
 
@@ -888,6 +919,8 @@ tk_status tk_set_tuning(tk_ctx *c, const tk_tuning *t)
     if (t->rows_per_tile < 0 || (t->rows_per_tile > 0 && t->rows_per_tile < 3))
         return fail(c, TK_E_INVALID, "rows_per_tile must be 0 or >= 3");
     if (t->graph_steps < 0 || t->graph_steps > 100000) return fail(c, TK_E_INVALID, "graph_steps out of range");
+    if (t->graph_steps > 0 && c->stream == nullptr)
+        return fail(c, TK_E_INVALID, "graph_steps > 0 needs a stream other than the NULL stream (it cannot be captured)");
     if (t->prefetch_rows != 0 && t->prefetch_rows != 1 && t->prefetch_rows != 3)
         return fail(c, TK_E_INVALID, "prefetch_rows must be 0, 1 or 3");
     if (t->flags & ~TK_TUNE_NT_STORES) return fail(c, TK_E_INVALID, "unknown tuning flags");
@@ -915,25 +948,20 @@ tk_status tk_get_tuning(const tk_ctx *c, tk_tuning *t)
     return TK_OK;
 }
 
-tk_status tk_autotune(tk_ctx *c, int warmup, int steps, double *best_ms_per_step, int *n_tried)
+// What a run of steps changes, which the autotuner saves and restores: the
+// current state (and its compensation terms), the waveform rings and the
+// control block.  Each span is placed at a 256-byte aligned offset of the
+// save area.
+struct SaveSpan {
+    size_t off, bytes, save;
+};
+static std::vector<SaveSpan> autotune_spans(const tk_ctx *c, size_t *total)
 {
-    if (!c) return TK_E_INVALID;
-    if (!c->ws) return fail(c, TK_E_STATE, "no workspace bound");
-    if (warmup < 0 || warmup > 100000 || steps < 1 || steps > 100000)
-        return fail(c, TK_E_INVALID, "warmup must be in [0, 1e5] and steps in [1, 1e5]");
-    warmup += warmup & 1;
-    steps += steps & 1;
-    TK_HIP(c, hipStreamSynchronize(c->stream));
-
-    // what a run changes: the current state, the waveform rings, the control block
-    struct Span {
-        size_t off, bytes, save;
-    };
-    std::vector<Span> spans;
-    size_t total = 0;
+    std::vector<SaveSpan> spans;
+    size_t t = 0;
     auto add = [&](size_t off, size_t bytes) {
-        spans.push_back(Span{off, bytes, total});
-        total += align_up(bytes, 256);
+        spans.push_back(SaveSpan{off, bytes, t});
+        t += align_up(bytes, 256);
     };
     for (const HostInst &h : c->inst) {
         const size_t pts = (size_t)h.desc.n_theta * h.pitch;
@@ -942,13 +970,42 @@ tk_status tk_autotune(tk_ctx *c, int warmup, int steps, double *best_ms_per_step
         add(h.off_wave, (size_t)h.wave_cap * h.desc.n_theta * 16);
     }
     add(c->off_ctl, sizeof(DevCtl));
-    char *save = nullptr;
-    if (hipMalloc(&save, total) != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(c, TK_E_NOMEM, "autotune: no device memory for the state copy");
+    *total = t;
+    return spans;
+}
+
+tk_status tk_autotune_bytes(const tk_ctx *c, size_t *bytes)
+{
+    if (!c || !bytes) return TK_E_INVALID;
+    (void)autotune_spans(c, bytes);
+    return TK_OK;
+}
+
+tk_status tk_autotune(tk_ctx *c, int warmup, int steps, void *save_area, size_t save_bytes,
+                      double *best_ms_per_step, int *n_tried)
+{
+    if (!c) return TK_E_INVALID;
+    if (!c->ws) return fail(c, TK_E_STATE, "no workspace bound");
+    if (warmup < 0 || warmup > 100000 || steps < 1 || steps > 100000)
+        return fail(c, TK_E_INVALID, "warmup must be in [0, 1e5] and steps in [1, 1e5]");
+    size_t total = 0;
+    const std::vector<SaveSpan> spans = autotune_spans(c, &total);
+    if (!save_area) return fail(c, TK_E_INVALID, "autotune: null save area");
+    if ((uintptr_t)save_area % 256 != 0) return fail(c, TK_E_INVALID, "autotune: save area must be 256-byte aligned");
+    if (save_bytes < total) return fail(c, TK_E_NOMEM, "autotune: save area smaller than tk_autotune_bytes");
+    {
+        hipPointerAttribute_t attr;
+        if (hipPointerGetAttributes(&attr, save_area) != hipSuccess || attr.type != hipMemoryTypeDevice) {
+            (void)hipGetLastError();
+            return fail(c, TK_E_INVALID, "autotune: save area is not device memory");
+        }
     }
+    warmup += warmup & 1;
+    steps += steps & 1;
+    TK_HIP(c, hipStreamSynchronize(c->stream));
+    char *save = (char *)save_area;
     hipError_t e = hipSuccess;
-    for (const Span &sp : spans)
+    for (const SaveSpan &sp : spans)
         if (e == hipSuccess)
             e = hipMemcpyAsync(save + sp.save, c->ws + sp.off, sp.bytes, hipMemcpyDeviceToDevice, c->stream);
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1009,11 +1066,10 @@ tk_status tk_autotune(tk_ctx *c, int warmup, int steps, double *best_ms_per_step
     }
     // restore the simulation as it was
     hipError_t er = hipStreamSynchronize(c->stream);
-    for (const Span &sp : spans)
+    for (const SaveSpan &sp : spans)
         if (er == hipSuccess)
             er = hipMemcpyAsync(c->ws + sp.off, save + sp.save, sp.bytes, hipMemcpyDeviceToDevice, c->stream);
     if (er == hipSuccess) er = hipStreamSynchronize(c->stream);
-    (void)hipFree(save);
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     c->step = step0;

@@ -1,9 +1,12 @@
 """Python binding of libtk.so (the C ABI in include/tk.h).
 
 Argument marshalling only: every step of the time stepper runs in the HIP
-kernels behind the C ABI.  PyTorch supplies the device workspace (a uint8
-tensor on the current HIP device) and the stream.  There is no fallback:
-if libtk.so is missing or no HIP device is visible, calls raise.
+kernels behind the C ABI.  PyTorch supplies the device memory (the
+workspace and the autotuner's save area, uint8 tensors on the current HIP
+device) and the stream: by default each Stepper gets a torch stream of its
+own, because the NULL stream cannot be captured into HIP graphs.  There is
+no fallback: if libtk.so is missing or no HIP device is visible, calls
+raise.
 """
 import ctypes
 import os
@@ -25,9 +28,10 @@ _STATUS = {0: "TK_OK", 1: "TK_E_INVALID", 2: "TK_E_NOMEM", 3: "TK_E_DEVICE", 4: 
            5: "TK_E_UNSTABLE", 6: "TK_E_NONFINITE"}
 
 EXPORTS = ["tk_abi_version", "tk_init_grid", "tk_workspace_bytes", "tk_bind_workspace",
-           "tk_set_fields", "tk_get_fields", "tk_set_source", "tk_step", "tk_extract",
-           "tk_get_step", "tk_set_step", "tk_set_tuning", "tk_get_tuning", "tk_autotune", "tk_synchronize",
-           "tk_destroy", "tk_last_error", "tk_stable_dt", "tk_richardson"]
+           "tk_set_fields", "tk_get_fields", "tk_set_source", "tk_step", "tk_prepare", "tk_get_counters",
+           "tk_extract", "tk_get_step", "tk_set_step", "tk_set_tuning", "tk_get_tuning", "tk_autotune_bytes",
+           "tk_autotune", "tk_synchronize", "tk_destroy", "tk_last_error", "tk_stable_dt", "tk_richardson"]
+ABI_VERSION = 4
 
 
 class TkError(RuntimeError):
@@ -56,6 +60,11 @@ class SourceDesc(ctypes.Structure):
 TK_TUNE_NT_STORES = 1
 
 
+class Counters(ctypes.Structure):
+    _fields_ = [("graphs_instantiated", ctypes.c_long), ("graph_launches", ctypes.c_long),
+                ("eager_launches", ctypes.c_long)]
+
+
 class Tuning(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int), ("rows_per_tile", ctypes.c_int),
                 ("graph_steps", ctypes.c_int), ("prefetch_rows", ctypes.c_int),
@@ -74,6 +83,8 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
     lib = ctypes.CDLL(LIB_PATH)
+    if lib.tk_abi_version() != ABI_VERSION:
+        raise RuntimeError(f"{LIB_PATH} has ABI version {lib.tk_abi_version()}, the binding {ABI_VERSION}: rebuild it")
     vp, st = ctypes.c_void_p, ctypes.c_int
     sig = {
         "tk_abi_version": (ctypes.c_int, []),
@@ -85,12 +96,16 @@ def load():
         "tk_get_fields": (st, [vp, ctypes.c_int, _dp, _dp]),
         "tk_set_source": (st, [vp, ctypes.c_int, ctypes.POINTER(SourceDesc)]),
         "tk_step": (st, [vp, ctypes.c_long]),
+        "tk_prepare": (st, [vp, ctypes.c_long]),
+        "tk_get_counters": (st, [vp, ctypes.POINTER(Counters)]),
         "tk_extract": (st, [vp, ctypes.c_int, _dp, ctypes.c_long, ctypes.POINTER(ctypes.c_long)]),
         "tk_get_step": (st, [vp, ctypes.POINTER(ctypes.c_long)]),
         "tk_set_step": (st, [vp, ctypes.c_long]),
         "tk_set_tuning": (st, [vp, ctypes.POINTER(Tuning)]),
         "tk_get_tuning": (st, [vp, ctypes.POINTER(Tuning)]),
-        "tk_autotune": (st, [vp, ctypes.c_int, ctypes.c_int, _dp, ctypes.POINTER(ctypes.c_int)]),
+        "tk_autotune_bytes": (st, [vp, ctypes.POINTER(ctypes.c_size_t)]),
+        "tk_autotune": (st, [vp, ctypes.c_int, ctypes.c_int, vp, ctypes.c_size_t, _dp,
+                             ctypes.POINTER(ctypes.c_int)]),
         "tk_synchronize": (st, [vp]),
         "tk_destroy": (st, [vp]),
         "tk_last_error": (ctypes.c_char_p, [vp]),
@@ -166,7 +181,8 @@ def richardson(w1, w2, w3, order=2):
 
 class Stepper:
     """A context over one or more instances, with its workspace in a torch
-    tensor on the current HIP device and work on the current torch stream."""
+    tensor on the current HIP device.  Work goes on `stream` if given, else
+    on a new torch stream of default priority owned by the Stepper."""
 
     def __init__(self, instances, precision=TK_FP64, force_dt=False, wave_capacity=0,
                  stream=None, device=None):
@@ -182,7 +198,7 @@ class Stepper:
         descs = (InstanceDesc * self.n_inst)(*[make_desc(i, force_dt, wave_capacity)
                                                for i in self.instances])
         with torch.cuda.device(self.device):
-            self.stream = stream if stream is not None else torch.cuda.current_stream()
+            self.stream = stream if stream is not None else torch.cuda.Stream()
         ctx = ctypes.c_void_p()
         _check(lib.tk_init_grid(descs, self.n_inst, precision, ctypes.c_void_p(self.stream.cuda_stream),
                                 ctypes.byref(ctx)))
@@ -192,6 +208,9 @@ class Stepper:
         _check(lib.tk_workspace_bytes(ctx, ctypes.byref(nbytes)), ctx)
         self.workspace_bytes = nbytes.value
         self.workspace = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=self.device)
+        # the tensor is allocated on torch's current stream and used on self.stream
+        torch.cuda.current_stream(self.device).synchronize()
+        self.workspace.record_stream(self.stream)
         _check(lib.tk_bind_workspace(ctx, ctypes.c_void_p(self.workspace.data_ptr()), nbytes.value), ctx)
         for k, inst in enumerate(self.instances):
             if inst.get("source") is not None:
@@ -232,6 +251,17 @@ class Stepper:
     def step(self, n):
         _check(self.lib.tk_step(self.ctx, int(n)), self.ctx)
 
+    def prepare(self, n):
+        """Host-side work of a later step(n) done now: work list, and the HIP
+        graph if graph_steps > 0 and n >= graph_steps."""
+        _check(self.lib.tk_prepare(self.ctx, int(n)), self.ctx)
+
+    def counters(self):
+        c = Counters()
+        _check(self.lib.tk_get_counters(self.ctx, ctypes.byref(c)), self.ctx)
+        return dict(graphs_instantiated=c.graphs_instantiated, graph_launches=c.graph_launches,
+                    eager_launches=c.eager_launches)
+
     def extract(self, k, max_samples=1 << 20):
         nth = self.instances[k]["n_theta"]
         n = ctypes.c_long()
@@ -270,7 +300,16 @@ class Stepper:
         (ms per step of the winner, shapes tried)."""
         ms = ctypes.c_double()
         n = ctypes.c_int()
-        _check(self.lib.tk_autotune(self.ctx, int(warmup), int(steps), ctypes.byref(ms), ctypes.byref(n)), self.ctx)
+        nbytes = ctypes.c_size_t()
+        _check(self.lib.tk_autotune_bytes(self.ctx, ctypes.byref(nbytes)), self.ctx)
+        torch = self.torch
+        save = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=self.device)
+        torch.cuda.current_stream(self.device).synchronize()
+        try:
+            _check(self.lib.tk_autotune(self.ctx, int(warmup), int(steps), ctypes.c_void_p(save.data_ptr()),
+                                        nbytes.value, ctypes.byref(ms), ctypes.byref(n)), self.ctx)
+        finally:
+            del save  # tk_autotune is synchronous: the area is free again
         return ms.value, n.value
 
     def synchronize(self):

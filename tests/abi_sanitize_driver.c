@@ -93,6 +93,14 @@ int main(void)
         CHECK(tk_set_tuning(ctx, &t) == TK_E_INVALID);
         t.kernel = 9;
         CHECK(tk_set_tuning(ctx, &t) == TK_E_INVALID);
+        /* the NULL stream cannot be captured: no graphs on it */
+        t.kernel = TK_KERNEL_FUSED2;
+        t.rows_per_tile = 0;
+        t.graph_steps = 10;
+        CHECK(tk_set_tuning(ctx, &t) == TK_E_INVALID);
+        t.kernel = TK_KERNEL_TILED;
+        t.rows_per_tile = 8;
+        t.graph_steps = 0;
         tk_tuning got;
         CHECK(tk_get_tuning(ctx, &got) == TK_OK && got.kernel == TK_KERNEL_TILED && got.rows_per_tile == 8);
         /* calls that need the workspace */
@@ -100,7 +108,13 @@ int main(void)
         double buf[64];
         long n = -1;
         CHECK(tk_extract(ctx, 0, buf, 1, &n) == TK_E_STATE);
-        CHECK(tk_autotune(ctx, 1, 1, NULL, NULL) == TK_E_STATE);
+        CHECK(tk_autotune(ctx, 1, 1, NULL, 0, NULL, NULL) == TK_E_STATE);
+        CHECK(tk_prepare(ctx, 10) == TK_E_STATE);
+        size_t save_bytes = 0;
+        CHECK(tk_autotune_bytes(ctx, &save_bytes) == TK_OK && save_bytes > 0);
+        tk_counters cnt;
+        CHECK(tk_get_counters(ctx, &cnt) == TK_OK && cnt.graphs_instantiated == 0 && cnt.graph_launches == 0 &&
+              cnt.eager_launches == 0);
         CHECK(tk_get_fields(ctx, 0, buf, buf) == TK_E_STATE);
         tk_source_desc src;
         memset(&src, 0, sizeof src);

@@ -25,7 +25,7 @@ def test_library_exports_every_declared_symbol():
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(tk.EXPORTS)
-    assert lib.tk_abi_version() == 3
+    assert lib.tk_abi_version() == tk.ABI_VERSION == 4
 
 
 def test_struct_layout_matches_header():
@@ -70,7 +70,7 @@ def test_unstable_dt_rejected_unless_forced():
     assert lib.tk_workspace_bytes(ctx, ctypes.byref(n)) == tk.TK_OK and n.value > 801 * 33 * 64
     # stepping (or tuning) without a bound workspace is a state error, not a crash
     assert lib.tk_step(ctx, 1) == tk.TK_E_STATE
-    assert lib.tk_autotune(ctx, 2, 4, None, None) == tk.TK_E_STATE
+    assert lib.tk_autotune(ctx, 2, 4, None, 0, None, None) == tk.TK_E_STATE
     assert lib.tk_destroy(ctx) == tk.TK_OK
 
 
@@ -99,20 +99,25 @@ def test_tuning_validation():
                 tk.Tuning(tk.TK_KERNEL_TILED, 0, 0, 3, 1, 0), tk.Tuning(tk.TK_KERNEL_TILED, 6, 0, 3, 1, 0),
                 tk.Tuning(5, 0, 0, 3, 1, 0)):
         assert lib.tk_set_tuning(ctx, ctypes.byref(bad)) == tk.TK_E_INVALID
-    ok = tk.Tuning(tk.TK_KERNEL_TWO_PASS, 8, 50, 1, tk.TK_TUNE_NT_STORES, 0)
+    # this context is on the NULL stream, which cannot be captured: graphs are refused there
+    for kern in (tk.TK_KERNEL_TWO_PASS, tk.TK_KERNEL_FUSED, tk.TK_KERNEL_FUSED2):
+        bad = tk.Tuning(kern, 0, 50, 1, tk.TK_TUNE_NT_STORES, 0)
+        assert lib.tk_set_tuning(ctx, ctypes.byref(bad)) == tk.TK_E_INVALID
+        assert b"NULL stream" in lib.tk_last_error(ctx)
+    ok = tk.Tuning(tk.TK_KERNEL_TWO_PASS, 8, 0, 1, tk.TK_TUNE_NT_STORES, 0)
     assert lib.tk_set_tuning(ctx, ctypes.byref(ok)) == tk.TK_OK
     got = tk.Tuning()
     assert lib.tk_get_tuning(ctx, ctypes.byref(got)) == tk.TK_OK
-    assert (got.kernel, got.rows_per_tile, got.graph_steps, got.prefetch_rows, got.flags) == (1, 8, 50, 1, 1)
+    assert (got.kernel, got.rows_per_tile, got.graph_steps, got.prefetch_rows, got.flags) == (1, 8, 0, 1, 1)
     ok = tk.Tuning(tk.TK_KERNEL_FUSED, 0, 0, 3, 0, 0)
     assert lib.tk_set_tuning(ctx, ctypes.byref(ok)) == tk.TK_OK
-    ok = tk.Tuning(tk.TK_KERNEL_FUSED2, 0, 100, 1, tk.TK_TUNE_NT_STORES, 0)
+    ok = tk.Tuning(tk.TK_KERNEL_FUSED2, 0, 0, 1, tk.TK_TUNE_NT_STORES, 0)
     assert lib.tk_set_tuning(ctx, ctypes.byref(ok)) == tk.TK_OK
     for rows in (4, 8):
-        ok = tk.Tuning(tk.TK_KERNEL_TILED, rows, 100, 3, 0, 0)
+        ok = tk.Tuning(tk.TK_KERNEL_TILED, rows, 0, 3, 0, 0)
         assert lib.tk_set_tuning(ctx, ctypes.byref(ok)) == tk.TK_OK
     for rows in (4, 16):
-        ok = tk.Tuning(tk.TK_KERNEL_FUSED2, rows, 100, 1, 0, 0)
+        ok = tk.Tuning(tk.TK_KERNEL_FUSED2, rows, 0, 1, 0, 0)
         assert lib.tk_set_tuning(ctx, ctypes.byref(ok)) == tk.TK_OK
     lib.tk_destroy(ctx)
 

@@ -60,7 +60,7 @@ def check(inst, steps, got, ref):
 
 
 def gpu_run(insts, steps, graph=0, chunks=None, rows=0, autotune=False, kernel=tk.TK_KERNEL_AUTO,
-            precision=tk.TK_FP64):
+            precision=tk.TK_FP64, counters=None):
     st = tk.Stepper(insts, force_dt=False, precision=precision)
     st.set_tuning(kernel=kernel, graph_steps=graph, rows_per_tile=rows)
     for k, inst in enumerate(insts):
@@ -71,6 +71,8 @@ def gpu_run(insts, steps, graph=0, chunks=None, rows=0, autotune=False, kernel=t
     for n in (chunks or [steps]):
         st.step(n)
     out = [st.get_fields(k) + (st.extract(k),) for k in range(len(insts))]
+    if counters is not None:
+        counters.update(st.counters())
     st.close()
     return out
 
@@ -108,7 +110,9 @@ def test_layer_small_grids_vs_oracle():
 def test_layer_graph_and_chunks_bitwise():
     insts = layered_instances()[:3]
     a = gpu_run(insts, 250)
-    b = gpu_run(insts, 250, graph=40, chunks=[7, 120, 123])
+    cnt = {}
+    b = gpu_run(insts, 250, graph=40, chunks=[7, 120, 123], counters=cnt)
+    assert cnt["graphs_instantiated"] == 1 and cnt["graph_launches"] == 6, cnt  # 3 + 3 replays of 40 steps
     for x, y in zip(a, b):
         for u, v in zip(x, y):
             assert np.array_equal(u, v)

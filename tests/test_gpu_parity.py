@@ -74,8 +74,9 @@ def check_parity(inst, steps, got, ref, phi0=None, pi0=None):
 
 
 def gpu_run(insts, steps, kernel=tk.TK_KERNEL_AUTO, rows=0, graph=0, inits=None, chunks=None,
-            prefetch=0, nt=True, waves=0, precision=tk.TK_FP64):
+            prefetch=0, nt=True, waves=0, precision=tk.TK_FP64, counters=None):
     st = tk.Stepper(insts, force_dt=True, precision=precision)
+    assert st.stream.cuda_stream != 0  # a capturable stream of the Stepper's own
     st.set_tuning(kernel=kernel, rows_per_tile=rows, graph_steps=graph, prefetch_rows=prefetch, nt_stores=nt,
                   waves_per_simd=waves)
     for k, inst in enumerate(insts):
@@ -83,8 +84,65 @@ def gpu_run(insts, steps, kernel=tk.TK_KERNEL_AUTO, rows=0, graph=0, inits=None,
         st.set_fields(k, phi0, pi0)
     for n in (chunks or [steps]):
         st.step(n)
-    out = [st.get_fields(k) + (st.extract(k),) for k in range(len(insts))]
+    out = [st.get_fields(k) + (st.extract(k, max_samples=4096),) for k in range(len(insts))]
+    if counters is not None:
+        counters.update(st.counters())
     st.close()
+    return out
+
+
+def expect_graph_replays(cnt, steps_chunks, G):
+    """The counters of a run stepped in `steps_chunks` with graph_steps G: one
+    graph instantiated, one replay per whole block of G inside each call."""
+    replays = sum(n // G for n in steps_chunks) if G > 0 else 0
+    assert cnt["graph_launches"] == replays, (cnt, replays)
+    assert cnt["graphs_instantiated"] == (1 if replays else 0), cnt
+
+
+def source_window(inst):
+    """Rows and columns of the particle source's window (6 sigma of the
+    two-cell Gaussian around the particle), or None without a source."""
+    src = inst.get("source")
+    if not src:
+        return None
+    M, a = inst["M"], inst["a"]
+    rp = M + np.sqrt(M * M - a * a)
+    rsp = oracle.tortoise(M, a, src["r0"] - rp)
+    h = (inst["rstar_max"] - inst["rstar_min"]) / (inst["n_r"] - 1)
+    dth = np.pi / (inst["n_theta"] - 1)
+    rs = inst["rstar_min"] + h * np.arange(inst["n_r"])
+    th = dth * np.arange(inst["n_theta"])
+    wr = src.get("window_sigmas", 6.0) * src.get("sigma_r_cells", 2.0) * h
+    wt = src.get("window_sigmas", 6.0) * src.get("sigma_th_cells", 2.0) * dth
+    cols = np.nonzero(np.abs(rs - rsp) <= wr + h)[0]
+    rows = np.nonzero(np.abs(th - np.pi / 2) <= wt + dth)[0]
+    return rows, cols
+
+
+def check_local(inst, got, ref, bar=TOL):
+    """Element-wise bar where the solution is most delicate: the source
+    window and the rows at and next to the poles.  Each region's largest
+    pointwise difference over its largest reference value, per field; a
+    region whose reference is exactly zero (odd m + s poles) must be exactly
+    zero too."""
+    nt = inst["n_theta"]
+    regions = {"poles": (np.array([0, 1, nt - 2, nt - 1]), np.arange(inst["n_r"]))}
+    win = source_window(inst)
+    if win is not None:
+        regions["source"] = win
+    out = {}
+    for name, (rows, cols) in regions.items():
+        for f, (g, r) in {"phi": (got[0], ref[0]), "pi": (got[1], ref[1])}.items():
+            gs, rs_ = g[np.ix_(rows, cols)], r[np.ix_(rows, cols)]
+            scale = np.abs(rs_).max()
+            if scale == 0.0:
+                assert np.all(gs == 0.0), (inst.get("name"), name, f)
+                out[f"{name}.{f}"] = 0.0
+                continue
+            e = float(np.abs(gs - rs_).max() / scale)
+            out[f"{name}.{f}"] = e
+            assert e <= bar, (inst.get("name"), name, f, e)
+    say("  local max-relative:", {k: f"{v:.2e}" for k, v in out.items()})
     return out
 
 
@@ -129,46 +187,72 @@ def test_first_workload_full_run():
     check_parity(inst, steps, got, oracle_run(inst, steps))
 
 
+@pytest.mark.timeout(900)
 def test_second_workload_prefix():
+    # 8001 x 129, a = 0.9: 3000 steps (10M) in graph replays of 100 steps
     inst = W.config2()["instances"][0]
-    steps = 300
+    steps = 3000
     say("second workload 8001x129, a=0.9, steps", steps)
-    got, = gpu_run([inst], steps, graph=100)
-    check_parity(inst, steps, got, oracle_run(inst, steps))
+    cnt = {}
+    got, = gpu_run([inst], steps, graph=100, counters=cnt)
+    expect_graph_replays(cnt, [steps], 100)
+    ref = oracle_run(inst, steps)
+    check_parity(inst, steps, got, ref)
+    check_local(inst, got, ref)
 
 
+@pytest.mark.timeout(900)
 def test_third_workload_sourced_prefix():
+    # 16001 x 257, sourced: 2000 steps (2.9M), long enough for the field to
+    # fill the source's neighbourhood; graph replays of 100 steps
     inst = W.config3()["instances"][0]
-    steps = 40
+    steps = 2000
     say("third workload 16001x257 sourced, steps", steps)
-    got, = gpu_run([inst], steps)
+    cnt = {}
+    got, = gpu_run([inst], steps, graph=100, counters=cnt)
+    expect_graph_replays(cnt, [steps], 100)
     ref = oracle_run(inst, steps)
     assert np.linalg.norm(ref[0]) > 0
     check_parity(inst, steps, got, ref)
+    check_local(inst, got, ref)
 
 
+@pytest.mark.timeout(900)
 def test_fifth_workload_prefix():
-    # 16001 x 129, sourced, at the size and launch shape of the precision study
+    # 16001 x 129, sourced, at the size and launch shape of the precision
+    # study: 2000 steps (4M) in both precisions against the oracle
     inst = W.config5()["instances"][0]
-    steps = 200
+    steps = 2000
     say("fifth workload 16001x129 sourced, steps", steps)
     got, = gpu_run([inst], steps, graph=100)
     ref = oracle_run(inst, steps)
     check_parity(inst, steps, got, ref)
+    check_local(inst, got, ref)
     c, = gpu_run([inst], steps, graph=100, precision=tk.TK_FP32_COMP)
     e = joint_rel(c[0], c[1], ref[0], ref[1])
     say("  FP32C joint rel L2 vs oracle", f"{e:.2e}")
     assert e < 1e-5
+    # FP32C in the source window: the increment there is accumulated in FP64
+    loc = check_local(inst, c, ref, bar=1e-4)
+    say("  FP32C local", loc)
 
 
+@pytest.mark.timeout(1200)
 def test_batched_uneven_workload_vs_oracle():
+    # the benchmark's path: 40 uneven instances, the AUTO kernel (two steps
+    # per pass over whole strips), 200 steps in graph replays of 100 steps
     insts = W.config4()["instances"]
-    steps = 6
+    steps = 200
     say("batched 40 instances, steps", steps, "points", W.points(insts))
-    res = gpu_run(insts, steps, graph=3)
+    cnt = {}
+    res = gpu_run(insts, steps, graph=100, counters=cnt)
+    expect_graph_replays(cnt, [steps], 100)
+    assert cnt["eager_launches"] == 0
     worst = 0.0
     for inst, got in zip(insts, res):
-        e = check_parity(inst, steps, got, oracle_run(inst, steps))
+        ref = oracle_run(inst, steps)
+        e = check_parity(inst, steps, got, ref)
+        check_local(inst, got, ref)
         worst = max(worst, e["joint"])
     say("worst joint rel L2", worst)
 
@@ -237,8 +321,12 @@ def test_graph_replay_equals_eager_bitwise(kernel, G, rows):
     # an odd block size ends each replay with a one-step launch and flips the
     # state buffer an odd number of times per replay
     insts = small_instances()
-    eager = gpu_run(insts, 70, kernel=kernel, rows=rows, graph=0)
-    graph = gpu_run(insts, 70, kernel=kernel, rows=rows, graph=G, chunks=[25, 20, 5, 20])
+    c_eager, c_graph = {}, {}
+    eager = gpu_run(insts, 70, kernel=kernel, rows=rows, graph=0, counters=c_eager)
+    chunks = [25, 20, 5, 20]
+    graph = gpu_run(insts, 70, kernel=kernel, rows=rows, graph=G, chunks=chunks, counters=c_graph)
+    expect_graph_replays(c_eager, [70], 0)
+    expect_graph_replays(c_graph, chunks, G)  # the replays really ran
     for (a, b) in zip(eager, graph):
         assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
 
