@@ -35,9 +35,13 @@ struct LCoef {
 
 // Coefficients of the layer system at one point from the radial record R
 // (held in registers for a whole march), the row's angular record A and the
-// position's map factors L (nullptr outside a layered instance).  1/sqrt is
+// position's map factors L, read from the table in global memory where they
+// are used (nullptr outside a layered instance).  The pointer goes to the
+// table itself, not to a local copy: a pointer selected between a local
+// record and null keeps the record in scratch memory, and a copy held in
+// registers for the whole march costs the kernel its second wave.  1/sqrt is
 // the hardware estimate refined by Newton steps, as in the fused kernels.
-__device__ __forceinline__ LCoef lcoef_of(const Radial &R, const Angular &A, const LayerTab *L)
+__device__ __forceinline__ LCoef lcoef_of(const Radial &R, const Angular &A, const TK_GLOBAL LayerTab *L)
 {
     const double Sh2 = R.rho2 - R.a2D * A.sn2;
     const double sig = inv_sqrt(Sh2);  // 1 / Sigma-hat
@@ -125,9 +129,7 @@ __global__ void __launch_bounds__(256) k_layer_half(const DevInst *__restrict__ 
     const int nt = I.n_theta;
     const int q = 2 * i + 1;
     const Radial R = load_entry(gload_ptr(I.rad) + q);
-    LayerTab Lq;
-    if (tab) Lq = load_entry(gload_ptr(tab) + q);
-    const LayerTab *L = tab ? &Lq : nullptr;
+    const TK_GLOBAL LayerTab *L = tab ? gload_ptr(tab) + q : nullptr;
     double4 *hf = (double4 *)I.half;
     const int jb = it.j0 > 1 ? it.j0 : 1, je = it.j1 < nt - 1 ? it.j1 : nt - 1;
     P4 m0 = ld_p4(row_ptr(I.u[b], I, jb - 1) + i), m1 = ld_p4(row_ptr(I.u[b], I, jb - 1) + i + 1);
@@ -189,9 +191,7 @@ __global__ void __launch_bounds__(256) k_layer_full(const DevInst *__restrict__ 
     const cd e = source_phase(I, t);
     const int q = 2 * i;
     const Radial R = load_entry(gload_ptr(I.rad) + q);
-    LayerTab Lq;
-    if (tab) Lq = load_entry(gload_ptr(tab) + q);
-    const LayerTab *L = tab ? &Lq : nullptr;
+    const TK_GLOBAL LayerTab *L = tab ? gload_ptr(tab) + q : nullptr;
     const int jb = it.j0 > 1 ? it.j0 : 1, je = it.j1 < nt - 1 ? it.j1 : nt - 1;
     P4 m0 = ld_p4(row_ptr(I.half, I, jb - 1) + i - 1), m1 = ld_p4(row_ptr(I.half, I, jb - 1) + i);
     P4 c0 = ld_p4(row_ptr(I.half, I, jb) + i - 1), c1 = ld_p4(row_ptr(I.half, I, jb) + i);
@@ -341,12 +341,8 @@ __global__ void __launch_bounds__(256) k_layer_fused(const DevInst *__restrict__
     const cd e1 = source_phase(I, t1), e2 = source_phase(I, t2);
     const Radial Rh = load_entry(gload_ptr(I.rad) + (2 * ih + 1));
     const Radial Rn = load_entry(gload_ptr(I.rad) + (2 * in));
-    LayerTab Lh, Ln;
-    if (tab) {
-        Lh = load_entry(gload_ptr(tab) + (2 * ih + 1));
-        Ln = load_entry(gload_ptr(tab) + (2 * in));
-    }
-    const LayerTab *pLh = tab ? &Lh : nullptr, *pLn = tab ? &Ln : nullptr;
+    const TK_GLOBAL LayerTab *Lh = tab ? gload_ptr(tab) + (2 * ih + 1) : nullptr;
+    const TK_GLOBAL LayerTab *Ln = tab ? gload_ptr(tab) + (2 * in) : nullptr;
     const bool sampling = (interior || edge) && i == I.i_obs && I.extract_every > 0 &&
                           (n + 1) % I.extract_every == 0;
     TK_GLOBAL double *wv = nullptr;
@@ -358,7 +354,7 @@ __global__ void __launch_bounds__(256) k_layer_fused(const DevInst *__restrict__
     // Eq. (3) at half node i + 1/2, row j (1 <= j <= nt - 2), from u^n rows j-1, j, j+1 of columns i, i+1
     auto half = [&](const P4 &m0, const P4 &m1, const P4 &c0, const P4 &c1, const P4 &p0, const P4 &p1, int j) {
         const Angular A = angular_row(I, j);
-        const LCoef c = lcoef_of(Rh, A, pLh);
+        const LCoef c = lcoef_of(Rh, A, Lh);
         const P4 bar = half_sum(c1, c0);
         return lw_layer(c, bar, half_sum(m1, m0).phi, bar.phi, half_sum(p1, p0).phi, bar.pi, c1 - c0, 0.5 * I.dt, I,
                         source_of(I, Rh.srcg, A, e1));
@@ -403,7 +399,7 @@ __global__ void __launch_bounds__(256) k_layer_fused(const DevInst *__restrict__
         const P4 HpL = left(Hp);
         // Eq. (4) at node in, row j (u^n at the own column: in = i for the lanes that store)
         const Angular A = angular_row(I, j);
-        const LCoef c = lcoef_of(Rn, A, pLn);
+        const LCoef c = lcoef_of(Rn, A, Ln);
         const P4 til = half_sum(H0, H0L);
         P4 out = lw_layer(c, Ua0, half_sum(Hm, HmL).phi, til.phi, half_sum(Hp, HpL).phi, til.pi, H0 - H0L, I.dt, I,
                           source_of(I, Rn.srcg, A, e2));

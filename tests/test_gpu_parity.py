@@ -119,12 +119,13 @@ def source_window(inst):
     return rows, cols
 
 
-def check_local(inst, got, ref, bar=TOL):
+def check_local(inst, got, ref, bar=TOL, global_scale=()):
     """Element-wise bar where the solution is most delicate: the source
     window and the rows at and next to the poles.  Each region's largest
-    pointwise difference over its largest reference value, per field; a
-    region whose reference is exactly zero (odd m + s poles) must be exactly
-    zero too."""
+    pointwise difference over its largest reference value, per field (over
+    the field's largest value anywhere for the regions named in
+    global_scale); a region whose reference is exactly zero (odd m + s
+    poles) must be exactly zero too."""
     nt = inst["n_theta"]
     regions = {"poles": (np.array([0, 1, nt - 2, nt - 1]), np.arange(inst["n_r"]))}
     win = source_window(inst)
@@ -134,7 +135,7 @@ def check_local(inst, got, ref, bar=TOL):
     for name, (rows, cols) in regions.items():
         for f, (g, r) in {"phi": (got[0], ref[0]), "pi": (got[1], ref[1])}.items():
             gs, rs_ = g[np.ix_(rows, cols)], r[np.ix_(rows, cols)]
-            scale = np.abs(rs_).max()
+            scale = np.abs(r).max() if name in global_scale else np.abs(rs_).max()
             if scale == 0.0:
                 assert np.all(gs == 0.0), (inst.get("name"), name, f)
                 out[f"{name}.{f}"] = 0.0
@@ -232,8 +233,11 @@ def test_fifth_workload_prefix():
     e = joint_rel(c[0], c[1], ref[0], ref[1])
     say("  FP32C joint rel L2 vs oracle", f"{e:.2e}")
     assert e < 1e-5
-    # FP32C in the source window: the increment there is accumulated in FP64
-    loc = check_local(inst, c, ref, bar=1e-4)
+    # FP32C in the source window, where the increment is accumulated in FP64,
+    # to 1e-4 of the window's values; at the poles, where the field is still
+    # tiny after 4M, FP32 rounding is relative to the whole field, so there
+    # to 1e-4 of the largest value anywhere
+    loc = check_local(inst, c, ref, bar=1e-4, global_scale=("poles",))
     say("  FP32C local", loc)
 
 
