@@ -119,21 +119,28 @@ def source_window(inst):
     return rows, cols
 
 
-def check_local(inst, got, ref, bar=TOL, global_scale=()):
+def check_local(inst, steps, got, ref, bar=TOL, global_scale=()):
     """Element-wise bar where the solution is most delicate: the source
     window and the rows at and next to the poles.  Each region's largest
     pointwise difference over its largest reference value, per field (over
     the field's largest value anywhere for the regions named in
     global_scale); a region whose reference is exactly zero (odd m + s
-    poles) must be exactly zero too."""
+    poles) must be exactly zero too.  With the FP64 bar, a region that misses
+    it is held to max(bar, 4 e_ld) instead, e_ld being the FP64 oracle's own
+    distance to its long-double build in that region: where a region's
+    values are orders of magnitude below the rest of the field (the poles of
+    a high-m mode), rounding at the scale of the whole field sets the floor,
+    whatever the evaluation order."""
     nt = inst["n_theta"]
     regions = {"poles": (np.array([0, 1, nt - 2, nt - 1]), np.arange(inst["n_r"]))}
     win = source_window(inst)
     if win is not None:
         regions["source"] = win
     out = {}
+    lref = []
     for name, (rows, cols) in regions.items():
-        for f, (g, r) in {"phi": (got[0], ref[0]), "pi": (got[1], ref[1])}.items():
+        for k, f in ((0, "phi"), (1, "pi")):
+            g, r = got[k], ref[k]
             gs, rs_ = g[np.ix_(rows, cols)], r[np.ix_(rows, cols)]
             scale = np.abs(r).max() if name in global_scale else np.abs(rs_).max()
             if scale == 0.0:
@@ -142,7 +149,15 @@ def check_local(inst, got, ref, bar=TOL, global_scale=()):
                 continue
             e = float(np.abs(gs - rs_).max() / scale)
             out[f"{name}.{f}"] = e
-            assert e <= bar, (inst.get("name"), name, f, e)
+            if e > bar and bar == TOL:
+                if not lref:
+                    lref.append(oracle_run(inst, steps, kind="ld"))
+                ls = lref[0][k][np.ix_(rows, cols)]
+                floor = float(np.abs(rs_ - ls).max() / scale)
+                say(f"  {name}.{f}: {e:.2e} against the oracle's long-double distance {floor:.2e}")
+                assert e <= max(bar, 4 * floor), (inst.get("name"), name, f, e, floor)
+            else:
+                assert e <= bar, (inst.get("name"), name, f, e)
     say("  local max-relative:", {k: f"{v:.2e}" for k, v in out.items()})
     return out
 
@@ -199,7 +214,7 @@ def test_second_workload_prefix():
     expect_graph_replays(cnt, [steps], 100)
     ref = oracle_run(inst, steps)
     check_parity(inst, steps, got, ref)
-    check_local(inst, got, ref)
+    check_local(inst, steps, got, ref)
 
 
 @pytest.mark.timeout(900)
@@ -215,7 +230,7 @@ def test_third_workload_sourced_prefix():
     ref = oracle_run(inst, steps)
     assert np.linalg.norm(ref[0]) > 0
     check_parity(inst, steps, got, ref)
-    check_local(inst, got, ref)
+    check_local(inst, steps, got, ref)
 
 
 @pytest.mark.timeout(900)
@@ -228,7 +243,7 @@ def test_fifth_workload_prefix():
     got, = gpu_run([inst], steps, graph=100)
     ref = oracle_run(inst, steps)
     check_parity(inst, steps, got, ref)
-    check_local(inst, got, ref)
+    check_local(inst, steps, got, ref)
     c, = gpu_run([inst], steps, graph=100, precision=tk.TK_FP32_COMP)
     e = joint_rel(c[0], c[1], ref[0], ref[1])
     say("  FP32C joint rel L2 vs oracle", f"{e:.2e}")
@@ -237,7 +252,7 @@ def test_fifth_workload_prefix():
     # to 1e-4 of the window's values; at the poles, where the field is still
     # tiny after 4M, FP32 rounding is relative to the whole field, so there
     # to 1e-4 of the largest value anywhere
-    loc = check_local(inst, c, ref, bar=1e-4, global_scale=("poles",))
+    loc = check_local(inst, steps, c, ref, bar=1e-4, global_scale=("poles",))
     say("  FP32C local", loc)
 
 
@@ -256,7 +271,7 @@ def test_batched_uneven_workload_vs_oracle():
     for inst, got in zip(insts, res):
         ref = oracle_run(inst, steps)
         e = check_parity(inst, steps, got, ref)
-        check_local(inst, got, ref)
+        check_local(inst, steps, got, ref)
         worst = max(worst, e["joint"])
     say("worst joint rel L2", worst)
 
