@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define TK_ABI_VERSION 4
+#define TK_ABI_VERSION 5
 
 typedef struct tk_ctx tk_ctx;
 
@@ -289,6 +289,24 @@ tk_status tk_get_tuning(const tk_ctx *ctx, tk_tuning *t);
 tk_status tk_autotune_bytes(const tk_ctx *ctx, size_t *bytes);
 tk_status tk_autotune(tk_ctx *ctx, int warmup, int steps, void *save_area, size_t save_bytes,
                       double *best_ms_per_step, int *n_tried);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture elsewhere in the process, tight serving loops, harnesses that
+ * forbid allocation): tk_autotune with its save area taken from a static
+ * scratch array inside the library instead of from the caller.  The array
+ * holds TK_AUTOTUNE_STATIC_MAX_BYTES (64 MiB) on each GPU the library runs
+ * on, from the first call on that GPU until the process ends; its address on
+ * the context's device is looked up on that first call.  A context whose
+ * tk_autotune_bytes exceeds it gets TK_E_NOMEM (nothing changed; use
+ * tk_autotune with a caller save area).  The call allocates no device memory
+ * and frees none.  Every call on one GPU shares that GPU's array, whose
+ * contents are overwritten before they are read; calls from one process are
+ * serialised, and calls from different processes have arrays of their own,
+ * so overlapping calls do not mix their saves, but they do time their
+ * candidates against each other.  Arguments, results and the restored
+ * simulation are those of tk_autotune. */
+#define TK_AUTOTUNE_STATIC_MAX_BYTES ((size_t)64 << 20)
+tk_status tk_autotune_static(tk_ctx *ctx, int warmup, int steps, double *best_ms_per_step, int *n_tried);
 
 /* Wait for all work enqueued by the context. */
 tk_status tk_synchronize(tk_ctx *ctx);

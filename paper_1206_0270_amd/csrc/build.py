@@ -24,7 +24,7 @@ BUILD = os.path.join(ROOT, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-HIP_SOURCES = ["tk_kernels.hip", "tk_layer.hip"]
+HIP_SOURCES = ["tk_kernels.hip", "tk_layer.hip", "tk_scratch.hip"]
 HOST_SOURCES = ["tk_setup.cpp", "tk_api.cpp", "tk_post.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wextra", "-Wno-unused-parameter",

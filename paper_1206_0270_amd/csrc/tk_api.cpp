@@ -14,6 +14,7 @@
 #include "tk_internal.h"
 #include "tk_kernels.h"
 #include "tk_layer_launch.h"
+#include "tk_scratch.h"
 
 using namespace tk;
 
@@ -52,6 +53,8 @@ struct tk_ctx {
     hipGraphExec_t gexec = nullptr;
     int g_steps = 0, g_flips = 0, g_kernel = -1, g_rows = -1, g_pf = -1, g_flags = -1, g_waves = -1;
     tk_counters counters{0, 0, 0};
+    // the autotuner's timing events, created with the workspace binding
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
 };
 
 namespace {
@@ -542,6 +545,9 @@ tk_status tk_bind_workspace(tk_ctx *c, void *dev_ptr, size_t bytes)
     hipPointerAttribute_t attr;
     if (hipPointerGetAttributes(&attr, dev_ptr) != hipSuccess || attr.type != hipMemoryTypeDevice)
         return fail(c, TK_E_INVALID, "workspace is not device memory");
+    if (!c->ev0) TK_HIP(c, hipEventCreate(&c->ev0));
+    if (!c->ev1) TK_HIP(c, hipEventCreate(&c->ev1));
+    c->device = attr.device;
     c->ws = (char *)dev_ptr;
     c->ws_bytes = bytes;
     tk_status st = TK_OK;
@@ -981,36 +987,20 @@ tk_status tk_autotune_bytes(const tk_ctx *c, size_t *bytes)
     return TK_OK;
 }
 
-tk_status tk_autotune(tk_ctx *c, int warmup, int steps, void *save_area, size_t save_bytes,
-                      double *best_ms_per_step, int *n_tried)
+// Time every candidate launch shape on the context's own instances and keep
+// the fastest; the state, step counter and waveform rings are saved to `save`
+// (device memory of at least the spans' total) and restored afterwards.
+static tk_status autotune_run(tk_ctx *c, int warmup, int steps, char *save, const std::vector<SaveSpan> &spans,
+                              double *best_ms_per_step, int *n_tried)
 {
-    if (!c) return TK_E_INVALID;
-    if (!c->ws) return fail(c, TK_E_STATE, "no workspace bound");
-    if (warmup < 0 || warmup > 100000 || steps < 1 || steps > 100000)
-        return fail(c, TK_E_INVALID, "warmup must be in [0, 1e5] and steps in [1, 1e5]");
-    size_t total = 0;
-    const std::vector<SaveSpan> spans = autotune_spans(c, &total);
-    if (!save_area) return fail(c, TK_E_INVALID, "autotune: null save area");
-    if ((uintptr_t)save_area % 256 != 0) return fail(c, TK_E_INVALID, "autotune: save area must be 256-byte aligned");
-    if (save_bytes < total) return fail(c, TK_E_NOMEM, "autotune: save area smaller than tk_autotune_bytes");
-    {
-        hipPointerAttribute_t attr;
-        if (hipPointerGetAttributes(&attr, save_area) != hipSuccess || attr.type != hipMemoryTypeDevice) {
-            (void)hipGetLastError();
-            return fail(c, TK_E_INVALID, "autotune: save area is not device memory");
-        }
-    }
     warmup += warmup & 1;
     steps += steps & 1;
     TK_HIP(c, hipStreamSynchronize(c->stream));
-    char *save = (char *)save_area;
     hipError_t e = hipSuccess;
     for (const SaveSpan &sp : spans)
         if (e == hipSuccess)
             e = hipMemcpyAsync(save + sp.save, c->ws + sp.off, sp.bytes, hipMemcpyDeviceToDevice, c->stream);
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (e == hipSuccess) e = hipEventCreate(&e0);
-    if (e == hipSuccess) e = hipEventCreate(&e1);
+    hipEvent_t e0 = c->ev0, e1 = c->ev1;
 
     const tk_tuning keep = c->tuning;
     const long long step0 = c->step;
@@ -1070,8 +1060,6 @@ tk_status tk_autotune(tk_ctx *c, int warmup, int steps, void *save_area, size_t 
         if (er == hipSuccess)
             er = hipMemcpyAsync(c->ws + sp.off, save + sp.save, sp.bytes, hipMemcpyDeviceToDevice, c->stream);
     if (er == hipSuccess) er = hipStreamSynchronize(c->stream);
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
     c->step = step0;
     c->cur = cur0;
     if (er != hipSuccess && st == TK_OK) st = fail(c, TK_E_DEVICE, std::string("autotune restore: ") + hipGetErrorString(er));
@@ -1090,6 +1078,57 @@ tk_status tk_autotune(tk_ctx *c, int warmup, int steps, void *save_area, size_t 
     return TK_OK;
 }
 
+static tk_status autotune_args(tk_ctx *c, int warmup, int steps)
+{
+    if (!c) return TK_E_INVALID;
+    if (!c->ws) return fail(c, TK_E_STATE, "no workspace bound");
+    if (warmup < 0 || warmup > 100000 || steps < 1 || steps > 100000)
+        return fail(c, TK_E_INVALID, "warmup must be in [0, 1e5] and steps in [1, 1e5]");
+    return TK_OK;
+}
+
+tk_status tk_autotune(tk_ctx *c, int warmup, int steps, void *save_area, size_t save_bytes,
+                      double *best_ms_per_step, int *n_tried)
+{
+    tk_status st = autotune_args(c, warmup, steps);
+    if (st != TK_OK) return st;
+    size_t total = 0;
+    const std::vector<SaveSpan> spans = autotune_spans(c, &total);
+    if (!save_area) return fail(c, TK_E_INVALID, "autotune: null save area");
+    if ((uintptr_t)save_area % 256 != 0) return fail(c, TK_E_INVALID, "autotune: save area must be 256-byte aligned");
+    if (save_bytes < total) return fail(c, TK_E_NOMEM, "autotune: save area smaller than tk_autotune_bytes");
+    {
+        hipPointerAttribute_t attr;
+        if (hipPointerGetAttributes(&attr, save_area) != hipSuccess || attr.type != hipMemoryTypeDevice) {
+            (void)hipGetLastError();
+            return fail(c, TK_E_INVALID, "autotune: save area is not device memory");
+        }
+    }
+    return autotune_run(c, warmup, steps, (char *)save_area, spans, best_ms_per_step, n_tried);
+}
+
+tk_status tk_autotune_static(tk_ctx *c, int warmup, int steps, double *best_ms_per_step, int *n_tried)
+{
+    tk_status st = autotune_args(c, warmup, steps);
+    if (st != TK_OK) return st;
+    size_t total = 0;
+    const std::vector<SaveSpan> spans = autotune_spans(c, &total);
+    if (total > kScratchBytes) {
+        char b[256];
+        std::snprintf(b, sizeof b,
+                      "autotune_static: the context's save area needs %zu bytes, more than the %zu bytes of the "
+                      "static scratch area (use tk_autotune with a caller save area)",
+                      total, kScratchBytes);
+        return fail(c, TK_E_NOMEM, b);
+    }
+    static_assert(kScratchBytes == (size_t)TK_AUTOTUNE_STATIC_MAX_BYTES, "the header states the scratch size");
+    std::lock_guard<std::mutex> g(scratch_user_lock());
+    void *area = nullptr;
+    const hipError_t e = scratch_area(c->device, &area);
+    if (e != hipSuccess) return fail(c, TK_E_DEVICE, std::string("autotune_static: scratch area: ") + hipGetErrorString(e));
+    return autotune_run(c, warmup, steps, (char *)area, spans, best_ms_per_step, n_tried);
+}
+
 tk_status tk_synchronize(tk_ctx *c)
 {
     if (!c) return TK_E_INVALID;
@@ -1102,6 +1141,8 @@ tk_status tk_destroy(tk_ctx *c)
     if (!c) return TK_E_INVALID;
     if (c->ws) (void)hipStreamSynchronize(c->stream);
     drop_graph(c);
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
     delete c;
     return TK_OK;
 }

@@ -30,8 +30,10 @@ _STATUS = {0: "TK_OK", 1: "TK_E_INVALID", 2: "TK_E_NOMEM", 3: "TK_E_DEVICE", 4: 
 EXPORTS = ["tk_abi_version", "tk_init_grid", "tk_workspace_bytes", "tk_bind_workspace",
            "tk_set_fields", "tk_get_fields", "tk_set_source", "tk_step", "tk_prepare", "tk_get_counters",
            "tk_extract", "tk_get_step", "tk_set_step", "tk_set_tuning", "tk_get_tuning", "tk_autotune_bytes",
-           "tk_autotune", "tk_synchronize", "tk_destroy", "tk_last_error", "tk_stable_dt", "tk_richardson"]
-ABI_VERSION = 4
+           "tk_autotune", "tk_autotune_static", "tk_synchronize", "tk_destroy", "tk_last_error", "tk_stable_dt",
+           "tk_richardson"]
+ABI_VERSION = 5
+AUTOTUNE_STATIC_MAX_BYTES = 64 << 20
 
 
 class TkError(RuntimeError):
@@ -106,6 +108,7 @@ def load():
         "tk_autotune_bytes": (st, [vp, ctypes.POINTER(ctypes.c_size_t)]),
         "tk_autotune": (st, [vp, ctypes.c_int, ctypes.c_int, vp, ctypes.c_size_t, _dp,
                              ctypes.POINTER(ctypes.c_int)]),
+        "tk_autotune_static": (st, [vp, ctypes.c_int, ctypes.c_int, _dp, ctypes.POINTER(ctypes.c_int)]),
         "tk_synchronize": (st, [vp]),
         "tk_destroy": (st, [vp]),
         "tk_last_error": (ctypes.c_char_p, [vp]),
@@ -310,6 +313,18 @@ class Stepper:
                                         nbytes.value, ctypes.byref(ms), ctypes.byref(n)), self.ctx)
         finally:
             del save  # tk_autotune is synchronous: the area is free again
+        return ms.value, n.value
+
+    def autotune_static(self, warmup=2, steps=10):
+        """autotune() with the library's static scratch area as the save
+        area (no device memory is allocated for the call); TkError with
+        TK_E_NOMEM if the state is larger than that area."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int()
+        torch = self.torch
+        torch.cuda.current_stream(self.device).synchronize()
+        _check(self.lib.tk_autotune_static(self.ctx, int(warmup), int(steps), ctypes.byref(ms), ctypes.byref(n)),
+               self.ctx)
         return ms.value, n.value
 
     def synchronize(self):

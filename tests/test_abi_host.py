@@ -25,7 +25,7 @@ def test_library_exports_every_declared_symbol():
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(tk.EXPORTS)
-    assert lib.tk_abi_version() == tk.ABI_VERSION == 4
+    assert lib.tk_abi_version() == tk.ABI_VERSION == 5
 
 
 def test_struct_layout_matches_header():
