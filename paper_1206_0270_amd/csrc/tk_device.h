@@ -277,6 +277,60 @@ __device__ __forceinline__ Q4<T> bracket_fused(const CoefF<T> &c, cx<T> pm, cx<T
     return br;
 }
 
+// ---------------------------------------------------------------------------
+// Differences form of the same bracket (the FP32-compensated kernels).  The
+// angular part of S_Pi is applied to undivided differences down the theta
+// columns, d2 = X_{j+1} - 2 X_j + X_{j-1} and d1 = X_{j+1} - X_{j-1}, formed
+// from the compensated values before any product and summed over the two
+// columns whose average Eqs. (3)-(4) take:
+//   cthth (d2 Phi_a / dtheta^2 + cot d1 Phi_a / (2 dtheta)) = A2 D2 + A1 D1,
+//   A2 = cthth / (2 dtheta^2), A1 = cthth cot / (4 dtheta),
+// with D2, D1 the sums over the two columns.  In a weighted sum of values
+// the weights are of size cthth / dtheta^2 and the values' rounding enters
+// multiplied by them; here it enters relative to the differences.
+// ---------------------------------------------------------------------------
+
+template <typename T>
+struct CoefD {
+    T bh, A2, A1;
+    cx<T> ct, c0, dh;
+};
+
+template <typename T>
+__device__ __forceinline__ CoefD<T> coef_diff(const RadF<T> &R, const AngF<T> &A)
+{
+    CoefD<T> c;
+    const T Sh2 = fma(-R.D2h, A.sa, R.rho2);
+    const T sig = inv_sqrt(Sh2);
+    const T W = sig * sig;
+    c.bh = R.rho_h * sig;
+    c.A2 = R.D2h * W;
+    c.A1 = c.A2 * A.kc;
+    const T cti = fma(R.D2h, A.kcs, R.ct_im0);
+    c.ct = mkc(W * R.ct_re, W * cti);
+    c.c0 = mkc(W * fma(-R.D2h, A.V2, R.c0_re), W * R.c0_im);
+    // d/h = (b (b' + ct) - c1) / h; b' + Re ct = W (K sin^2 sig + ct_re)
+    const T t = fma(R.K * A.sn2, sig, R.ct_re);
+    c.dh = mkc(W * fma(c.bh, t, -R.c1h_re), W * fma(c.bh, cti, -R.c1h_im));
+    return c;
+}
+
+// Bracket D du / h - S with S_Pi = ct pi0 + c0 ph0 + A2 D2 + A1 D1.
+template <typename T>
+__device__ __forceinline__ Q4<T> bracket_diff(const CoefD<T> &c, cx<T> D2, cx<T> D1, cx<T> ph0, cx<T> pi0,
+                                              const Q4<T> &du)
+{
+    const T sre = fma(c.ct.re, pi0.re,
+                      fma(-c.ct.im, pi0.im, fma(c.c0.re, ph0.re, fma(-c.c0.im, ph0.im, fma(c.A2, D2.re, c.A1 * D1.re)))));
+    const T sim = fma(c.ct.re, pi0.im,
+                      fma(c.ct.im, pi0.re, fma(c.c0.re, ph0.im, fma(c.c0.im, ph0.re, fma(c.A2, D2.im, c.A1 * D1.im)))));
+    Q4<T> br;
+    br.phi = mkc(fma(c.bh, du.phi.re, -pi0.re), fma(c.bh, du.phi.im, -pi0.im));
+    br.pi = mkc(fma(c.dh.re, du.phi.re, fma(-c.dh.im, du.phi.im, fma(-c.bh, du.pi.re, -sre))),
+                fma(c.dh.re, du.phi.im, fma(c.dh.im, du.phi.re, fma(-c.bh, du.pi.im, -sim))));
+    return br;
+}
+
 // base - fac * br
 template <typename T>
 __device__ __forceinline__ Q4<T> lw_update(const Q4<T> &base, T fac, const Q4<T> &br)

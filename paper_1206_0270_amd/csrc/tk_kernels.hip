@@ -7,6 +7,8 @@
 // points: 2 KB per row per access in FP64.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "tk_device.h"
 #include "tk_kernels.h"
 
@@ -471,50 +473,41 @@ __device__ __forceinline__ St<typename P::T> pole_row(bool even, const St<typena
     return o;
 }
 
-// Eq. (3) at half row r: u^n rows r-1 (UM), r (U0), r+1 (UP) of this column
-// and nm, n0, np of the column to the right (Phi only on rows r -+ 1).
+// A half-step value: one number per component in FP64, a compensated pair
+// s + e (both FP32) in the compensated form, so that the rounding of Eq. (3)
+// does not reach the differences Eq. (4) takes of it.
 template <class P>
-__device__ __forceinline__ Q4<typename P::T> half_core(const Lane<P> &L, const Level &lv, const Q4<typename P::T> &UM,
-                                                       const Q4<typename P::T> &U0, const Q4<typename P::T> &UP,
-                                                       cx<typename P::T> nm, const Q4<typename P::T> &n0,
-                                                       cx<typename P::T> np, int r)
+using Half = typename std::conditional<P::kComp, St<typename P::T>, Q4<typename P::T>>::type;
+
+// Pole rows of a half-step row: the pair form in double, split into s + e.
+template <class P>
+__device__ __forceinline__ Half<P> pole_hrow(bool even, const Half<P> &x1, const Half<P> &x2)
 {
     using T = typename P::T;
-    const DevInst &I = *L.I;
-    // lanes without a half node (c = n_r - 1 and off the grid) feed only
-    // out_row lanes that do not update: computing them unmasked (FP64) or
-    // returning zero (FP32C) gives the same stored results
-    if constexpr (P::kMaskHalo)
-        if (!L.hv) return zero_q4<T>();
-    const Q4<T> du = n0 - U0;
-    const Q4<T> bar = mid_from(U0, du);
-    const CoefF<T> cf = coef_fused(radf_of(L, 0), angf_of<P>(I, r));
-    const T fac = T(0.5) * L.dt;
     if constexpr (!P::kComp) {
-        Q4<T> br = bracket_fused(cf, nm + UM.phi, np + UP.phi, bar.phi, bar.pi, du, no_source<T>());
-        add_source(L.gh, I, r, lv.eh, br);
-        return lw_update(bar, fac, br);
+        return pole_half(even, x1, x2);
     } else {
-        Q4<T> h = lw_update(bar, fac, bracket_fused(cf, nm + UM.phi, np + UP.phi, bar.phi, bar.pi, du,
-                                                    mkc(T(0), T(0))));
-        if (L.near_h) {  // FP64 source increment (dt/2) F
-            const double gj = src_theta(I, r);
-            if (gj != 0.0) {
-                const cd F = source_value(L.gh, gj, lv.eh);
-                const double f64 = 0.5 * I.dt;
-                h.pi = mkc((T)((double)h.pi.re + f64 * F.re), (T)((double)h.pi.im + f64 * F.im));
-            }
+        St<T> o;
+        T *of = &o.f.phi.re, *oc = &o.c.phi.re;
+        for (int k = 0; k < 4; ++k) {
+            const double v = pole_x(value_of<P>(x1, k), value_of<P>(x2, k));
+            const T f = (T)v;
+            of[k] = even ? f : T(0);
+            oc[k] = even ? (T)(v - (double)f) : T(0);
         }
-        return h;
+        return o;
     }
 }
 
-// The same with the column to the right taken by lane shuffles.
 template <class P>
-__device__ __forceinline__ Q4<typename P::T> half_row(const Lane<P> &L, const Level &lv, const Q4<typename P::T> &UM,
-                                                      const Q4<typename P::T> &U0, const Q4<typename P::T> &UP, int r)
+__device__ __forceinline__ Half<P> zero_half()
 {
-    return half_core(L, lv, UM, U0, UP, shfl_down1<P>(UM.phi), shfl_down1<P>(U0), shfl_down1<P>(UP.phi), r);
+    using T = typename P::T;
+    if constexpr (!P::kComp) {
+        return zero_q4<T>();
+    } else {
+        return St<T>{zero_q4<T>(), zero_q4<T>()};
+    }
 }
 
 // exact sum a + b = s + e (two-sum)
@@ -525,14 +518,147 @@ __device__ __forceinline__ void two_sum(float a, float b, float &s, float &e)
     e = (a - (s - bb)) + (b - bb);
 }
 
+// Compensated form: the angular differences of Phi down one column at its
+// middle row, from the values x + e of rows j-1 (M), j (Z), j+1 (P): the
+// first differences of x and of e separately (a difference of neighbouring
+// FP32 values is exact when they are within a factor of two of each other),
+// then d2 = d+ - d- and d1 = d+ + d-, each from its two parts.
+template <typename T>
+struct AngD {
+    cx<T> d2, d1;
+};
+template <typename T>
+__device__ __forceinline__ AngD<T> col_diffs(const St<T> &M, const St<T> &Z, const St<T> &P)
+{
+    AngD<T> a;
+    const T *m = &M.f.phi.re, *z = &Z.f.phi.re, *p = &P.f.phi.re;
+    const T *mc = &M.c.phi.re, *zc = &Z.c.phi.re, *pc = &P.c.phi.re;
+    T *d2 = &a.d2.re, *d1 = &a.d1.re;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const T ep = p[k] - z[k], em = z[k] - m[k];
+        const T gp = pc[k] - zc[k], gm = zc[k] - mc[k];
+        d2[k] = (ep - em) + (gp - gm);
+        d1[k] = (ep + em) + (gp + gm);
+    }
+    return a;
+}
+
+// x1 - x0 for compensated values: (f1 - f0) + (c1 - c0) per component
+template <typename T>
+__device__ __forceinline__ Q4<T> comp_diff(const St<T> &x1, const St<T> &x0)
+{
+    return (x1.f - x0.f) + (x1.c - x0.c);
+}
+
+// What the stage at a point needs from beyond its own column.  FP64: Phi on
+// rows j -+ 1 and the whole row j of the neighbouring column.  Compensated:
+// the neighbour's row j (value and term), and the angular differences of Phi
+// down both columns.
+template <class P, bool COMP = P::kComp>
+struct Around;
+template <class P>
+struct Around<P, false> {
+    cx<typename P::T> m;
+    Q4<typename P::T> z;
+    cx<typename P::T> p;
+};
+template <class P>
+struct Around<P, true> {
+    St<typename P::T> z;
+    AngD<typename P::T> own, nb;
+};
+
+// Eq. (3) at half row r: u^n rows r-1 (UM), r (U0), r+1 (UP) of this column
+// and what it needs of the column to the right (nb).
+template <class P>
+__device__ __forceinline__ Half<P> half_core(const Lane<P> &L, const Level &lv, const St<typename P::T> &UM,
+                                             const St<typename P::T> &U0, const St<typename P::T> &UP,
+                                             const Around<P> &nb, int r)
+{
+    using T = typename P::T;
+    const DevInst &I = *L.I;
+    // lanes without a half node (c = n_r - 1 and off the grid) feed only
+    // out_row lanes that do not update: computing them unmasked (FP64) or
+    // returning zero (FP32C) gives the same stored results
+    if constexpr (P::kMaskHalo)
+        if (!L.hv) return zero_half<P>();
+    const T fac = T(0.5) * L.dt;
+    if constexpr (!P::kComp) {
+        const Q4<T> du = nb.z - U0.f;
+        const Q4<T> bar = mid_from(U0.f, du);
+        const CoefF<T> cf = coef_fused(radf_of(L, 0), angf_of<P>(I, r));
+        Q4<T> br = bracket_fused(cf, nb.m + UM.f.phi, nb.p + UP.f.phi, bar.phi, bar.pi, du, no_source<T>());
+        add_source(L.gh, I, r, lv.eh, br);
+        return lw_update(bar, fac, br);
+    } else {
+        (void)UM;
+        (void)UP;
+        const Q4<T> du = comp_diff(nb.z, U0);
+        // the average (u_i + u_{i+1}) / 2 = u_i + du / 2 as a pair s + e
+        St<T> bar;
+        {
+            const T *f = &U0.f.phi.re, *c = &U0.c.phi.re, *d = &du.phi.re;
+            T *bs = &bar.f.phi.re, *be = &bar.c.phi.re;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                T e;
+                two_sum(f[k], T(0.5) * d[k], bs[k], e);
+                be[k] = e + c[k];
+            }
+        }
+        const CoefD<T> cf = coef_diff(radf_of(L, 0), angf_of<P>(I, r));
+        const Q4<T> br = bracket_diff(cf, nb.own.d2 + nb.nb.d2, nb.own.d1 + nb.nb.d1, bar.f.phi, bar.f.pi, du);
+        // u^{n+1/2} = bar - (dt/2) [.] as a pair
+        St<T> h;
+        {
+            const T *bp = &br.phi.re, *bs = &bar.f.phi.re, *be = &bar.c.phi.re;
+            T *hs = &h.f.phi.re, *he = &h.c.phi.re;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) two_sum(bs[k], fma(-fac, bp[k], be[k]), hs[k], he[k]);
+        }
+        if (L.near_h) {  // FP64 source increment (dt/2) F
+            const double gj = src_theta(I, r);
+            if (gj != 0.0) {
+                const cd F = source_value(L.gh, gj, lv.eh);
+                const double f64 = 0.5 * I.dt;
+                const double vr = ((double)h.f.pi.re + (double)h.c.pi.re) + f64 * F.re;
+                const double vi = ((double)h.f.pi.im + (double)h.c.pi.im) + f64 * F.im;
+                h.f.pi = mkc((T)vr, (T)vi);
+                h.c.pi = mkc((T)(vr - (double)h.f.pi.re), (T)(vi - (double)h.f.pi.im));
+            }
+        }
+        return h;
+    }
+}
+
+// The same with the column to the right taken by lane shuffles.
+template <class P>
+__device__ __forceinline__ Half<P> half_row(const Lane<P> &L, const Level &lv, const St<typename P::T> &UM,
+                                            const St<typename P::T> &U0, const St<typename P::T> &UP, int r)
+{
+    Around<P> nb;
+    if constexpr (!P::kComp) {
+        nb.m = shfl_down1<P>(UM.f.phi);
+        nb.z = shfl_down1<P>(U0.f);
+        nb.p = shfl_down1<P>(UP.f.phi);
+    } else {
+        nb.own = col_diffs(UM, U0, UP);
+        nb.z.f = shfl_down1<P>(U0.f);
+        nb.z.c = shfl_down1<P>(U0.c);
+        nb.nb.d2 = shfl_down1<P>(nb.own.d2);
+        nb.nb.d1 = shfl_down1<P>(nb.own.d1);
+    }
+    return half_core(L, lv, UM, U0, UP, nb, r);
+}
+
 // Eq. (4) at output row o: u^n row o (Uo), half rows o-1 (HM), o (H0), o+1
-// (HP) of this column (at c+1/2) and lm, l0, lp of the column at c-1/2 (Phi
-// only on rows o -+ 1).
+// (HP) of this column (at c+1/2) and what it needs of the half column at
+// c-1/2 (nb).
 template <class P>
 __device__ __forceinline__ St<typename P::T> out_core(const Lane<P> &L, const Level &lv, const St<typename P::T> &Uo,
-                                                      const Q4<typename P::T> &HM, const Q4<typename P::T> &H0,
-                                                      const Q4<typename P::T> &HP, cx<typename P::T> lm,
-                                                      const Q4<typename P::T> &l0, cx<typename P::T> lp, int o)
+                                                      const Half<P> &HM, const Half<P> &H0, const Half<P> &HP,
+                                                      const Around<P> &nb, int o)
 {
     using T = typename P::T;
     const DevInst &I = *L.I;
@@ -540,15 +666,21 @@ __device__ __forceinline__ St<typename P::T> out_core(const Lane<P> &L, const Le
     res.f = zero_q4<T>();
     res.c = zero_q4<T>();
     if (!L.icol) return res;
-    const Q4<T> du = H0 - l0;
-    const Q4<T> til = mid_from(l0, du);
-    const CoefF<T> cf = coef_fused(radf_of(L, 1), angf_of<P>(I, o));
     if constexpr (!P::kComp) {
-        Q4<T> br = bracket_fused(cf, HM.phi + lm, HP.phi + lp, til.phi, til.pi, du, no_source<T>());
+        const Q4<T> du = H0 - nb.z;
+        const Q4<T> til = mid_from(nb.z, du);
+        const CoefF<T> cf = coef_fused(radf_of(L, 1), angf_of<P>(I, o));
+        Q4<T> br = bracket_fused(cf, HM.phi + nb.m, HP.phi + nb.p, til.phi, til.pi, du, no_source<T>());
         add_source(L.gn, I, o, lv.ef, br);
         res.f = lw_update(Uo.f, L.dt, br);
     } else {
-        const Q4<T> br = bracket_fused(cf, HM.phi + lm, HP.phi + lp, til.phi, til.pi, du, mkc(T(0), T(0)));
+        (void)HM;
+        (void)HP;
+        const Q4<T> du = comp_diff(H0, nb.z);
+        // the averaged fields enter S only through ct and c0: one FP32 value each
+        const Q4<T> til = mid_from(nb.z.f, du);
+        const CoefD<T> cf = coef_diff(radf_of(L, 1), angf_of<P>(I, o));
+        const Q4<T> br = bracket_diff(cf, nb.own.d2 + nb.nb.d2, nb.own.d1 + nb.nb.d1, til.phi, til.pi, du);
         const T *bp = &br.phi.re, *fp = &Uo.f.phi.re, *cp = &Uo.c.phi.re;
         T *rf = &res.f.phi.re, *rc = &res.c.phi.re;
         const double gj = L.near_n ? src_theta(I, o) : 0.0;
@@ -571,20 +703,31 @@ __device__ __forceinline__ St<typename P::T> out_core(const Lane<P> &L, const Le
     return res;
 }
 
-// The same with the column at c-1/2 taken by lane shuffles.
+// The same with the half column at c-1/2 taken by lane shuffles.
 template <class P>
 __device__ __forceinline__ St<typename P::T> out_row(const Lane<P> &L, const Level &lv, const St<typename P::T> &Uo,
-                                                     const Q4<typename P::T> &HM, const Q4<typename P::T> &H0,
-                                                     const Q4<typename P::T> &HP, int o)
+                                                     const Half<P> &HM, const Half<P> &H0, const Half<P> &HP, int o)
 {
-    return out_core(L, lv, Uo, HM, H0, HP, shfl_up1<P>(HM.phi), shfl_up1<P>(H0), shfl_up1<P>(HP.phi), o);
+    Around<P> nb;
+    if constexpr (!P::kComp) {
+        nb.m = shfl_up1<P>(HM.phi);
+        nb.z = shfl_up1<P>(H0);
+        nb.p = shfl_up1<P>(HP.phi);
+    } else {
+        nb.own = col_diffs(HM, H0, HP);
+        nb.z.f = shfl_up1<P>(H0.f);
+        nb.z.c = shfl_up1<P>(H0.c);
+        nb.nb.d2 = shfl_up1<P>(nb.own.d2);
+        nb.nb.d1 = shfl_up1<P>(nb.own.d1);
+    }
+    return out_core(L, lv, Uo, HM, H0, HP, nb, o);
 }
 
 template <class P>
 struct Roll {
     using T = typename P::T;
     St<T> U[3];    // u^n(c, row), slot = (row - r_lo) mod 3 (rows r-1, r, r+1 at march row r)
-    Q4<T> H[3];    // u^{n+1/2}(c+1/2, row), same slots (rows r-2, r-1, r)
+    Half<P> H[3];  // u^{n+1/2}(c+1/2, row), same slots (rows r-2, r-1, r)
     St<T> pre[3];  // prefetched u^n rows (same slots, or slot 0 only at depth 1)
     St<T> keep;    // an output row kept for the pole condition
 };
@@ -642,8 +785,8 @@ __device__ __forceinline__ void march(const Lane<P> &L, const Level &lv, Roll<P>
     const int nt = L.nt;
     const bool even = L.I->m_even;
     advance_rows<P, SR>(L, R, r, u_last);
-    R.H[SR] = half_row(L, lv, R.U[SM].f, R.U[SR].f, R.U[SP].f, r);
-    if (POLES && north && r == 2) R.H[SP] = pole_half(even, R.H[SM], R.H[SR]);  // half row 0
+    R.H[SR] = half_row(L, lv, R.U[SM], R.U[SR], R.U[SP], r);
+    if (POLES && north && r == 2) R.H[SP] = pole_hrow<P>(even, R.H[SM], R.H[SR]);  // half row 0
     const int o = r - 1;
     if (!POLES || (o >= out_lo && o <= out_hi)) {
         const St<T> v = out_row(L, lv, R.U[SM], R.H[SP], R.H[SM], R.H[SR], o);
@@ -665,7 +808,7 @@ __device__ __forceinline__ void south(const Lane<P> &L, const Level &lv, Roll<P>
     constexpr int SP = (SR + 1) % 3;  // row nt-1 (free slot)
     const int nt = L.nt;
     const bool even = L.I->m_even;
-    R.H[SP] = pole_half(even, R.H[SR], R.H[SM]);  // half row nt-1
+    R.H[SP] = pole_hrow<P>(even, R.H[SR], R.H[SM]);  // half row nt-1
     const St<T> v = out_row(L, lv, R.U[SR], R.H[SM], R.H[SR], R.H[SP], nt - 2);
     emit(L, lv, nt - 2, v);
     emit(L, lv, nt - 1, pole_row<P>(even, v, R.keep));
@@ -678,9 +821,9 @@ template <class P>
 struct Roll2 {
     using T = typename P::T;
     St<T> U[3], pre[3];  // u^n rows and the prefetch ring
-    Q4<T> H[3];          // u^{n+1/2} half rows
+    Half<P> H[3];        // u^{n+1/2} half rows
     St<T> V[3];          // u^{n+1} rows (level-1 output)
-    Q4<T> G[3];          // u^{n+3/2} half rows
+    Half<P> G[3];        // u^{n+3/2} half rows
     St<T> keep;          // a u^{n+2} row kept for a pole
 };
 
@@ -719,11 +862,11 @@ __device__ __forceinline__ void march2(const Lane<P> &L, const Level &l1, const 
     // level 1: half rows r-2 (SP), r-1 (SM), r (S); u^n rows r-1 (SM), r (S), r+1 (SP)
     if (!EDGE || r <= nt - 2) {
         advance_rows<P, S>(L, R, r, nt - 1);
-        R.H[S] = half_row(L, l1, R.U[SM].f, R.U[S].f, R.U[SP].f, r);
+        R.H[S] = half_row(L, l1, R.U[SM], R.U[S], R.U[SP], r);
     } else {  // r = nt-1: half row nt-1 from nt-2 (SM), nt-3 (SP); unused after that
-        R.H[S] = pole_half(even, R.H[SM], R.H[SP]);
+        R.H[S] = pole_hrow<P>(even, R.H[SM], R.H[SP]);
     }
-    if (EDGE && r == 2) R.H[SP] = pole_half(even, R.H[SM], R.H[S]);  // half row 0 from 1 (SM), 2 (S)
+    if (EDGE && r == 2) R.H[SP] = pole_hrow<P>(even, R.H[SM], R.H[S]);  // half row 0 from 1 (SM), 2 (S)
     const bool v_new = !EDGE || (r >= 2 && r <= nt - 1);              // u^{n+1} row r-1 this iteration
     St<typename P::T> vn;
     if (v_new) {
@@ -732,10 +875,10 @@ __device__ __forceinline__ void march2(const Lane<P> &L, const Level &l1, const 
     }
     // level 2: u^{n+1} rows r-4 (SM), r-3 (S), r-2 (SP); its half rows r-5 (SP), r-4 (SM), r-3 (S)
     if (!EDGE || (r >= 4 && r <= nt + 1))
-        R.G[S] = half_row(L, l2, R.V[SM].f, R.V[S].f, R.V[SP].f, r - 3);
+        R.G[S] = half_row(L, l2, R.V[SM], R.V[S], R.V[SP], r - 3);
     else if (r == nt + 2)  // half row nt-1 from nt-2 (SM), nt-3 (SP)
-        R.G[S] = pole_half(even, R.G[SM], R.G[SP]);
-    if (EDGE && r == 5) R.G[SP] = pole_half(even, R.G[SM], R.G[S]);  // half row 0 from 1 (SM), 2 (S)
+        R.G[S] = pole_hrow<P>(even, R.G[SM], R.G[SP]);
+    if (EDGE && r == 5) R.G[SP] = pole_hrow<P>(even, R.G[SM], R.G[S]);  // half row 0 from 1 (SM), 2 (S)
     if (!EDGE || (r >= 5 && r <= nt + 2)) {                          // u^{n+2} row o = r-4
         const int o = r - 4;
         const St<typename P::T> v = out_row(L, l2, R.V[SM], R.G[SP], R.G[SM], R.G[S], o);
@@ -808,11 +951,11 @@ __device__ __forceinline__ void march2c(const Lane<P> &L, const Level &l1, const
     const bool even = L.I->m_even;
     if (!EDGE || r <= B.h1_hi) {
         advance_rows<P, S>(L, R, r, B.h1_hi + 1);
-        R.H[S] = half_row<P>(L, l1, R.U[SM].f, R.U[S].f, R.U[SP].f, r);
+        R.H[S] = half_row<P>(L, l1, R.U[SM], R.U[S], R.U[SP], r);
     } else if (B.south && r == nt - 1) {
-        R.H[S] = pole_half(even, R.H[SM], R.H[SP]);
+        R.H[S] = pole_hrow<P>(even, R.H[SM], R.H[SP]);
     }
-    if (EDGE && B.north && r == 2) R.H[SP] = pole_half(even, R.H[SM], R.H[S]);
+    if (EDGE && B.north && r == 2) R.H[SP] = pole_hrow<P>(even, R.H[SM], R.H[S]);
     const bool v_new = !EDGE || (r - 1 >= B.v_lo && r - 1 <= B.v_hi);
     St<typename P::T> vn;
     if (v_new) {
@@ -820,10 +963,10 @@ __device__ __forceinline__ void march2c(const Lane<P> &L, const Level &l1, const
         if (!EDGE || (r - 1 >= B.o_lo && r - 1 <= B.o_hi)) sample(L, l1, r - 1, vn);
     }
     if (!EDGE || (r - 3 >= B.g_lo && r - 3 <= B.g_hi))
-        R.G[S] = half_row<P>(L, l2, R.V[SM].f, R.V[S].f, R.V[SP].f, r - 3);
+        R.G[S] = half_row<P>(L, l2, R.V[SM], R.V[S], R.V[SP], r - 3);
     else if (B.south && r == nt + 2)
-        R.G[S] = pole_half(even, R.G[SM], R.G[SP]);
-    if (EDGE && B.north && r == 5) R.G[SP] = pole_half(even, R.G[SM], R.G[S]);
+        R.G[S] = pole_hrow<P>(even, R.G[SM], R.G[SP]);
+    if (EDGE && B.north && r == 5) R.G[SP] = pole_hrow<P>(even, R.G[SM], R.G[S]);
     if (!EDGE || (r - 4 >= B.o_lo && r - 4 <= B.o_hi)) {
         const int o = r - 4;
         const St<typename P::T> v = out_row<P>(L, l2, R.V[SM], R.G[SP], R.G[SM], R.G[S], o);
@@ -1003,17 +1146,30 @@ __device__ __forceinline__ St<typename P::T> lds_get(const typename Vec4Of<typen
     return v;
 }
 
-template <typename T>
-__device__ __forceinline__ void lds_put_half(typename Vec4Of<T>::type *s, int idx, const Q4<T> &v)
+// A half-step value in LDS: one 4-vector (FP64), two (the compensated pair).
+template <class P>
+__device__ __forceinline__ void lds_put_half(typename Vec4Of<typename P::T>::type *s, int idx, const Half<P> &v)
 {
-    s[idx] = typename Vec4Of<T>::type{v.phi.re, v.phi.im, v.pi.re, v.pi.im};
+    using V = typename Vec4Of<typename P::T>::type;
+    if constexpr (!P::kComp) {
+        s[idx] = V{v.phi.re, v.phi.im, v.pi.re, v.pi.im};
+    } else {
+        s[2 * idx] = V{v.f.phi.re, v.f.phi.im, v.f.pi.re, v.f.pi.im};
+        s[2 * idx + 1] = V{v.c.phi.re, v.c.phi.im, v.c.pi.re, v.c.pi.im};
+    }
 }
 
-template <typename T>
-__device__ __forceinline__ Q4<T> lds_get_half(const typename Vec4Of<T>::type *s, int idx)
+template <class P>
+__device__ __forceinline__ Half<P> lds_get_half(const typename Vec4Of<typename P::T>::type *s, int idx)
 {
-    const auto a = s[idx];
-    return Q4<T>{mkc(a.x, a.y), mkc(a.z, a.w)};
+    using T = typename P::T;
+    if constexpr (!P::kComp) {
+        const auto a = s[idx];
+        return Q4<T>{mkc(a.x, a.y), mkc(a.z, a.w)};
+    } else {
+        const auto a = s[2 * idx], b = s[2 * idx + 1];
+        return St<T>{Q4<T>{mkc(a.x, a.y), mkc(a.z, a.w)}, Q4<T>{mkc(b.x, b.y), mkc(b.z, b.w)}};
+    }
 }
 
 }  // namespace
@@ -1043,7 +1199,7 @@ __global__ void __launch_bounds__(64 * kFusedWavesPerBlock)
     __shared__ T s_rad[P::kRadRegs ? 2 : 2 * kRadF * 64];
     __shared__ double s_share[(P::kRadRegs ? 2 * kRadF + 2 : 2) * 64];
     __shared__ V s_u[(TRC + 4) * 64 * KV];  // u^n rows a_lo .. a_hi
-    __shared__ V s_h[(TRC + 2) * 64];       // half rows h_lo .. h_hi
+    __shared__ V s_h[(TRC + 2) * 64 * KV];  // half rows h_lo .. h_hi
     __shared__ V s_p[4 * 64 * KV];          // output rows 1, 2 and nt-2, nt-3 for the poles
     const int lane = (int)(threadIdx.x & 63);
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -1092,27 +1248,43 @@ __global__ void __launch_bounds__(64 * kFusedWavesPerBlock)
     }
     for (int r = h_lo + wv; r <= h_hi; r += NW) {
         const int k = (r - a_lo) * 64;
-        const Q4<T> UM = lds_get<P>(s_u, k - 64 + lane).f, U0 = lds_get<P>(s_u, k + lane).f;
-        const Q4<T> UP = lds_get<P>(s_u, k + 64 + lane).f;
-        const cx<T> nm = lds_get<P>(s_u, k - 64 + lr).f.phi, np = lds_get<P>(s_u, k + 64 + lr).f.phi;
-        const Q4<T> n0 = lds_get<P>(s_u, k + lr).f;
-        lds_put_half(s_h, (r - h_lo) * 64 + lane, half_core(L, lv, UM, U0, UP, nm, n0, np, r));
+        const St<T> UM = lds_get<P>(s_u, k - 64 + lane), U0 = lds_get<P>(s_u, k + lane);
+        const St<T> UP = lds_get<P>(s_u, k + 64 + lane);
+        Around<P> nb;
+        if constexpr (!P::kComp) {
+            nb.m = lds_get<P>(s_u, k - 64 + lr).f.phi;
+            nb.z = lds_get<P>(s_u, k + lr).f;
+            nb.p = lds_get<P>(s_u, k + 64 + lr).f.phi;
+        } else {
+            nb.z = lds_get<P>(s_u, k + lr);
+            nb.own = col_diffs(UM, U0, UP);
+            nb.nb = col_diffs(lds_get<P>(s_u, k - 64 + lr), nb.z, lds_get<P>(s_u, k + 64 + lr));
+        }
+        lds_put_half<P>(s_h, (r - h_lo) * 64 + lane, half_core(L, lv, UM, U0, UP, nb, r));
     }
     __syncthreads();
     // half row `row` of lane l, the pole rows from the rows next to them
-    auto half_at = [&](int row, int l) -> Q4<T> {
-        if (row == 0) return pole_half(even, lds_get_half<T>(s_h, (1 - h_lo) * 64 + l),
-                                       lds_get_half<T>(s_h, (2 - h_lo) * 64 + l));
-        if (row == nt - 1) return pole_half(even, lds_get_half<T>(s_h, (nt - 2 - h_lo) * 64 + l),
-                                            lds_get_half<T>(s_h, (nt - 3 - h_lo) * 64 + l));
-        return lds_get_half<T>(s_h, (row - h_lo) * 64 + l);
+    auto half_at = [&](int row, int l) -> Half<P> {
+        if (row == 0) return pole_hrow<P>(even, lds_get_half<P>(s_h, (1 - h_lo) * 64 + l),
+                                          lds_get_half<P>(s_h, (2 - h_lo) * 64 + l));
+        if (row == nt - 1) return pole_hrow<P>(even, lds_get_half<P>(s_h, (nt - 2 - h_lo) * 64 + l),
+                                               lds_get_half<P>(s_h, (nt - 3 - h_lo) * 64 + l));
+        return lds_get_half<P>(s_h, (row - h_lo) * 64 + l);
     };
     for (int o = o_lo + wv; o <= o_hi; o += NW) {
         const St<T> Uo = lds_get<P>(s_u, (o - a_lo) * 64 + lane);
-        const Q4<T> HM = half_at(o - 1, lane), H0 = half_at(o, lane), HP = half_at(o + 1, lane);
-        const cx<T> lm = half_at(o - 1, ll).phi, lp = half_at(o + 1, ll).phi;
-        const Q4<T> l0 = half_at(o, ll);
-        const St<T> v = out_core(L, lv, Uo, HM, H0, HP, lm, l0, lp, o);
+        const Half<P> HM = half_at(o - 1, lane), H0 = half_at(o, lane), HP = half_at(o + 1, lane);
+        Around<P> nb;
+        if constexpr (!P::kComp) {
+            nb.m = half_at(o - 1, ll).phi;
+            nb.z = half_at(o, ll);
+            nb.p = half_at(o + 1, ll).phi;
+        } else {
+            nb.z = half_at(o, ll);
+            nb.own = col_diffs(HM, H0, HP);
+            nb.nb = col_diffs(half_at(o - 1, ll), nb.z, half_at(o + 1, ll));
+        }
+        const St<T> v = out_core(L, lv, Uo, HM, H0, HP, nb, o);
         emit(L, lv, o, v);
         if (north && o <= 2) lds_put<P>(s_p, (o - 1) * 64 + lane, v);
         if (southp && o >= nt - 3) lds_put<P>(s_p, (2 + (nt - 2 - o)) * 64 + lane, v);
