@@ -55,8 +55,9 @@ def workload(name):
 
 def kernel_name(prec, prefetch, nt, waves, two_step=False, chunked=False):
     """The fused kernel variant as rocprofv3 names it (template arguments:
-    prefetch depth, non-temporal stores, occupancy target)."""
-    k = ("k_fused2c" if chunked else "k_fused2") if two_step else "k_fused"
+    prefetch depth, non-temporal stores, occupancy target).  The compensated
+    form runs its two-step march on whole strips with the chunked kernel."""
+    k = ("k_fused2c" if chunked or prec == "fp32c" else "k_fused2") if two_step else "k_fused"
     return f"{k}<{KERNEL_POLICY[prec]}<{prefetch}, {'true' if nt else 'false'}, {waves or 1}>>"
 
 

@@ -1395,13 +1395,23 @@ hipError_t launch_as(const DevInst *d_inst, const WorkItem *d_work, int n_work, 
 {
     if (n_work <= 0) return hipSuccess;
     const int blocks = (n_work + kFusedWavesPerBlock - 1) / kFusedWavesPerBlock;
+    // The compensated form marches whole strips with the chunked kernel's
+    // code too (a strip is the chunk [0, n_theta), the same march with the
+    // same pole bookkeeping): the whole-strip kernel's unrolled head and tail
+    // keep its half-step pairs in more registers than the register file
+    // holds for two waves per SIMD.
+    if constexpr (P::kComp) chunked = chunked || two_step;
     if (two_step && chunked)
         hipLaunchKernelGGL(k_fused2c<P>, dim3(blocks), dim3(64 * kFusedWavesPerBlock), 0, s, d_inst, d_work, n_work,
                            ctl, kstep, kflip);
-    else if (two_step)
-        hipLaunchKernelGGL(k_fused2<P>, dim3(blocks), dim3(64 * kFusedWavesPerBlock), 0, s, d_inst, d_work, n_work,
-                           ctl, kstep, kflip);
-    else
+    else if constexpr (!P::kComp) {
+        if (two_step)
+            hipLaunchKernelGGL(k_fused2<P>, dim3(blocks), dim3(64 * kFusedWavesPerBlock), 0, s, d_inst, d_work,
+                               n_work, ctl, kstep, kflip);
+        else
+            hipLaunchKernelGGL(k_fused<P>, dim3(blocks), dim3(64 * kFusedWavesPerBlock), 0, s, d_inst, d_work,
+                               n_work, cols, ctl, kstep, kflip);
+    } else
         hipLaunchKernelGGL(k_fused<P>, dim3(blocks), dim3(64 * kFusedWavesPerBlock), 0, s, d_inst, d_work, n_work,
                            cols, ctl, kstep, kflip);
     return hipGetLastError();

@@ -24,6 +24,9 @@
  *   FM_HALF_PAIR  the radial averages and the half-step values of Eq. (3)
  *                 carry an FP32 compensation term (a value is s + e); without
  *                 it they are single FP32 numbers.
+ *   FM_COEF64     the coefficients keep their FP64 values (each product with
+ *                 a coefficient is rounded once); without it they are
+ *                 rounded to FP32 first.
  *
  * With FM_ARITH32 off, the arithmetic is double on the stored value f + c,
  * so FM_STORE32 alone isolates the storage format.  With every flag off the
@@ -42,7 +45,7 @@
 #include <omp.h>
 #endif
 
-enum { FM_ARITH32 = 1, FM_STORE32 = 2, FM_DIFF_RAD = 4, FM_DIFF_ANG = 8, FM_HALF_PAIR = 16 };
+enum { FM_ARITH32 = 1, FM_STORE32 = 2, FM_DIFF_RAD = 4, FM_DIFF_ANG = 8, FM_HALF_PAIR = 16, FM_COEF64 = 32 };
 
 /* Must match the ctypes Structure in tests/fp32c_model.py */
 typedef struct {
@@ -233,7 +236,7 @@ static inline pr at(const double *s, const double *e, size_t o) { return (pr){s[
 
 typedef struct {
     const ar *A;
-    int diff_rad, diff_ang, pairs;
+    int diff_rad, diff_ang, pairs, coef64;
 } form;
 
 /* Difference a - b of two pairs: from s and e (a difference of values), or
@@ -283,19 +286,20 @@ static void bracket(const fm_grid *g, const form *F, size_t c, const pr ph[3][2]
 {
     const ar *A = F->A;
     const int wsum = A->a32 && !F->diff_ang;
-    const double bh = rd(A, g->bh[c]), bih = rd(A, g->bih[c]);
-    const double dhr = rd(A, g->dhr[c]), dhi = rd(A, g->dhi[c]);
-    const double ctr = rd(A, g->ctr[c]), cti = rd(A, g->cti[c]);
+    const ar C = {A->a32 && !F->coef64}; /* rounding of the coefficients themselves */
+    const double bh = rd(&C, g->bh[c]), bih = rd(&C, g->bih[c]);
+    const double dhr = rd(&C, g->dhr[c]), dhi = rd(&C, g->dhi[c]);
+    const double ctr = rd(&C, g->ctr[c]), cti = rd(&C, g->cti[c]);
     const double A2 = g->A2[c], A1 = g->A1[c];
-    const double c0r = rd(A, wsum ? g->c0r[c] - 2 * A2 : g->c0r[c]), c0i = rd(A, g->c0i[c]);
+    const double c0r = rd(&C, wsum ? g->c0r[c] - 2 * A2 : g->c0r[c]), c0i = rd(&C, g->c0i[c]);
     double ang[2];
     for (int k = 0; k < 2; ++k) {
         if (wsum) {
-            ang[k] = add(A, mul(A, rd(A, A2 + A1), ph[2][k].s), mul(A, rd(A, A2 - A1), ph[0][k].s));
+            ang[k] = add(A, mul(A, rd(&C, A2 + A1), ph[2][k].s), mul(A, rd(&C, A2 - A1), ph[0][k].s));
         } else {
             double dp = pdiff(F, ph[2][k], ph[1][k], 1);
             double dm = pdiff(F, ph[1][k], ph[0][k], 1);
-            ang[k] = add(A, mul(A, rd(A, A2), sub(A, dp, dm)), mul(A, rd(A, A1), add(A, dp, dm)));
+            ang[k] = add(A, mul(A, rd(&C, A2), sub(A, dp, dm)), mul(A, rd(&C, A1), add(A, dp, dm)));
         }
     }
     const double p0r = A->a32 ? pi[0].s : pi[0].s + pi[0].e, p0i = A->a32 ? pi[1].s : pi[1].s + pi[1].e;
@@ -333,7 +337,8 @@ static void fm_step1(fm_grid *g)
     const int nr = d->nr, nth = d->nth;
     const int flags = d->flags;
     ar A = {(flags & FM_ARITH32) != 0};
-    form F = {&A, (flags & FM_DIFF_RAD) != 0, (flags & FM_DIFF_ANG) != 0, (flags & FM_HALF_PAIR) != 0};
+    form F = {&A, (flags & FM_DIFF_RAD) != 0, (flags & FM_DIFF_ANG) != 0, (flags & FM_HALF_PAIR) != 0,
+              (flags & FM_COEF64) != 0};
     const double dt = d->dt, tn = (double)g->step * dt;
     double ehr, ehi, efr, efi;
     time_factor(d, tn, &ehr, &ehi);

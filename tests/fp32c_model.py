@@ -19,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "fp32c_model.c")
 LIB = os.path.join(HERE, "_fp32c_model.so")
 
-ARITH32, STORE32, DIFF_RAD, DIFF_ANG, HALF_PAIR = 1, 2, 4, 8, 16
+ARITH32, STORE32, DIFF_RAD, DIFF_ANG, HALF_PAIR, COEF64 = 1, 2, 4, 8, 16, 32
 
 # named arithmetic forms
 FORMS = {
