@@ -21,6 +21,21 @@ sys.path.insert(0, ROOT)
 METRIC = "grid-point updates/sec (batched modes) + % HBM roofline; FP32-comp vs FP64"
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_UPDATE = {"fp64": 64, "fp32c": 48}
+# Vector-ALU peaks of the MI355X (256 CUs at 2.4 GHz): FP64 78.6 TFLOP/s, FP32
+# 157.3 TFLOP/s (the FP32 figure counts packed instructions; the kernels are
+# built without them, so their FP32 issues at the FP64 rate).
+ALU_PEAK_TFLOPS = {"fp64": 78.6, "fp32c": 157.3}
+# Floating-point operations per point update (both stages of Eqs. (3)-(4))
+# as the fused kernels' formulas are written, an FMA counting two: FP64, per
+# stage, the radial difference and average (12), the coefficients at the
+# point (39: Sigma-hat, its inverse square root with two Newton steps, the
+# ten products of the factored coefficients), the bracket (42) and the
+# update (8): 101, 202 per update.  The compensated form, per stage, adds the
+# Kahan terms to every difference (radial 12, angular column differences 20),
+# keeps the average and the half step as two-sum pairs (32 + 32 in Eq. (3),
+# 32 for the update of Eq. (4)) and drops a Newton step and the folded
+# weights: 312 FP32 operations per update.
+FLOPS_PER_UPDATE = {"fp64": 202, "fp32c": 312}
 KERNEL_POLICY = {"fp64": "PolicyF64", "fp32c": "PolicyF32C"}
 KERNEL_SOURCES = ["paper_1206_0270_amd/csrc/tk_kernels.hip", "paper_1206_0270_amd/csrc/tk_device.h",
                   "paper_1206_0270_amd/csrc/tk_internal.h"]
@@ -254,6 +269,129 @@ def precision_study(args):
                           "joint_rel_l2_vs_oracle": pref},
     }
     print(json.dumps(out), flush=True)
+
+
+def noise_study(args):
+    """How the scheme carries rounding-sized noise on the fifth workload's
+    grid: FP64, no source, (Phi, Pi) set to white noise of 1e-20 per value,
+    stepped for noise_window M; the field norm and the position of its
+    largest value every 50M, at the workload's r* spacing and time step and
+    with each halved or doubled.  One JSON line.  A growth that changes with
+    h or dt would be a property of the discretisation; one that does not is
+    the equation's own."""
+    import numpy as np
+    import torch
+    from paper_1206_0270_amd import tk
+    from paper_1206_0270_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    cases = [("h=0.0375 dt=1/500 (fifth workload)", 16001, 1 / 500), ("h=0.075 dt=1/500", 8001, 1 / 500),
+             ("h=0.0375 dt=1/1000", 16001, 1 / 1000), ("h=0.01875 dt=1/500", 32001, 1 / 500)]
+    out = {}
+    for name, n_r, dt in cases:
+        inst = W.instance(a=0.9, m=2, n_r=n_r, n_theta=129, rstar_min=-300.0, rstar_max=300.0, dt=dt,
+                          extract_every=0)
+        rng = np.random.default_rng(3)
+        shp = (inst["n_theta"], n_r)
+
+        def noise():
+            x = (rng.standard_normal(shp) + 1j * rng.standard_normal(shp)) * 1e-20
+            x[:, 0] = 0
+            x[:, -1] = 0
+            return x
+
+        st = tk.Stepper([inst], precision=tk.TK_FP64, force_dt=True)
+        phi0, pi0 = noise(), noise()
+        st.set_fields(0, phi0, pi0)
+        norm0 = float(np.sqrt(np.linalg.norm(phi0) ** 2 + np.linalg.norm(pi0) ** 2))
+        chunk = int(round(50.0 / dt))
+        rows = []
+        for k in range(int(args.noise_window / 50)):
+            st.step(chunk)
+            phi, pi = st.get_fields(0)
+            a = np.abs(phi)
+            j, i = np.unravel_index(np.argmax(a), a.shape)
+            norm = float(np.sqrt(np.sum(a ** 2) + np.sum(np.abs(pi) ** 2)))
+            rows.append({"t": 50.0 * (k + 1), "norm_over_initial": norm / norm0,
+                         "argmax_rstar": inst["rstar_min"] + i * (inst["rstar_max"] - inst["rstar_min"]) / (n_r - 1),
+                         "argmax_row": int(j)})
+            print(f"# {name}: t={rows[-1]['t']:.0f}M norm x{rows[-1]['norm_over_initial']:.3g} "
+                  f"max at r*={rows[-1]['argmax_rstar']:.1f}M row {j}", file=sys.stderr, flush=True)
+        st.close()
+        out[name] = rows
+    print(json.dumps({"metric": "growth of white noise (1e-20 per value) under the FP64 scheme, no source",
+                      "instance": "a=0.9, s=-2, m=2, 129 theta rows, r* in [-300,300]M, Dirichlet ends",
+                      "cases": out}), flush=True)
+
+
+def sensitivity_study(args):
+    """One mode of the fifth workload (index sens_instance) with the source
+    switched on abruptly and over 200M: the FP64 run; an FP64 run whose state
+    at sens_at M is perturbed value by value by a relative N(0, 2^-24) (one
+    FP32 rounding of every value); and the FP32-compensated run.  Waveform
+    (projected on l = max(|m|, 2) at the observer) relative differences to the
+    FP64 run at checkpoints.  One JSON line."""
+    import numpy as np
+    import torch
+    from paper_1206_0270_amd import tk
+    from paper_1206_0270_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    res = {}
+    for ramp in (0.0, 200.0):
+        inst = W.config5()["instances"][args.sens_instance]
+        if ramp:
+            inst = dict(inst, source=dict(inst["source"], ramp=ramp))
+        dt = inst["dt"]
+        n1 = int(round(args.sens_at / dt))
+        n2 = int(round(args.sens_window / dt))
+        cap = int(args.sens_window) + 64
+
+        def stepper(prec):
+            st = tk.Stepper([inst], precision=prec, wave_capacity=cap)
+            st.set_tuning(kernel=tk.TK_KERNEL_AUTO, rows_per_tile=0, graph_steps=100)
+            return st
+
+        a = stepper(tk.TK_FP64)
+        a.set_fields(0, *W.initial_data(inst))
+        a.step(n1)
+        wa1 = a.extract(0, cap)
+        phi, pi = a.get_fields(0)
+        rng = np.random.default_rng(1)
+
+        def perturb(x):
+            e = 2.0 ** -24
+            return x.real * (1 + e * rng.standard_normal(x.shape)) + 1j * x.imag * (1 + e * rng.standard_normal(x.shape))
+
+        b = stepper(tk.TK_FP64)
+        b.set_fields(0, perturb(phi), perturb(pi))
+        b.set_step(n1)
+        a.step(n2 - n1)
+        b.step(n2 - n1)
+        w64 = projected_waveform(inst, np.concatenate([wa1, a.extract(0, cap)]))
+        w64p = projected_waveform(inst, b.extract(0, cap))
+        a.close()
+        b.close()
+        c = stepper(tk.TK_FP32_COMP)
+        c.set_fields(0, *W.initial_data(inst))
+        for k in range(0, n2, 100000):
+            c.step(min(100000, n2 - k))
+            c.synchronize()
+            print(f"# ramp {ramp}: fp32c {min(k + 100000, n2)} of {n2} steps", file=sys.stderr, flush=True)
+        w32 = projected_waveform(inst, c.extract(0, cap))
+        c.close()
+        K = inst["extract_every"]
+        rows = []
+        for T in args.sens_checkpoints:
+            i = int(round(T / (K * dt))) - 1
+            j = i - (len(w64) - len(w64p))
+            rows.append({"t": T, "abs_w64": float(abs(w64[i])),
+                         "fp32c": float(abs(w32[i] - w64[i]) / abs(w64[i])),
+                         "fp64_perturbed": float(abs(w64p[j] - w64[i]) / abs(w64[i])) if j >= 0 else None})
+        res[f"ramp {ramp:g}M"] = rows
+    print(json.dumps({"metric": "relative waveform difference to the FP64 run at the observer: FP32C, and FP64 "
+                                f"with every value of the state perturbed by one FP32 rounding at {args.sens_at:g}M",
+                      "instance": W.config5()["instances"][args.sens_instance]["name"], "cases": res}), flush=True)
 
 
 def richardson_study(args):
@@ -742,16 +880,25 @@ def run_leg(args, insts, inits, precision):
     roof = None
     if n_launch > 0:
         launch_s = main_ms / 1e3 / n_launch
+        upd = points * spl  # point updates per launch
         moved = points * bpp
-        achieved = moved / launch_s / 1e9
-        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_entry(kname, args.workload),
+        gbs = moved / launch_s / 1e9
+        tflops = FLOPS_PER_UPDATE[precision] * upd / launch_s / 1e12
+        issue = valu_entry(kname, args.workload, upd / launch_s)
+        # The fused kernels are bound by vector-ALU issue (the counters show
+        # the VALU busy most cycles at a fraction of the HBM bandwidth), so the
+        # roofline is the ALU one; the bytes the launch moves are reported
+        # beside it against the HBM peak.
+        roof = {"bound": "alu", "achieved": tflops, "peak": ALU_PEAK_TFLOPS[precision], "unit": "TFLOP/s",
+                "frac": tflops / ALU_PEAK_TFLOPS[precision], "traffic": traffic_entry(kname, args.workload),
                 "kernel": kname, "avg_launch_ms": launch_s * 1e3, "launches_timed": n_launch,
-                "bytes_per_launch": moved, "bytes_per_point_per_launch": bpp, "updates_per_point_per_launch": spl,
-                # the same launch priced at one read and one write of the state per update (SURVEY's
-                # per-update figure): twice the bytes actually moved for the two-step kernel
-                "effective_GBps_at_per_update_bytes": points * spl * bpp / launch_s / 1e9,
-                "issue": valu_entry(kname, args.workload, points * spl / launch_s)}
+                "flops_per_update": FLOPS_PER_UPDATE[precision], "updates_per_point_per_launch": spl,
+                "hbm": {"achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                        "bytes_per_launch": moved, "bytes_per_point_per_launch": bpp,
+                        # the same launch priced at one read and one write of the state per update: twice
+                        # the bytes actually moved for the two-step kernel
+                        "effective_GBps_at_per_update_bytes": upd * bpp / launch_s / 1e9},
+                "issue": issue}
     st.close()
     del st
     torch.cuda.empty_cache()
@@ -789,6 +936,16 @@ def build_parser():
     ap.add_argument("--study-layer", type=float, default=0.0,
                     help="precision study: end the grids in a hyperboloidal layer from this r* (M) on and read the "
                          "waveform at null infinity (0 = the plain grids, observer at 290M)")
+    ap.add_argument("--noise-study", action="store_true",
+                    help="instead of the throughput line, evolve white noise under the FP64 scheme at four resolutions")
+    ap.add_argument("--noise-window", type=float, default=500.0, help="noise study: simulated time (M)")
+    ap.add_argument("--sensitivity-study", action="store_true",
+                    help="instead of the throughput line, compare FP32C and a once-perturbed FP64 run with FP64")
+    ap.add_argument("--sens-instance", type=int, default=1, help="sensitivity study: fifth-workload instance index")
+    ap.add_argument("--sens-at", type=float, default=300.0, help="sensitivity study: perturbation time (M)")
+    ap.add_argument("--sens-window", type=float, default=1000.0, help="sensitivity study: simulated time (M)")
+    ap.add_argument("--sens-checkpoints", type=float, nargs="+",
+                    default=[300.0, 350.0, 400.0, 450.0, 500.0, 600.0, 700.0, 800.0, 900.0, 1000.0])
     ap.add_argument("--richardson", action="store_true",
                     help="instead of the throughput line, run the three-resolution Richardson study")
     ap.add_argument("--rich-window", type=float, default=330.0, help="Richardson study: simulated time (M)")
@@ -846,6 +1003,12 @@ def main(argv=None):
 
     if args.precision_study:
         precision_study(args)
+        return
+    if args.noise_study:
+        noise_study(args)
+        return
+    if args.sensitivity_study:
+        sensitivity_study(args)
         return
     if args.richardson:
         richardson_study(args)
