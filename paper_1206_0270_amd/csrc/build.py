@@ -3,13 +3,15 @@
 hipcc compiles the kernels (tk_kernels.hip, tk_layer.hip) and the host C++ (setup, C ABI)
 and links them into paper_1206_0270_amd/libtk.so.  Objects go to _build/.
 
-Every kernel must run without scratch memory: the build reads the compiler's
-resource report of each kernel and fails if one uses scratch (register spills
-or private arrays kept in memory).  Launch shapes that spilled registers are
-the only ones that ever computed wrong values here (the cross-lane column
-exchange reads a neighbour's register whatever that lane's state), and a
-private array in scratch turns register reads into memory traffic inside the
-march.  The report goes to _build/kernel_resources.txt.
+Every kernel must run without spills: the build reads the compiler's resource
+report of each kernel and fails if one uses scratch memory (register spills or
+private arrays kept in memory) or accumulation registers (which, with no
+matrix-core code here, only ever hold spilled values).  A spill inside a
+divergent region saves and restores only the active lanes, and the cross-lane
+column exchange reads a neighbour's register whatever that lane's state:
+launch shapes that spilled are the only ones that ever computed wrong values
+here.  A private array in scratch also turns register reads into memory
+traffic inside the march.  The report goes to _build/kernel_resources.txt.
 """
 import os
 import re
@@ -93,10 +95,13 @@ def build(verbose=False, extra=()):
             f.write(f"{name} {r}\n")
     if not report:
         raise RuntimeError("no kernel resource report from hipcc")
-    bad = {k: v for k, v in report.items() if v.get("ScratchSize", 0) > 0 or v.get("VGPRs Spill", 0) > 0}
+    # No kernel here uses the matrix cores, so accumulation registers would
+    # only hold spilled values, which are refused like scratch spills.
+    bad = {k: v for k, v in report.items()
+           if v.get("ScratchSize", 0) > 0 or v.get("VGPRs Spill", 0) > 0 or v.get("AGPRs", 0) > 0}
     if bad:
-        raise RuntimeError("kernels using scratch memory (spills or private arrays in memory): "
-                           + "; ".join(f"{k}: {v}" for k, v in bad.items()))
+        raise RuntimeError("kernels spilling registers (to scratch memory or to accumulation registers) or keeping "
+                           "private arrays in memory: " + "; ".join(f"{k}: {v}" for k, v in bad.items()))
     for src in HOST_SOURCES:
         obj = os.path.join(BUILD, src + ".o")
         run([HIPCC, *COMMON, "-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", *extra, "-c",
