@@ -97,8 +97,10 @@ def valu_entry(name, wl, updates_per_s):
     """Vector-ALU issue figures of the kernel from the committed rocprofv3
     SQ counter summary, if taken on the current kernel source: VALU busy
     fraction, wave64 VALU instructions per point update, resident waves per
-    SIMD, and the update rate at which the VALU would be busy every cycle at
-    the clock measured under load (the issue ceiling)."""
+    SIMD, executed floating-point operations per update, and the update rate
+    at which every SIMD would issue one VALU instruction every cycle at the
+    2.4 GHz peak clock (the issue peak; 1024 SIMDs, 16 lanes each, so a wave64
+    instruction takes 4 cycles)."""
     path = os.path.join(ROOT, "profiles", "issue.json")
     if not os.path.exists(path):
         return None
@@ -108,11 +110,10 @@ def valu_entry(name, wl, updates_per_s):
         ent = data.get(f"{name}:{wl}")
         if not ent or ent.get("kernel_hash") != kernel_hash():
             return None
-        # 1024 SIMDs, 16 FP64/FP32 lanes each: a wave64 VALU instruction takes 4 cycles
-        ceiling = 1024 * ent["clock_hz"] * 64 / (4 * ent["lane_instr_per_update"])
+        peak = 1024 * 2.4e9 * 64 / (4 * ent["lane_instr_per_update"])
         return {"valu_busy": ent["valu_busy"], "lane_instr_per_update": ent["lane_instr_per_update"],
-                "waves_per_simd": ent["waves_per_simd"], "clock_hz": ent["clock_hz"],
-                "issue_ceiling_updates_per_s": ceiling, "frac_of_issue_ceiling": updates_per_s / ceiling,
+                "waves_per_simd": ent["waves_per_simd"], "flops_per_update_executed": ent["flops_per_update_executed"],
+                "issue_peak_updates_per_s": peak, "frac_of_issue_peak": updates_per_s / peak,
                 "source": ent.get("source")}
     except Exception:
         return None
