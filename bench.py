@@ -494,6 +494,7 @@ def layer_throughput(args):
     tuning = st.get_tuning()
     tuning["graph_steps"] = 100
     st.set_tuning(**tuning)
+    st.prepare(args.layer_steps)  # work list and graph capture, outside the timed region
     st.step(args.layer_warmup)
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
