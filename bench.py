@@ -473,9 +473,10 @@ def richardson_study(args):
 
 
 def layer_throughput(args):
-    """Step rate of the layer's two-pass kernels on a batch that fills the
-    GPU: the fifth workload's six modes (m = 2, 3, 4 x a = 0.5, 0.9; 16001 x 129
-    on [-300, 300]M), each ending in a layer on [250, 300]M, sourced."""
+    """Step rate of a layered batch that fills the GPU, with the kernel the
+    autotuner picks: the fifth workload's six modes (m = 2, 3, 4 x a = 0.5,
+    0.9; 16001 x 129 on [-300, 300]M), each ending in a layer on [250, 300]M,
+    sourced."""
     import torch
     from paper_1206_0270_amd import tk
     from paper_1206_0270_amd import workloads as W
@@ -509,9 +510,9 @@ def layer_throughput(args):
     ups_t = pts_t * args.layer_steps / (ms_t / 1e3)
     print(f"# throughput: {pts_t} points, {args.layer_steps} steps in {ms_t / 1e3:.2f} s", file=sys.stderr,
           flush=True)
-    # state traffic per update: one read and one write (64 B) for the single-pass kernel; the two-pass
-    # kernels also write and read the half-step array and read u^n twice (160 B)
-    lay_bytes = 160.0 if tuning["kernel"] == tk.TK_KERNEL_TWO_PASS else 64.0
+    # state traffic per update: one read and one write (64 B) for a one-step pass, half that for the
+    # two-step pass; the two-pass kernels also write and read the half-step array and read u^n twice (160 B)
+    lay_bytes = {tk.TK_KERNEL_TWO_PASS: 160.0, tk.TK_KERNEL_FUSED2: 32.0}.get(tuning["kernel"], 64.0)
     return {"workload": "6 x 16001 x 129 on [-300,300]M, layers on [250,300]M, sourced", "points": pts_t,
             "steps": args.layer_steps, "ms_per_step": ms_t / args.layer_steps, "updates_per_s": ups_t,
             "tuning": tuning, "bytes_per_update": lay_bytes, "achieved_GBps": ups_t * lay_bytes / 1e9,

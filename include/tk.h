@@ -94,8 +94,8 @@ typedef struct {
      * max(0, rstar_min) < R, R + 2h <= rstar_max, and a particle source
      * confined to rho < R.  In TK_FP32_COMP the columns whose stencil reaches
      * into the layer are computed in FP64 on the stored (compensated) values.
-     * A context with a layered instance steps one step per pass (see
-     * tk_kernel). */
+     * See tk_kernel for the kernels that step a context with a layered
+     * instance. */
     double layer_start;
 } tk_instance_desc;
 
@@ -163,14 +163,19 @@ typedef enum {
                                to give the marching kernels enough waves;
                                results are bitwise those of FUSED */
 } tk_kernel;
-/* A context with a hyperboloidal layer (tk_instance_desc.layer_start) steps
- * one step per pass.  AUTO and FUSED: FUSED on the columns whose stencil
- * stays below the layer and the layer's single-pass kernel over the layer's
- * columns; TWO_PASS: the layer's half-step and full-step passes over whole
- * instances (the same results up to rounding order).  rows_per_tile is then
- * the chunk of rows of FUSED's work items (0 = whole columns; the layer's
- * kernel beside it marches chunks of 8 rows), or of the two passes' (0 = 16);
- * FUSED2 and TILED are refused with TK_E_INVALID. */
+/* A context with a hyperboloidal layer (tk_instance_desc.layer_start):
+ * TK_FP64: AUTO, FUSED2 and FUSED march whole instances as for plain ones,
+ * in a form that takes the layer's coefficients beyond rho = R and
+ * extrapolates the null-infinity column inside the pass (one u^n row in
+ * flight: prefetch_rows is ignored); FUSED2 is again bitwise FUSED.
+ * TWO_PASS: the layer's half-step and full-step passes over whole instances
+ * (rows_per_tile: rows per chunk, 0 = 16; the same results as FUSED up to
+ * rounding order).  TK_FP32_COMP: AUTO and FUSED step one step per pass,
+ * FUSED on the columns whose stencil stays below the layer and the layer's
+ * single-pass FP64 kernel over the layer's columns (rows_per_tile is the
+ * chunk of rows of FUSED's work items; the layer's kernel marches chunks of
+ * 8 rows).  TILED, and FUSED2 in TK_FP32_COMP, are refused with
+ * TK_E_INVALID. */
 
 enum {
     TK_TUNE_NT_STORES = 1 /* fused kernel: non-temporal stores of u^{n+1} */

@@ -32,6 +32,7 @@ struct tk_ctx {
     std::vector<WorkItem> work;        // fused decomposition
     int work_rows = 0;                 // rows_per_tile the work list was built for
     int work_cols = 0;                 // strip width it was built for
+    bool work_chunked = false;         // it holds chunks of rows (the two-step pass takes its chunked form)
     size_t work_cap = 0;               // capacity of the work list area (items)
     std::vector<DevInst> hdev;         // host mirror of the device descriptors
     std::vector<std::vector<Radial>> hrad;   // host copies of the coefficient tables
@@ -116,30 +117,6 @@ std::string validate(const tk_instance_desc &d)
     return "";
 }
 
-// Fused work list: strips of `cols` output columns x chunks of rows,
-// longest first (waves are dispatched roughly in order).
-void build_work(tk_ctx *c, int rows, int cols, int min_rows)
-{
-    c->work.clear();
-    for (size_t k = 0; k < c->inst.size(); ++k) {
-        const tk_instance_desc &d = c->inst[k].desc;
-        int rc = rows > 0 ? std::max(rows, min_rows) : d.n_theta;
-        for (int j0 = 0; j0 < d.n_theta; j0 += rc) {
-            int j1 = std::min(d.n_theta, j0 + rc);
-            // keep a pole chunk at least min_rows rows (the one-step pole
-            // extrapolation needs rows 1, 2; a two-step chunk keeps four rows
-            // from a pole it does not hold)
-            if (d.n_theta - j1 > 0 && d.n_theta - j1 < min_rows) j1 = d.n_theta;
-            for (int i0 = 0; i0 < d.n_r; i0 += cols) c->work.push_back(WorkItem{(int)k, i0, j0, j1});
-            if (j1 == d.n_theta) break;
-        }
-    }
-    std::stable_sort(c->work.begin(), c->work.end(),
-                     [](const WorkItem &x, const WorkItem &y) { return (x.j1 - x.j0) > (y.j1 - y.j0); });
-    c->work_rows = rows;
-    c->work_cols = cols;
-}
-
 // First output column whose stencil reaches into the layer (the half node
 // i + 1/2 beyond rho = R); n_r for an instance without a layer.
 int layer_first_column(const HostInst &h)
@@ -149,6 +126,46 @@ int layer_first_column(const HostInst &h)
     int i = 0;
     while (i < d.n_r && !(d.rstar_min + (i + 0.5) * h.h > d.layer_start)) ++i;
     return i;
+}
+
+// Fused work list: strips of `cols` output columns (lanes i0 - halo ..
+// i0 - halo + 63) x chunks of `rows` rows, longest first (waves are
+// dispatched roughly in order).  rows == 0: whole strips, except that a
+// strip whose lanes reach a hyperboloidal layer is cut into chunks of
+// kLayerStripRows rows: the layer's waves take longer per row, and whole
+// strips all run at once, so that they would set the pass's time.
+void build_work(tk_ctx *c, int rows, int cols, int min_rows, int halo)
+{
+    c->work.clear();
+    c->work_chunked = false;
+    for (size_t k = 0; k < c->inst.size(); ++k) {
+        const tk_instance_desc &d = c->inst[k].desc;
+        const int iL = layer_first_column(c->inst[k]);
+        for (int i0 = 0; i0 < d.n_r; i0 += cols) {
+            // an instance ending in a hyperboloidal layer: its last strip
+            // holds its last three columns, the null-infinity column and
+            // the two it is extrapolated from (columns the strip shares
+            // with the one before are written twice with equal values)
+            const bool last = d.layer_start != 0.0 && i0 + cols >= d.n_r;
+            const int s0 = last ? std::max(0, std::min(i0, d.n_r - 3)) : i0;
+            const bool touch = d.layer_start != 0.0 && s0 - halo + 63 >= iL;
+            const int rc = rows > 0 ? std::max(rows, min_rows) : touch ? kLayerStripRows : d.n_theta;
+            for (int j0 = 0; j0 < d.n_theta; j0 += rc) {
+                int j1 = std::min(d.n_theta, j0 + rc);
+                // keep a pole chunk at least min_rows rows (the one-step pole
+                // extrapolation needs rows 1, 2; a two-step chunk keeps four rows
+                // from a pole it does not hold)
+                if (d.n_theta - j1 > 0 && d.n_theta - j1 < min_rows) j1 = d.n_theta;
+                c->work.push_back(WorkItem{(int)k, s0, j0, j1});
+                c->work_chunked = c->work_chunked || j1 - j0 < d.n_theta;
+                if (j1 == d.n_theta) break;
+            }
+        }
+    }
+    std::stable_sort(c->work.begin(), c->work.end(),
+                     [](const WorkItem &x, const WorkItem &y) { return (x.j1 - x.j0) > (y.j1 - y.j0); });
+    c->work_rows = rows;
+    c->work_cols = cols;
 }
 
 // Strips of `cols` columns from column i0s to the end of instance k (or to
@@ -309,13 +326,25 @@ DevInst make_dev(const tk_ctx *c, const HostInst &h)
     D.src_ramp_inv = h.src.ramp > 0.0 ? 1.0 / h.src.ramp : 0.0;
     D.a2 = d.a * d.a;
     D.kct = -2.0 * d.s * d.a;
+    const size_t k = (size_t)(&h - c->inst.data());  // h is an element of c->inst
+    const bool lay = d.layer_start != 0.0 && k < c->off_lay.size();
+    D.lay = lay ? ws + c->off_lay[k] : nullptr;
+    D.lay_on = lay ? 1 : 0;
+    D.lay_c0 = layer_first_column(h);
     return D;
+}
+
+// Whether a layered context steps with the layer kernels (the compensated
+// form's split step, or the two-pass layer step) rather than with the
+// marching kernels over whole instances (FP64 one- and two-step).
+bool layer_kernels(const tk_ctx *c, int kernel)
+{
+    return c->layered && (c->prec != TK_FP64 || kernel == TK_KERNEL_TWO_PASS);
 }
 
 int resolve_kernel(const tk_ctx *c)
 {
-    if (c->layered)  // the layer's kernels: single pass, or half pass + full pass
-        return c->tuning.kernel == TK_KERNEL_TWO_PASS ? TK_KERNEL_TWO_PASS : TK_KERNEL_FUSED;
+    if (c->layered && c->prec != TK_FP64) return TK_KERNEL_FUSED;  // the split step
     int k = c->tuning.kernel;
     if (k == TK_KERNEL_AUTO) k = c->tuning.rows_per_tile == 0 ? TK_KERNEL_FUSED2 : TK_KERNEL_FUSED;
     if (c->prec != TK_FP64 && k == TK_KERNEL_TWO_PASS) k = TK_KERNEL_FUSED;
@@ -324,7 +353,7 @@ int resolve_kernel(const tk_ctx *c)
 
 tk_status ensure_work(tk_ctx *c, int kernel)
 {
-    if (c->layered) {
+    if (layer_kernels(c, kernel)) {
         const int rows = c->tuning.rows_per_tile;
         const bool split = kernel != TK_KERNEL_TWO_PASS;
         const int cols = split ? kLayerFusedCols : kLayerCols;
@@ -343,7 +372,7 @@ tk_status ensure_work(tk_ctx *c, int kernel)
     const int rows = c->tuning.rows_per_tile;
     const int cols = kernel == TK_KERNEL_FUSED2 ? kFused2Cols : kFusedCols;
     if (!c->work.empty() && c->work_rows == rows && c->work_cols == cols) return TK_OK;
-    build_work(c, rows, cols, kernel == TK_KERNEL_FUSED2 ? 4 : 3);
+    build_work(c, rows, cols, kernel == TK_KERNEL_FUSED2 ? 4 : 3, kernel == TK_KERNEL_FUSED2 ? 2 : 1);
     if (c->work.size() > c->work_cap) return fail(c, TK_E_STATE, "work list exceeds its reserved area");
     TK_HIP(c, hipMemcpyAsync(c->ws + c->off_work, c->work.data(), c->work.size() * sizeof(WorkItem),
                              hipMemcpyHostToDevice, c->stream));
@@ -357,7 +386,7 @@ hipError_t launch_one(tk_ctx *c, int kernel, int steps, int kstep, int kflip)
 {
     const DevInst *di = (const DevInst *)(c->ws + c->off_inst);
     const DevCtl *ctl = (const DevCtl *)(c->ws + c->off_ctl);
-    if (c->layered) {
+    if (layer_kernels(c, kernel)) {
         // split: the one-step fused kernel below the layers, then the layer kernel over them
         if (kernel != TK_KERNEL_TWO_PASS && !c->work.empty()) {
             FusedShape f;
@@ -387,9 +416,9 @@ hipError_t launch_one(tk_ctx *c, int kernel, int steps, int kstep, int kflip)
     f.nt = (c->tuning.flags & TK_TUNE_NT_STORES) != 0;
     f.waves = c->tuning.waves_per_simd == 0 ? 1 : c->tuning.waves_per_simd;
     f.two_step = steps == 2;
-    f.chunked = c->tuning.rows_per_tile > 0;
+    f.chunked = c->work_chunked;
     return launch_fused(c->prec == TK_FP64, di, wk, (int)c->work.size(), c->work_cols, ctl, kstep, kflip, f,
-                        c->stream);
+                        c->stream, c->layered);
 }
 
 // The launches of n steps: pairs of steps with the two-step kernel, the
@@ -918,10 +947,11 @@ tk_status tk_set_tuning(tk_ctx *c, const tk_tuning *t)
         return fail(c, TK_E_INVALID, "the two-step kernel takes whole strips (rows_per_tile 0) or chunks of >= 4 rows");
     if (t->kernel == TK_KERNEL_TWO_PASS && c->prec != TK_FP64)
         return fail(c, TK_E_INVALID, "the two-pass kernel is FP64 only");
-    if (c->layered && t->kernel != TK_KERNEL_AUTO && t->kernel != TK_KERNEL_FUSED && t->kernel != TK_KERNEL_TWO_PASS)
+    if (c->layered && t->kernel == TK_KERNEL_TILED)
+        return fail(c, TK_E_INVALID, "the tiled kernel has no hyperboloidal layer form");
+    if (c->layered && c->prec != TK_FP64 && t->kernel == TK_KERNEL_FUSED2)
         return fail(c, TK_E_INVALID,
-                    "a context with a hyperboloidal layer steps with the layer's kernels (AUTO or FUSED: one pass; "
-                    "TWO_PASS: half and full passes)");
+                    "a compensated-form context with a hyperboloidal layer steps one step at a time (AUTO or FUSED)");
     if (t->rows_per_tile < 0 || (t->rows_per_tile > 0 && t->rows_per_tile < 3))
         return fail(c, TK_E_INVALID, "rows_per_tile must be 0 or >= 3");
     if (t->graph_steps < 0 || t->graph_steps > 100000) return fail(c, TK_E_INVALID, "graph_steps out of range");
@@ -1021,11 +1051,18 @@ static tk_status autotune_run(tk_ctx *c, int warmup, int steps, char *save, cons
     for (int rows : {8, 4})
         for (int ntf : {(int)TK_TUNE_NT_STORES, 0}) cand.push_back(tk_tuning{TK_KERNEL_TILED, rows, 0, 3, ntf, 0});
     if (c->prec == TK_FP64) cand.push_back(tk_tuning{TK_KERNEL_TWO_PASS, 0, 0, 3, TK_TUNE_NT_STORES, 0});
-    if (c->layered) {  // the layer kernels: one pass or two, rows per chunk
+    if (c->layered) {
         cand.clear();
-        for (int rows : {0, 8, 32, 64}) cand.push_back(tk_tuning{TK_KERNEL_FUSED, rows, 0, 3, TK_TUNE_NT_STORES, 0});
-        if (c->prec == TK_FP64)
+        if (c->prec == TK_FP64) {
+            // the layered marching kernels (one u^n row in flight), and the
+            // layer's two-pass step
+            for (int rows : {0, 32, 16})
+                for (int ntf : {(int)TK_TUNE_NT_STORES, 0}) cand.push_back(tk_tuning{TK_KERNEL_FUSED2, rows, 0, 1, ntf, 0});
+            for (int rows : {0, 64, 16}) cand.push_back(tk_tuning{TK_KERNEL_FUSED, rows, 0, 1, TK_TUNE_NT_STORES, 0});
             for (int rows : {0, 32}) cand.push_back(tk_tuning{TK_KERNEL_TWO_PASS, rows, 0, 3, TK_TUNE_NT_STORES, 0});
+        } else {  // the split step, rows per chunk of its one-step part
+            for (int rows : {0, 8, 32, 64}) cand.push_back(tk_tuning{TK_KERNEL_FUSED, rows, 0, 3, TK_TUNE_NT_STORES, 0});
+        }
     }
 
     tk_status st = e == hipSuccess ? TK_OK : fail(c, TK_E_DEVICE, std::string("autotune setup: ") + hipGetErrorString(e));

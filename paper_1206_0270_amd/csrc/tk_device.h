@@ -191,6 +191,16 @@ __device__ __forceinline__ double inv_sqrt(double x)
     y = fma(y, fma(-hx * y, y, 0.5), y);
     return y;
 }
+// 1/x from the hardware estimate and two Newton steps y <- y + y (1 - x y)
+// (each squares the relative error): within an ulp or two of the rounded
+// quotient, for x finite and away from zero and the denormal range.
+__device__ __forceinline__ double recip(double x)
+{
+    double y = __builtin_amdgcn_rcp(x);
+    y = fma(y, fma(-x, y, 1.0), y);
+    y = fma(y, fma(-x, y, 1.0), y);
+    return y;
+}
 __device__ __forceinline__ float inv_sqrt(float x)
 {
     float y = __builtin_amdgcn_rsqf(x);
@@ -227,12 +237,16 @@ struct AngF {
     T sa, sn2, kcs, V2, kc;
 };
 
-// Coefficients of the fused bracket at one point: bh = b/h, dh = d/h, ct,
-// c0a = c0 - 2 A2f, and the row weights Ap, Am = (A2f +- A1f)/2.
+// Coefficients of the fused bracket at one point: bh = b/h (the Phi row's
+// speed; bih the Pi row's, the same value outside a hyperboloidal layer),
+// dh = d/h, ct, c0a = c0 - 2 A2f, and the row weights Ap, Am = (A2f +-
+// A1f)/2; with Sh2 = Sigma-hat^2 and sig = 1/Sigma-hat for the layer's
+// transformation.
 template <typename T>
 struct CoefF {
-    T bh, Ap, Am;
+    T bh, bih, Ap, Am;
     cx<T> ct, c0a, dh;
+    T Sh2, sig;
 };
 
 template <typename T>
@@ -242,7 +256,10 @@ __device__ __forceinline__ CoefF<T> coef_fused(const RadF<T> &R, const AngF<T> &
     const T Sh2 = fma(-R.D2h, A.sa, R.rho2);
     const T sig = inv_sqrt(Sh2);
     const T W = sig * sig;
+    c.Sh2 = Sh2;
+    c.sig = sig;
     c.bh = R.rho_h * sig;
+    c.bih = c.bh;
     const T A2 = R.D2h * W;  // A2f / 2
     const T A1 = A2 * A.kc;  // A1f / 2
     c.Ap = A2 + A1;
@@ -272,8 +289,8 @@ __device__ __forceinline__ Q4<T> bracket_fused(const CoefF<T> &c, cx<T> pm, cx<T
                           fma(c.c0a.re, ph0.im, fma(c.c0a.im, ph0.re, fma(c.Ap, pp.im, fma(c.Am, pm.im, F.im))))));
     Q4<T> br;
     br.phi = mkc(fma(c.bh, du.phi.re, -pi0.re), fma(c.bh, du.phi.im, -pi0.im));
-    br.pi = mkc(fma(c.dh.re, du.phi.re, fma(-c.dh.im, du.phi.im, fma(-c.bh, du.pi.re, -sre))),
-                fma(c.dh.re, du.phi.im, fma(c.dh.im, du.phi.re, fma(-c.bh, du.pi.im, -sim))));
+    br.pi = mkc(fma(c.dh.re, du.phi.re, fma(-c.dh.im, du.phi.im, fma(-c.bih, du.pi.re, -sre))),
+                fma(c.dh.re, du.phi.im, fma(c.dh.im, du.phi.re, fma(-c.bih, du.pi.im, -sim))));
     return br;
 }
 

@@ -69,11 +69,18 @@ struct alignas(16) DevInst {
     const AngularF *angf;  // [n_theta]
     double *wave;          // [wave_cap][n_theta][2]
     // source
-    int src_kind, pad1, pad2, pad3;
+    int src_kind;
+    int lay_c0;  // first column whose half node lies beyond rho = R (n_r without a layer)
+    int pad2, pad3;
     double src_amp, src_phase0, src_Omega, src_rstar_p;
     double src_sig_r, src_sig_th, src_win, src_t0;
     double a2, kct;        // a^2 and -2 s a (to rebuild a^2 Delta and Im ct's cos part)
     double src_ramp_inv, pad6;  // 1 / T_on of the source's switch-on (0: none)
+    // hyperboloidal layer: the instance's LayerTab table [2 n_r - 1] (the
+    // map factors rho', H, rho'' per radial position), or null without one
+    // (its first column: lay_c0 above)
+    const void *lay;
+    long long lay_on;
 };
 
 // Fused-kernel work item: a block of columns [i0, i0 + width) x rows [j0, j1)

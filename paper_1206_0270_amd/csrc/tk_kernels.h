@@ -31,9 +31,15 @@ struct FusedShape {
 // of 64 lanes per block.  One step: the strips are `cols` output columns
 // wide (at most kFusedCols) and may be split in rows; two steps: strips of
 // kFused2Cols columns over all rows.  Buffers as for the two-pass step.
-// Returns hipErrorInvalidValue for a shape that is not compiled.
+// Returns hipErrorInvalidValue for a shape that is not compiled.  layered
+// (FP64 only): the instances may end in hyperboloidal layers (the layer's
+// coefficients beyond rho = R, the null-infinity column extrapolated inside
+// the march); the work list must keep each layered instance's last column at
+// least two columns into a strip's output columns.  The layered form is
+// compiled with one u^n row in flight (the prefetch depth is ignored).
 hipError_t launch_fused(bool fp64, const DevInst *d_inst, const WorkItem *d_work, int n_work, int cols,
-                        const DevCtl *ctl, int kstep, int kflip, const FusedShape &f, hipStream_t s);
+                        const DevCtl *ctl, int kstep, int kflip, const FusedShape &f, hipStream_t s,
+                        bool layered = false);
 
 // One step on tiles: one block of kFusedWavesPerBlock waves per work item
 // (strips of kFusedCols columns split into chunks of `rows` rows, 4 or 8),
@@ -49,6 +55,9 @@ hipError_t launch_bump(DevCtl *ctl, int n, int flips, hipStream_t s);
 // and time step.
 constexpr int kFusedCols = 62;
 constexpr int kFused2Cols = 60;
+// Rows per chunk of a marching strip that reaches a hyperboloidal layer when
+// the other strips run whole.
+constexpr int kLayerStripRows = 32;
 constexpr int kFusedWavesPerBlock = 4;
 
 }  // namespace tk

@@ -11,6 +11,7 @@
 
 #include "tk_device.h"
 #include "tk_kernels.h"
+#include "tk_layer.h"
 
 namespace tk {
 
@@ -184,9 +185,20 @@ struct PolicyF64 {
     static constexpr bool kComp = false;
     static constexpr bool kRadRegs = true;  // radial factors in registers (else LDS)
     static constexpr bool kMaskHalo = false;  // lanes off the grid load and compute unmasked
+    static constexpr bool kLayer = false;     // instances may end in a hyperboloidal layer
     static constexpr int kPD = PD;
     static constexpr bool kNT = NT;
     static constexpr int kWaves = W;
+};
+// The FP64 form for contexts whose instances may end in a hyperboloidal
+// layer (Section 2.3, item 2): the layer's coefficients on the lanes beyond
+// rho = R, and the null-infinity column extrapolated inside the march.  The
+// kernels run it on the waves that reach the layer only; the others run
+// the plain form (Plain), so that their code is the plain kernels' own.
+template <int PD, bool NT, int W>
+struct PolicyF64L : PolicyF64<PD, NT, W> {
+    static constexpr bool kLayer = true;
+    using Plain = PolicyF64<3, NT, W>;
 };
 template <int PD, bool NT, int W>
 struct PolicyF32C {
@@ -194,6 +206,7 @@ struct PolicyF32C {
     static constexpr bool kComp = true;
     static constexpr bool kRadRegs = false;
     static constexpr bool kMaskHalo = true;  // measured faster with them masked
+    static constexpr bool kLayer = false;
     static constexpr int kPD = PD;
     static constexpr bool kNT = NT;
     static constexpr int kWaves = W;
@@ -316,6 +329,13 @@ struct Lane {
     bool near_h, near_n;  // half node / node lies on the source window
     double gh, gn;        // tabulated A g_r there
     T dt;
+    // hyperboloidal layer (kLayer): the lane's map factors in LDS (rho', H,
+    // rho'' of the half node at lf[0], lf[64], lf[128], of the node 192
+    // further on), whether the half node and the node lie in the layer,
+    // whether any lane of the wave has one in it, and whether this lane
+    // holds (any lane of the wave holds) the null-infinity column
+    const double *lf;
+    bool lay_h, lay_n, wlay, scri, wscri;
 };
 
 template <class P>
@@ -551,6 +571,44 @@ __device__ __forceinline__ Q4<T> comp_diff(const St<T> &x1, const St<T> &x0)
     return (x1.f - x0.f) + (x1.c - x0.c);
 }
 
+// The layer system's coefficients at a point beyond rho = R (Section 2.3,
+// item 2), from the plain ones in the fused kernels' factored form.  With the
+// map factors rho', H, rho'' of the point (lf[0], lf[64], lf[128]),
+// w = rho' b + (1 - b) and v = 1 + H b: the Phi row's speed becomes
+// b rho' / w, the Pi row's b rho' / v, d becomes d rho' / (w^2 v), ct becomes
+// (ct w + d H + b^2 rho' rho'' - b H b') / (w v), and the angular weights and
+// c0 (so the folded c0a) take the factor 1 / (w v).  Near null infinity 1 - b
+// is below the rounding of b, so it is formed as -X / Dn with
+// X = a^2 Delta sin^2 and Dn = Sh (Sh + rho); then w = num / Dn with
+// num = rho' b Dn - X, and one reciprocal r = 1 / (num v) gives
+// 1/w = Dn v r, 1/v = num r and 1/(w v) = Dn r.
+__device__ __forceinline__ void layer_transform(CoefF<double> &c, const RadF<double> &R, const AngF<double> &A,
+                                                const double *lf, double h)
+{
+    const double rhop = lf[0], H = lf[64], rhopp = lf[128];
+    const double b = c.bh * h;
+    const double rho = R.rho_h * h;
+    const double Sh = c.Sh2 * c.sig;
+    const double Dn = Sh * (Sh + rho);
+    const double num = fma(rhop * b, Dn, -(R.D2h * A.sa));
+    const double v = fma(H, b, 1.0);
+    const double r = recip(num * v);  // num v = w v Dn > 0 in the layer
+    const double fw = Dn * r;
+    const double iw = fw * v, iv = num * r;
+    const double bp = R.K * A.sn2 * (c.sig * c.sig) * c.sig;  // b' = K sin^2 W sig
+    const double dre = c.dh.re * h, dim = c.dh.im * h;
+    const double g = b * b * rhop * rhopp - b * H * bp;
+    c.ct = mk(fma(c.ct.re, iv, fma(dre, H, g) * fw), fma(c.ct.im, iv, dim * H * fw));
+    const double bh = c.bh * rhop;
+    c.bh = bh * iw;
+    c.bih = bh * iv;
+    const double dd = rhop * iw * fw;
+    c.dh = mk(c.dh.re * dd, c.dh.im * dd);
+    c.Ap *= fw;
+    c.Am *= fw;
+    c.c0a = mk(c.c0a.re * fw, c.c0a.im * fw);
+}
+
 // What the stage at a point needs from beyond its own column.  FP64: Phi on
 // rows j -+ 1 and the whole row j of the neighbouring column.  Compensated:
 // the neighbour's row j (value and term), and the angular differences of Phi
@@ -587,7 +645,9 @@ __device__ __forceinline__ Half<P> half_core(const Lane<P> &L, const Level &lv, 
     if constexpr (!P::kComp) {
         const Q4<T> du = nb.z - U0.f;
         const Q4<T> bar = mid_from(U0.f, du);
-        const CoefF<T> cf = coef_fused(radf_of(L, 0), angf_of<P>(I, r));
+        CoefF<T> cf = coef_fused(radf_of(L, 0), angf_of<P>(I, r));
+        if constexpr (P::kLayer)
+            if (L.wlay && L.lay_h) layer_transform(cf, radf_of(L, 0), angf_of<P>(I, r), L.lf, I.h);
         Q4<T> br = bracket_fused(cf, nb.m + UM.f.phi, nb.p + UP.f.phi, bar.phi, bar.pi, du, no_source<T>());
         add_source(L.gh, I, r, lv.eh, br);
         return lw_update(bar, fac, br);
@@ -669,7 +729,9 @@ __device__ __forceinline__ St<typename P::T> out_core(const Lane<P> &L, const Le
     if constexpr (!P::kComp) {
         const Q4<T> du = H0 - nb.z;
         const Q4<T> til = mid_from(nb.z, du);
-        const CoefF<T> cf = coef_fused(radf_of(L, 1), angf_of<P>(I, o));
+        CoefF<T> cf = coef_fused(radf_of(L, 1), angf_of<P>(I, o));
+        if constexpr (P::kLayer)
+            if (L.wlay && L.lay_n) layer_transform(cf, radf_of(L, 1), angf_of<P>(I, o), L.lf + 192, I.h);
         Q4<T> br = bracket_fused(cf, HM.phi + nb.m, HP.phi + nb.p, til.phi, til.pi, du, no_source<T>());
         add_source(L.gn, I, o, lv.ef, br);
         res.f = lw_update(Uo.f, L.dt, br);
@@ -720,7 +782,19 @@ __device__ __forceinline__ St<typename P::T> out_row(const Lane<P> &L, const Lev
         nb.nb.d2 = shfl_up1<P>(nb.own.d2);
         nb.nb.d1 = shfl_up1<P>(nb.own.d1);
     }
-    return out_core(L, lv, Uo, HM, H0, HP, nb, o);
+    St<typename P::T> v = out_core(L, lv, Uo, HM, H0, HP, nb, o);
+    if constexpr (P::kLayer) {
+        if (L.wscri) {
+            // null infinity (Section 2.3, item 2): no characteristic enters,
+            // the last node takes the linear extrapolation 2 u_{N-2} - u_{N-3}
+            // of the new values of the two columns to its left
+            const Q4<typename P::T> a = shfl_up1<P>(v.f), b = shfl_up1<P>(a);
+            if (L.scri)
+                v.f = Q4<typename P::T>{mkc(2.0 * a.phi.re - b.phi.re, 2.0 * a.phi.im - b.phi.im),
+                                        mkc(2.0 * a.pi.re - b.pi.re, 2.0 * a.pi.im - b.pi.im)};
+        }
+    }
+    return v;
 }
 
 template <class P>
@@ -993,7 +1067,8 @@ __device__ __forceinline__ void march2c(const Lane<P> &L, const Level &l1, const
 // lane's radial factors (half node, node) go to its LDS slots.
 template <class P>
 __device__ __forceinline__ void init_lane(Lane<P> &L, const DevInst &I, const WorkItem &it, int lane, int halo,
-                                          int cols, int buf, typename P::T *rad, bool load_rad = true)
+                                          int cols, int buf, typename P::T *rad, bool load_rad = true,
+                                          double *lay = nullptr)
 {
     using T = typename P::T;
     L.I = &I;
@@ -1043,29 +1118,46 @@ __device__ __forceinline__ void init_lane(Lane<P> &L, const DevInst &I, const Wo
     L.gn = L.icol ? Rn.srcg : 0.0;
     L.near_h = L.gh != 0.0;
     L.near_n = L.gn != 0.0;
+    if constexpr (P::kLayer) {
+        // the map factors go to the wave's LDS area (lay: this lane's
+        // column of it), read back by this lane only
+        const TK_GLOBAL LayerTab *tab = I.lay_on ? gload_ptr((const LayerTab *)I.lay) : nullptr;
+        LayerTab th{0.0, 0.0, 0.0, 0.0}, tn{0.0, 0.0, 0.0, 0.0};
+        if (tab != nullptr && L.hv) th = load_entry(tab + (2 * L.c + 1));
+        if (tab != nullptr && L.icol) tn = load_entry(tab + 2 * L.c);
+        L.lay_h = th.H != 0.0;
+        L.lay_n = tn.H != 0.0;
+        lay[0] = th.rhop;
+        lay[64] = th.H;
+        lay[128] = th.rhopp;
+        lay[192] = tn.rhop;
+        lay[256] = tn.H;
+        lay[320] = tn.rhopp;
+        L.lf = lay;
+        L.scri = tab != nullptr && L.c == nr - 1;
+        L.wlay = __any(L.lay_h || L.lay_n) != 0;
+        L.wscri = __any(L.scri) != 0;
+    }
+}
+
+// Whether a wave whose lanes hold columns i0 - halo .. i0 - halo + 63 of the
+// item's instance reaches its layer: lay_c0 is the first column with a half
+// node (so with every later node) beyond rho = R, and the null-infinity
+// column lies beyond it.
+__device__ __forceinline__ bool touches_layer(const DevInst &I, const WorkItem &it, int halo)
+{
+    return I.lay_on != 0 && it.i0 - halo + 63 >= I.lay_c0;
 }
 
 }  // namespace
 
-// One step.  The wave index within the block is made uniform explicitly so
-// that the work item, the instance descriptor and the angular tables are
-// read with scalar loads into scalar registers.
+// One wave's work item of k_fused (the kernel picks the form).
 template <class P>
-__global__ void __launch_bounds__(64 * kFusedWavesPerBlock) __attribute__((amdgpu_waves_per_eu(P::kWaves, 8)))
-    k_fused(const DevInst *__restrict__ insts, const WorkItem *__restrict__ work, int n_work, int cols,
-            const DevCtl *__restrict__ ctl, int kstep, int kflip)
+__device__ __forceinline__ void k_fused_wave(const DevInst &I, const WorkItem &it, int lane, int cols, int buf,
+                                              typename P::T *rad, double *lay, long long n)
 {
-    using T = typename P::T;
-    __shared__ T s_rad[kFusedWavesPerBlock][P::kRadRegs ? 2 : 2 * kRadF * 64];
-    const int lane = (int)(threadIdx.x & 63);
-    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int w = (int)blockIdx.x * kFusedWavesPerBlock + wv;
-    if (w >= n_work) return;  // whole wave leaves together; no block barriers below
-    const WorkItem it = work[w];
-    const DevInst &I = insts[it.inst];
-    const long long n = ctl->step + kstep;
     Lane<P> L;
-    init_lane(L, I, it, lane, 1, cols, (int)((ctl->cur + kflip) & 1), &s_rad[wv][2 * lane]);
+    init_lane(L, I, it, lane, 1, cols, buf, rad, true, lay);
     const Level lv = make_level(I, n);
 
     const int nt = I.n_theta;
@@ -1103,6 +1195,35 @@ __global__ void __launch_bounds__(64 * kFusedWavesPerBlock) __attribute__((amdgp
         default: south<P, 2>(L, lv, R); break;
         }
     }
+}
+
+// One step.  The wave index within the block is made uniform explicitly so
+// that the work item, the instance descriptor and the angular tables are
+// read with scalar loads into scalar registers.
+template <class P>
+__global__ void __launch_bounds__(64 * kFusedWavesPerBlock) __attribute__((amdgpu_waves_per_eu(P::kWaves, 8)))
+    k_fused(const DevInst *__restrict__ insts, const WorkItem *__restrict__ work, int n_work, int cols,
+            const DevCtl *__restrict__ ctl, int kstep, int kflip)
+{
+    using T = typename P::T;
+    __shared__ T s_rad[kFusedWavesPerBlock][P::kRadRegs ? 2 : 2 * kRadF * 64];
+    __shared__ double s_lay[kFusedWavesPerBlock][P::kLayer ? 6 * 64 : 1];
+    const int lane = (int)(threadIdx.x & 63);
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int w = (int)blockIdx.x * kFusedWavesPerBlock + wv;
+    if (w >= n_work) return;  // whole wave leaves together; no block barriers below
+    const WorkItem it = work[w];
+    const DevInst &I = insts[it.inst];
+    const long long n = ctl->step + kstep;
+    const int buf = (int)((ctl->cur + kflip) & 1);
+    if constexpr (P::kLayer) {
+        // a wave whose columns all stay below the layer runs the plain form
+        if (!touches_layer(I, it, 1)) {
+            k_fused_wave<typename P::Plain>(I, it, lane, cols, buf, &s_rad[wv][2 * lane], nullptr, n);
+            return;
+        }
+    }
+    k_fused_wave<P>(I, it, lane, cols, buf, &s_rad[wv][2 * lane], &s_lay[wv][P::kLayer ? lane : 0], n);
 }
 
 namespace {
@@ -1296,25 +1417,13 @@ __global__ void __launch_bounds__(64 * kFusedWavesPerBlock)
         emit(L, lv, nt - 1, pole_row<P>(even, lds_get<P>(s_p, 128 + lane), lds_get<P>(s_p, 192 + lane)));
 }
 
-// Two steps (n -> n+2) in one pass over whole column strips: u^n is read
-// and u^{n+2} written once; u^{n+1} exists only in registers (and in the
-// waveform ring when sampled).
+// One wave's work item of k_fused2 (the kernel picks the form).
 template <class P>
-__global__ void __launch_bounds__(64 * kFusedWavesPerBlock) __attribute__((amdgpu_waves_per_eu(P::kWaves, 8)))
-    k_fused2(const DevInst *__restrict__ insts, const WorkItem *__restrict__ work, int n_work,
-             const DevCtl *__restrict__ ctl, int kstep, int kflip)
+__device__ __forceinline__ void k_fused2_wave(const DevInst &I, const WorkItem &it, int lane, int cols, int buf,
+                                               typename P::T *rad, double *lay, long long n)
 {
-    using T = typename P::T;
-    __shared__ T s_rad[kFusedWavesPerBlock][P::kRadRegs ? 2 : 2 * kRadF * 64];
-    const int lane = (int)(threadIdx.x & 63);
-    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int w = (int)blockIdx.x * kFusedWavesPerBlock + wv;
-    if (w >= n_work) return;  // whole wave leaves together; no block barriers below
-    const WorkItem it = work[w];
-    const DevInst &I = insts[it.inst];
-    const long long n = ctl->step + kstep;
     Lane<P> L;
-    init_lane(L, I, it, lane, 2, kFused2Cols, (int)((ctl->cur + kflip) & 1), &s_rad[wv][2 * lane]);
+    init_lane(L, I, it, lane, 2, cols, buf, rad, true, lay);
     const Level l1 = make_level(I, n), l2 = make_level(I, n + 1);
     const int nt = I.n_theta;  // >= 5: the six head iterations all exist
 
@@ -1342,17 +1451,17 @@ __global__ void __launch_bounds__(64 * kFusedWavesPerBlock) __attribute__((amdgp
     if (r + 5 <= nt + 2) march2<P, 2, true>(L, l1, l2, R, r + 5);
 }
 
-// The two-step kernel on chunks of rows (for workloads whose whole strips
-// give too few waves): the same march as k_fused2 over the iterations of
-// the chunk, level 1 recomputing the u^{n+1} rows of the halo.  Bitwise the
-// results of k_fused2 and k_fused.
+// Two steps (n -> n+2) in one pass over whole column strips: u^n is read
+// and u^{n+2} written once; u^{n+1} exists only in registers (and in the
+// waveform ring when sampled).
 template <class P>
 __global__ void __launch_bounds__(64 * kFusedWavesPerBlock) __attribute__((amdgpu_waves_per_eu(P::kWaves, 8)))
-    k_fused2c(const DevInst *__restrict__ insts, const WorkItem *__restrict__ work, int n_work,
-              const DevCtl *__restrict__ ctl, int kstep, int kflip)
+    k_fused2(const DevInst *__restrict__ insts, const WorkItem *__restrict__ work, int n_work,
+             const DevCtl *__restrict__ ctl, int kstep, int kflip)
 {
     using T = typename P::T;
     __shared__ T s_rad[kFusedWavesPerBlock][P::kRadRegs ? 2 : 2 * kRadF * 64];
+    __shared__ double s_lay[kFusedWavesPerBlock][P::kLayer ? 6 * 64 : 1];
     const int lane = (int)(threadIdx.x & 63);
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int w = (int)blockIdx.x * kFusedWavesPerBlock + wv;
@@ -1360,8 +1469,24 @@ __global__ void __launch_bounds__(64 * kFusedWavesPerBlock) __attribute__((amdgp
     const WorkItem it = work[w];
     const DevInst &I = insts[it.inst];
     const long long n = ctl->step + kstep;
+    const int buf = (int)((ctl->cur + kflip) & 1);
+    if constexpr (P::kLayer) {
+        // a wave whose columns all stay below the layer runs the plain form
+        if (!touches_layer(I, it, 2)) {
+            k_fused2_wave<typename P::Plain>(I, it, lane, kFused2Cols, buf, &s_rad[wv][2 * lane], nullptr, n);
+            return;
+        }
+    }
+    k_fused2_wave<P>(I, it, lane, kFused2Cols, buf, &s_rad[wv][2 * lane], &s_lay[wv][P::kLayer ? lane : 0], n);
+}
+
+// One wave's work item of k_fused2c (the kernel picks the form).
+template <class P>
+__device__ __forceinline__ void k_fused2c_wave(const DevInst &I, const WorkItem &it, int lane, int cols, int buf,
+                                                typename P::T *rad, double *lay, long long n)
+{
     Lane<P> L;
-    init_lane(L, I, it, lane, 2, kFused2Cols, (int)((ctl->cur + kflip) & 1), &s_rad[wv][2 * lane]);
+    init_lane(L, I, it, lane, 2, cols, buf, rad, true, lay);
     const Level l1 = make_level(I, n), l2 = make_level(I, n + 1);
     const Chunk2 B = chunk2_of(I.n_theta, it.j0, it.j1);
     // every check holds from iteration steady_lo on and through steady_hi
@@ -1387,6 +1512,36 @@ __global__ void __launch_bounds__(64 * kFusedWavesPerBlock) __attribute__((amdgp
         if (r + 1 <= B.r_hi) march2c<P, 1, true>(L, l1, l2, R, r + 1, B);
         if (r + 2 <= B.r_hi) march2c<P, 2, true>(L, l1, l2, R, r + 2, B);
     }
+}
+
+// The two-step kernel on chunks of rows (for workloads whose whole strips
+// give too few waves): the same march as k_fused2 over the iterations of
+// the chunk, level 1 recomputing the u^{n+1} rows of the halo.  Bitwise the
+// results of k_fused2 and k_fused.
+template <class P>
+__global__ void __launch_bounds__(64 * kFusedWavesPerBlock) __attribute__((amdgpu_waves_per_eu(P::kWaves, 8)))
+    k_fused2c(const DevInst *__restrict__ insts, const WorkItem *__restrict__ work, int n_work,
+              const DevCtl *__restrict__ ctl, int kstep, int kflip)
+{
+    using T = typename P::T;
+    __shared__ T s_rad[kFusedWavesPerBlock][P::kRadRegs ? 2 : 2 * kRadF * 64];
+    __shared__ double s_lay[kFusedWavesPerBlock][P::kLayer ? 6 * 64 : 1];
+    const int lane = (int)(threadIdx.x & 63);
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int w = (int)blockIdx.x * kFusedWavesPerBlock + wv;
+    if (w >= n_work) return;  // whole wave leaves together; no block barriers below
+    const WorkItem it = work[w];
+    const DevInst &I = insts[it.inst];
+    const long long n = ctl->step + kstep;
+    const int buf = (int)((ctl->cur + kflip) & 1);
+    if constexpr (P::kLayer) {
+        // a wave whose columns all stay below the layer runs the plain form
+        if (!touches_layer(I, it, 2)) {
+            k_fused2c_wave<typename P::Plain>(I, it, lane, kFused2Cols, buf, &s_rad[wv][2 * lane], nullptr, n);
+            return;
+        }
+    }
+    k_fused2c_wave<P>(I, it, lane, kFused2Cols, buf, &s_rad[wv][2 * lane], &s_lay[wv][P::kLayer ? lane : 0], n);
 }
 
 template <class P>
@@ -1464,9 +1619,24 @@ hipError_t launch_tiled(bool fp64, const DevInst *d_inst, const WorkItem *d_work
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_fused(bool fp64, const DevInst *d_inst, const WorkItem *d_work, int n_work, int cols,
-                        const DevCtl *ctl, int kstep, int kflip, const FusedShape &f, hipStream_t s)
+// The layered form is compiled with one u^n row in flight only: with three,
+// the layer's extra coefficient work needs more registers than two waves per
+// SIMD leave, and the compiler would spill.
+hipError_t launch_layered(const DevInst *d_inst, const WorkItem *d_work, int n_work, int cols, const DevCtl *ctl,
+                          int kstep, int kflip, const FusedShape &f, hipStream_t s)
 {
+    if (f.waves != 1) return hipErrorInvalidValue;
+    if (f.nt)
+        return launch_as<PolicyF64L<1, true, 1>>(d_inst, d_work, n_work, cols, ctl, kstep, kflip, f.two_step,
+                                                 f.chunked, s);
+    return launch_as<PolicyF64L<1, false, 1>>(d_inst, d_work, n_work, cols, ctl, kstep, kflip, f.two_step, f.chunked,
+                                              s);
+}
+
+hipError_t launch_fused(bool fp64, const DevInst *d_inst, const WorkItem *d_work, int n_work, int cols,
+                        const DevCtl *ctl, int kstep, int kflip, const FusedShape &f, hipStream_t s, bool layered)
+{
+    if (fp64 && layered) return launch_layered(d_inst, d_work, n_work, cols, ctl, kstep, kflip, f, s);
     if (fp64) return launch_variant<PolicyF64>(d_inst, d_work, n_work, cols, ctl, kstep, kflip, f, s);
     return launch_variant<PolicyF32C>(d_inst, d_work, n_work, cols, ctl, kstep, kflip, f, s);
 }

@@ -119,12 +119,14 @@ def test_layer_graph_and_chunks_bitwise():
 
 
 def test_layer_row_chunks_kernels_and_autotune():
-    """Two forms step a layered context: the single pass (AUTO, FUSED: the
-    one-step fused kernel below the layers, the layer kernel over them) and
-    the two-pass layer kernels over whole instances.  Within each form every
-    chunking of rows (3, 8, 64, whole columns; 16 by default) gives the same
-    bits; the two forms agree to rounding (they order the interior arithmetic
-    differently), and so does the autotuner's choice."""
+    """Three forms step a layered FP64 context: the two-step marching pass
+    (AUTO, FUSED2), the one-step marching pass (FUSED), both with the layer's
+    coefficients beyond rho = R and null infinity extrapolated inside the
+    pass, and the two-pass layer kernels.  FUSED2 is bitwise FUSED, whole
+    strips or chunks of rows (and an odd step count); within each form every
+    chunking of rows gives the same bits; the two-pass form agrees to
+    rounding (it orders the interior arithmetic differently), and so does the
+    autotuner's choice."""
     insts = layered_instances()
     ref = {}
     for kernel in (tk.TK_KERNEL_FUSED, tk.TK_KERNEL_TWO_PASS):
@@ -134,6 +136,16 @@ def test_layer_row_chunks_kernels_and_autotune():
             for x, y in zip(ref[kernel], got):
                 for u, v in zip(x, y):
                     assert np.array_equal(u, v), (kernel, rows)
+    for rows in (0, 4, 16):
+        got = gpu_run(insts, 120, rows=rows, kernel=tk.TK_KERNEL_FUSED2)
+        for x, y in zip(ref[tk.TK_KERNEL_FUSED], got):
+            for u, v in zip(x, y):
+                assert np.array_equal(u, v), ("FUSED2", rows)
+    odd = gpu_run(insts, 121, kernel=tk.TK_KERNEL_FUSED2)
+    odd1 = gpu_run(insts, 121, kernel=tk.TK_KERNEL_FUSED)
+    for x, y in zip(odd1, odd):
+        for u, v in zip(x, y):
+            assert np.array_equal(u, v), "odd step count"
     auto = gpu_run(insts, 120)
     for x, y in zip(ref[tk.TK_KERNEL_FUSED], auto):
         for u, v in zip(x, y):
@@ -142,6 +154,45 @@ def test_layer_row_chunks_kernels_and_autotune():
     for inst, a, b, c in zip(insts, ref[tk.TK_KERNEL_FUSED], ref[tk.TK_KERNEL_TWO_PASS], tuned):
         for u, v, w in zip(a, b, c):
             assert rel(v, u) <= 1e-13 and rel(w, u) <= 1e-13, inst["name"]
+
+
+@pytest.mark.parametrize("n_r", [121, 122, 125, 126])
+def test_layer_last_strip_holds_null_infinity(n_r):
+    """Radial sizes that leave the marching kernels' last strip (62 columns
+    one-step, 60 two-step) with one or two columns: that strip is moved back
+    to hold the last three, so that null infinity is extrapolated inside it.
+    Against the oracle, and the two-step pass bitwise the one-step one."""
+    S = 40.0
+    h = (S + 40.0) / (n_r - 1)
+    inst = W.instance(a=0.7, m=2, n_r=n_r, n_theta=11, rstar_min=-40.0, rstar_max=S, layer_start=20.0,
+                      dt=W.stable_dt(0.7, 2, -2, h, 11), rstar_obs=S, extract_every=3,
+                      init=dict(center=10.0, width=3.0, amps={2: 1.0 - 0.5j}), name=f"layer.{n_r}x11.tail")
+    steps = 300
+    one, = gpu_run([inst], steps, kernel=tk.TK_KERNEL_FUSED)
+    two, = gpu_run([inst], steps, kernel=tk.TK_KERNEL_FUSED2)
+    for u, v in zip(one, two):
+        assert np.array_equal(u, v)
+    check(inst, steps, two, oracle_run(inst, steps))
+
+
+def test_layer_strips_chunked_beside_whole_ones():
+    """With whole strips asked for (rows_per_tile 0), the strips whose lanes
+    reach the layer are cut into chunks of 32 rows and the others run whole,
+    in one pass of the chunked two-step kernel.  73 rows (chunks of 32, 32,
+    9): bitwise the one-step pass and uniform chunks, and the oracle."""
+    S = 40.0
+    n_r, n_th = 250, 73
+    h = (S + 40.0) / (n_r - 1)
+    inst = W.instance(a=0.9, m=2, n_r=n_r, n_theta=n_th, rstar_min=-40.0, rstar_max=S, layer_start=20.0,
+                      dt=W.stable_dt(0.9, 2, -2, h, n_th), rstar_obs=S, extract_every=5,
+                      init=dict(center=10.0, width=3.0, amps={2: 1.0, 3: 0.25j}), name="layer.250x73.mixed")
+    steps = 160
+    mixed, = gpu_run([inst], steps, kernel=tk.TK_KERNEL_FUSED2)
+    for kernel, rows in ((tk.TK_KERNEL_FUSED, 0), (tk.TK_KERNEL_FUSED2, 16)):
+        other, = gpu_run([inst], steps, kernel=kernel, rows=rows)
+        for u, v in zip(mixed, other):
+            assert np.array_equal(u, v), (kernel, rows)
+    check(inst, steps, mixed, oracle_run(inst, steps))
 
 
 def test_layer_second_workload_size():
@@ -183,10 +234,15 @@ def test_layer_rejections():
             st.set_tuning(kernel=tk.TK_KERNEL_TWO_PASS)
     finally:
         st.close()
+    st = tk.Stepper([inst], precision=tk.TK_FP32_COMP)
+    try:
+        with pytest.raises(tk.TkError):   # the compensated form's layered step is the split one-step pass
+            st.set_tuning(kernel=tk.TK_KERNEL_FUSED2)
+    finally:
+        st.close()
     st = tk.Stepper([inst])
     try:
-        with pytest.raises(tk.TkError):
-            st.set_tuning(kernel=tk.TK_KERNEL_FUSED2)
+        st.set_tuning(kernel=tk.TK_KERNEL_FUSED2)
         with pytest.raises(tk.TkError):
             st.set_tuning(kernel=tk.TK_KERNEL_TILED, rows_per_tile=4)
         with pytest.raises(tk.TkError):   # the particle inside the layer

@@ -8,6 +8,8 @@ import subprocess
 
 import pytest
 
+from paper_1206_0270_amd.csrc import build as libbuild
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 BUILD = os.path.join(ROOT, "_build")
 SAN = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", "-g", "-O1"]
@@ -49,7 +51,7 @@ def test_host_library_entry_points_under_sanitizers():
     # the library's host code (C ABI, validation, work lists, layout, post-
     # processing) rebuilt with the sanitizers and driven from C without a
     # device; the kernels' objects are linked as built
-    kobjs = [os.path.join(BUILD, k) for k in ("tk_kernels.hip.o", "tk_layer.hip.o")]
+    kobjs = [os.path.join(BUILD, k + ".o") for k in libbuild.HIP_SOURCES]
     if not all(os.path.exists(k) for k in kobjs):
         pytest.skip("build the library first (its kernels' objects are linked here)")
     out = os.path.join(BUILD, "san")
