@@ -472,6 +472,15 @@ def richardson_study(args):
     print(json.dumps(out), flush=True)
 
 
+def state_bytes_per_update(kernel):
+    """FP64 state traffic per update of a layered context's step: one read and
+    one write (64 B) for a one-step pass, half that for the two-step pass; the
+    two-pass layer kernels also write and read the half-step array and read
+    u^n twice (160 B)."""
+    from paper_1206_0270_amd import tk
+    return {tk.TK_KERNEL_TWO_PASS: 160.0, tk.TK_KERNEL_FUSED2: 32.0}.get(kernel, 64.0)
+
+
 def layer_throughput(args):
     """Step rate of a layered batch that fills the GPU, with the kernel the
     autotuner picks: the fifth workload's six modes (m = 2, 3, 4 x a = 0.5,
@@ -510,9 +519,7 @@ def layer_throughput(args):
     ups_t = pts_t * args.layer_steps / (ms_t / 1e3)
     print(f"# throughput: {pts_t} points, {args.layer_steps} steps in {ms_t / 1e3:.2f} s", file=sys.stderr,
           flush=True)
-    # state traffic per update: one read and one write (64 B) for a one-step pass, half that for the
-    # two-step pass; the two-pass kernels also write and read the half-step array and read u^n twice (160 B)
-    lay_bytes = {tk.TK_KERNEL_TWO_PASS: 160.0, tk.TK_KERNEL_FUSED2: 32.0}.get(tuning["kernel"], 64.0)
+    lay_bytes = state_bytes_per_update(tuning["kernel"])
     return {"workload": "6 x 16001 x 129 on [-300,300]M, layers on [250,300]M, sourced", "points": pts_t,
             "steps": args.layer_steps, "ms_per_step": ms_t / args.layer_steps, "updates_per_s": ups_t,
             "tuning": tuning, "bytes_per_update": lay_bytes, "achieved_GBps": ups_t * lay_bytes / 1e9,
@@ -528,7 +535,8 @@ def layer_study(args):
     its wall within the window.  The projected waveform at r* = 50M of the two
     short domains against the long one's, over the window after the direct
     signal arrives; the waveform at null infinity beside it; and the step
-    rate of the layer's two-pass kernels.  One JSON line."""
+    rates of the contexts, with the kernels the autotuner picks.  One JSON
+    line."""
     import numpy as np
     import torch
     from paper_1206_0270_amd import tk
@@ -593,7 +601,7 @@ def layer_study(args):
     thr = layer_throughput(args)
     w_scri = out["layer"]["waves"][1][:n]
     tail = times >= T - 100.0
-    lay_bytes = 64.0  # the single-pass layer kernel: u^n read once, u^{n+1} written once
+    lay_bytes = state_bytes_per_update(out["layer"]["kernel"])
     ups = out["layer"]["updates_per_s"]
     res = {
         "metric": "hyperboloidal layer: waveform at r*=50M against a domain 7x longer; step rate of its kernels",
