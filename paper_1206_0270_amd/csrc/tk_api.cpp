@@ -38,9 +38,10 @@ struct tk_ctx {
     std::vector<std::vector<Radial>> hrad;   // host copies of the coefficient tables
     std::vector<std::vector<Angular>> hang;
     std::vector<std::vector<AngularF>> hangf;
-    // hyperboloidal layer: any instance with one makes the context step one
-    // step per pass, split by columns (the one-step fused kernel below the
-    // layers, the layer kernel over them) or with the layer's two passes
+    // hyperboloidal layer: any instance with one makes the context step with
+    // the marching kernels' layered form (FP64), the compensated form's split
+    // step (the one-step fused kernel below the layers, the layer kernel over
+    // them), or the layer's two passes (FP64, TWO_PASS)
     bool layered = false;
     size_t off_linst = 0;              // LayerInst per instance
     std::vector<size_t> off_lay;       // LayerTab table per instance (layered ones)
