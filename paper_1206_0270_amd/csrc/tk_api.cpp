@@ -1018,6 +1018,30 @@ tk_status tk_autotune_bytes(const tk_ctx *c, size_t *bytes)
     return TK_OK;
 }
 
+// Rows per chunk that fill the device with two-step waves when whole strips
+// do not: the smallest chunks (at least 4 rows) that keep the work list
+// within one wave per slot at two waves per SIMD, so that all of it runs at
+// once with the least halo recomputed; 0 when whole strips already give at
+// least that many waves.
+static int fill_rows(const tk_ctx *c)
+{
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess || cus <= 0)
+        return 0;
+    const long slots = 2L * 4L * cus;
+    long strips = 0;
+    int nt_max = 0;
+    for (const HostInst &h : c->inst) {
+        strips += (h.desc.n_r + kFused2Cols - 1) / kFused2Cols;
+        nt_max = std::max(nt_max, h.desc.n_theta);
+    }
+    if (strips <= 0 || strips >= slots) return 0;
+    const long per = slots / strips;  // chunks per strip
+    if (per < 2) return 0;
+    const int rows = (int)((nt_max + per - 1) / per);
+    return rows >= 4 && rows < nt_max ? rows : 0;
+}
+
 // Time every candidate launch shape on the context's own instances and keep
 // the fastest; the state, step counter and waveform rings are saved to `save`
 // (device memory of at least the spans' total) and restored afterwards.
@@ -1043,7 +1067,10 @@ static tk_status autotune_run(tk_ctx *c, int warmup, int steps, char *save, cons
     // and the two-pass kernel (FP64)
     const int shapes[][3] = {{3, 1, 0}, {3, 0, 0}, {1, 1, 0}, {1, 0, 0}};
     std::vector<tk_tuning> cand;
-    for (int rows : {0, 32, 16})
+    std::vector<int> rows2 = {0, 32, 16};
+    const int fill = fill_rows(c);
+    if (fill > 0 && fill != 16 && fill != 32) rows2.push_back(fill);
+    for (int rows : rows2)
         for (const auto &sh : shapes)
             cand.push_back(tk_tuning{TK_KERNEL_FUSED2, rows, 0, sh[0], sh[1] ? TK_TUNE_NT_STORES : 0, sh[2]});
     for (int rows : {0, 64, 16})
