@@ -472,12 +472,14 @@ def richardson_study(args):
     print(json.dumps(out), flush=True)
 
 
-def state_bytes_per_update(kernel):
-    """FP64 state traffic per update of a layered context's step: one read and
-    one write (64 B) for a one-step pass, half that for the two-step pass; the
-    two-pass layer kernels also write and read the half-step array and read
-    u^n twice (160 B)."""
+def state_bytes_per_update(kernel, precision="fp64"):
+    """State traffic per update of a layered context's step: one read and one
+    write (64 B FP64, 48 B for the compensated storage) for a one-step pass,
+    half that for the two-step pass; the two-pass layer kernels (FP64) also
+    write and read the half-step array and read u^n twice (160 B)."""
     from paper_1206_0270_amd import tk
+    if precision == "fp32c":
+        return 48.0  # the compensated form's layered step is one step per pass
     return {tk.TK_KERNEL_TWO_PASS: 160.0, tk.TK_KERNEL_FUSED2: 32.0}.get(kernel, 64.0)
 
 
@@ -485,7 +487,7 @@ def layer_throughput(args):
     """Step rate of a layered batch that fills the GPU, with the kernel the
     autotuner picks: the fifth workload's six modes (m = 2, 3, 4 x a = 0.5,
     0.9; 16001 x 129 on [-300, 300]M), each ending in a layer on [250, 300]M,
-    sourced."""
+    sourced; in the precision --precision names."""
     import torch
     from paper_1206_0270_amd import tk
     from paper_1206_0270_amd import workloads as W
@@ -497,7 +499,7 @@ def layer_throughput(args):
     dt_t = min(i["dt"] for i in thr)
     for i in thr:
         i["dt"] = dt_t
-    st = tk.Stepper(thr)
+    st = tk.Stepper(thr, precision=tk.TK_FP32_COMP if args.precision == "fp32c" else tk.TK_FP64)
     for k, i in enumerate(thr):
         st.set_fields(k, *W.initial_data(i))
     st.autotune(warmup=2, steps=10)
@@ -519,8 +521,9 @@ def layer_throughput(args):
     ups_t = pts_t * args.layer_steps / (ms_t / 1e3)
     print(f"# throughput: {pts_t} points, {args.layer_steps} steps in {ms_t / 1e3:.2f} s", file=sys.stderr,
           flush=True)
-    lay_bytes = state_bytes_per_update(tuning["kernel"])
-    return {"workload": "6 x 16001 x 129 on [-300,300]M, layers on [250,300]M, sourced", "points": pts_t,
+    lay_bytes = state_bytes_per_update(tuning["kernel"], args.precision)
+    return {"workload": "6 x 16001 x 129 on [-300,300]M, layers on [250,300]M, sourced", "precision": args.precision,
+            "points": pts_t,
             "steps": args.layer_steps, "ms_per_step": ms_t / args.layer_steps, "updates_per_s": ups_t,
             "tuning": tuning, "bytes_per_update": lay_bytes, "achieved_GBps": ups_t * lay_bytes / 1e9,
             "frac_of_8TBps": ups_t * lay_bytes / 8e12}
