@@ -277,10 +277,13 @@ tk_status tk_set_tuning(tk_ctx *ctx, const tk_tuning *t);
 tk_status tk_get_tuning(const tk_ctx *ctx, tk_tuning *t);
 
 /* Autotuner: time every compiled launch shape (kernel, u^n prefetch depth,
- * store kind; rows per tile 0, 32 and 16 for the two-step kernel, 0, 64 and
- * 16 for the one-step kernel, 8 and 4 for the tiled kernel) on this
- * context's own instances and keep the fastest; graph_steps stays as it
- * was.  Each candidate runs `warmup` untimed and then `steps` timed steps
+ * store kind; rows per tile 0, 32 and 16 for the two-step kernel, and, when
+ * whole strips give fewer waves than two per SIMD of the device, the
+ * smallest chunk of at least 4 rows that keeps the work list within that
+ * many waves; 0, 64 and 16 for the one-step kernel, 8 and 4 for the tiled
+ * kernel; a context with a hyperboloidal layer tries the shapes of its own
+ * forms, see tk_kernel) on this context's own instances and keep the
+ * fastest; graph_steps stays as it was.  Each candidate runs `warmup` untimed and then `steps` timed steps
  * (both rounded up to even), timed with HIP events on the context's stream.
  * The state, the step counter and the waveform rings are copied to
  * save_area and restored afterwards, so the simulation is left as it was
