@@ -285,8 +285,9 @@ void layout(tk_ctx *c)
     c->need = off;
 }
 
-DevInst make_dev(const tk_ctx *c, const HostInst &h)
+DevInst make_dev(const tk_ctx *c, size_t k)
 {
+    const HostInst &h = c->inst[k];
     DevInst D;
     std::memset(&D, 0, sizeof D);
     const tk_instance_desc &d = h.desc;
@@ -327,7 +328,6 @@ DevInst make_dev(const tk_ctx *c, const HostInst &h)
     D.src_ramp_inv = h.src.ramp > 0.0 ? 1.0 / h.src.ramp : 0.0;
     D.a2 = d.a * d.a;
     D.kct = -2.0 * d.s * d.a;
-    const size_t k = (size_t)(&h - c->inst.data());  // h is an element of c->inst
     const bool lay = d.layer_start != 0.0 && k < c->off_lay.size();
     D.lay = lay ? ws + c->off_lay[k] : nullptr;
     D.lay_on = lay ? 1 : 0;
@@ -600,7 +600,7 @@ tk_status tk_bind_workspace(tk_ctx *c, void *dev_ptr, size_t bytes)
         for (int j = 0; j < h.desc.n_theta; ++j)
             angf[j] = AngularF{(float)ang[j].sa, (float)ang[j].sn2, (float)ang[j].kcs, (float)ang[j].V2,
                                (float)ang[j].cot_h, 0.0f, 0.0f, 0.0f};
-        c->hdev[k] = make_dev(c, h);
+        c->hdev[k] = make_dev(c, k);
         hipError_t e = hipMemcpyAsync(c->ws + h.off_rad, rad.data(), rad.size() * sizeof(Radial),
                                       hipMemcpyHostToDevice, c->stream);
         if (e == hipSuccess)
@@ -802,7 +802,7 @@ tk_status tk_set_source(tk_ctx *c, int inst, const tk_source_desc *src)
     h.src = s;
     h.src_Omega = Om;
     h.src_rstar_p = rsp;
-    c->hdev[inst] = make_dev(c, h);
+    c->hdev[inst] = make_dev(c, (size_t)inst);
     fill_source(h, c->hrad[inst].data(), c->hang[inst].data());
     TK_HIP(c, hipMemcpyAsync(c->ws + h.off_rad, c->hrad[inst].data(), c->hrad[inst].size() * sizeof(Radial),
                              hipMemcpyHostToDevice, c->stream));
