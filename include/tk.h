@@ -92,10 +92,8 @@ typedef struct {
      * there), so rstar_obs = rstar_max samples the waveform at null
      * infinity.  Requires s = -2 (whose Phi has a finite limit there),
      * max(0, rstar_min) < R, R + 2h <= rstar_max, and a particle source
-     * confined to rho < R.  In TK_FP32_COMP the columns whose stencil reaches
-     * into the layer are computed in FP64 on the stored (compensated) values.
-     * See tk_kernel for the kernels that step a context with a layered
-     * instance. */
+     * confined to rho < R.  See tk_kernel for the kernels that step a
+     * context with a layered instance. */
     double layer_start;
 } tk_instance_desc;
 
@@ -164,18 +162,17 @@ typedef enum {
                                results are bitwise those of FUSED */
 } tk_kernel;
 /* A context with a hyperboloidal layer (tk_instance_desc.layer_start):
- * TK_FP64: AUTO, FUSED2 and FUSED march whole instances as for plain ones,
- * in a form that takes the layer's coefficients beyond rho = R and
- * extrapolates the null-infinity column inside the pass (one u^n row in
- * flight: prefetch_rows is ignored); FUSED2 is again bitwise FUSED.
- * TWO_PASS: the layer's half-step and full-step passes over whole instances
- * (rows_per_tile: rows per chunk, 0 = 16; the same results as FUSED up to
- * rounding order).  TK_FP32_COMP: AUTO and FUSED step one step per pass,
- * FUSED on the columns whose stencil stays below the layer and the layer's
- * single-pass FP64 kernel over the layer's columns (rows_per_tile is the
- * chunk of rows of FUSED's work items; the layer's kernel marches chunks of
- * 8 rows).  TILED, and FUSED2 in TK_FP32_COMP, are refused with
- * TK_E_INVALID. */
+ * AUTO, FUSED2 and FUSED march whole instances as for plain ones, in a form
+ * that takes the layer's coefficients beyond rho = R and extrapolates the
+ * null-infinity column inside the pass (one u^n row in flight:
+ * prefetch_rows is ignored); FUSED2 is again bitwise FUSED.  In
+ * TK_FP32_COMP the layer's coefficients are in the compensated form's FP32
+ * arithmetic and the null-infinity column is formed in double from the
+ * stored pairs.  With rows_per_tile 0 the strips that reach a layer run in
+ * chunks of 32 rows, the others whole.  TK_FP64 only, TWO_PASS: the layer's
+ * half-step and full-step passes over whole instances (rows_per_tile: rows
+ * per chunk, 0 = 16; the same results as FUSED up to rounding order).  TILED
+ * is refused with TK_E_INVALID. */
 
 enum {
     TK_TUNE_NT_STORES = 1 /* fused kernel: non-temporal stores of u^{n+1} */

@@ -335,17 +335,16 @@ DevInst make_dev(const tk_ctx *c, size_t k)
     return D;
 }
 
-// Whether a layered context steps with the layer kernels (the compensated
-// form's split step, or the two-pass layer step) rather than with the
-// marching kernels over whole instances (FP64 one- and two-step).
+// Whether a layered context steps with the layer kernels (the two-pass
+// layer step, FP64) rather than with the marching kernels' layered form over
+// whole instances (one and two steps a pass, both precisions).
 bool layer_kernels(const tk_ctx *c, int kernel)
 {
-    return c->layered && (c->prec != TK_FP64 || kernel == TK_KERNEL_TWO_PASS);
+    return c->layered && kernel == TK_KERNEL_TWO_PASS;
 }
 
 int resolve_kernel(const tk_ctx *c)
 {
-    if (c->layered && c->prec != TK_FP64) return TK_KERNEL_FUSED;  // the split step
     int k = c->tuning.kernel;
     if (k == TK_KERNEL_AUTO) k = c->tuning.rows_per_tile == 0 ? TK_KERNEL_FUSED2 : TK_KERNEL_FUSED;
     if (c->prec != TK_FP64 && k == TK_KERNEL_TWO_PASS) k = TK_KERNEL_FUSED;
@@ -950,9 +949,6 @@ tk_status tk_set_tuning(tk_ctx *c, const tk_tuning *t)
         return fail(c, TK_E_INVALID, "the two-pass kernel is FP64 only");
     if (c->layered && t->kernel == TK_KERNEL_TILED)
         return fail(c, TK_E_INVALID, "the tiled kernel has no hyperboloidal layer form");
-    if (c->layered && c->prec != TK_FP64 && t->kernel == TK_KERNEL_FUSED2)
-        return fail(c, TK_E_INVALID,
-                    "a compensated-form context with a hyperboloidal layer steps one step at a time (AUTO or FUSED)");
     if (t->rows_per_tile < 0 || (t->rows_per_tile > 0 && t->rows_per_tile < 3))
         return fail(c, TK_E_INVALID, "rows_per_tile must be 0 or >= 3");
     if (t->graph_steps < 0 || t->graph_steps > 100000) return fail(c, TK_E_INVALID, "graph_steps out of range");
@@ -1081,16 +1077,13 @@ static tk_status autotune_run(tk_ctx *c, int warmup, int steps, char *save, cons
     if (c->prec == TK_FP64) cand.push_back(tk_tuning{TK_KERNEL_TWO_PASS, 0, 0, 3, TK_TUNE_NT_STORES, 0});
     if (c->layered) {
         cand.clear();
-        if (c->prec == TK_FP64) {
-            // the layered marching kernels (one u^n row in flight), and the
-            // layer's two-pass step
-            for (int rows : {0, 32, 16})
-                for (int ntf : {(int)TK_TUNE_NT_STORES, 0}) cand.push_back(tk_tuning{TK_KERNEL_FUSED2, rows, 0, 1, ntf, 0});
-            for (int rows : {0, 64, 16}) cand.push_back(tk_tuning{TK_KERNEL_FUSED, rows, 0, 1, TK_TUNE_NT_STORES, 0});
+        // the layered marching kernels (one u^n row in flight), and the
+        // layer's two-pass step (FP64)
+        for (int rows : {0, 32, 16})
+            for (int ntf : {(int)TK_TUNE_NT_STORES, 0}) cand.push_back(tk_tuning{TK_KERNEL_FUSED2, rows, 0, 1, ntf, 0});
+        for (int rows : {0, 64, 16}) cand.push_back(tk_tuning{TK_KERNEL_FUSED, rows, 0, 1, TK_TUNE_NT_STORES, 0});
+        if (c->prec == TK_FP64)
             for (int rows : {0, 32}) cand.push_back(tk_tuning{TK_KERNEL_TWO_PASS, rows, 0, 3, TK_TUNE_NT_STORES, 0});
-        } else {  // the split step, rows per chunk of its one-step part
-            for (int rows : {0, 8, 32, 64}) cand.push_back(tk_tuning{TK_KERNEL_FUSED, rows, 0, 3, TK_TUNE_NT_STORES, 0});
-        }
     }
 
     tk_status st = e == hipSuccess ? TK_OK : fail(c, TK_E_DEVICE, std::string("autotune setup: ") + hipGetErrorString(e));

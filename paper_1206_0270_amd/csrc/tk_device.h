@@ -307,10 +307,14 @@ __device__ __forceinline__ Q4<T> bracket_fused(const CoefF<T> &c, cx<T> pm, cx<T
 // multiplied by them; here it enters relative to the differences.
 // ---------------------------------------------------------------------------
 
+// bh: the Phi row's speed over h, bih the Pi row's (the same value outside a
+// hyperboloidal layer); Sh2 = Sigma-hat^2 and sig = 1/Sigma-hat for the
+// layer's transformation.
 template <typename T>
 struct CoefD {
-    T bh, A2, A1;
+    T bh, bih, A2, A1;
     cx<T> ct, c0, dh;
+    T Sh2, sig;
 };
 
 template <typename T>
@@ -320,7 +324,10 @@ __device__ __forceinline__ CoefD<T> coef_diff(const RadF<T> &R, const AngF<T> &A
     const T Sh2 = fma(-R.D2h, A.sa, R.rho2);
     const T sig = inv_sqrt(Sh2);
     const T W = sig * sig;
+    c.Sh2 = Sh2;
+    c.sig = sig;
     c.bh = R.rho_h * sig;
+    c.bih = c.bh;
     c.A2 = R.D2h * W;
     c.A1 = c.A2 * A.kc;
     const T cti = fma(R.D2h, A.kcs, R.ct_im0);
@@ -343,8 +350,8 @@ __device__ __forceinline__ Q4<T> bracket_diff(const CoefD<T> &c, cx<T> D2, cx<T>
                       fma(c.ct.im, pi0.re, fma(c.c0.re, ph0.im, fma(c.c0.im, ph0.re, fma(c.A2, D2.im, c.A1 * D1.im)))));
     Q4<T> br;
     br.phi = mkc(fma(c.bh, du.phi.re, -pi0.re), fma(c.bh, du.phi.im, -pi0.im));
-    br.pi = mkc(fma(c.dh.re, du.phi.re, fma(-c.dh.im, du.phi.im, fma(-c.bh, du.pi.re, -sre))),
-                fma(c.dh.re, du.phi.im, fma(c.dh.im, du.phi.re, fma(-c.bh, du.pi.im, -sim))));
+    br.pi = mkc(fma(c.dh.re, du.phi.re, fma(-c.dh.im, du.phi.im, fma(-c.bih, du.pi.re, -sre))),
+                fma(c.dh.re, du.phi.im, fma(c.dh.im, du.phi.re, fma(-c.bih, du.pi.im, -sim))));
     return br;
 }
 

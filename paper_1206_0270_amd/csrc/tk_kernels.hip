@@ -211,6 +211,14 @@ struct PolicyF32C {
     static constexpr bool kNT = NT;
     static constexpr int kWaves = W;
 };
+// The compensated form's layered counterpart of PolicyF64L: the layer's
+// transformation in the differences form's FP32 coefficients, null infinity
+// extrapolated from the compensated values in FP64.
+template <int PD, bool NT, int W>
+struct PolicyF32CL : PolicyF32C<PD, NT, W> {
+    static constexpr bool kLayer = true;
+    using Plain = PolicyF32C<PD, NT, W>;
+};
 
 template <typename T>
 struct St {  // stored value of a point: f (+ c in the compensated form)
@@ -609,6 +617,38 @@ __device__ __forceinline__ void layer_transform(CoefF<double> &c, const RadF<dou
     c.c0a = mk(c.c0a.re * fw, c.c0a.im * fw);
 }
 
+// The same transformation of the differences form's coefficients (FP32
+// arithmetic on the map factors rounded to it; the angular weights A2, A1 and
+// c0 take the factor 1 / (w v)).  1 - b is negative and under one per cent of
+// rho' b across the layers used here (R >= 10M, a <= 0.99), so w is formed in
+// FP32 without cancellation.
+__device__ __forceinline__ void layer_transform(CoefD<float> &c, const RadF<float> &R, const AngF<float> &A,
+                                                const double *lf, float h)
+{
+    const float rhop = (float)lf[0], H = (float)lf[64], rhopp = (float)lf[128];
+    const float b = c.bh * h;
+    const float rho = R.rho_h * h;
+    const float Sh = c.Sh2 * c.sig;
+    const float Dn = Sh * (Sh + rho);
+    const float num = fmaf(rhop * b, Dn, -(R.D2h * A.sa));
+    const float v = fmaf(H, b, 1.0f);
+    const float r = 1.0f / (num * v);
+    const float fw = Dn * r;
+    const float iw = fw * v, iv = num * r;
+    const float bp = R.K * A.sn2 * (c.sig * c.sig) * c.sig;
+    const float dre = c.dh.re * h, dim = c.dh.im * h;
+    const float g = b * b * rhop * rhopp - b * H * bp;
+    c.ct = mkc(fmaf(c.ct.re, iv, fmaf(dre, H, g) * fw), fmaf(c.ct.im, iv, dim * H * fw));
+    const float bh = c.bh * rhop;
+    c.bh = bh * iw;
+    c.bih = bh * iv;
+    const float dd = rhop * iw * fw;
+    c.dh = mkc(c.dh.re * dd, c.dh.im * dd);
+    c.A2 *= fw;
+    c.A1 *= fw;
+    c.c0 = mkc(c.c0.re * fw, c.c0.im * fw);
+}
+
 // What the stage at a point needs from beyond its own column.  FP64: Phi on
 // rows j -+ 1 and the whole row j of the neighbouring column.  Compensated:
 // the neighbour's row j (value and term), and the angular differences of Phi
@@ -667,7 +707,9 @@ __device__ __forceinline__ Half<P> half_core(const Lane<P> &L, const Level &lv, 
                 be[k] = e + c[k];
             }
         }
-        const CoefD<T> cf = coef_diff(radf_of(L, 0), angf_of<P>(I, r));
+        CoefD<T> cf = coef_diff(radf_of(L, 0), angf_of<P>(I, r));
+        if constexpr (P::kLayer)
+            if (L.wlay && L.lay_h) layer_transform(cf, radf_of(L, 0), angf_of<P>(I, r), L.lf, (T)I.h);
         const Q4<T> br = bracket_diff(cf, nb.own.d2 + nb.nb.d2, nb.own.d1 + nb.nb.d1, bar.f.phi, bar.f.pi, du);
         // u^{n+1/2} = bar - (dt/2) [.] as a pair
         St<T> h;
@@ -741,7 +783,9 @@ __device__ __forceinline__ St<typename P::T> out_core(const Lane<P> &L, const Le
         const Q4<T> du = comp_diff(H0, nb.z);
         // the averaged fields enter S only through ct and c0: one FP32 value each
         const Q4<T> til = mid_from(nb.z.f, du);
-        const CoefD<T> cf = coef_diff(radf_of(L, 1), angf_of<P>(I, o));
+        CoefD<T> cf = coef_diff(radf_of(L, 1), angf_of<P>(I, o));
+        if constexpr (P::kLayer)
+            if (L.wlay && L.lay_n) layer_transform(cf, radf_of(L, 1), angf_of<P>(I, o), L.lf + 192, (T)I.h);
         const Q4<T> br = bracket_diff(cf, nb.own.d2 + nb.nb.d2, nb.own.d1 + nb.nb.d1, til.phi, til.pi, du);
         const T *bp = &br.phi.re, *fp = &Uo.f.phi.re, *cp = &Uo.c.phi.re;
         T *rf = &res.f.phi.re, *rc = &res.c.phi.re;
@@ -787,11 +831,30 @@ __device__ __forceinline__ St<typename P::T> out_row(const Lane<P> &L, const Lev
         if (L.wscri) {
             // null infinity (Section 2.3, item 2): no characteristic enters,
             // the last node takes the linear extrapolation 2 u_{N-2} - u_{N-3}
-            // of the new values of the two columns to its left
-            const Q4<typename P::T> a = shfl_up1<P>(v.f), b = shfl_up1<P>(a);
-            if (L.scri)
-                v.f = Q4<typename P::T>{mkc(2.0 * a.phi.re - b.phi.re, 2.0 * a.phi.im - b.phi.im),
-                                        mkc(2.0 * a.pi.re - b.pi.re, 2.0 * a.pi.im - b.pi.im)};
+            // of the new values of the two columns to its left (in the
+            // compensated form in double on f + c, split back into f + c)
+            using T = typename P::T;
+            if constexpr (!P::kComp) {
+                const Q4<T> a = shfl_up1<P>(v.f), b = shfl_up1<P>(a);
+                if (L.scri)
+                    v.f = Q4<T>{mkc(2.0 * a.phi.re - b.phi.re, 2.0 * a.phi.im - b.phi.im),
+                                mkc(2.0 * a.pi.re - b.pi.re, 2.0 * a.pi.im - b.pi.im)};
+            } else {
+                St<T> a, b;
+                a.f = shfl_up1<P>(v.f);
+                a.c = shfl_up1<P>(v.c);
+                b.f = shfl_up1<P>(a.f);
+                b.c = shfl_up1<P>(a.c);
+                if (L.scri) {
+                    T *of = &v.f.phi.re, *oc = &v.c.phi.re;
+                    for (int k = 0; k < 4; ++k) {
+                        const double x = 2.0 * value_of<P>(a, k) - value_of<P>(b, k);
+                        const T f = (T)x;
+                        of[k] = f;
+                        oc[k] = bf16_round((T)(x - (double)f));
+                    }
+                }
+            }
         }
     }
     return v;
@@ -1633,10 +1696,22 @@ hipError_t launch_layered(const DevInst *d_inst, const WorkItem *d_work, int n_w
                                               s);
 }
 
+hipError_t launch_layered_comp(const DevInst *d_inst, const WorkItem *d_work, int n_work, int cols, const DevCtl *ctl,
+                               int kstep, int kflip, const FusedShape &f, hipStream_t s)
+{
+    if (f.waves != 1) return hipErrorInvalidValue;
+    if (f.nt)
+        return launch_as<PolicyF32CL<1, true, 1>>(d_inst, d_work, n_work, cols, ctl, kstep, kflip, f.two_step,
+                                                  f.chunked, s);
+    return launch_as<PolicyF32CL<1, false, 1>>(d_inst, d_work, n_work, cols, ctl, kstep, kflip, f.two_step,
+                                               f.chunked, s);
+}
+
 hipError_t launch_fused(bool fp64, const DevInst *d_inst, const WorkItem *d_work, int n_work, int cols,
                         const DevCtl *ctl, int kstep, int kflip, const FusedShape &f, hipStream_t s, bool layered)
 {
     if (fp64 && layered) return launch_layered(d_inst, d_work, n_work, cols, ctl, kstep, kflip, f, s);
+    if (layered) return launch_layered_comp(d_inst, d_work, n_work, cols, ctl, kstep, kflip, f, s);
     if (fp64) return launch_variant<PolicyF64>(d_inst, d_work, n_work, cols, ctl, kstep, kflip, f, s);
     return launch_variant<PolicyF32C>(d_inst, d_work, n_work, cols, ctl, kstep, kflip, f, s);
 }

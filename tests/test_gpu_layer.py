@@ -173,6 +173,14 @@ def test_layer_last_strip_holds_null_infinity(n_r):
     for u, v in zip(one, two):
         assert np.array_equal(u, v)
     check(inst, steps, two, oracle_run(inst, steps))
+    # the compensated form: the same bitwise relation, and within its bar of FP64
+    one32, = gpu_run([inst], steps, kernel=tk.TK_KERNEL_FUSED, precision=tk.TK_FP32_COMP)
+    two32, = gpu_run([inst], steps, kernel=tk.TK_KERNEL_FUSED2, precision=tk.TK_FP32_COMP)
+    for u, v in zip(one32, two32):
+        assert np.array_equal(u, v)
+    e = [rel(a, b) for a, b in zip(two32, two)]
+    say(inst["name"], "fp32c vs fp64", [f"{x:.2e}" for x in e])
+    assert max(e) <= 2e-5, e
 
 
 def test_layer_strips_chunked_beside_whole_ones():
@@ -193,6 +201,14 @@ def test_layer_strips_chunked_beside_whole_ones():
         for u, v in zip(mixed, other):
             assert np.array_equal(u, v), (kernel, rows)
     check(inst, steps, mixed, oracle_run(inst, steps))
+    mixed32, = gpu_run([inst], steps, kernel=tk.TK_KERNEL_FUSED2, precision=tk.TK_FP32_COMP)
+    for kernel, rows in ((tk.TK_KERNEL_FUSED, 0), (tk.TK_KERNEL_FUSED2, 16)):
+        other, = gpu_run([inst], steps, kernel=kernel, rows=rows, precision=tk.TK_FP32_COMP)
+        for u, v in zip(mixed32, other):
+            assert np.array_equal(u, v), ("fp32c", kernel, rows)
+    e = [rel(a, b) for a, b in zip(mixed32, mixed)]
+    say(inst["name"], "fp32c vs fp64", [f"{x:.2e}" for x in e])
+    assert max(e) <= 2e-5, e
 
 
 def test_layer_second_workload_size():
@@ -208,10 +224,13 @@ def test_layer_second_workload_size():
 
 
 def test_layer_fp32c_vs_fp64():
-    """FP32-compensated storage with layers: k_fused's FP32C form below the
-    layers, the layer's columns in FP64 on the stored values.  Against the
-    FP64 run after 150 steps: the FP32C bar of the plain grids (fields within
-    relative L2 2e-5), the waveform at null infinity too; chunkings bitwise."""
+    """FP32-compensated storage with layers: the marching kernels' layered
+    compensated form (the layer's coefficients in the differences form's
+    FP32, null infinity extrapolated in double on f + c).  Against the FP64
+    run after 150 steps: the FP32C bar of the plain grids (fields within
+    relative L2 2e-5), the waveform at null infinity too; the two-step pass
+    (AUTO, FUSED2 in whole strips and in chunks) bitwise the one-step one in
+    any chunking, odd step counts included."""
     insts = layered_instances()
     ref = gpu_run(insts, 150)
     got = gpu_run(insts, 150, precision=tk.TK_FP32_COMP)
@@ -219,11 +238,17 @@ def test_layer_fp32c_vs_fp64():
         e = dict(phi=rel(p32, p64), pi=rel(q32, q64), wave=rel(w32, w64))
         say(inst["name"], "fp32c vs fp64", {k: f"{v:.2e}" for k, v in e.items()})
         assert max(e.values()) <= 2e-5, e
-    for rows in (3, 64):
-        again = gpu_run(insts, 150, precision=tk.TK_FP32_COMP, rows=rows)
+    for kernel, rows in ((tk.TK_KERNEL_FUSED, 0), (tk.TK_KERNEL_FUSED, 3), (tk.TK_KERNEL_FUSED, 64),
+                         (tk.TK_KERNEL_FUSED2, 4), (tk.TK_KERNEL_FUSED2, 16)):
+        again = gpu_run(insts, 150, precision=tk.TK_FP32_COMP, rows=rows, kernel=kernel)
         for x, y in zip(got, again):
             for u, v in zip(x, y):
-                assert np.array_equal(u, v), rows
+                assert np.array_equal(u, v), (kernel, rows)
+    odd = gpu_run(insts, 151, precision=tk.TK_FP32_COMP, kernel=tk.TK_KERNEL_FUSED2)
+    odd1 = gpu_run(insts, 151, precision=tk.TK_FP32_COMP, kernel=tk.TK_KERNEL_FUSED)
+    for x, y in zip(odd1, odd):
+        for u, v in zip(x, y):
+            assert np.array_equal(u, v), "odd step count"
 
 
 def test_layer_rejections():
@@ -236,8 +261,9 @@ def test_layer_rejections():
         st.close()
     st = tk.Stepper([inst], precision=tk.TK_FP32_COMP)
     try:
-        with pytest.raises(tk.TkError):   # the compensated form's layered step is the split one-step pass
-            st.set_tuning(kernel=tk.TK_KERNEL_FUSED2)
+        st.set_tuning(kernel=tk.TK_KERNEL_FUSED2)
+        with pytest.raises(tk.TkError):
+            st.set_tuning(kernel=tk.TK_KERNEL_TILED, rows_per_tile=4)
     finally:
         st.close()
     st = tk.Stepper([inst])
