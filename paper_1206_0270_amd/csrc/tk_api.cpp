@@ -39,15 +39,14 @@ struct tk_ctx {
     std::vector<std::vector<Angular>> hang;
     std::vector<std::vector<AngularF>> hangf;
     // hyperboloidal layer: any instance with one makes the context step with
-    // the marching kernels' layered form (FP64), the compensated form's split
-    // step (the one-step fused kernel below the layers, the layer kernel over
-    // them), or the layer's two passes (FP64, TWO_PASS)
+    // the marching kernels' layered form, or the layer's two passes (FP64,
+    // TWO_PASS)
     bool layered = false;
     size_t off_linst = 0;              // LayerInst per instance
     std::vector<size_t> off_lay;       // LayerTab table per instance (layered ones)
     size_t off_lwork = 0, lwork_cap = 0;  // the layer kernels' work list area (items)
     std::vector<WorkItem> lwork;
-    int lwork_rows = -1, lwork_cols = -1;  // rows per chunk and columns per strip it was built for
+    int lwork_rows = -1;               // rows per chunk it was built for
     long long step = 0;
     int cur = 0;  // state buffer holding u^step (mirror of the device control block)
     tk_tuning tuning{TK_KERNEL_AUTO, 0, 0, 3, TK_TUNE_NT_STORES, 0};
@@ -183,43 +182,21 @@ void push_strips(std::vector<WorkItem> &out, int k, const tk_instance_desc &d, i
     }
 }
 
-// Work lists of a layered context.  Split (the single-pass form): the
-// one-step fused kernel's strips of kFusedCols columns over each instance's
-// columns below its first layer column, in chunks of `rows` rows (0 = whole
-// columns), and the layer kernel's strips of kLayerFusedCols columns from
-// there on, in chunks of kLayerSplitRows rows (the layers are a few columns
-// wide: short chunks give them waves enough); one-step updates read only
-// u^n, so the layer kernel, launched after the fused one, overwrites
-// whatever part of the fused kernel's last strip reaches into the layer.
-// Two-pass: the layer kernels' strips of kLayerCols columns over whole
-// instances in chunks of `rows` rows (0 = kLayerRows).
-void build_layer_work(tk_ctx *c, int rows, bool split)
+// Work list of the layer's two passes: strips of kLayerCols columns over
+// whole instances in chunks of `rows` rows (0 = kLayerRows).
+void build_layer_work(tk_ctx *c, int rows)
 {
     c->lwork.clear();
-    c->work.clear();
-    for (size_t k = 0; k < c->inst.size(); ++k) {
-        const tk_instance_desc &d = c->inst[k].desc;
-        if (split) {
-            const int iL = layer_first_column(c->inst[k]);
-            push_strips(c->work, (int)k, d, 0, iL, kFusedCols, rows);
-            push_strips(c->lwork, (int)k, d, iL, d.n_r, kLayerFusedCols, kLayerSplitRows);
-        } else {
-            push_strips(c->lwork, (int)k, d, 0, d.n_r, kLayerCols, rows > 0 ? rows : kLayerRows);
-        }
-    }
-    std::stable_sort(c->work.begin(), c->work.end(),
-                     [](const WorkItem &x, const WorkItem &y) { return (x.j1 - x.j0) > (y.j1 - y.j0); });
+    for (size_t k = 0; k < c->inst.size(); ++k)
+        push_strips(c->lwork, (int)k, c->inst[k].desc, 0, c->inst[k].desc.n_r, kLayerCols, rows > 0 ? rows : kLayerRows);
     c->lwork_rows = rows;
-    c->lwork_cols = split ? kLayerFusedCols : kLayerCols;
-    c->work_rows = -1;  // not a list of the plain kernels' shapes
-    c->work_cols = -1;
 }
 
 size_t layer_work_capacity(const tk_ctx *c)
 {
     size_t n = 0;  // chunks of at least 3 rows
     for (const HostInst &h : c->inst)
-        n += (size_t)((h.desc.n_r + kLayerFusedCols - 1) / kLayerFusedCols) * (h.desc.n_theta / 3 + 1);
+        n += (size_t)((h.desc.n_r + kLayerCols - 1) / kLayerCols) * (h.desc.n_theta / 3 + 1);
     return n;
 }
 
@@ -355,17 +332,11 @@ tk_status ensure_work(tk_ctx *c, int kernel)
 {
     if (layer_kernels(c, kernel)) {
         const int rows = c->tuning.rows_per_tile;
-        const bool split = kernel != TK_KERNEL_TWO_PASS;
-        const int cols = split ? kLayerFusedCols : kLayerCols;
-        if (!c->lwork.empty() && c->lwork_rows == rows && c->lwork_cols == cols) return TK_OK;
-        build_layer_work(c, rows, split);
-        if (c->lwork.size() > c->lwork_cap || c->work.size() > c->work_cap)
-            return fail(c, TK_E_STATE, "layer work list exceeds its reserved area");
+        if (!c->lwork.empty() && c->lwork_rows == rows) return TK_OK;
+        build_layer_work(c, rows);
+        if (c->lwork.size() > c->lwork_cap) return fail(c, TK_E_STATE, "layer work list exceeds its reserved area");
         TK_HIP(c, hipMemcpyAsync(c->ws + c->off_lwork, c->lwork.data(), c->lwork.size() * sizeof(WorkItem),
                                  hipMemcpyHostToDevice, c->stream));
-        if (!c->work.empty())
-            TK_HIP(c, hipMemcpyAsync(c->ws + c->off_work, c->work.data(), c->work.size() * sizeof(WorkItem),
-                                     hipMemcpyHostToDevice, c->stream));
         TK_HIP(c, hipStreamSynchronize(c->stream));
         return TK_OK;
     }
@@ -386,24 +357,9 @@ hipError_t launch_one(tk_ctx *c, int kernel, int steps, int kstep, int kflip)
 {
     const DevInst *di = (const DevInst *)(c->ws + c->off_inst);
     const DevCtl *ctl = (const DevCtl *)(c->ws + c->off_ctl);
-    if (layer_kernels(c, kernel)) {
-        // split: the one-step fused kernel below the layers, then the layer kernel over them
-        if (kernel != TK_KERNEL_TWO_PASS && !c->work.empty()) {
-            FusedShape f;
-            f.prefetch = c->tuning.prefetch_rows == 1 ? 1 : 3;
-            f.nt = (c->tuning.flags & TK_TUNE_NT_STORES) != 0;
-            f.waves = 1;
-            f.two_step = false;
-            f.chunked = false;
-            hipError_t e = launch_fused(c->prec == TK_FP64, di, (const WorkItem *)(c->ws + c->off_work),
-                                        (int)c->work.size(), kFusedCols, ctl, kstep, kflip, f, c->stream);
-            if (e != hipSuccess) return e;
-        }
-        return launch_layer(c->prec == TK_FP64, kernel != TK_KERNEL_TWO_PASS, di,
-                            (const LayerInst *)(c->ws + c->off_linst),
-                            (int)c->inst.size(), (const WorkItem *)(c->ws + c->off_lwork), (int)c->lwork.size(), ctl,
-                            kstep, kflip, c->stream);
-    }
+    if (layer_kernels(c, kernel))  // the layer's two passes
+        return launch_layer(di, (const LayerInst *)(c->ws + c->off_linst), (int)c->inst.size(),
+                            (const WorkItem *)(c->ws + c->off_lwork), (int)c->lwork.size(), ctl, kstep, kflip, c->stream);
     if (kernel == TK_KERNEL_TWO_PASS)
         return launch_two_pass(di, (const int2 *)(c->ws + c->off_blocks), (int)c->blocks.size(), ctl, kstep, kflip,
                                c->stream);

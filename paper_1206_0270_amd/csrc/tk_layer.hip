@@ -1,11 +1,11 @@
 // Kernels of the hyperboloidal outer layer (Section 2.3, item 2).
 //
-// A layered context steps one step per pass: by default the plain one-step
-// fused kernel below the layers and k_layer_fused (both stages in one pass,
-// DPP lane exchange) over them, or, as the alternative form, k_layer_half
-// (Eq. (3) into the half-step array) and k_layer_full (Eq. (4)) over whole
-// instances; k_layer_scri then fills the null-infinity column.  The layer
-// kernels march chunks of theta rows with their radial factors in registers.
+// A layered context steps with the marching kernels' layered form
+// (tk_kernels.hip); these kernels are the alternative FP64 form, one step
+// in two passes over whole instances: k_layer_half (Eq. (3) into the
+// half-step array) and k_layer_full (Eq. (4)), then k_layer_scri for the
+// null-infinity column.  They march chunks of theta rows with their radial
+// factors in registers.
 // Their coefficients are the plain ones of the first-order system (the
 // radial and angular tables the other kernels read) turned into the layer's
 // by the per-position factors rho', H, rho'' of the map.  Changing to
@@ -236,197 +236,10 @@ __global__ void __launch_bounds__(256) k_layer_full(const DevInst *__restrict__ 
     }
 }
 
-// State storage.  FP64: double4 per point.  FP32-compensated: float4 values
-// f and a ushort4 of bf16 terms c per point, the value being f + c; the
-// layer's columns are computed in FP64 on that value and stored back split
-// as f = fl32(v), c = bf16(fl32(v - f)), as the host stores fields.
-__device__ __forceinline__ float bf16_to_float(unsigned short b) { return __uint_as_float((unsigned)b << 16); }
-__device__ __forceinline__ unsigned short float_to_bf16(float x) { return __builtin_bit_cast(unsigned short, (__bf16)x); }
-
-template <bool COMP>
-__device__ __forceinline__ P4 load_state(const void *u, const void *uc, size_t o)
-{
-    if constexpr (!COMP) {
-        return ld_p4((const double4 *)u + o);
-    } else {
-        const fvec4 a = gload_ptr((const fvec4 *)u)[o];
-        const hvec4 b = gload_ptr((const hvec4 *)uc)[o];
-        return P4{mk((double)a.x + (double)bf16_to_float(b.x), (double)a.y + (double)bf16_to_float(b.y)),
-                  mk((double)a.z + (double)bf16_to_float(b.z), (double)a.w + (double)bf16_to_float(b.w))};
-    }
-}
-
-template <bool COMP>
-__device__ __forceinline__ void store_state(void *u, void *uc, size_t o, const P4 &v)
-{
-    if constexpr (!COMP) {
-        st_p4((double4 *)u + o, v);
-    } else {
-        const double x[4] = {v.phi.re, v.phi.im, v.pi.re, v.pi.im};
-        float f[4];
-        unsigned short c[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            f[q] = (float)x[q];
-            c[q] = float_to_bf16((float)(x[q] - (double)f[q]));
-        }
-        const fvec4 a = {f[0], f[1], f[2], f[3]};
-        const hvec4 b = {c[0], c[1], c[2], c[3]};
-        gstore_ptr((fvec4 *)u)[o] = a;
-        gstore_ptr((hvec4 *)uc)[o] = b;
-    }
-}
-
-// Lane exchange by DPP wave shifts (a vector move, no LDS round trip):
-// wave_shl:1 gives lane l the value of lane l+1, wave_shr:1 that of lane
-// l-1; the lane at the open end gets 0 (bound_ctrl), and it is a halo lane
-// whose result is never stored.  Every row and bank is enabled and
-// bound_ctrl covers the one lane without a source, so no old value is kept.
-template <int CTRL>
-__device__ __forceinline__ double dpp_move(double v)
-{
-    const unsigned long long x = __builtin_bit_cast(unsigned long long, v);
-    const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)x, CTRL, 0xf, 0xf, true);
-    const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(x >> 32), CTRL, 0xf, 0xf, true);
-    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
-}
-constexpr int kWaveShl1 = 0x130, kWaveShr1 = 0x138;
-template <int CTRL>
-__device__ __forceinline__ P4 dpp_p4(const P4 &v)
-{
-    return P4{mk(dpp_move<CTRL>(v.phi.re), dpp_move<CTRL>(v.phi.im)),
-              mk(dpp_move<CTRL>(v.pi.re), dpp_move<CTRL>(v.pi.im))};
-}
-
-// Both stages in one pass: lane l of a wave holds column i = i0 - 1 + l and
-// reads only its own column of u^n; it takes column i+1 from lane l+1, forms
-// the half step at i + 1/2 (Eq. (3)) on each row, takes the one at i - 1/2
-// from lane l-1, and forms u^{n+1} at node i (Eq. (4)); lanes 1 .. 62 write
-// columns i0 .. i0 + 61 (lanes 0 and 63 are halo).  The rows march with the
-// u^n rows j, j+1 and the half-step rows j-1, j, j+1 (own and from lane l-1)
-// in registers, the half row one ahead of the output row; a chunk recomputes
-// the half rows on either side of it.  Pole rows of the half step come from
-// its rows 1, 2 (n_theta-2, n_theta-3), as in the two-pass form, and so do
-// the pole rows of u^{n+1}.  Bitwise the results of k_layer_half +
-// k_layer_full (FP64 storage).  Every lane runs the whole march (the shifts
-// need their source lanes); lanes off the grid read clamped columns and store
-// nothing.  COMP: FP32-compensated storage, FP64 arithmetic.
-template <bool COMP>
-__global__ void __launch_bounds__(256) k_layer_fused(const DevInst *__restrict__ insts,
-                                                     const LayerInst *__restrict__ lays,
-                                                     const WorkItem *__restrict__ work, int n_work,
-                                                     const DevCtl *__restrict__ ctl, int kstep, int kflip)
-{
-    const int w = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
-    if (w >= n_work) return;  // whole waves only
-    const WorkItem it = work[w];
-    const DevInst &I = insts[it.inst];
-    const int lane = (int)(threadIdx.x & 63);
-    const int i = it.i0 - 1 + lane;
-    const int N = I.n_r, nt = I.n_theta;
-    const LayerTab *tab = lays[it.inst].on ? lays[it.inst].tab : nullptr;
-    // own column on the grid (clamped); the half node i + 1/2 exists for 0 <= i <= N - 2
-    const int ic = i < 0 ? 0 : (i > N - 1 ? N - 1 : i);
-    const bool has_half = i >= 0 && i <= N - 2 && lane <= 62;
-    const int ih = i < 0 ? 0 : (i > N - 2 ? N - 2 : i);
-    const bool out_lane = lane >= 1 && lane <= 62;
-    const bool interior = out_lane && i >= 1 && i <= N - 2;
-    const bool edge = out_lane && (i == 0 || (i == N - 1 && tab == nullptr));
-    const int in = interior ? i : 1;
-    const long long n = ctl->step + kstep;
-    const int b = (int)((ctl->cur + kflip) & 1);
-    // the two stages' times, formed as k_layer_half and k_layer_full form them
-    const double t1 = (double)n * I.dt;
-    const double t2 = (double)n * I.dt + 0.5 * I.dt;
-    const cd e1 = source_phase(I, t1), e2 = source_phase(I, t2);
-    const Radial Rh = load_entry(gload_ptr(I.rad) + (2 * ih + 1));
-    const Radial Rn = load_entry(gload_ptr(I.rad) + (2 * in));
-    const TK_GLOBAL LayerTab *Lh = tab ? gload_ptr(tab) + (2 * ih + 1) : nullptr;
-    const TK_GLOBAL LayerTab *Ln = tab ? gload_ptr(tab) + (2 * in) : nullptr;
-    const bool sampling = (interior || edge) && i == I.i_obs && I.extract_every > 0 &&
-                          (n + 1) % I.extract_every == 0;
-    TK_GLOBAL double *wv = nullptr;
-    if (sampling) wv = gstore_ptr(I.wave) + (size_t)(((n + 1) / I.extract_every - 1) % I.wave_cap) * nt * 2;
-
-    auto ldu = [&](int j) { return load_state<COMP>(I.u[b], I.c[b], (size_t)j * I.pitch + ic); };
-    auto right = [](const P4 &v) { return dpp_p4<kWaveShl1>(v); };  // column i + 1
-    auto left = [](const P4 &v) { return dpp_p4<kWaveShr1>(v); };   // half node i - 1/2
-    // Eq. (3) at half node i + 1/2, row j (1 <= j <= nt - 2), from u^n rows j-1, j, j+1 of columns i, i+1
-    auto half = [&](const P4 &m0, const P4 &m1, const P4 &c0, const P4 &c1, const P4 &p0, const P4 &p1, int j) {
-        const Angular A = angular_row(I, j);
-        const LCoef c = lcoef_of(Rh, A, Lh);
-        const P4 bar = half_sum(c1, c0);
-        return lw_layer(c, bar, half_sum(m1, m0).phi, bar.phi, half_sum(p1, p0).phi, bar.pi, c1 - c0, 0.5 * I.dt, I,
-                        source_of(I, Rh.srcg, A, e1));
-    };
-    auto store = [&](int j, const P4 &o) {
-        if (interior || edge) {
-            store_state<COMP>(I.u[b ^ 1], I.c[b ^ 1], (size_t)j * I.pitch + i, o);
-            if (sampling) {
-                wv[2 * j] = o.phi.re;
-                wv[2 * j + 1] = o.phi.im;
-            }
-        }
-    };
-    const int jb = it.j0 > 1 ? it.j0 : 1, je = it.j1 < nt - 1 ? it.j1 : nt - 1;
-    // half rows jb - 1 and jb; u^n rows jb, jb + 1 (own column and lane l+1's) kept for the march
-    P4 Ua0 = ldu(jb), Ub0 = ldu(jb + 1);
-    P4 Ua1 = right(Ua0), Ub1 = right(Ub0);
-    const P4 Um0 = ldu(jb - 1), Um1 = right(Um0);
-    P4 H0 = half(Um0, Um1, Ua0, Ua1, Ub0, Ub1, jb), Hm;
-    if (jb >= 2) {
-        const P4 Un0 = ldu(jb - 2);
-        Hm = half(Un0, right(Un0), Um0, Um1, Ua0, Ua1, jb - 1);
-    } else {  // jb = 1: the pole row of the half step from its rows 1, 2
-        const P4 U30 = ldu(3);
-        const P4 H2 = half(Ua0, Ua1, Ub0, Ub1, U30, right(U30), 2);
-        Hm = I.m_even ? pole_bc(H0, H2) : zero4();
-    }
-    if (!has_half) H0 = Hm = zero4();
-    P4 HmL = left(Hm), H0L = left(H0);
-    P4 f1 = zero4(), f2 = zero4(), last = zero4(), before = zero4();
-    for (int j = jb; j < je; ++j) {
-        P4 Hp;
-        P4 Uc0 = Ub0, Uc1 = Ub1;
-        if (j + 1 <= nt - 2) {
-            Uc0 = ldu(j + 2);
-            Uc1 = right(Uc0);
-            Hp = half(Ua0, Ua1, Ub0, Ub1, Uc0, Uc1, j + 1);
-        } else {
-            Hp = I.m_even ? pole_bc(H0, Hm) : zero4();
-        }
-        if (!has_half) Hp = zero4();
-        const P4 HpL = left(Hp);
-        // Eq. (4) at node in, row j (u^n at the own column: in = i for the lanes that store)
-        const Angular A = angular_row(I, j);
-        const LCoef c = lcoef_of(Rn, A, Ln);
-        const P4 til = half_sum(H0, H0L);
-        P4 out = lw_layer(c, Ua0, half_sum(Hm, HmL).phi, til.phi, half_sum(Hp, HpL).phi, til.pi, H0 - H0L, I.dt, I,
-                          source_of(I, Rn.srcg, A, e2));
-        if (edge) out = zero4();
-        store(j, out);
-        if (j == 1) f1 = out;
-        if (j == 2) f2 = out;
-        before = last;
-        last = out;
-        Hm = H0;
-        H0 = Hp;
-        HmL = H0L;
-        H0L = HpL;
-        Ua0 = Ub0;
-        Ua1 = Ub1;
-        Ub0 = Uc0;
-        Ub1 = Uc1;
-    }
-    if (it.j0 == 0) store(0, I.m_even && !edge ? pole_bc(f1, f2) : zero4());
-    if (it.j1 == nt) store(nt - 1, I.m_even && !edge ? pole_bc(last, before) : zero4());
-}
-
 // The last node of each layered instance (future null infinity): the linear
 // extrapolation 2 u_{N-2} - u_{N-3} of the new values on rows 1 .. n_theta-2,
 // then the pole rows from its rows 1, 2 (n_theta-2, n_theta-3).  One block
-// per instance, threads striding over rows.  COMP: FP32-compensated storage.
-template <bool COMP>
+// per instance, threads striding over rows.
 __global__ void __launch_bounds__(256) k_layer_scri(const DevInst *__restrict__ insts,
                                                     const LayerInst *__restrict__ lays, const DevCtl *__restrict__ ctl,
                                                     int kstep, int kflip)
@@ -436,14 +249,14 @@ __global__ void __launch_bounds__(256) k_layer_scri(const DevInst *__restrict__ 
     const DevInst &I = insts[k];
     const long long n = ctl->step + kstep;
     const int b = (int)((ctl->cur + kflip) & 1);
-    void *un = I.u[b ^ 1], *unc = I.c[b ^ 1];
+    double4 *un = (double4 *)I.u[b ^ 1];
     const int nt = I.n_theta, N = I.n_r;
     const bool sampling = I.i_obs == N - 1 && I.extract_every > 0 && (n + 1) % I.extract_every == 0;
     TK_GLOBAL double *wv = nullptr;
     if (sampling) wv = gstore_ptr(I.wave) + (size_t)(((n + 1) / I.extract_every - 1) % I.wave_cap) * nt * 2;
     auto ext = [&](int j) {
-        const P4 a = load_state<COMP>(un, unc, (size_t)j * I.pitch + N - 2);
-        const P4 c = load_state<COMP>(un, unc, (size_t)j * I.pitch + N - 3);
+        const P4 a = ld_p4(un + (size_t)j * I.pitch + N - 2);
+        const P4 c = ld_p4(un + (size_t)j * I.pitch + N - 3);
         return P4{mk(2.0 * a.phi.re - c.phi.re, 2.0 * a.phi.im - c.phi.im),
                   mk(2.0 * a.pi.re - c.pi.re, 2.0 * a.pi.im - c.pi.im)};
     };
@@ -455,7 +268,7 @@ __global__ void __launch_bounds__(256) k_layer_scri(const DevInst *__restrict__ 
             o = zero4();
         else
             o = j == 0 ? pole_bc(ext(1), ext(2)) : pole_bc(ext(nt - 2), ext(nt - 3));
-        store_state<COMP>(un, unc, (size_t)j * I.pitch + N - 1, o);
+        st_p4(un + (size_t)j * I.pitch + N - 1, o);
         if (sampling) {
             wv[2 * j] = o.phi.re;
             wv[2 * j + 1] = o.phi.im;
@@ -465,35 +278,18 @@ __global__ void __launch_bounds__(256) k_layer_scri(const DevInst *__restrict__ 
 
 }  // namespace
 
-hipError_t launch_layer(bool fp64, bool fused, const DevInst *d_inst, const LayerInst *d_lay, int n_inst,
-                        const WorkItem *d_work, int n_work, const DevCtl *ctl, int kstep, int kflip, hipStream_t s)
+hipError_t launch_layer(const DevInst *d_inst, const LayerInst *d_lay, int n_inst, const WorkItem *d_work, int n_work,
+                        const DevCtl *ctl, int kstep, int kflip, hipStream_t s)
 {
     if (n_work <= 0) return hipSuccess;
-    if (!fp64 && !fused) return hipErrorInvalidValue;  // the two passes keep an FP64 half-step array
     const int blocks = (n_work + 3) / 4;
-    hipError_t e;
-    if (fused) {
-        if (fp64)
-            hipLaunchKernelGGL(k_layer_fused<false>, dim3(blocks), dim3(256), 0, s, d_inst, d_lay, d_work, n_work, ctl,
-                               kstep, kflip);
-        else
-            hipLaunchKernelGGL(k_layer_fused<true>, dim3(blocks), dim3(256), 0, s, d_inst, d_lay, d_work, n_work, ctl,
-                               kstep, kflip);
-        e = hipGetLastError();
-    } else {
-        hipLaunchKernelGGL(k_layer_half, dim3(blocks), dim3(256), 0, s, d_inst, d_lay, d_work, n_work, ctl, kstep,
-                           kflip);
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_layer_full, dim3(blocks), dim3(256), 0, s, d_inst, d_lay, d_work, n_work, ctl, kstep,
-                           kflip);
-        e = hipGetLastError();
-    }
+    hipLaunchKernelGGL(k_layer_half, dim3(blocks), dim3(256), 0, s, d_inst, d_lay, d_work, n_work, ctl, kstep, kflip);
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (fp64)
-        hipLaunchKernelGGL(k_layer_scri<false>, dim3(n_inst), dim3(256), 0, s, d_inst, d_lay, ctl, kstep, kflip);
-    else
-        hipLaunchKernelGGL(k_layer_scri<true>, dim3(n_inst), dim3(256), 0, s, d_inst, d_lay, ctl, kstep, kflip);
+    hipLaunchKernelGGL(k_layer_full, dim3(blocks), dim3(256), 0, s, d_inst, d_lay, d_work, n_work, ctl, kstep, kflip);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_layer_scri, dim3(n_inst), dim3(256), 0, s, d_inst, d_lay, ctl, kstep, kflip);
     return hipGetLastError();
 }
 
