@@ -478,8 +478,8 @@ def state_bytes_per_update(kernel, precision="fp64"):
     half that for the two-step pass; the two-pass layer kernels (FP64) also
     write and read the half-step array and read u^n twice (160 B)."""
     from paper_1206_0270_amd import tk
-    if precision == "fp32c":
-        return 48.0  # the compensated form's layered step is one step per pass
+    if precision == "fp32c":  # one read and one write of f (16 B) and c (8 B)
+        return 24.0 if kernel == tk.TK_KERNEL_FUSED2 else 48.0
     return {tk.TK_KERNEL_TWO_PASS: 160.0, tk.TK_KERNEL_FUSED2: 32.0}.get(kernel, 64.0)
 
 
