@@ -183,6 +183,39 @@ def test_layer_last_strip_holds_null_infinity(n_r):
     assert max(e) <= 2e-5, e
 
 
+def test_layer_random_grids_vs_oracle():
+    """Seeded random layered grids (ragged radial sizes around the strip
+    widths, 5 to 41 rows, layers from two cells to half the domain, spins
+    and m of both pole rules, sourced and source-free) in one context, the
+    two-step layered form in whole strips (AUTO) and in 4-row chunks, each
+    against the oracle's layer after 200 steps, and the two bitwise equal."""
+    rng = W.rng_for(2024)
+    insts = []
+    for k in range(8):
+        n_r = int(rng.choice([61, 62, 63, 64, 119, 120, 121, 122, 181, 183]))
+        n_th = int(rng.choice([5, 6, 9, 17, 23, 41]))
+        a = float(rng.choice([0.0, 0.5, 0.9, 0.99]))
+        m = int(rng.choice([-3, -2, 1, 2, 3, 4]))
+        S = float(rng.uniform(25.0, 60.0))
+        h = (S + 40.0) / (n_r - 1)
+        R = float(rng.uniform(max(0.5 * S, 10.0), S - 2.5 * h))
+        src = k % 2 == 1
+        init = None if src else dict(center=0.5 * R, width=3.0, amps={max(abs(m), 2): 1.0 + 0.3j})
+        source = dict(r0=6.0 + 2 * rng.uniform(), phase0=0.4, sigma_r_cells=2.0, sigma_th_cells=1.5,
+                      window_sigmas=5.0, ramp=3.0) if src else None
+        insts.append(W.instance(a=a, m=m, n_r=n_r, n_theta=n_th, rstar_min=-40.0, rstar_max=S,
+                                dt=W.stable_dt(a, m, -2, h, n_th), rstar_obs=S, extract_every=4, init=init,
+                                source=source, layer_start=R, name=f"rnd{k}.{n_r}x{n_th}.a{a}.m{m}.R{R:.1f}.S{S:.1f}"))
+    steps = 200
+    say("random layered grids", [i["name"] for i in insts])
+    whole = gpu_run(insts, steps)
+    chunks = gpu_run(insts, steps, kernel=tk.TK_KERNEL_FUSED2, rows=4)
+    for inst, a, b in zip(insts, whole, chunks):
+        for u, v in zip(a, b):
+            assert np.array_equal(u, v), inst["name"]
+        check(inst, steps, a, oracle_run(inst, steps))
+
+
 def test_layer_strips_chunked_beside_whole_ones():
     """With whole strips asked for (rows_per_tile 0), the strips whose lanes
     reach the layer are cut into chunks of 32 rows and the others run whole,
