@@ -256,6 +256,22 @@ def test_layer_second_workload_size():
     check(inst, steps, got, oracle_run(inst, steps))
 
 
+def test_layer_fifth_workload_grid_pulse_in_the_layer():
+    """16001 x 129 on [-300, 300]M with a layer on [250, 300]M, the fifth
+    workload's grid, with a pulse placed inside the layer so that the layer's
+    columns and null infinity carry the field from the first step: 400 steps
+    of the autotuner's default shape (two steps a pass, the layer's strips in
+    chunks beside whole strips) against the oracle's layer, the waveform read
+    at null infinity."""
+    inst = W.instance(a=0.9, m=2, n_r=16001, n_theta=129, rstar_min=-300.0, rstar_max=300.0, layer_start=250.0,
+                      extract_every=20, init=dict(center=275.0, width=5.0, amps={2: 1.0 - 0.5j, 3: 0.3j}),
+                      name="layer.16001x129.a0.9.pulse_in_layer")
+    steps = 400
+    say(inst["name"], "steps", steps)
+    got, = gpu_run([inst], steps, graph=100)
+    check(inst, steps, got, oracle_run(inst, steps))
+
+
 def test_layer_fp32c_vs_fp64():
     """FP32-compensated storage with layers: the marching kernels' layered
     compensated form (the layer's coefficients in the differences form's
