@@ -52,15 +52,15 @@ def kernel_hash():
 def workload(name):
     from paper_1206_0270_amd import workloads as W
     if name == "batched":
-        insts = W.config4()["instances"]
+        insts = W.batched_40_uneven()["instances"]
         desc = ("batched uneven: 40 instances, m=1..8 x a in {0,0.3,0.6,0.9,0.99}, "
                 "N_r 4001-16001, N_theta 33-257, r* in [-300,300]M, half Gaussian data, "
                 "half circular-orbit sources")
     elif name == "single":
-        insts = W.config2()["instances"]
+        insts = W.kerr_8001x129()["instances"]
         desc = "single instance: Kerr a=0.9, s=-2, m=2, 8001 x 129 on [-300,300]M, Gaussian data"
     elif name == "precision":
-        insts = W.config5()["instances"]
+        insts = W.six_modes_16001x129()["instances"]
         desc = ("precision-study workload: 6 instances m=2,3,4 x a=0.5,0.9, circular orbits r0=8M, "
                 "16001 x 129 on [-300,300]M")
     else:
@@ -182,7 +182,7 @@ def precision_study(args):
     from paper_1206_0270_amd import workloads as W
 
     torch.cuda.set_device(0)
-    insts = W.config5()["instances"]
+    insts = W.six_modes_16001x129()["instances"]
     if args.study_ramp > 0:  # every source switched on smoothly over study_ramp
         insts = [dict(i, source=dict(i["source"], ramp=args.study_ramp)) for i in insts]
     if args.study_layer > 0:  # grids ending in a layer on [study_layer, 300]M, waveform read at null infinity
@@ -340,7 +340,7 @@ def sensitivity_study(args):
     torch.cuda.set_device(0)
     res = {}
     for ramp in (0.0, 200.0):
-        inst = W.config5()["instances"][args.sens_instance]
+        inst = W.six_modes_16001x129()["instances"][args.sens_instance]
         if ramp:
             inst = dict(inst, source=dict(inst["source"], ramp=ramp))
         dt = inst["dt"]
@@ -392,7 +392,7 @@ def sensitivity_study(args):
         res[f"ramp {ramp:g}M"] = rows
     print(json.dumps({"metric": "relative waveform difference to the FP64 run at the observer: FP32C, and FP64 "
                                 f"with every value of the state perturbed by one FP32 rounding at {args.sens_at:g}M",
-                      "instance": W.config5()["instances"][args.sens_instance]["name"], "cases": res}), flush=True)
+                      "instance": W.six_modes_16001x129()["instances"][args.sens_instance]["name"], "cases": res}), flush=True)
 
 
 def richardson_study(args):

@@ -185,7 +185,7 @@ def _rand_amp(rng):
 # The five workloads
 # ---------------------------------------------------------------------------
 
-def config1():
+def schwarzschild_801x33():
     """Schwarzschild a=0, s=-2, m=2, source-free; r* in [-100, 100] with 801
     points, theta with 33 points; Gaussian pulse (center 10M, sd 4M) times the
     l=2 profile, Pi = 0; waveform at r* = 90M; T = 100M."""
@@ -195,7 +195,7 @@ def config1():
     return dict(instances=[inst], steps=4000, T=100.0)
 
 
-def config2():
+def kerr_8001x129():
     """Kerr a=0.9, s=-2, m=2, source-free; 8001 x 129 on [-300, 300]M;
     Gaussian (center 20M, sd 6M) times A_2 Y_2 + A_3 Y_3, A_l complex normal;
     T = 1000M."""
@@ -207,7 +207,7 @@ def config2():
     return dict(instances=[inst], steps=300000, T=1000.0)
 
 
-def config3():
+def kerr_sourced_16001x257():
     """Kerr a=0.9, m=2, particle on a prograde circular equatorial orbit at
     r0 = 10M, Gaussian 2 cells wide in r* and theta, seeded phase; 16001 x 257
     on [-300, 300]M; zero initial data; waveform at r* = 290M every 1M;
@@ -220,7 +220,7 @@ def config3():
     return dict(instances=[inst], steps=3500000, T=5000.0)
 
 
-def config4():
+def batched_40_uneven():
     """Batched, uneven sizes: m = 1..8 x a in {0, 0.3, 0.6, 0.9, 0.99}
     (40 instances).  Per instance: N_r uniform in 4001..16001, N_theta odd
     uniform in 33..257, r* in [-300, 300]M; half Gaussian initial data (the
@@ -248,7 +248,7 @@ def config4():
     return dict(instances=insts, steps=1000, T=None)
 
 
-def config5():
+def six_modes_16001x129():
     """Precision study: m = 2, 3, 4 x a in {0.5, 0.9}; circular orbits at
     r0 = 8M; 16001 x 129 on [-300, 300]M; dt = 1/500; T = 20000M."""
     rng = rng_for(5)
@@ -263,7 +263,8 @@ def config5():
     return dict(instances=insts, steps=10000000, T=20000.0)
 
 
-CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4, 5: config5}
+WORKLOADS = {f.__name__: f for f in (schwarzschild_801x33, kerr_8001x129, kerr_sourced_16001x257,
+                                        batched_40_uneven, six_modes_16001x129)}
 
 
 def points(insts):

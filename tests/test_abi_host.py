@@ -44,7 +44,7 @@ def _init(insts):
 
 
 def test_init_validation_errors():
-    good = W.config1()["instances"][0]
+    good = W.schwarzschild_801x33()["instances"][0]
     lib = tk.load()
     for field, val in [("n_r", 3), ("a", 1.0), ("s", 3), ("dt", -1.0), ("rstar_obs", 1e9)]:
         d = tk.make_desc(good)
@@ -58,7 +58,7 @@ def test_init_validation_errors():
 
 
 def test_unstable_dt_rejected_unless_forced():
-    inst = dict(W.config1()["instances"][0])
+    inst = dict(W.schwarzschild_801x33()["instances"][0])
     inst["dt"] = 0.125  # dr*/2: above the angular stability bound
     st, ctx = _init([tk.make_desc(inst)])
     assert st == tk.TK_E_UNSTABLE
@@ -74,20 +74,21 @@ def test_unstable_dt_rejected_unless_forced():
     assert lib.tk_destroy(ctx) == tk.TK_OK
 
 
-@pytest.mark.parametrize("k", [1, 2, 3, 5])
+@pytest.mark.parametrize("k", ["schwarzschild_801x33", "kerr_8001x129", "kerr_sourced_16001x257",
+                               "six_modes_16001x129"])
 def test_workload_dts_are_below_library_bound(k):
-    for inst in W.CONFIGS[k]()["instances"]:
+    for inst in W.WORKLOADS[k]()["instances"]:
         bound = tk.stable_dt(inst)
         assert inst["dt"] <= bound * (1 + 1e-12), (inst["name"], inst["dt"], bound)
 
 
 def test_batched_workload_dts_are_below_library_bound():
-    for inst in W.config4()["instances"]:
+    for inst in W.batched_40_uneven()["instances"]:
         assert inst["dt"] <= tk.stable_dt(inst) * (1 + 1e-12), inst["name"]
 
 
 def test_tuning_validation():
-    inst = W.config1()["instances"][0]
+    inst = W.schwarzschild_801x33()["instances"][0]
     st, ctx = _init([tk.make_desc(inst)])
     assert st == tk.TK_OK
     lib = tk.load()
@@ -179,7 +180,7 @@ def test_stepper_refuses_without_a_device():
     import torch
     if torch.cuda.is_available():
         pytest.skip("a HIP device is visible here")
-    inst = W.config1()["instances"][0]
+    inst = W.schwarzschild_801x33()["instances"][0]
     with pytest.raises(RuntimeError, match="no HIP device"):
         tk.Stepper([inst])
 

@@ -195,8 +195,8 @@ def test_small_grids_vs_oracle(kernel):
 
 
 def test_first_workload_full_run():
-    inst = W.config1()["instances"][0]
-    steps = W.config1()["steps"]
+    inst = W.schwarzschild_801x33()["instances"][0]
+    steps = W.schwarzschild_801x33()["steps"]
     say("first workload 801x33, a=0, steps", steps)
     got, = gpu_run([inst], steps)
     assert got[2].shape == (100, 33)
@@ -206,7 +206,7 @@ def test_first_workload_full_run():
 @pytest.mark.timeout(900)
 def test_second_workload_prefix():
     # 8001 x 129, a = 0.9: 3000 steps (10M) in graph replays of 100 steps
-    inst = W.config2()["instances"][0]
+    inst = W.kerr_8001x129()["instances"][0]
     steps = 3000
     say("second workload 8001x129, a=0.9, steps", steps)
     cnt = {}
@@ -221,7 +221,7 @@ def test_second_workload_prefix():
 def test_third_workload_sourced_prefix():
     # 16001 x 257, sourced: 2000 steps (2.9M), long enough for the field to
     # fill the source's neighbourhood; graph replays of 100 steps
-    inst = W.config3()["instances"][0]
+    inst = W.kerr_sourced_16001x257()["instances"][0]
     steps = 2000
     say("third workload 16001x257 sourced, steps", steps)
     cnt = {}
@@ -237,7 +237,7 @@ def test_third_workload_sourced_prefix():
 def test_fifth_workload_prefix():
     # 16001 x 129, sourced, at the size and launch shape of the precision
     # study: 2000 steps (4M) in both precisions against the oracle
-    inst = W.config5()["instances"][0]
+    inst = W.six_modes_16001x129()["instances"][0]
     steps = 2000
     say("fifth workload 16001x129 sourced, steps", steps)
     got, = gpu_run([inst], steps, graph=100)
@@ -260,7 +260,7 @@ def test_fifth_workload_prefix():
 def test_batched_uneven_workload_vs_oracle():
     # the benchmark's path: 40 uneven instances, the AUTO kernel (two steps
     # per pass over whole strips), 200 steps in graph replays of 100 steps
-    insts = W.config4()["instances"]
+    insts = W.batched_40_uneven()["instances"]
     steps = 200
     say("batched 40 instances, steps", steps, "points", W.points(insts))
     cnt = {}

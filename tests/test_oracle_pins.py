@@ -397,7 +397,7 @@ def test_schwarzschild_qnm():
     with open(os.path.join(GOLDEN, "schwarzschild_qnm_l2.json")) as f:
         gold = json.load(f)
     want = complex(*gold["M_omega"])
-    inst = W.config1()["instances"][0]
+    inst = W.schwarzschild_801x33()["instances"][0]
     dt = inst["dt"]
     # the first workload's grid and pulse, observed at r* = 30M
     g = oracle.Grid(a=0.0, m=2, n_r=801, n_theta=33, rstar_min=-100.0, rstar_max=100.0,
@@ -423,7 +423,7 @@ def test_schwarzschild_qnm():
 # ---------------------------------------------------------------------------
 
 def test_literal_half_dr_step_is_unstable_and_chosen_step_is_not():
-    inst = W.config1()["instances"][0]
+    inst = W.schwarzschild_801x33()["instances"][0]
     phi, pi = W.initial_data(inst)
     amp0 = np.max(np.abs(phi))
     for dt, steps, blow in [(0.125, 800, True), (inst["dt"], 4000, False)]:

@@ -99,7 +99,7 @@ def test_static_autotune_matches_autotune_twice_in_a_row(precision):
 
 
 def test_static_autotune_refuses_a_state_above_its_area():
-    inst = W.config3()["instances"][0]  # 16001 x 257 in FP64: about 132 MB of state
+    inst = W.kerr_sourced_16001x257()["instances"][0]  # 16001 x 257 in FP64: about 132 MB of state
     st = stepper([inst], tk.TK_FP64)
     st.step(3)
     before = st.get_fields(0)
