@@ -172,7 +172,7 @@ def waveform_errors(w_ref, w, floor=1e-3):
 
 
 def precision_study(args):
-    """The fifth workload (m = 2, 3, 4 x a = 0.5, 0.9; circular orbits at
+    """The six-mode workload (m = 2, 3, 4 x a = 0.5, 0.9; circular orbits at
     r0 = 8M; 16001 x 129 on [-300, 300]M; dt = 1/500) in FP64 and in the
     FP32-compensated form on the GPU over a window of window_M, and on a short
     prefix against the FP64 oracle.  One JSON line."""
@@ -273,7 +273,7 @@ def precision_study(args):
 
 
 def noise_study(args):
-    """How the scheme carries rounding-sized noise on the fifth workload's
+    """How the scheme carries rounding-sized noise on the six-mode workload's
     grid: FP64, no source, (Phi, Pi) set to white noise of 1e-20 per value,
     stepped for noise_window M; the field norm and the position of its
     largest value every 50M, at the workload's r* spacing and time step and
@@ -286,7 +286,7 @@ def noise_study(args):
     from paper_1206_0270_amd import workloads as W
 
     torch.cuda.set_device(0)
-    cases = [("h=0.0375 dt=1/500 (fifth workload)", 16001, 1 / 500), ("h=0.075 dt=1/500", 8001, 1 / 500),
+    cases = [("h=0.0375 dt=1/500 (six-mode workload)", 16001, 1 / 500), ("h=0.075 dt=1/500", 8001, 1 / 500),
              ("h=0.0375 dt=1/1000", 16001, 1 / 1000), ("h=0.01875 dt=1/500", 32001, 1 / 500)]
     out = {}
     for name, n_r, dt in cases:
@@ -326,7 +326,7 @@ def noise_study(args):
 
 
 def sensitivity_study(args):
-    """One mode of the fifth workload (index sens_instance) with the source
+    """One mode of the six-mode workload (index sens_instance) with the source
     switched on abruptly and over 200M: the FP64 run; an FP64 run whose state
     at sens_at M is perturbed value by value by a relative N(0, 2^-24) (one
     FP32 rounding of every value); and the FP32-compensated run.  Waveform
@@ -485,7 +485,7 @@ def state_bytes_per_update(kernel, precision="fp64"):
 
 def layer_throughput(args):
     """Step rate of a layered batch that fills the GPU, with the kernel the
-    autotuner picks: the fifth workload's six modes (m = 2, 3, 4 x a = 0.5,
+    autotuner picks: the six modes (m = 2, 3, 4 x a = 0.5,
     0.9; 16001 x 129 on [-300, 300]M), each ending in a layer on [250, 300]M,
     sourced; in the precision --precision names."""
     import torch
@@ -955,7 +955,7 @@ def build_parser():
     ap.add_argument("--noise-window", type=float, default=500.0, help="noise study: simulated time (M)")
     ap.add_argument("--sensitivity-study", action="store_true",
                     help="instead of the throughput line, compare FP32C and a once-perturbed FP64 run with FP64")
-    ap.add_argument("--sens-instance", type=int, default=1, help="sensitivity study: fifth-workload instance index")
+    ap.add_argument("--sens-instance", type=int, default=1, help="sensitivity study: instance index in the six-mode workload")
     ap.add_argument("--sens-at", type=float, default=300.0, help="sensitivity study: perturbation time (M)")
     ap.add_argument("--sens-window", type=float, default=1000.0, help="sensitivity study: simulated time (M)")
     ap.add_argument("--sens-checkpoints", type=float, nargs="+",

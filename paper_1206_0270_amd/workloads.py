@@ -224,7 +224,7 @@ def batched_40_uneven():
     """Batched, uneven sizes: m = 1..8 x a in {0, 0.3, 0.6, 0.9, 0.99}
     (40 instances).  Per instance: N_r uniform in 4001..16001, N_theta odd
     uniform in 33..257, r* in [-300, 300]M; half Gaussian initial data (the
-    second workload's form), half circular-orbit sources with r0 in
+    8001 x 129 workload's form), half circular-orbit sources with r0 in
     [6, 15]M; per-instance stable time step."""
     rng = rng_for(4)
     insts = []

@@ -2,9 +2,9 @@
 
 TEST INFRASTRUCTURE (not collected by pytest).  One sourced Kerr mode
 (a = 0.9, m = 2, s = -2, circular orbit at r0 = 8M, dt = 1/500 as in the
-fifth workload) on a short r* grid, run in FP64 and in the FP32 forms named
+six-mode workload) on a short r* grid, run in FP64 and in the FP32 forms named
 on the command line; prints the waveform amplitude and phase errors of each
-form against the FP64 run (the error of the fifth workload's precision study:
+form against the FP64 run (the error of the six-mode workload's precision study:
 projection on the l = max(|m|, 2) harmonic, samples above 1e-3 of the peak).
 
     python tests/fp32c_study.py [--probe wall|layer] [--nth 33] [--h 0.0375]

@@ -256,8 +256,8 @@ def test_layer_second_workload_size():
     check(inst, steps, got, oracle_run(inst, steps))
 
 
-def test_layer_fifth_workload_grid_pulse_in_the_layer():
-    """16001 x 129 on [-300, 300]M with a layer on [250, 300]M, the fifth
+def test_layer_16001x129_pulse_in_the_layer():
+    """16001 x 129 on [-300, 300]M with a layer on [250, 300]M, the six-mode
     workload's grid, with a pulse placed inside the layer so that the layer's
     columns and null infinity carry the field from the first step: 400 steps
     of the autotuner's default shape (two steps a pass, the layer's strips in

@@ -6,7 +6,7 @@ Bar (FP64), element by element on the same seeded inputs:
     where e_ld is the FP64 oracle's own distance to its long-double build on
     the same run (only computed when a field misses 1e-12).  When a field
     decays by orders of magnitude while rounding noise accumulates (Pi on the
-    first workload loses 100x in 100M), no FP64 evaluation order can do
+    801 x 33 workload loses 100x in 100M), no FP64 evaluation order can do
     better than that floor.
 Determinism checks (batched vs alone, tile shapes, graph vs eager,
 checkpoint/resume) are bitwise.
@@ -197,7 +197,7 @@ def test_small_grids_vs_oracle(kernel):
 def test_first_workload_full_run():
     inst = W.schwarzschild_801x33()["instances"][0]
     steps = W.schwarzschild_801x33()["steps"]
-    say("first workload 801x33, a=0, steps", steps)
+    say("Schwarzschild 801x33, steps", steps)
     got, = gpu_run([inst], steps)
     assert got[2].shape == (100, 33)
     check_parity(inst, steps, got, oracle_run(inst, steps))
@@ -208,7 +208,7 @@ def test_second_workload_prefix():
     # 8001 x 129, a = 0.9: 3000 steps (10M) in graph replays of 100 steps
     inst = W.kerr_8001x129()["instances"][0]
     steps = 3000
-    say("second workload 8001x129, a=0.9, steps", steps)
+    say("Kerr 8001x129, a=0.9, steps", steps)
     cnt = {}
     got, = gpu_run([inst], steps, graph=100, counters=cnt)
     expect_graph_replays(cnt, [steps], 100)
@@ -223,7 +223,7 @@ def test_third_workload_sourced_prefix():
     # fill the source's neighbourhood; graph replays of 100 steps
     inst = W.kerr_sourced_16001x257()["instances"][0]
     steps = 2000
-    say("third workload 16001x257 sourced, steps", steps)
+    say("Kerr 16001x257 sourced, steps", steps)
     cnt = {}
     got, = gpu_run([inst], steps, graph=100, counters=cnt)
     expect_graph_replays(cnt, [steps], 100)
@@ -234,12 +234,12 @@ def test_third_workload_sourced_prefix():
 
 
 @pytest.mark.timeout(900)
-def test_fifth_workload_prefix():
+def test_six_mode_workload_prefix():
     # 16001 x 129, sourced, at the size and launch shape of the precision
     # study: 2000 steps (4M) in both precisions against the oracle
     inst = W.six_modes_16001x129()["instances"][0]
     steps = 2000
-    say("fifth workload 16001x129 sourced, steps", steps)
+    say("six-mode 16001x129 sourced, steps", steps)
     got, = gpu_run([inst], steps, graph=100)
     ref = oracle_run(inst, steps)
     check_parity(inst, steps, got, ref)

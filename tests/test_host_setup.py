@@ -83,7 +83,7 @@ def test_tables_match_oracle_coefficients(exe, a, m):
 
 
 def test_stability_bound_values(exe):
-    # first workload grid: 1/40 is admissible, the literal dr*/2 = 0.125 is not
+    # the 801 x 33 workload's grid: 1/40 is admissible, the literal dr*/2 = 0.125 is not
     _, _, B = tables(exe, 1.0, 0.0, -2, 2, 801, 33, -100.0, 100.0)
     assert 1 / 40 <= B < 0.125
     assert abs(B - 0.02560) < 2e-4  # (8*0.01/w^4)^(1/3), w^2 = (2+16)/(27 dth^2)

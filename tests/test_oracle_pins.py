@@ -399,7 +399,7 @@ def test_schwarzschild_qnm():
     want = complex(*gold["M_omega"])
     inst = W.schwarzschild_801x33()["instances"][0]
     dt = inst["dt"]
-    # the first workload's grid and pulse, observed at r* = 30M
+    # the 801 x 33 workload's grid and pulse, observed at r* = 30M
     g = oracle.Grid(a=0.0, m=2, n_r=801, n_theta=33, rstar_min=-100.0, rstar_max=100.0,
                     dt=dt, i_obs=520, extract_every=4)
     phi, pi = W.initial_data(inst)
@@ -440,7 +440,7 @@ def test_literal_half_dr_step_is_unstable_and_chosen_step_is_not():
 
 
 def test_dt_rule_values():
-    # rule values for the first workload's grid and the three large grids
+    # rule values for the 801 x 33 workload's grid and the three large grids
     assert W.stable_dt(0.0, 2, -2, 0.25, 33) == 1.0 / 40
     assert W.stable_dt(0.9, 2, -2, 0.075, 129) <= 1.0 / 250
     assert abs(W.kappa(0.0) - 1.0 / 27) < 1e-6  # max (r-2M)/r^3 at r = 3M
@@ -561,11 +561,11 @@ def test_waveform_samples_are_field_columns():
 
 
 # ---------------------------------------------------------------------------
-# O2: self-convergence on the first workload's physics
+# O2: self-convergence on the 801 x 33 workload's physics
 # ---------------------------------------------------------------------------
 
 def test_self_convergence_first_workload_physics():
-    # three resolutions of the first workload's problem up to T = 20M
+    # three resolutions of the 801 x 33 workload's problem up to T = 20M
     base = dict(a=0.0, m=2, rstar_min=-100.0, rstar_max=100.0)
     init = dict(center=10.0, width=4.0, amps={2: 1.0})
     sols = []
