@@ -280,17 +280,18 @@ tk_status tk_get_tuning(const tk_ctx *ctx, tk_tuning *t);
  * many waves; 0, 64 and 16 for the one-step kernel, 8 and 4 for the tiled
  * kernel; a context with a hyperboloidal layer tries the shapes of its own
  * forms, see tk_kernel) on this context's own instances and keep the
- * fastest; graph_steps stays as it was.  Each candidate runs `warmup` untimed and then `steps` timed steps
- * (both rounded up to even), timed with HIP events on the context's stream.
- * The state, the step counter and the waveform rings are copied to
- * save_area and restored afterwards, so the simulation is left as it was
- * found.  save_area: caller-owned device memory of at least
- * tk_autotune_bytes bytes, 256-byte aligned, free for the duration of the
- * call (the library allocates nothing).  Synchronous; not for use during
- * stream capture.  On success *best_ms_per_step and *n_tried (each may be
- * NULL) receive the winner's time per step and the number of shapes timed.
- * TK_E_NOMEM if save_bytes is too small, TK_E_INVALID if save_area is not
- * aligned device memory. */
+ * fastest; graph_steps stays as it was.  Each candidate runs `warmup`
+ * untimed and then `steps` timed steps (both rounded up to even), timed with
+ * HIP events on the context's stream, in two passes over the candidates in
+ * opposite orders (its faster time counts).  The state, the step counter and
+ * the waveform rings are copied to save_area and restored afterwards, so the
+ * simulation is left as it was found.  save_area: caller-owned device memory
+ * of at least tk_autotune_bytes bytes, 256-byte aligned, free for the
+ * duration of the call (the library allocates nothing).  Synchronous; not
+ * for use during stream capture.  On success *best_ms_per_step and *n_tried
+ * (each may be NULL) receive the winner's time per step and the number of
+ * shapes timed.  TK_E_NOMEM if save_bytes is too small, TK_E_INVALID if
+ * save_area is not aligned device memory. */
 tk_status tk_autotune_bytes(const tk_ctx *ctx, size_t *bytes);
 tk_status tk_autotune(tk_ctx *ctx, int warmup, int steps, void *save_area, size_t save_bytes,
                       double *best_ms_per_step, int *n_tried);

@@ -1043,31 +1043,39 @@ static tk_status autotune_run(tk_ctx *c, int warmup, int steps, char *save, cons
     }
 
     tk_status st = e == hipSuccess ? TK_OK : fail(c, TK_E_DEVICE, std::string("autotune setup: ") + hipGetErrorString(e));
-    double best = 1e300;
-    tk_tuning best_t = keep;
-    int tried = 0;
-    for (const tk_tuning &t : cand) {
-        if (st != TK_OK) break;
-        c->tuning = t;
-        const int kernel = resolve_kernel(c);
-        if (kernel != TK_KERNEL_TWO_PASS || c->layered) st = ensure_work(c, kernel);
-        int flips = 0;
-        if (st == TK_OK && warmup > 0) st = enqueue_steps(c, kernel, warmup, &flips);
-        if (st == TK_OK && (e = hipEventRecord(e0, c->stream)) != hipSuccess)
-            st = fail(c, TK_E_DEVICE, std::string("autotune event: ") + hipGetErrorString(e));
-        if (st == TK_OK) st = enqueue_steps(c, kernel, steps, &flips);
-        if (st == TK_OK && (e = hipEventRecord(e1, c->stream)) != hipSuccess)
-            st = fail(c, TK_E_DEVICE, std::string("autotune event: ") + hipGetErrorString(e));
-        float ms = 0.0f;
-        if (st == TK_OK && ((e = hipEventSynchronize(e1)) != hipSuccess || (e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess))
-            st = fail(c, TK_E_DEVICE, std::string("autotune timing: ") + hipGetErrorString(e));
-        if (st != TK_OK) break;
-        ++tried;
-        if (ms / steps < best) {
-            best = ms / steps;
-            best_t = t;
+    // two passes over the candidates in opposite orders, each candidate's
+    // faster time counting: a clock still rising while the first candidates
+    // run (after the device sat idle) would otherwise favour the later ones
+    std::vector<double> t_best(cand.size(), 1e300);
+    for (int pass = 0; pass < 2 && st == TK_OK; ++pass) {
+        for (size_t q = 0; q < cand.size(); ++q) {
+            const size_t i = pass == 0 ? q : cand.size() - 1 - q;
+            c->tuning = cand[i];
+            const int kernel = resolve_kernel(c);
+            if (kernel != TK_KERNEL_TWO_PASS || c->layered) st = ensure_work(c, kernel);
+            int flips = 0;
+            if (st == TK_OK && warmup > 0) st = enqueue_steps(c, kernel, warmup, &flips);
+            if (st == TK_OK && (e = hipEventRecord(e0, c->stream)) != hipSuccess)
+                st = fail(c, TK_E_DEVICE, std::string("autotune event: ") + hipGetErrorString(e));
+            if (st == TK_OK) st = enqueue_steps(c, kernel, steps, &flips);
+            if (st == TK_OK && (e = hipEventRecord(e1, c->stream)) != hipSuccess)
+                st = fail(c, TK_E_DEVICE, std::string("autotune event: ") + hipGetErrorString(e));
+            float ms = 0.0f;
+            if (st == TK_OK &&
+                ((e = hipEventSynchronize(e1)) != hipSuccess || (e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess))
+                st = fail(c, TK_E_DEVICE, std::string("autotune timing: ") + hipGetErrorString(e));
+            if (st != TK_OK) break;
+            t_best[i] = std::min(t_best[i], (double)ms / steps);
         }
     }
+    double best = 1e300;
+    tk_tuning best_t = keep;
+    const int tried = (int)cand.size();
+    for (size_t i = 0; i < cand.size(); ++i)
+        if (t_best[i] < best) {
+            best = t_best[i];
+            best_t = cand[i];
+        }
     // restore the simulation as it was
     hipError_t er = hipStreamSynchronize(c->stream);
     for (const SaveSpan &sp : spans)
