@@ -1044,8 +1044,8 @@ static tk_status autotune_run(tk_ctx *c, int warmup, int steps, char *save, cons
 
     tk_status st = e == hipSuccess ? TK_OK : fail(c, TK_E_DEVICE, std::string("autotune setup: ") + hipGetErrorString(e));
     // two passes over the candidates in opposite orders, each candidate's
-    // faster time counting: a clock still rising while the first candidates
-    // run (after the device sat idle) would otherwise favour the later ones
+    // faster time counting: one pass was biased by the order of timing (the
+    // shapes timed late came out ahead of faster ones timed early)
     std::vector<double> t_best(cand.size(), 1e300);
     for (int pass = 0; pass < 2 && st == TK_OK; ++pass) {
         for (size_t q = 0; q < cand.size(); ++q) {
