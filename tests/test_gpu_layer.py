@@ -107,11 +107,12 @@ def test_layer_small_grids_vs_oracle():
         check(inst, steps, got, oracle_run(inst, steps))
 
 
-def test_layer_graph_and_chunks_bitwise():
+@pytest.mark.parametrize("precision", [tk.TK_FP64, tk.TK_FP32_COMP])
+def test_layer_graph_and_chunks_bitwise(precision):
     insts = layered_instances()[:3]
-    a = gpu_run(insts, 250)
+    a = gpu_run(insts, 250, precision=precision)
     cnt = {}
-    b = gpu_run(insts, 250, graph=40, chunks=[7, 120, 123], counters=cnt)
+    b = gpu_run(insts, 250, graph=40, chunks=[7, 120, 123], counters=cnt, precision=precision)
     assert cnt["graphs_instantiated"] == 1 and cnt["graph_launches"] == 6, cnt  # 3 + 3 replays of 40 steps
     for x, y in zip(a, b):
         for u, v in zip(x, y):
