@@ -939,7 +939,7 @@ def build_parser():
     ap.add_argument("--no-nt", action="store_true", help="plain (not non-temporal) stores")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-legs", action="store_true",
-                    help="time only --precision on --workload (no second precision, no single-mode leg)")
+                    help="time only --precision on --workload (no second precision, no single-mode or layered leg)")
     ap.add_argument("--precision-study", action="store_true",
                     help="instead of the throughput line, run the FP32-compensated vs FP64 waveform study")
     ap.add_argument("--study-window", type=float, default=600.0, help="precision study: simulated time (M)")
@@ -1077,6 +1077,16 @@ def main(argv=None):
         s_insts, s_desc = workload("single")
         single = run_leg(args, s_insts, [W.initial_data(i) for i in s_insts], "fp64")
         single["workload"] = s_desc
+    layered = None
+    if not args.no_legs and args.workload == "batched":
+        # the six 16001 x 129 modes ending in hyperboloidal layers, timed over
+        # the same step counts; reported beside the line, never in its place
+        la = argparse.Namespace(**vars(args))
+        la.layer_steps, la.layer_warmup, la.precision = args.steps, args.warmup, "fp64"
+        try:
+            layered = layer_throughput(la)
+        except Exception as exc:
+            print(f"# layered leg not measured: {exc}", file=sys.stderr, flush=True)
 
     leg = main_leg
     out = {
@@ -1112,6 +1122,11 @@ def main(argv=None):
                                            "Cache, so no HBM roofline is claimed for it"}
         if "fp32c" in legs:
             out["fp32c"]["fp32c_batched_over_fp64_single_mode"] = legs["fp32c"]["value"] / single["value"]
+    if layered is not None:
+        out["fp64_layered"] = {"workload": layered["workload"], "value": layered["updates_per_s"],
+                               "ms_per_step": layered["ms_per_step"], "tuning": layered["tuning"],
+                               "bytes_per_update": layered["bytes_per_update"],
+                               "frac_of_8TBps": layered["frac_of_8TBps"]}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(insts)
     print(json.dumps(out), flush=True)
