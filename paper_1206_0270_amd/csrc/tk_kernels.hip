@@ -186,6 +186,7 @@ struct PolicyF64 {
     static constexpr bool kRadRegs = true;  // radial factors in registers (else LDS)
     static constexpr bool kMaskHalo = false;  // lanes off the grid load and compute unmasked
     static constexpr bool kLayer = false;     // instances may end in a hyperboloidal layer
+    static constexpr bool kEdge = true;       // a lane may hold a Dirichlet column (see Inner)
     static constexpr int kPD = PD;
     static constexpr bool kNT = NT;
     static constexpr int kWaves = W;
@@ -207,6 +208,7 @@ struct PolicyF32C {
     static constexpr bool kRadRegs = false;
     static constexpr bool kMaskHalo = true;  // measured faster with them masked
     static constexpr bool kLayer = false;
+    static constexpr bool kEdge = true;
     static constexpr int kPD = PD;
     static constexpr bool kNT = NT;
     static constexpr int kWaves = W;
@@ -218,6 +220,15 @@ template <int PD, bool NT, int W>
 struct PolicyF32CL : PolicyF32C<PD, NT, W> {
     static constexpr bool kLayer = true;
     using Plain = PolicyF32C<PD, NT, W>;
+};
+
+// A policy's form for waves whose 64 columns all lie strictly inside the
+// radial grid (every lane holds a column 1 .. N_r - 2): no lane holds a
+// Dirichlet column, so Eq. (4) needs no per-lane zero mask there.  Every
+// lane of such a wave computes exactly what the general form computes.
+template <class P>
+struct Inner : P {
+    static constexpr bool kEdge = false;
 };
 
 template <typename T>
@@ -326,6 +337,13 @@ template <class P>
 struct Lane {
     using T = typename P::T;
     const DevInst *I;
+    // the instance's angular rows, waveform ring and extraction column, read
+    // once: the march's stores could alias the descriptor as far as the
+    // compiler knows, so reading them through I reloads them on every row
+    const Angular *ang;
+    const AngularF *angf;
+    double *wave;
+    int i_obs;
     const void *u, *uc;  // u^n values (and bf16 terms)
     void *un, *unc;      // u^{n+1}
     T *rad;              // this lane's radial factors in LDS: [2 nodes][kRadF/2 pairs] with a stride of 64 pairs
@@ -385,19 +403,19 @@ __device__ __forceinline__ RadF<typename P::T> radf_of(const Lane<P> &L, int k)
 
 // Uniform angular factors of a row (scalar loads; floats for FP32).
 template <class P>
-__device__ __forceinline__ AngF<typename P::T> angf_of(const DevInst &I, int row)
+__device__ __forceinline__ AngF<typename P::T> angf_of(const Lane<P> &L, int row)
 {
     if constexpr (!P::kComp) {
-        const TK_CONST Angular *A = cload_ptr(I.ang) + row;
+        const TK_CONST Angular *A = cload_ptr(L.ang) + row;
         return AngF<double>{A->sa, A->sn2, A->kcs, A->V2, A->cot_h};
     } else {
-        const TK_CONST AngularF *A = cload_ptr(I.angf) + row;
+        const TK_CONST AngularF *A = cload_ptr(L.angf) + row;
         return AngF<float>{A->sa, A->sn2, A->kcs, A->V2, A->cot_h};
     }
 }
 
 // g_theta of the particle source on a row (0 off its window)
-__device__ __forceinline__ double src_theta(const DevInst &I, int row) { return (cload_ptr(I.ang) + row)->srcg; }
+__device__ __forceinline__ double src_theta(const Angular *ang, int row) { return (cload_ptr(ang) + row)->srcg; }
 
 // The bracket's source argument off the source: -0 makes its innermost
 // multiply-add a plain multiply.
@@ -411,9 +429,9 @@ __device__ __forceinline__ cx<T> no_source()
 // whose theta factor is non-zero.  The test is on the table entry's bits, a
 // wave-uniform scalar comparison, so rows off the window (and instances
 // without a source) skip the work; g_r = 0 makes F zero in the other lanes.
-__device__ __forceinline__ void add_source(double gq, const DevInst &I, int row, cd e, Q4<double> &br)
+__device__ __forceinline__ void add_source(double gq, const Angular *ang, int row, cd e, Q4<double> &br)
 {
-    const unsigned long long bits = *(const TK_CONST unsigned long long *)&(cload_ptr(I.ang) + row)->srcg;
+    const unsigned long long bits = *(const TK_CONST unsigned long long *)&(cload_ptr(ang) + row)->srcg;
     if (bits != 0ull) {
         asm volatile("");  // keeps this a branch: selects would do the work on every row
         const cd F = source_value(gq, __builtin_bit_cast(double, bits), e);
@@ -432,8 +450,8 @@ __device__ __forceinline__ double value_of(const St<typename P::T> &v, int k)
 template <class P>
 __device__ __forceinline__ void sample(const Lane<P> &L, const Level &lv, int row, const St<typename P::T> &v)
 {
-    if (lv.ext && L.ov && L.c == L.I->i_obs) {
-        TK_GLOBAL double *w = gstore_ptr(L.I->wave) + ((size_t)lv.wslot * L.nt + row) * 2;
+    if (lv.ext && L.ov && L.c == L.i_obs) {
+        TK_GLOBAL double *w = gstore_ptr(L.wave) + ((size_t)lv.wslot * L.nt + row) * 2;
         w[0] = value_of<P>(v, 0);
         w[1] = value_of<P>(v, 1);
     }
@@ -685,11 +703,11 @@ __device__ __forceinline__ Half<P> half_core(const Lane<P> &L, const Level &lv, 
     if constexpr (!P::kComp) {
         const Q4<T> du = nb.z - U0.f;
         const Q4<T> bar = mid_from(U0.f, du);
-        CoefF<T> cf = coef_fused(radf_of(L, 0), angf_of<P>(I, r));
+        CoefF<T> cf = coef_fused(radf_of(L, 0), angf_of<P>(L, r));
         if constexpr (P::kLayer)
-            if (L.wlay && L.lay_h) layer_transform(cf, radf_of(L, 0), angf_of<P>(I, r), L.lf, I.h);
+            if (L.wlay && L.lay_h) layer_transform(cf, radf_of(L, 0), angf_of<P>(L, r), L.lf, I.h);
         Q4<T> br = bracket_fused(cf, nb.m + UM.f.phi, nb.p + UP.f.phi, bar.phi, bar.pi, du, no_source<T>());
-        add_source(L.gh, I, r, lv.eh, br);
+        add_source(L.gh, L.ang, r, lv.eh, br);
         return lw_update(bar, fac, br);
     } else {
         (void)UM;
@@ -707,9 +725,9 @@ __device__ __forceinline__ Half<P> half_core(const Lane<P> &L, const Level &lv, 
                 be[k] = e + c[k];
             }
         }
-        CoefD<T> cf = coef_diff(radf_of(L, 0), angf_of<P>(I, r));
+        CoefD<T> cf = coef_diff(radf_of(L, 0), angf_of<P>(L, r));
         if constexpr (P::kLayer)
-            if (L.wlay && L.lay_h) layer_transform(cf, radf_of(L, 0), angf_of<P>(I, r), L.lf, (T)I.h);
+            if (L.wlay && L.lay_h) layer_transform(cf, radf_of(L, 0), angf_of<P>(L, r), L.lf, (T)I.h);
         const Q4<T> br = bracket_diff(cf, nb.own.d2 + nb.nb.d2, nb.own.d1 + nb.nb.d1, bar.f.phi, bar.f.pi, du);
         // u^{n+1/2} = bar - (dt/2) [.] as a pair
         St<T> h;
@@ -720,7 +738,7 @@ __device__ __forceinline__ Half<P> half_core(const Lane<P> &L, const Level &lv, 
             for (int k = 0; k < 4; ++k) two_sum(bs[k], fma(-fac, bp[k], be[k]), hs[k], he[k]);
         }
         if (L.near_h) {  // FP64 source increment (dt/2) F
-            const double gj = src_theta(I, r);
+            const double gj = src_theta(L.ang, r);
             if (gj != 0.0) {
                 const cd F = source_value(L.gh, gj, lv.eh);
                 const double f64 = 0.5 * I.dt;
@@ -767,15 +785,15 @@ __device__ __forceinline__ St<typename P::T> out_core(const Lane<P> &L, const Le
     St<T> res;
     res.f = zero_q4<T>();
     res.c = zero_q4<T>();
-    if (!L.icol) return res;
+    if (P::kEdge && !L.icol) return res;
     if constexpr (!P::kComp) {
         const Q4<T> du = H0 - nb.z;
         const Q4<T> til = mid_from(nb.z, du);
-        CoefF<T> cf = coef_fused(radf_of(L, 1), angf_of<P>(I, o));
+        CoefF<T> cf = coef_fused(radf_of(L, 1), angf_of<P>(L, o));
         if constexpr (P::kLayer)
-            if (L.wlay && L.lay_n) layer_transform(cf, radf_of(L, 1), angf_of<P>(I, o), L.lf + 192, I.h);
+            if (L.wlay && L.lay_n) layer_transform(cf, radf_of(L, 1), angf_of<P>(L, o), L.lf + 192, I.h);
         Q4<T> br = bracket_fused(cf, HM.phi + nb.m, HP.phi + nb.p, til.phi, til.pi, du, no_source<T>());
-        add_source(L.gn, I, o, lv.ef, br);
+        add_source(L.gn, L.ang, o, lv.ef, br);
         res.f = lw_update(Uo.f, L.dt, br);
     } else {
         (void)HM;
@@ -783,13 +801,13 @@ __device__ __forceinline__ St<typename P::T> out_core(const Lane<P> &L, const Le
         const Q4<T> du = comp_diff(H0, nb.z);
         // the averaged fields enter S only through ct and c0: one FP32 value each
         const Q4<T> til = mid_from(nb.z.f, du);
-        CoefD<T> cf = coef_diff(radf_of(L, 1), angf_of<P>(I, o));
+        CoefD<T> cf = coef_diff(radf_of(L, 1), angf_of<P>(L, o));
         if constexpr (P::kLayer)
-            if (L.wlay && L.lay_n) layer_transform(cf, radf_of(L, 1), angf_of<P>(I, o), L.lf + 192, (T)I.h);
+            if (L.wlay && L.lay_n) layer_transform(cf, radf_of(L, 1), angf_of<P>(L, o), L.lf + 192, (T)I.h);
         const Q4<T> br = bracket_diff(cf, nb.own.d2 + nb.nb.d2, nb.own.d1 + nb.nb.d1, til.phi, til.pi, du);
         const T *bp = &br.phi.re, *fp = &Uo.f.phi.re, *cp = &Uo.c.phi.re;
         T *rf = &res.f.phi.re, *rc = &res.c.phi.re;
-        const double gj = L.near_n ? src_theta(I, o) : 0.0;
+        const double gj = L.near_n ? src_theta(L.ang, o) : 0.0;
         if (gj != 0.0) {
             // FP64 accumulation where the source injects: u + c - dt [.] + dt F
             const cd F = source_value(L.gn, gj, lv.ef);
@@ -1135,6 +1153,10 @@ __device__ __forceinline__ void init_lane(Lane<P> &L, const DevInst &I, const Wo
 {
     using T = typename P::T;
     L.I = &I;
+    L.ang = I.ang;
+    L.angf = I.angf;
+    L.wave = I.wave;
+    L.i_obs = I.i_obs;
     L.u = I.u[buf];
     L.uc = I.c[buf];
     L.un = I.u[buf ^ 1];
@@ -1210,6 +1232,13 @@ __device__ __forceinline__ void init_lane(Lane<P> &L, const DevInst &I, const Wo
 __device__ __forceinline__ bool touches_layer(const DevInst &I, const WorkItem &it, int halo)
 {
     return I.lay_on != 0 && it.i0 - halo + 63 >= I.lay_c0;
+}
+
+// Whether every lane of such a wave holds an interior column (1 .. N_r - 2),
+// so that the wave can run a policy's Inner form.
+__device__ __forceinline__ bool inner_wave(const DevInst &I, const WorkItem &it, int halo)
+{
+    return it.i0 - halo >= 1 && it.i0 - halo + 63 <= I.n_r - 2;
 }
 
 }  // namespace
@@ -1539,6 +1568,11 @@ __global__ void __launch_bounds__(64 * kFusedWavesPerBlock) __attribute__((amdgp
             k_fused2_wave<typename P::Plain>(I, it, lane, kFused2Cols, buf, &s_rad[wv][2 * lane], nullptr, n);
             return;
         }
+    } else if (inner_wave(I, it, 2)) {
+        // the form without the Dirichlet mask (only in this kernel: a second
+        // body made the chunked kernel's short marches measurably slower)
+        k_fused2_wave<Inner<P>>(I, it, lane, kFused2Cols, buf, &s_rad[wv][2 * lane], nullptr, n);
+        return;
     }
     k_fused2_wave<P>(I, it, lane, kFused2Cols, buf, &s_rad[wv][2 * lane], &s_lay[wv][P::kLayer ? lane : 0], n);
 }

@@ -364,6 +364,26 @@ def test_two_step_kernel_equals_one_step_bitwise(precision, steps):
             assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
 
 
+@pytest.mark.parametrize("n_r", [122, 123, 124, 183])
+def test_two_step_interior_waves_bitwise(n_r):
+    # the two-step kernel runs the waves whose 64 lanes all hold interior
+    # columns without the Dirichlet mask: strips start every 60 columns, so
+    # the strip at column 60 is such a wave from N_r = 123 on (its last lane
+    # at N_r - 2) and not at 122 (its last lane on the Dirichlet column)
+    rng = np.random.default_rng(n_r)
+    inst = W.instance(a=0.7, m=2, n_r=n_r, n_theta=13, rstar_min=-20.0, rstar_max=25.0, rstar_obs=20.0,
+                      extract_every=3, init=dict(center=2.0, width=3.0,
+                                                 amps={2: complex(rng.standard_normal(), rng.standard_normal())}),
+                      source=dict(r0=7.0, phase0=0.4, sigma_r_cells=2.0, sigma_th_cells=2.0, window_sigmas=6.0),
+                      name=f"interior.{n_r}")
+    say("interior waves, n_r", n_r)
+    one = gpu_run([inst], 30, kernel=tk.TK_KERNEL_FUSED)
+    for pf in (3, 1):
+        two = gpu_run([inst], 30, kernel=tk.TK_KERNEL_FUSED2, prefetch=pf)
+        assert all(np.array_equal(x, y) for x, y in zip(one[0], two[0]))
+    check_parity(inst, 30, one[0], oracle_run(inst, 30))
+
+
 def test_checkpoint_resume_bitwise():
     insts = small_instances()
     full = gpu_run(insts, 60)
