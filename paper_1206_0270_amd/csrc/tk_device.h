@@ -249,12 +249,13 @@ struct CoefF {
     T Sh2, sig;
 };
 
+// The same from a given sig = 1/Sigma-hat (the two-step kernel hands level
+// 1's value to level 2, which needs the same points), and from scratch.
 template <typename T>
-__device__ __forceinline__ CoefF<T> coef_fused(const RadF<T> &R, const AngF<T> &A)
+__device__ __forceinline__ CoefF<T> coef_fused_sig(const RadF<T> &R, const AngF<T> &A, T sig)
 {
     CoefF<T> c;
     const T Sh2 = fma(-R.D2h, A.sa, R.rho2);
-    const T sig = inv_sqrt(Sh2);
     const T W = sig * sig;
     c.Sh2 = Sh2;
     c.sig = sig;
@@ -271,6 +272,11 @@ __device__ __forceinline__ CoefF<T> coef_fused(const RadF<T> &R, const AngF<T> &
     const T t = fma(R.K * A.sn2, sig, R.ct_re);
     c.dh = mkc(W * fma(c.bh, t, -R.c1h_re), W * fma(c.bh, cti, -R.c1h_im));
     return c;
+}
+template <typename T>
+__device__ __forceinline__ CoefF<T> coef_fused(const RadF<T> &R, const AngF<T> &A)
+{
+    return coef_fused_sig(R, A, inv_sqrt(fma(-R.D2h, A.sa, R.rho2)));
 }
 
 // Bracket D du / h - S at a point: pm, pp = the two values whose average is

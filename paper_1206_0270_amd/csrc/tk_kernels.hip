@@ -362,6 +362,10 @@ struct Lane {
     // holds (any lane of the wave holds) the null-infinity column
     const double *lf;
     bool lay_h, lay_n, wlay, scri, wscri;
+    // whole-strip two-step kernel (FP64, no layer): this lane's column of the
+    // wave's LDS ring [3 slots][half node, node][64 lanes] through which
+    // level 1 hands 1/Sigma-hat to level 2
+    double *sgr;
 };
 
 template <class P>
@@ -685,12 +689,26 @@ struct Around<P, true> {
     AngD<typename P::T> own, nb;
 };
 
+// How the FP64 row functions get 1/Sigma-hat at their point (SG): computed
+// (kSigNew), computed and left at sgw for a later level (kSigPut), or taken
+// as sgv, the value an earlier level left (kSigGet).
+constexpr int kSigNew = 0, kSigPut = 1, kSigGet = 2;
+
+template <class P, int SG>
+__device__ __forceinline__ CoefF<typename P::T> coef_at(const Lane<P> &L, int k, int row, double *sgw, double sgv)
+{
+    if constexpr (SG == kSigGet) return coef_fused_sig(radf_of(L, k), angf_of<P>(L, row), sgv);
+    const CoefF<typename P::T> cf = coef_fused(radf_of(L, k), angf_of<P>(L, row));
+    if constexpr (SG == kSigPut) *sgw = cf.sig;
+    return cf;
+}
+
 // Eq. (3) at half row r: u^n rows r-1 (UM), r (U0), r+1 (UP) of this column
 // and what it needs of the column to the right (nb).
-template <class P>
+template <class P, int SG = kSigNew>
 __device__ __forceinline__ Half<P> half_core(const Lane<P> &L, const Level &lv, const St<typename P::T> &UM,
                                              const St<typename P::T> &U0, const St<typename P::T> &UP,
-                                             const Around<P> &nb, int r)
+                                             const Around<P> &nb, int r, double *sgw = nullptr, double sgv = 0.0)
 {
     using T = typename P::T;
     const DevInst &I = *L.I;
@@ -703,7 +721,7 @@ __device__ __forceinline__ Half<P> half_core(const Lane<P> &L, const Level &lv, 
     if constexpr (!P::kComp) {
         const Q4<T> du = nb.z - U0.f;
         const Q4<T> bar = mid_from(U0.f, du);
-        CoefF<T> cf = coef_fused(radf_of(L, 0), angf_of<P>(L, r));
+        CoefF<T> cf = coef_at<P, SG>(L, 0, r, sgw, sgv);
         if constexpr (P::kLayer)
             if (L.wlay && L.lay_h) layer_transform(cf, radf_of(L, 0), angf_of<P>(L, r), L.lf, I.h);
         Q4<T> br = bracket_fused(cf, nb.m + UM.f.phi, nb.p + UP.f.phi, bar.phi, bar.pi, du, no_source<T>());
@@ -753,9 +771,10 @@ __device__ __forceinline__ Half<P> half_core(const Lane<P> &L, const Level &lv, 
 }
 
 // The same with the column to the right taken by lane shuffles.
-template <class P>
+template <class P, int SG = kSigNew>
 __device__ __forceinline__ Half<P> half_row(const Lane<P> &L, const Level &lv, const St<typename P::T> &UM,
-                                            const St<typename P::T> &U0, const St<typename P::T> &UP, int r)
+                                            const St<typename P::T> &U0, const St<typename P::T> &UP, int r,
+                                            double *sgw = nullptr, double sgv = 0.0)
 {
     Around<P> nb;
     if constexpr (!P::kComp) {
@@ -769,16 +788,17 @@ __device__ __forceinline__ Half<P> half_row(const Lane<P> &L, const Level &lv, c
         nb.nb.d2 = shfl_down1<P>(nb.own.d2);
         nb.nb.d1 = shfl_down1<P>(nb.own.d1);
     }
-    return half_core(L, lv, UM, U0, UP, nb, r);
+    return half_core<P, SG>(L, lv, UM, U0, UP, nb, r, sgw, sgv);
 }
 
 // Eq. (4) at output row o: u^n row o (Uo), half rows o-1 (HM), o (H0), o+1
 // (HP) of this column (at c+1/2) and what it needs of the half column at
 // c-1/2 (nb).
-template <class P>
+template <class P, int SG = kSigNew>
 __device__ __forceinline__ St<typename P::T> out_core(const Lane<P> &L, const Level &lv, const St<typename P::T> &Uo,
                                                       const Half<P> &HM, const Half<P> &H0, const Half<P> &HP,
-                                                      const Around<P> &nb, int o)
+                                                      const Around<P> &nb, int o, double *sgw = nullptr,
+                                                      double sgv = 0.0)
 {
     using T = typename P::T;
     const DevInst &I = *L.I;
@@ -789,7 +809,7 @@ __device__ __forceinline__ St<typename P::T> out_core(const Lane<P> &L, const Le
     if constexpr (!P::kComp) {
         const Q4<T> du = H0 - nb.z;
         const Q4<T> til = mid_from(nb.z, du);
-        CoefF<T> cf = coef_fused(radf_of(L, 1), angf_of<P>(L, o));
+        CoefF<T> cf = coef_at<P, SG>(L, 1, o, sgw, sgv);
         if constexpr (P::kLayer)
             if (L.wlay && L.lay_n) layer_transform(cf, radf_of(L, 1), angf_of<P>(L, o), L.lf + 192, I.h);
         Q4<T> br = bracket_fused(cf, HM.phi + nb.m, HP.phi + nb.p, til.phi, til.pi, du, no_source<T>());
@@ -828,9 +848,10 @@ __device__ __forceinline__ St<typename P::T> out_core(const Lane<P> &L, const Le
 }
 
 // The same with the half column at c-1/2 taken by lane shuffles.
-template <class P>
+template <class P, int SG = kSigNew>
 __device__ __forceinline__ St<typename P::T> out_row(const Lane<P> &L, const Level &lv, const St<typename P::T> &Uo,
-                                                     const Half<P> &HM, const Half<P> &H0, const Half<P> &HP, int o)
+                                                     const Half<P> &HM, const Half<P> &H0, const Half<P> &HP, int o,
+                                                     double *sgw = nullptr, double sgv = 0.0)
 {
     Around<P> nb;
     if constexpr (!P::kComp) {
@@ -844,7 +865,7 @@ __device__ __forceinline__ St<typename P::T> out_row(const Lane<P> &L, const Lev
         nb.nb.d2 = shfl_up1<P>(nb.own.d2);
         nb.nb.d1 = shfl_up1<P>(nb.own.d1);
     }
-    St<typename P::T> v = out_core(L, lv, Uo, HM, H0, HP, nb, o);
+    St<typename P::T> v = out_core<P, SG>(L, lv, Uo, HM, H0, HP, nb, o, sgw, sgv);
     if constexpr (P::kLayer) {
         if (L.wscri) {
             // null infinity (Section 2.3, item 2): no characteristic enters,
@@ -1014,10 +1035,19 @@ __device__ __forceinline__ void march2(const Lane<P> &L, const Level &l1, const 
     constexpr int SP = (S + 1) % 3;  // rows r+1 and r-2 (and r-5)
     const int nt = L.nt;
     const bool even = L.I->m_even;
+    // Level 2 needs Sigma-hat at half row r-3 and node row r-4, the points
+    // level 1 took in iteration r-3, which left 1/Sigma-hat in ring slot S;
+    // read before level 1 refills the slot.  Where level 2 forms a row here,
+    // level 1 formed the same row there (rows 1 .. nt-2 of both kinds).
+    constexpr bool kShare = !P::kComp && !P::kLayer;
+    constexpr int SG1 = kShare ? kSigPut : kSigNew, SG2 = kShare ? kSigGet : kSigNew;
+    double *const sgh = kShare ? L.sgr + (2 * S) * 64 : nullptr;
+    double *const sgn = kShare ? L.sgr + (2 * S + 1) * 64 : nullptr;
+    const double sg2h = kShare ? *sgh : 0.0, sg2n = kShare ? *sgn : 0.0;
     // level 1: half rows r-2 (SP), r-1 (SM), r (S); u^n rows r-1 (SM), r (S), r+1 (SP)
     if (!EDGE || r <= nt - 2) {
         advance_rows<P, S>(L, R, r, nt - 1);
-        R.H[S] = half_row(L, l1, R.U[SM], R.U[S], R.U[SP], r);
+        R.H[S] = half_row<P, SG1>(L, l1, R.U[SM], R.U[S], R.U[SP], r, sgh);
     } else {  // r = nt-1: half row nt-1 from nt-2 (SM), nt-3 (SP); unused after that
         R.H[S] = pole_hrow<P>(even, R.H[SM], R.H[SP]);
     }
@@ -1025,18 +1055,18 @@ __device__ __forceinline__ void march2(const Lane<P> &L, const Level &l1, const 
     const bool v_new = !EDGE || (r >= 2 && r <= nt - 1);              // u^{n+1} row r-1 this iteration
     St<typename P::T> vn;
     if (v_new) {
-        vn = out_row(L, l1, R.U[SM], R.H[SP], R.H[SM], R.H[S], r - 1);
+        vn = out_row<P, SG1>(L, l1, R.U[SM], R.H[SP], R.H[SM], R.H[S], r - 1, sgn);
         sample(L, l1, r - 1, vn);
     }
     // level 2: u^{n+1} rows r-4 (SM), r-3 (S), r-2 (SP); its half rows r-5 (SP), r-4 (SM), r-3 (S)
     if (!EDGE || (r >= 4 && r <= nt + 1))
-        R.G[S] = half_row(L, l2, R.V[SM], R.V[S], R.V[SP], r - 3);
+        R.G[S] = half_row<P, SG2>(L, l2, R.V[SM], R.V[S], R.V[SP], r - 3, nullptr, sg2h);
     else if (r == nt + 2)  // half row nt-1 from nt-2 (SM), nt-3 (SP)
         R.G[S] = pole_hrow<P>(even, R.G[SM], R.G[SP]);
     if (EDGE && r == 5) R.G[SP] = pole_hrow<P>(even, R.G[SM], R.G[S]);  // half row 0 from 1 (SM), 2 (S)
     if (!EDGE || (r >= 5 && r <= nt + 2)) {                          // u^{n+2} row o = r-4
         const int o = r - 4;
-        const St<typename P::T> v = out_row(L, l2, R.V[SM], R.G[SP], R.G[SM], R.G[S], o);
+        const St<typename P::T> v = out_row<P, SG2>(L, l2, R.V[SM], R.G[SP], R.G[SM], R.G[S], o, nullptr, sg2n);
         emit(L, l2, o, v);
         if (EDGE) {
             const bool pn = o == 2, ps = o == nt - 2;  // row 0 from rows 1, 2; row nt-1 from nt-2, nt-3
@@ -1175,6 +1205,7 @@ __device__ __forceinline__ void init_lane(Lane<P> &L, const DevInst &I, const Wo
     L.ov = lane >= halo && lane < halo + cols && L.c < nr;
     L.dt = (T)I.dt;
     L.rad = rad;
+    L.sgr = nullptr;
     if (!load_rad) return;  // the radial factors come from another wave (tiled kernel)
     const Radial Rh = load_entry(gload_ptr(I.rad) + (L.hv ? 2 * L.c + 1 : 0));
     const Radial Rn = load_entry(gload_ptr(I.rad) + (L.icol ? 2 * L.c : 0));
@@ -1512,10 +1543,11 @@ __global__ void __launch_bounds__(64 * kFusedWavesPerBlock)
 // One wave's work item of k_fused2 (the kernel picks the form).
 template <class P>
 __device__ __forceinline__ void k_fused2_wave(const DevInst &I, const WorkItem &it, int lane, int cols, int buf,
-                                               typename P::T *rad, double *lay, long long n)
+                                               typename P::T *rad, double *lay, double *sg, long long n)
 {
     Lane<P> L;
     init_lane(L, I, it, lane, 2, cols, buf, rad, true, lay);
+    L.sgr = sg;
     const Level l1 = make_level(I, n), l2 = make_level(I, n + 1);
     const int nt = I.n_theta;  // >= 5: the six head iterations all exist
 
@@ -1554,6 +1586,7 @@ __global__ void __launch_bounds__(64 * kFusedWavesPerBlock) __attribute__((amdgp
     using T = typename P::T;
     __shared__ T s_rad[kFusedWavesPerBlock][P::kRadRegs ? 2 : 2 * kRadF * 64];
     __shared__ double s_lay[kFusedWavesPerBlock][P::kLayer ? 6 * 64 : 1];
+    __shared__ double s_sig[kFusedWavesPerBlock][P::kComp ? 1 : 6 * 64];  // Lane::sgr
     const int lane = (int)(threadIdx.x & 63);
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int w = (int)blockIdx.x * kFusedWavesPerBlock + wv;
@@ -1565,16 +1598,18 @@ __global__ void __launch_bounds__(64 * kFusedWavesPerBlock) __attribute__((amdgp
     if constexpr (P::kLayer) {
         // a wave whose columns all stay below the layer runs the plain form
         if (!touches_layer(I, it, 2)) {
-            k_fused2_wave<typename P::Plain>(I, it, lane, kFused2Cols, buf, &s_rad[wv][2 * lane], nullptr, n);
+            k_fused2_wave<typename P::Plain>(I, it, lane, kFused2Cols, buf, &s_rad[wv][2 * lane], nullptr,
+                                             &s_sig[wv][lane], n);
             return;
         }
     } else if (inner_wave(I, it, 2)) {
         // the form without the Dirichlet mask (only in this kernel: a second
         // body made the chunked kernel's short marches measurably slower)
-        k_fused2_wave<Inner<P>>(I, it, lane, kFused2Cols, buf, &s_rad[wv][2 * lane], nullptr, n);
+        k_fused2_wave<Inner<P>>(I, it, lane, kFused2Cols, buf, &s_rad[wv][2 * lane], nullptr, &s_sig[wv][lane], n);
         return;
     }
-    k_fused2_wave<P>(I, it, lane, kFused2Cols, buf, &s_rad[wv][2 * lane], &s_lay[wv][P::kLayer ? lane : 0], n);
+    k_fused2_wave<P>(I, it, lane, kFused2Cols, buf, &s_rad[wv][2 * lane], &s_lay[wv][P::kLayer ? lane : 0],
+                     &s_sig[wv][lane], n);
 }
 
 // One wave's work item of k_fused2c (the kernel picks the form).
