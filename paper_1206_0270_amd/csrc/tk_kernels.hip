@@ -1134,9 +1134,18 @@ __device__ __forceinline__ void march2c(const Lane<P> &L, const Level &l1, const
     constexpr int SP = (S + 1) % 3;
     const int nt = B.nt;
     const bool even = L.I->m_even;
+    // level 1's 1/Sigma-hat for level 2 as in march2: the chunk's bounds keep
+    // every row level 2 forms among the rows level 1 formed three
+    // iterations earlier (g_lo..g_hi within r_lo..h1_hi, o_lo..o_hi within
+    // v_lo..v_hi)
+    constexpr bool kShare = !P::kComp && !P::kLayer;
+    constexpr int SG1 = kShare ? kSigPut : kSigNew, SG2 = kShare ? kSigGet : kSigNew;
+    double *const sgh = kShare ? L.sgr + (2 * S) * 64 : nullptr;
+    double *const sgn = kShare ? L.sgr + (2 * S + 1) * 64 : nullptr;
+    const double sg2h = kShare ? *sgh : 0.0, sg2n = kShare ? *sgn : 0.0;
     if (!EDGE || r <= B.h1_hi) {
         advance_rows<P, S>(L, R, r, B.h1_hi + 1);
-        R.H[S] = half_row<P>(L, l1, R.U[SM], R.U[S], R.U[SP], r);
+        R.H[S] = half_row<P, SG1>(L, l1, R.U[SM], R.U[S], R.U[SP], r, sgh);
     } else if (B.south && r == nt - 1) {
         R.H[S] = pole_hrow<P>(even, R.H[SM], R.H[SP]);
     }
@@ -1144,17 +1153,17 @@ __device__ __forceinline__ void march2c(const Lane<P> &L, const Level &l1, const
     const bool v_new = !EDGE || (r - 1 >= B.v_lo && r - 1 <= B.v_hi);
     St<typename P::T> vn;
     if (v_new) {
-        vn = out_row<P>(L, l1, R.U[SM], R.H[SP], R.H[SM], R.H[S], r - 1);
+        vn = out_row<P, SG1>(L, l1, R.U[SM], R.H[SP], R.H[SM], R.H[S], r - 1, sgn);
         if (!EDGE || (r - 1 >= B.o_lo && r - 1 <= B.o_hi)) sample(L, l1, r - 1, vn);
     }
     if (!EDGE || (r - 3 >= B.g_lo && r - 3 <= B.g_hi))
-        R.G[S] = half_row<P>(L, l2, R.V[SM], R.V[S], R.V[SP], r - 3);
+        R.G[S] = half_row<P, SG2>(L, l2, R.V[SM], R.V[S], R.V[SP], r - 3, nullptr, sg2h);
     else if (B.south && r == nt + 2)
         R.G[S] = pole_hrow<P>(even, R.G[SM], R.G[SP]);
     if (EDGE && B.north && r == 5) R.G[SP] = pole_hrow<P>(even, R.G[SM], R.G[S]);
     if (!EDGE || (r - 4 >= B.o_lo && r - 4 <= B.o_hi)) {
         const int o = r - 4;
-        const St<typename P::T> v = out_row<P>(L, l2, R.V[SM], R.G[SP], R.G[SM], R.G[S], o);
+        const St<typename P::T> v = out_row<P, SG2>(L, l2, R.V[SM], R.G[SP], R.G[SM], R.G[S], o, nullptr, sg2n);
         emit(L, l2, o, v);
         if (EDGE) {
             const bool pn = B.north && o == 2, ps = B.south && o == nt - 2;
@@ -1615,10 +1624,11 @@ __global__ void __launch_bounds__(64 * kFusedWavesPerBlock) __attribute__((amdgp
 // One wave's work item of k_fused2c (the kernel picks the form).
 template <class P>
 __device__ __forceinline__ void k_fused2c_wave(const DevInst &I, const WorkItem &it, int lane, int cols, int buf,
-                                                typename P::T *rad, double *lay, long long n)
+                                                typename P::T *rad, double *lay, double *sg, long long n)
 {
     Lane<P> L;
     init_lane(L, I, it, lane, 2, cols, buf, rad, true, lay);
+    L.sgr = sg;
     const Level l1 = make_level(I, n), l2 = make_level(I, n + 1);
     const Chunk2 B = chunk2_of(I.n_theta, it.j0, it.j1);
     // every check holds from iteration steady_lo on and through steady_hi
@@ -1658,6 +1668,7 @@ __global__ void __launch_bounds__(64 * kFusedWavesPerBlock) __attribute__((amdgp
     using T = typename P::T;
     __shared__ T s_rad[kFusedWavesPerBlock][P::kRadRegs ? 2 : 2 * kRadF * 64];
     __shared__ double s_lay[kFusedWavesPerBlock][P::kLayer ? 6 * 64 : 1];
+    __shared__ double s_sig[kFusedWavesPerBlock][P::kComp ? 1 : 6 * 64];  // Lane::sgr
     const int lane = (int)(threadIdx.x & 63);
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int w = (int)blockIdx.x * kFusedWavesPerBlock + wv;
@@ -1669,11 +1680,13 @@ __global__ void __launch_bounds__(64 * kFusedWavesPerBlock) __attribute__((amdgp
     if constexpr (P::kLayer) {
         // a wave whose columns all stay below the layer runs the plain form
         if (!touches_layer(I, it, 2)) {
-            k_fused2c_wave<typename P::Plain>(I, it, lane, kFused2Cols, buf, &s_rad[wv][2 * lane], nullptr, n);
+            k_fused2c_wave<typename P::Plain>(I, it, lane, kFused2Cols, buf, &s_rad[wv][2 * lane], nullptr,
+                                              &s_sig[wv][P::kComp ? 0 : lane], n);
             return;
         }
     }
-    k_fused2c_wave<P>(I, it, lane, kFused2Cols, buf, &s_rad[wv][2 * lane], &s_lay[wv][P::kLayer ? lane : 0], n);
+    k_fused2c_wave<P>(I, it, lane, kFused2Cols, buf, &s_rad[wv][2 * lane], &s_lay[wv][P::kLayer ? lane : 0],
+                      &s_sig[wv][P::kComp ? 0 : lane], n);
 }
 
 template <class P>
