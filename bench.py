@@ -36,6 +36,17 @@ ALU_PEAK_TFLOPS = {"fp64": 78.6, "fp32c": 157.3}
 # 32 for the update of Eq. (4)) and drops a Newton step and the folded
 # weights: 312 FP32 operations per update.
 FLOPS_PER_UPDATE = {"fp64": 202, "fp32c": 312}
+# The FP64 two-step kernels form Sigma-hat and 1/Sigma-hat once for both
+# levels (level 2 takes level 1's value at the same point): per level-2 stage
+# point the multiply-add of Sigma-hat^2 (2) and the inverse square root (12:
+# the estimate, x/2, and two Newton steps of 5) are not formed again, 28 per
+# level-2 update, 14 per update on average.
+FLOPS_SHARED_TWO_STEP = {"fp64": 14, "fp32c": 0}
+
+
+def flops_per_update(precision, two_step):
+    """FP64 / FP32 operations per point update the launch's formulas need."""
+    return FLOPS_PER_UPDATE[precision] - (FLOPS_SHARED_TWO_STEP[precision] if two_step else 0)
 KERNEL_POLICY = {"fp64": "PolicyF64", "fp32c": "PolicyF32C"}
 KERNEL_SOURCES = ["paper_1206_0270_amd/csrc/tk_kernels.hip", "paper_1206_0270_amd/csrc/tk_device.h",
                   "paper_1206_0270_amd/csrc/tk_internal.h"]
@@ -897,7 +908,8 @@ def run_leg(args, insts, inits, precision):
         upd = points * spl  # point updates per launch
         moved = points * bpp
         gbs = moved / launch_s / 1e9
-        tflops = FLOPS_PER_UPDATE[precision] * upd / launch_s / 1e12
+        fpu = flops_per_update(precision, two_step)
+        tflops = fpu * upd / launch_s / 1e12
         issue = valu_entry(kname, args.workload, upd / launch_s)
         # The fused kernels are bound by vector-ALU issue (the counters show
         # the VALU busy most cycles at a fraction of the HBM bandwidth), so the
@@ -906,7 +918,7 @@ def run_leg(args, insts, inits, precision):
         roof = {"bound": "alu", "achieved": tflops, "peak": ALU_PEAK_TFLOPS[precision], "unit": "TFLOP/s",
                 "frac": tflops / ALU_PEAK_TFLOPS[precision], "traffic": traffic_entry(kname, args.workload),
                 "kernel": kname, "avg_launch_ms": launch_s * 1e3, "launches_timed": n_launch,
-                "flops_per_update": FLOPS_PER_UPDATE[precision], "updates_per_point_per_launch": spl,
+                "flops_per_update": fpu, "updates_per_point_per_launch": spl,
                 "hbm": {"achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
                         "bytes_per_launch": moved, "bytes_per_point_per_launch": bpp,
                         # the same launch priced at one read and one write of the state per update: twice

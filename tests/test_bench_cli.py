@@ -90,3 +90,14 @@ def test_driver_run_times_whole_two_step_launches_in_graphs():
         for req in (0, 1, 7, 10, 100):
             G = bench.bench_graph_steps(K, req, True)
             assert G % 2 == 0 and G <= K and G <= req
+
+
+def test_two_step_flops_per_update():
+    # the FP64 two-step launches do not form Sigma-hat^2 (one multiply-add) and
+    # 1/Sigma-hat (estimate, x/2 and two Newton steps of a multiply and two
+    # multiply-adds) again at level 2's two stage points: 28 per level-2
+    # update, half that per update over both levels
+    per_point = 2 + 1 + 1 + 2 * (1 + 2 + 2)
+    assert bench.flops_per_update("fp64", False) == 202
+    assert bench.flops_per_update("fp64", True) == 202 - 2 * per_point // 2
+    assert bench.flops_per_update("fp32c", True) == bench.flops_per_update("fp32c", False) == 312
