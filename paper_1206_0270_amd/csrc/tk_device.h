@@ -324,11 +324,10 @@ struct CoefD {
 };
 
 template <typename T>
-__device__ __forceinline__ CoefD<T> coef_diff(const RadF<T> &R, const AngF<T> &A)
+__device__ __forceinline__ CoefD<T> coef_diff_sig(const RadF<T> &R, const AngF<T> &A, T sig)
 {
     CoefD<T> c;
     const T Sh2 = fma(-R.D2h, A.sa, R.rho2);
-    const T sig = inv_sqrt(Sh2);
     const T W = sig * sig;
     c.Sh2 = Sh2;
     c.sig = sig;
@@ -343,6 +342,11 @@ __device__ __forceinline__ CoefD<T> coef_diff(const RadF<T> &R, const AngF<T> &A
     const T t = fma(R.K * A.sn2, sig, R.ct_re);
     c.dh = mkc(W * fma(c.bh, t, -R.c1h_re), W * fma(c.bh, cti, -R.c1h_im));
     return c;
+}
+template <typename T>
+__device__ __forceinline__ CoefD<T> coef_diff(const RadF<T> &R, const AngF<T> &A)
+{
+    return coef_diff_sig(R, A, inv_sqrt(fma(-R.D2h, A.sa, R.rho2)));
 }
 
 // Bracket D du / h - S with S_Pi = ct pi0 + c0 ph0 + A2 D2 + A1 D1.

@@ -362,10 +362,10 @@ struct Lane {
     // holds (any lane of the wave holds) the null-infinity column
     const double *lf;
     bool lay_h, lay_n, wlay, scri, wscri;
-    // whole-strip two-step kernel (FP64, no layer): this lane's column of the
-    // wave's LDS ring [3 slots][half node, node][64 lanes] through which
-    // level 1 hands 1/Sigma-hat to level 2
-    double *sgr;
+    // two-step kernels (no layer): this lane's column of the wave's LDS ring
+    // [3 slots][half node, node][64 lanes] through which level 1 hands
+    // 1/Sigma-hat to level 2
+    T *sgr;
 };
 
 template <class P>
@@ -695,12 +695,19 @@ struct Around<P, true> {
 constexpr int kSigNew = 0, kSigPut = 1, kSigGet = 2;
 
 template <class P, int SG>
-__device__ __forceinline__ CoefF<typename P::T> coef_at(const Lane<P> &L, int k, int row, double *sgw, double sgv)
+__device__ __forceinline__ auto coef_at(const Lane<P> &L, int k, int row, typename P::T *sgw, typename P::T sgv)
 {
-    if constexpr (SG == kSigGet) return coef_fused_sig(radf_of(L, k), angf_of<P>(L, row), sgv);
-    const CoefF<typename P::T> cf = coef_fused(radf_of(L, k), angf_of<P>(L, row));
-    if constexpr (SG == kSigPut) *sgw = cf.sig;
-    return cf;
+    if constexpr (!P::kComp) {
+        if constexpr (SG == kSigGet) return coef_fused_sig(radf_of(L, k), angf_of<P>(L, row), sgv);
+        const CoefF<typename P::T> cf = coef_fused(radf_of(L, k), angf_of<P>(L, row));
+        if constexpr (SG == kSigPut) *sgw = cf.sig;
+        return cf;
+    } else {
+        if constexpr (SG == kSigGet) return coef_diff_sig(radf_of(L, k), angf_of<P>(L, row), sgv);
+        const CoefD<typename P::T> cf = coef_diff(radf_of(L, k), angf_of<P>(L, row));
+        if constexpr (SG == kSigPut) *sgw = cf.sig;
+        return cf;
+    }
 }
 
 // Eq. (3) at half row r: u^n rows r-1 (UM), r (U0), r+1 (UP) of this column
@@ -708,7 +715,8 @@ __device__ __forceinline__ CoefF<typename P::T> coef_at(const Lane<P> &L, int k,
 template <class P, int SG = kSigNew>
 __device__ __forceinline__ Half<P> half_core(const Lane<P> &L, const Level &lv, const St<typename P::T> &UM,
                                              const St<typename P::T> &U0, const St<typename P::T> &UP,
-                                             const Around<P> &nb, int r, double *sgw = nullptr, double sgv = 0.0)
+                                             const Around<P> &nb, int r, typename P::T *sgw = nullptr,
+                                             typename P::T sgv = 0)
 {
     using T = typename P::T;
     const DevInst &I = *L.I;
@@ -743,7 +751,7 @@ __device__ __forceinline__ Half<P> half_core(const Lane<P> &L, const Level &lv, 
                 be[k] = e + c[k];
             }
         }
-        CoefD<T> cf = coef_diff(radf_of(L, 0), angf_of<P>(L, r));
+        CoefD<T> cf = coef_at<P, SG>(L, 0, r, sgw, sgv);
         if constexpr (P::kLayer)
             if (L.wlay && L.lay_h) layer_transform(cf, radf_of(L, 0), angf_of<P>(L, r), L.lf, (T)I.h);
         const Q4<T> br = bracket_diff(cf, nb.own.d2 + nb.nb.d2, nb.own.d1 + nb.nb.d1, bar.f.phi, bar.f.pi, du);
@@ -774,7 +782,7 @@ __device__ __forceinline__ Half<P> half_core(const Lane<P> &L, const Level &lv, 
 template <class P, int SG = kSigNew>
 __device__ __forceinline__ Half<P> half_row(const Lane<P> &L, const Level &lv, const St<typename P::T> &UM,
                                             const St<typename P::T> &U0, const St<typename P::T> &UP, int r,
-                                            double *sgw = nullptr, double sgv = 0.0)
+                                            typename P::T *sgw = nullptr, typename P::T sgv = 0)
 {
     Around<P> nb;
     if constexpr (!P::kComp) {
@@ -797,8 +805,8 @@ __device__ __forceinline__ Half<P> half_row(const Lane<P> &L, const Level &lv, c
 template <class P, int SG = kSigNew>
 __device__ __forceinline__ St<typename P::T> out_core(const Lane<P> &L, const Level &lv, const St<typename P::T> &Uo,
                                                       const Half<P> &HM, const Half<P> &H0, const Half<P> &HP,
-                                                      const Around<P> &nb, int o, double *sgw = nullptr,
-                                                      double sgv = 0.0)
+                                                      const Around<P> &nb, int o, typename P::T *sgw = nullptr,
+                                                      typename P::T sgv = 0)
 {
     using T = typename P::T;
     const DevInst &I = *L.I;
@@ -821,7 +829,7 @@ __device__ __forceinline__ St<typename P::T> out_core(const Lane<P> &L, const Le
         const Q4<T> du = comp_diff(H0, nb.z);
         // the averaged fields enter S only through ct and c0: one FP32 value each
         const Q4<T> til = mid_from(nb.z.f, du);
-        CoefD<T> cf = coef_diff(radf_of(L, 1), angf_of<P>(L, o));
+        CoefD<T> cf = coef_at<P, SG>(L, 1, o, sgw, sgv);
         if constexpr (P::kLayer)
             if (L.wlay && L.lay_n) layer_transform(cf, radf_of(L, 1), angf_of<P>(L, o), L.lf + 192, (T)I.h);
         const Q4<T> br = bracket_diff(cf, nb.own.d2 + nb.nb.d2, nb.own.d1 + nb.nb.d1, til.phi, til.pi, du);
@@ -851,7 +859,7 @@ __device__ __forceinline__ St<typename P::T> out_core(const Lane<P> &L, const Le
 template <class P, int SG = kSigNew>
 __device__ __forceinline__ St<typename P::T> out_row(const Lane<P> &L, const Level &lv, const St<typename P::T> &Uo,
                                                      const Half<P> &HM, const Half<P> &H0, const Half<P> &HP, int o,
-                                                     double *sgw = nullptr, double sgv = 0.0)
+                                                     typename P::T *sgw = nullptr, typename P::T sgv = 0)
 {
     Around<P> nb;
     if constexpr (!P::kComp) {
@@ -1039,11 +1047,12 @@ __device__ __forceinline__ void march2(const Lane<P> &L, const Level &l1, const 
     // level 1 took in iteration r-3, which left 1/Sigma-hat in ring slot S;
     // read before level 1 refills the slot.  Where level 2 forms a row here,
     // level 1 formed the same row there (rows 1 .. nt-2 of both kinds).
-    constexpr bool kShare = !P::kComp && !P::kLayer;
+    using T = typename P::T;
+    constexpr bool kShare = !P::kLayer;
     constexpr int SG1 = kShare ? kSigPut : kSigNew, SG2 = kShare ? kSigGet : kSigNew;
-    double *const sgh = kShare ? L.sgr + (2 * S) * 64 : nullptr;
-    double *const sgn = kShare ? L.sgr + (2 * S + 1) * 64 : nullptr;
-    const double sg2h = kShare ? *sgh : 0.0, sg2n = kShare ? *sgn : 0.0;
+    T *const sgh = kShare ? L.sgr + (2 * S) * 64 : nullptr;
+    T *const sgn = kShare ? L.sgr + (2 * S + 1) * 64 : nullptr;
+    const T sg2h = kShare ? *sgh : T(0), sg2n = kShare ? *sgn : T(0);
     // level 1: half rows r-2 (SP), r-1 (SM), r (S); u^n rows r-1 (SM), r (S), r+1 (SP)
     if (!EDGE || r <= nt - 2) {
         advance_rows<P, S>(L, R, r, nt - 1);
@@ -1138,11 +1147,12 @@ __device__ __forceinline__ void march2c(const Lane<P> &L, const Level &l1, const
     // every row level 2 forms among the rows level 1 formed three
     // iterations earlier (g_lo..g_hi within r_lo..h1_hi, o_lo..o_hi within
     // v_lo..v_hi)
-    constexpr bool kShare = !P::kComp && !P::kLayer;
+    using T = typename P::T;
+    constexpr bool kShare = !P::kLayer;
     constexpr int SG1 = kShare ? kSigPut : kSigNew, SG2 = kShare ? kSigGet : kSigNew;
-    double *const sgh = kShare ? L.sgr + (2 * S) * 64 : nullptr;
-    double *const sgn = kShare ? L.sgr + (2 * S + 1) * 64 : nullptr;
-    const double sg2h = kShare ? *sgh : 0.0, sg2n = kShare ? *sgn : 0.0;
+    T *const sgh = kShare ? L.sgr + (2 * S) * 64 : nullptr;
+    T *const sgn = kShare ? L.sgr + (2 * S + 1) * 64 : nullptr;
+    const T sg2h = kShare ? *sgh : T(0), sg2n = kShare ? *sgn : T(0);
     if (!EDGE || r <= B.h1_hi) {
         advance_rows<P, S>(L, R, r, B.h1_hi + 1);
         R.H[S] = half_row<P, SG1>(L, l1, R.U[SM], R.U[S], R.U[SP], r, sgh);
@@ -1552,7 +1562,7 @@ __global__ void __launch_bounds__(64 * kFusedWavesPerBlock)
 // One wave's work item of k_fused2 (the kernel picks the form).
 template <class P>
 __device__ __forceinline__ void k_fused2_wave(const DevInst &I, const WorkItem &it, int lane, int cols, int buf,
-                                               typename P::T *rad, double *lay, double *sg, long long n)
+                                               typename P::T *rad, double *lay, typename P::T *sg, long long n)
 {
     Lane<P> L;
     init_lane(L, I, it, lane, 2, cols, buf, rad, true, lay);
@@ -1595,7 +1605,7 @@ __global__ void __launch_bounds__(64 * kFusedWavesPerBlock) __attribute__((amdgp
     using T = typename P::T;
     __shared__ T s_rad[kFusedWavesPerBlock][P::kRadRegs ? 2 : 2 * kRadF * 64];
     __shared__ double s_lay[kFusedWavesPerBlock][P::kLayer ? 6 * 64 : 1];
-    __shared__ double s_sig[kFusedWavesPerBlock][P::kComp ? 1 : 6 * 64];  // Lane::sgr
+    __shared__ T s_sig[kFusedWavesPerBlock][6 * 64];  // Lane::sgr
     const int lane = (int)(threadIdx.x & 63);
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int w = (int)blockIdx.x * kFusedWavesPerBlock + wv;
@@ -1624,7 +1634,7 @@ __global__ void __launch_bounds__(64 * kFusedWavesPerBlock) __attribute__((amdgp
 // One wave's work item of k_fused2c (the kernel picks the form).
 template <class P>
 __device__ __forceinline__ void k_fused2c_wave(const DevInst &I, const WorkItem &it, int lane, int cols, int buf,
-                                                typename P::T *rad, double *lay, double *sg, long long n)
+                                                typename P::T *rad, double *lay, typename P::T *sg, long long n)
 {
     Lane<P> L;
     init_lane(L, I, it, lane, 2, cols, buf, rad, true, lay);
@@ -1668,7 +1678,7 @@ __global__ void __launch_bounds__(64 * kFusedWavesPerBlock) __attribute__((amdgp
     using T = typename P::T;
     __shared__ T s_rad[kFusedWavesPerBlock][P::kRadRegs ? 2 : 2 * kRadF * 64];
     __shared__ double s_lay[kFusedWavesPerBlock][P::kLayer ? 6 * 64 : 1];
-    __shared__ double s_sig[kFusedWavesPerBlock][P::kComp ? 1 : 6 * 64];  // Lane::sgr
+    __shared__ T s_sig[kFusedWavesPerBlock][6 * 64];  // Lane::sgr
     const int lane = (int)(threadIdx.x & 63);
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int w = (int)blockIdx.x * kFusedWavesPerBlock + wv;
@@ -1681,12 +1691,12 @@ __global__ void __launch_bounds__(64 * kFusedWavesPerBlock) __attribute__((amdgp
         // a wave whose columns all stay below the layer runs the plain form
         if (!touches_layer(I, it, 2)) {
             k_fused2c_wave<typename P::Plain>(I, it, lane, kFused2Cols, buf, &s_rad[wv][2 * lane], nullptr,
-                                              &s_sig[wv][P::kComp ? 0 : lane], n);
+                                              &s_sig[wv][lane], n);
             return;
         }
     }
     k_fused2c_wave<P>(I, it, lane, kFused2Cols, buf, &s_rad[wv][2 * lane], &s_lay[wv][P::kLayer ? lane : 0],
-                      &s_sig[wv][P::kComp ? 0 : lane], n);
+                      &s_sig[wv][lane], n);
 }
 
 template <class P>
