@@ -36,12 +36,13 @@ ALU_PEAK_TFLOPS = {"fp64": 78.6, "fp32c": 157.3}
 # 32 for the update of Eq. (4)) and drops a Newton step and the folded
 # weights: 312 FP32 operations per update.
 FLOPS_PER_UPDATE = {"fp64": 202, "fp32c": 312}
-# The FP64 two-step kernels form Sigma-hat and 1/Sigma-hat once for both
-# levels (level 2 takes level 1's value at the same point): per level-2 stage
-# point the multiply-add of Sigma-hat^2 (2) and the inverse square root (12:
-# the estimate, x/2, and two Newton steps of 5) are not formed again, 28 per
-# level-2 update, 14 per update on average.
-FLOPS_SHARED_TWO_STEP = {"fp64": 14, "fp32c": 0}
+# The two-step kernels form Sigma-hat and 1/Sigma-hat once for both levels
+# (level 2 takes level 1's value at the same point): per level-2 stage point
+# the multiply-add of Sigma-hat^2 (2) and the inverse square root are not
+# formed again.  FP64: 12 for the root (the estimate, x/2, two Newton steps
+# of 5), 28 per level-2 update, 14 per update on average.  FP32C: 7 for the
+# root (one Newton step), 18 per level-2 update, 9 per update.
+FLOPS_SHARED_TWO_STEP = {"fp64": 14, "fp32c": 9}
 
 
 def flops_per_update(precision, two_step):
