@@ -12,6 +12,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -48,16 +49,29 @@ FLOPS_SHARED_TWO_STEP = {"fp64": 14, "fp32c": 9}
 def flops_per_update(precision, two_step):
     """FP64 / FP32 operations per point update the launch's formulas need."""
     return FLOPS_PER_UPDATE[precision] - (FLOPS_SHARED_TWO_STEP[precision] if two_step else 0)
+
+
 KERNEL_POLICY = {"fp64": "PolicyF64", "fp32c": "PolicyF32C"}
 KERNEL_SOURCES = ["paper_1206_0270_amd/csrc/tk_kernels.hip", "paper_1206_0270_amd/csrc/tk_device.h",
                   "paper_1206_0270_amd/csrc/tk_internal.h"]
 
 
+def _code_only(text):
+    """C/C++ source without its comments and blank lines: what the compiler
+    sees of it, so that a comment edit leaves the hash (and the counters
+    recorded under it) valid.  No string literal in the kernel sources holds a
+    comment marker."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return "\n".join(l.rstrip() for l in text.split("\n") if l.strip())
+
+
 def kernel_hash():
+    """Hash of the kernel sources' code (comments left out)."""
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, p)) as f:
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()[:16]
 
 

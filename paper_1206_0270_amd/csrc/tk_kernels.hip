@@ -689,9 +689,9 @@ struct Around<P, true> {
     AngD<typename P::T> own, nb;
 };
 
-// How the FP64 row functions get 1/Sigma-hat at their point (SG): computed
-// (kSigNew), computed and left at sgw for a later level (kSigPut), or taken
-// as sgv, the value an earlier level left (kSigGet).
+// How the row functions get 1/Sigma-hat at their point (SG), in either
+// form: computed (kSigNew), computed and left at sgw for a later level
+// (kSigPut), or taken as sgv, the value an earlier level left (kSigGet).
 constexpr int kSigNew = 0, kSigPut = 1, kSigGet = 2;
 
 template <class P, int SG>

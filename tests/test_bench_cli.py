@@ -104,3 +104,11 @@ def test_two_step_flops_per_update():
     per_point32 = 2 + 1 + 1 + (1 + 2 + 2)
     assert bench.flops_per_update("fp32c", False) == 312
     assert bench.flops_per_update("fp32c", True) == 312 - 2 * per_point32 // 2
+
+
+def test_kernel_hash_ignores_comments_only():
+    code = "int a; // one\n/* two\n three */ int b;\n\n  // four\nint c; /* five */\n"
+    # a block comment stands as one blank, as the compiler reads it
+    assert bench._code_only(code) == bench._code_only("int a;\n  int b;\nint c;\n")
+    assert bench._code_only(code) != bench._code_only("int a;\n  int b;\nint d;\n")
+    assert len(bench.kernel_hash()) == 16
