@@ -279,6 +279,50 @@ __device__ __forceinline__ CoefF<T> coef_fused(const RadF<T> &R, const AngF<T> &
     return coef_fused_sig(R, A, inv_sqrt(fma(-R.D2h, A.sa, R.rho2)));
 }
 
+// The same coefficients with the metric factor W = 1/Sigma-hat^2 left out:
+// every term of S_Pi and of d du carries it, so the plain (layer-free) form
+// sums the Pi row from these W-free factors and multiplies by W once.
+// P, M = Ap / W, Am / W = D2h (1 +- kc); ct, c0 = ct / W, c0a / W; d = (d/h) / W.
+template <typename T>
+struct CoefW {
+    T W, bh, P, M;
+    cx<T> ct, c0, d;
+};
+template <typename T>
+__device__ __forceinline__ CoefW<T> coef_w_sig(const RadF<T> &R, const AngF<T> &A, T sig)
+{
+    CoefW<T> c;
+    c.W = sig * sig;
+    c.bh = R.rho_h * sig;
+    c.P = fma(R.D2h, A.kc, R.D2h);
+    c.M = fma(-R.D2h, A.kc, R.D2h);
+    const T cti = fma(R.D2h, A.kcs, R.ct_im0);
+    c.ct = mkc(R.ct_re, cti);
+    c.c0 = mkc(fma(T(-4), R.D2h, fma(-R.D2h, A.V2, R.c0_re)), R.c0_im);
+    const T t = fma(R.K * A.sn2, sig, R.ct_re);
+    c.d = mkc(fma(c.bh, t, -R.c1h_re), fma(c.bh, cti, -R.c1h_im));
+    return c;
+}
+
+// Bracket D du / h - S from the W-free factors (arguments as bracket_fused's
+// below, no source term: the fused path adds it afterwards):
+//   Pi row = W (d' du_Phi - S'_Pi) - b du_Pi, S'_Pi = S_Pi / W.
+template <typename T>
+__device__ __forceinline__ Q4<T> bracket_w(const CoefW<T> &c, cx<T> pm, cx<T> pp, cx<T> ph0, cx<T> pi0,
+                                           const Q4<T> &du)
+{
+    const T sre = fma(c.ct.re, pi0.re,
+                      fma(-c.ct.im, pi0.im, fma(c.c0.re, ph0.re, fma(-c.c0.im, ph0.im, fma(c.P, pp.re, c.M * pm.re)))));
+    const T sim = fma(c.ct.re, pi0.im,
+                      fma(c.ct.im, pi0.re, fma(c.c0.re, ph0.im, fma(c.c0.im, ph0.re, fma(c.P, pp.im, c.M * pm.im)))));
+    const T xre = fma(c.d.re, du.phi.re, fma(-c.d.im, du.phi.im, -sre));
+    const T xim = fma(c.d.re, du.phi.im, fma(c.d.im, du.phi.re, -sim));
+    Q4<T> br;
+    br.phi = mkc(fma(c.bh, du.phi.re, -pi0.re), fma(c.bh, du.phi.im, -pi0.im));
+    br.pi = mkc(fma(c.W, xre, -(c.bh * du.pi.re)), fma(c.W, xim, -(c.bh * du.pi.im)));
+    return br;
+}
+
 // Bracket D du / h - S at a point: pm, pp = the two values whose average is
 // Phi on rows j-1, j+1; ph0, pi0 = averaged fields on row j; du = the
 // difference across the cell; F = source (zero off its window).

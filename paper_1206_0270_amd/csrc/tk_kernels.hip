@@ -236,6 +236,19 @@ struct St {  // stored value of a point: f (+ c in the compensated form)
     Q4<T> f, c;
 };
 
+// Componentwise choice between two rows (a select of whole structs would
+// keep them in memory).
+template <typename T>
+__device__ __forceinline__ Q4<T> pick(bool c, const Q4<T> &a, const Q4<T> &b)
+{
+    return Q4<T>{mkc(c ? a.phi.re : b.phi.re, c ? a.phi.im : b.phi.im), mkc(c ? a.pi.re : b.pi.re, c ? a.pi.im : b.pi.im)};
+}
+template <typename T>
+__device__ __forceinline__ St<T> pick(bool c, const St<T> &a, const St<T> &b)
+{
+    return St<T>{pick(c, a.f, b.f), pick(c, a.c, b.c)};
+}
+
 // Neighbour-column exchange inside the wave by DPP wave shifts (a vector
 // move, no LDS round trip): shfl_down1 gives lane l the value of lane l+1,
 // shfl_up1 that of lane l-1; the lane at the open end gets 0 (bound_ctrl; it
@@ -710,6 +723,19 @@ __device__ __forceinline__ auto coef_at(const Lane<P> &L, int k, int row, typena
     }
 }
 
+// The plain FP64 form's W-free coefficients (coef_w_sig), with 1/Sigma-hat
+// as coef_at takes it.
+template <class P, int SG>
+__device__ __forceinline__ CoefW<double> coef_w_at(const Lane<P> &L, int k, int row, double *sgw, double sgv)
+{
+    const RadF<double> R = radf_of(L, k);
+    const AngF<double> A = angf_of<P>(L, row);
+    if constexpr (SG == kSigGet) return coef_w_sig(R, A, sgv);
+    const double sig = inv_sqrt(fma(-R.D2h, A.sa, R.rho2));
+    if constexpr (SG == kSigPut) *sgw = sig;
+    return coef_w_sig(R, A, sig);
+}
+
 // Eq. (3) at half row r: u^n rows r-1 (UM), r (U0), r+1 (UP) of this column
 // and what it needs of the column to the right (nb).
 template <class P, int SG = kSigNew>
@@ -729,10 +755,18 @@ __device__ __forceinline__ Half<P> half_core(const Lane<P> &L, const Level &lv, 
     if constexpr (!P::kComp) {
         const Q4<T> du = nb.z - U0.f;
         const Q4<T> bar = mid_from(U0.f, du);
-        CoefF<T> cf = coef_at<P, SG>(L, 0, r, sgw, sgv);
-        if constexpr (P::kLayer)
-            if (L.wlay && L.lay_h) layer_transform(cf, radf_of(L, 0), angf_of<P>(L, r), L.lf, I.h);
-        Q4<T> br = bracket_fused(cf, nb.m + UM.f.phi, nb.p + UP.f.phi, bar.phi, bar.pi, du, no_source<T>());
+        // a lane outside the layer takes the plain form's value in either
+        // form of the wave, so that its bits do not depend on which waves
+        // a kernel's work list runs in the layered form
+        Q4<T> br = bracket_w(coef_w_at<P, SG>(L, 0, r, sgw, sgv), nb.m + UM.f.phi, nb.p + UP.f.phi, bar.phi, bar.pi, du);
+        if constexpr (P::kLayer) {
+            if (L.wlay) {
+                CoefF<T> cf = coef_at<P, SG>(L, 0, r, sgw, sgv);
+                if (L.lay_h) layer_transform(cf, radf_of(L, 0), angf_of<P>(L, r), L.lf, I.h);
+                br = pick(L.lay_h,
+                          bracket_fused(cf, nb.m + UM.f.phi, nb.p + UP.f.phi, bar.phi, bar.pi, du, no_source<T>()), br);
+            }
+        }
         add_source(L.gh, L.ang, r, lv.eh, br);
         return lw_update(bar, fac, br);
     } else {
@@ -817,10 +851,15 @@ __device__ __forceinline__ St<typename P::T> out_core(const Lane<P> &L, const Le
     if constexpr (!P::kComp) {
         const Q4<T> du = H0 - nb.z;
         const Q4<T> til = mid_from(nb.z, du);
-        CoefF<T> cf = coef_at<P, SG>(L, 1, o, sgw, sgv);
-        if constexpr (P::kLayer)
-            if (L.wlay && L.lay_n) layer_transform(cf, radf_of(L, 1), angf_of<P>(L, o), L.lf + 192, I.h);
-        Q4<T> br = bracket_fused(cf, HM.phi + nb.m, HP.phi + nb.p, til.phi, til.pi, du, no_source<T>());
+        Q4<T> br = bracket_w(coef_w_at<P, SG>(L, 1, o, sgw, sgv), HM.phi + nb.m, HP.phi + nb.p, til.phi, til.pi, du);
+        if constexpr (P::kLayer) {
+            if (L.wlay) {  // lanes outside the layer keep the plain value (half_core)
+                CoefF<T> cf = coef_at<P, SG>(L, 1, o, sgw, sgv);
+                if (L.lay_n) layer_transform(cf, radf_of(L, 1), angf_of<P>(L, o), L.lf + 192, I.h);
+                br = pick(L.lay_n, bracket_fused(cf, HM.phi + nb.m, HP.phi + nb.p, til.phi, til.pi, du, no_source<T>()),
+                          br);
+            }
+        }
         add_source(L.gn, L.ang, o, lv.ef, br);
         res.f = lw_update(Uo.f, L.dt, br);
     } else {
@@ -1011,18 +1050,6 @@ struct Roll2 {
     St<T> keep;          // a u^{n+2} row kept for a pole
 };
 
-// Componentwise choice between two rows (a select of whole structs would
-// keep them in memory).
-template <typename T>
-__device__ __forceinline__ Q4<T> pick(bool c, const Q4<T> &a, const Q4<T> &b)
-{
-    return Q4<T>{mkc(c ? a.phi.re : b.phi.re, c ? a.phi.im : b.phi.im), mkc(c ? a.pi.re : b.pi.re, c ? a.pi.im : b.pi.im)};
-}
-template <typename T>
-__device__ __forceinline__ St<T> pick(bool c, const St<T> &a, const St<T> &b)
-{
-    return St<T>{pick(c, a.f, b.f), pick(c, a.c, b.c)};
-}
 
 // Iteration r (1 <= r <= nt+2, slot S = (r - 1) mod 3).  Level 1 takes
 // u^n row r+1 and forms half row r and u^{n+1} row r-1.  Level 2, three rows
@@ -1604,7 +1631,6 @@ __global__ void __launch_bounds__(64 * kFusedWavesPerBlock) __attribute__((amdgp
 {
     using T = typename P::T;
     __shared__ T s_rad[kFusedWavesPerBlock][P::kRadRegs ? 2 : 2 * kRadF * 64];
-    __shared__ double s_lay[kFusedWavesPerBlock][P::kLayer ? 6 * 64 : 1];
     __shared__ T s_sig[kFusedWavesPerBlock][6 * 64];  // Lane::sgr
     const int lane = (int)(threadIdx.x & 63);
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -1614,21 +1640,14 @@ __global__ void __launch_bounds__(64 * kFusedWavesPerBlock) __attribute__((amdgp
     const DevInst &I = insts[it.inst];
     const long long n = ctl->step + kstep;
     const int buf = (int)((ctl->cur + kflip) & 1);
-    if constexpr (P::kLayer) {
-        // a wave whose columns all stay below the layer runs the plain form
-        if (!touches_layer(I, it, 2)) {
-            k_fused2_wave<typename P::Plain>(I, it, lane, kFused2Cols, buf, &s_rad[wv][2 * lane], nullptr,
-                                             &s_sig[wv][lane], n);
-            return;
-        }
-    } else if (inner_wave(I, it, 2)) {
+    static_assert(!P::kLayer, "layered contexts march whole strips with k_fused2c");
+    if (inner_wave(I, it, 2)) {
         // the form without the Dirichlet mask (only in this kernel: a second
         // body made the chunked kernel's short marches measurably slower)
         k_fused2_wave<Inner<P>>(I, it, lane, kFused2Cols, buf, &s_rad[wv][2 * lane], nullptr, &s_sig[wv][lane], n);
         return;
     }
-    k_fused2_wave<P>(I, it, lane, kFused2Cols, buf, &s_rad[wv][2 * lane], &s_lay[wv][P::kLayer ? lane : 0],
-                     &s_sig[wv][lane], n);
+    k_fused2_wave<P>(I, it, lane, kFused2Cols, buf, &s_rad[wv][2 * lane], nullptr, &s_sig[wv][lane], n);
 }
 
 // One wave's work item of k_fused2c (the kernel picks the form).
@@ -1709,12 +1728,14 @@ hipError_t launch_as(const DevInst *d_inst, const WorkItem *d_work, int n_work, 
     // code too (a strip is the chunk [0, n_theta), the same march with the
     // same pole bookkeeping): the whole-strip kernel's unrolled head and tail
     // keep its half-step pairs in more registers than the register file
-    // holds for two waves per SIMD.
-    if constexpr (P::kComp) chunked = chunked || two_step;
+    // holds for two waves per SIMD.  So does the layered FP64 form: on the
+    // waves that reach a layer the whole-strip kernel would form both the
+    // plain and the layer's bracket in more registers than that.
+    if constexpr (P::kComp || P::kLayer) chunked = chunked || two_step;
     if (two_step && chunked)
         hipLaunchKernelGGL(k_fused2c<P>, dim3(blocks), dim3(64 * kFusedWavesPerBlock), 0, s, d_inst, d_work, n_work,
                            ctl, kstep, kflip);
-    else if constexpr (!P::kComp) {
+    else if constexpr (!P::kComp && !P::kLayer) {
         if (two_step)
             hipLaunchKernelGGL(k_fused2<P>, dim3(blocks), dim3(64 * kFusedWavesPerBlock), 0, s, d_inst, d_work,
                                n_work, ctl, kstep, kflip);
