@@ -29,14 +29,16 @@ ALU_PEAK_TFLOPS = {"fp64": 78.6, "fp32c": 157.3}
 # Floating-point operations per point update (both stages of Eqs. (3)-(4))
 # as the fused kernels' formulas are written, an FMA counting two: FP64, per
 # stage, the radial difference and average (12), the coefficients at the
-# point (39: Sigma-hat, its inverse square root with two Newton steps, the
-# ten products of the factored coefficients), the bracket (42) and the
-# update (8): 101, 202 per update.  The compensated form, per stage, adds the
+# point (33: Sigma-hat^2 (2), its inverse square root with two Newton steps
+# (12), and the factored coefficients with the metric factor W left out of
+# the Pi row (19)), the bracket with the angular neighbour sums (44: 4 sums,
+# the Pi row's sum 22 times W once, the Phi row 4, the Pi row's b du 6) and
+# the update (8): 97, 194 per update.  The compensated form, per stage, adds the
 # Kahan terms to every difference (radial 12, angular column differences 20),
 # keeps the average and the half step as two-sum pairs (32 + 32 in Eq. (3),
 # 32 for the update of Eq. (4)) and drops a Newton step and the folded
 # weights: 312 FP32 operations per update.
-FLOPS_PER_UPDATE = {"fp64": 202, "fp32c": 312}
+FLOPS_PER_UPDATE = {"fp64": 194, "fp32c": 312}
 # The two-step kernels form Sigma-hat and 1/Sigma-hat once for both levels
 # (level 2 takes level 1's value at the same point): per level-2 stage point
 # the multiply-add of Sigma-hat^2 (2) and the inverse square root are not
